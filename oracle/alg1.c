@@ -1,0 +1,141 @@
+/*
+ * Algorithm 1 (Proposed convolution) of Flash, arXiv 2401.16732, in plain C.
+ *
+ * TEST INFRASTRUCTURE ONLY: part of the CPU oracle. Only the tests, the smoke
+ * check and the benchmark's CPU-baseline leg load it. It shares no code with
+ * the GPU library.
+ *
+ * For output channel i and row tile tau (one polynomial p of the ciphertext,
+ * one RNS limb q):
+ *     partial = 0
+ *     for each input channel j:
+ *         c = x[ciphertext holding (j, tau)]
+ *         t = sum over taps k of DRot(c, s_k) * f[i][j][k]      (CMult + DRot)
+ *         partial += DRot(t, o_j)
+ *     y = partial mod q                                          (one reduction)
+ * DRot(c, step) is c(x) * x^(-step) mod x^n + 1 (eq. drot); coefficient m of
+ * the result is (-1)^floor((m + step) / n) * c[(m + step) mod n] (closed form
+ * in the Appendix A proof). Sums are kept unreduced in int64, the paper's lazy
+ * reduction (Employing Lazy Reduction in Convolution): |c| < 2^31, |f| <= 128,
+ * at most 49 taps and 2^12 channels keep |partial| below 2^57.
+ *
+ * The layout (tap shifts s_k, channel offsets o_j, which ciphertext holds
+ * (j, tau)) is supplied by the caller.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* dst += DRot(src, step) * w  (w = 1 for the channel alignment). */
+static void drot_axpy(int64_t *dst, const int64_t *src, uint32_t n, uint32_t step, int64_t w)
+{
+    for (uint32_t m = 0; m < n; ++m) {
+        uint32_t k = m + step;
+        if (k < n)
+            dst[m] += w * src[k];
+        else
+            dst[m] -= w * src[k - n];
+    }
+}
+
+static void drot_axpy_u32(int64_t *dst, const uint32_t *src, uint32_t n, uint32_t step, int64_t w)
+{
+    for (uint32_t m = 0; m < n; ++m) {
+        uint32_t k = m + step;
+        if (k < n)
+            dst[m] += w * (int64_t)src[k];
+        else
+            dst[m] -= w * (int64_t)src[k - n];
+    }
+}
+
+/*
+ * One layer on one image.
+ *   x        : input ciphertexts [G][2][L][n]
+ *   in_ct    : [c_i * T]   in_ct[j*T + tau] = index of the ciphertext holding (j, tau)
+ *   chan_off : [c_i]       o_j
+ *   tap_off  : [n_taps]    s_k
+ *   filters  : [c_o][c_i][n_taps] int8
+ *   outs     : [n_out]     output channels to compute
+ *   y        : [n_out * T][2][L][n]
+ * Returns 0, or -1 on allocation failure.
+ */
+int oracle_alg1_layer(uint32_t n, uint32_t L, const uint32_t *q, uint32_t c_i, uint32_t T,
+                      uint32_t n_taps, const uint32_t *tap_off, const uint32_t *chan_off,
+                      const uint32_t *in_ct, const int8_t *filters, const uint32_t *x,
+                      uint32_t n_out, const uint32_t *outs, uint32_t *y)
+{
+    int64_t jobs = (int64_t)n_out * T * 2 * L;
+    int err = 0;
+#pragma omp parallel
+    {
+        int64_t *t = (int64_t *)malloc(sizeof(int64_t) * n);
+        int64_t *partial = (int64_t *)malloc(sizeof(int64_t) * n);
+        if (!t || !partial) {
+#pragma omp atomic write
+            err = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t job = 0; job < jobs; ++job) {
+            if (!t || !partial) continue;
+            uint32_t l = (uint32_t)(job % L);
+            uint32_t p = (uint32_t)((job / L) % 2);
+            uint32_t tau = (uint32_t)((job / (2 * L)) % T);
+            uint32_t oi = (uint32_t)(job / (2 * (int64_t)L * T));
+            uint32_t i = outs[oi];
+            memset(partial, 0, sizeof(int64_t) * n);
+            for (uint32_t j = 0; j < c_i; ++j) {
+                const uint32_t *c = x + (((size_t)in_ct[(size_t)j * T + tau] * 2 + p) * L + l) * n;
+                const int8_t *fk = filters + ((size_t)i * c_i + j) * n_taps;
+                memset(t, 0, sizeof(int64_t) * n);
+                for (uint32_t k = 0; k < n_taps; ++k)
+                    if (fk[k] != 0)
+                        drot_axpy_u32(t, c, n, tap_off[k], (int64_t)fk[k]);
+                drot_axpy(partial, t, n, chan_off[j], 1);
+            }
+            uint32_t *out = y + (((size_t)oi * T + tau) * 2 + p) * L * n + (size_t)l * n;
+            int64_t ql = (int64_t)q[l];
+            for (uint32_t m = 0; m < n; ++m) {
+                int64_t r = partial[m] % ql;
+                out[m] = (uint32_t)(r < 0 ? r + ql : r);
+            }
+        }
+        free(t);
+        free(partial);
+    }
+    return err ? -1 : 0;
+}
+
+/*
+ * Selected coefficients of Algorithm 1's output, by the closed form of the
+ * composed rotations: with e = o_j + s_k (< n),
+ *     y[m] = sum_j sum_k f[i][j][k] * (-1)^floor((m + e) / n) * c_(j,tau)[(m + e) mod n]  mod q.
+ * Point r asks for (output channel pt_i[r], tile pt_tau[r], poly pt_p[r],
+ * limb pt_l[r], coefficient pt_m[r]); the answer goes to val[r].
+ */
+void oracle_alg1_points(uint32_t n, uint32_t L, const uint32_t *q, uint32_t c_i, uint32_t T,
+                        uint32_t n_taps, const uint32_t *tap_off, const uint32_t *chan_off,
+                        const uint32_t *in_ct, const int8_t *filters, const uint32_t *x,
+                        uint64_t n_pts, const uint32_t *pt_i, const uint32_t *pt_tau,
+                        const uint32_t *pt_p, const uint32_t *pt_l, const uint32_t *pt_m,
+                        uint32_t *val)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < (int64_t)n_pts; ++r) {
+        uint32_t i = pt_i[r], tau = pt_tau[r], p = pt_p[r], l = pt_l[r], m = pt_m[r];
+        int64_t acc = 0;
+        for (uint32_t j = 0; j < c_i; ++j) {
+            const uint32_t *c = x + (((size_t)in_ct[(size_t)j * T + tau] * 2 + p) * L + l) * n;
+            const int8_t *fk = filters + ((size_t)i * c_i + j) * n_taps;
+            for (uint32_t k = 0; k < n_taps; ++k) {
+                uint32_t idx = m + chan_off[j] + tap_off[k];
+                int64_t v = (int64_t)c[idx % n];
+                if ((idx / n) % 2 == 1) v = -v;
+                acc += (int64_t)fk[k] * v;
+            }
+        }
+        int64_t ql = (int64_t)q[l];
+        int64_t rr = acc % ql;
+        val[r] = (uint32_t)(rr < 0 ? rr + ql : rr);
+    }
+}

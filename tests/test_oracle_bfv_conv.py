@@ -1,0 +1,218 @@
+"""Pins for the oracle's toy BFV, layout and Algorithm 1.
+
+What fixes each function (none of these retypes the function under test):
+  * encryption/decryption: fresh-ciphertext noise equals the sampled error
+    exactly; HAdd/CMult/DRot act on messages as the paper states; DRot leaves
+    the noise norm unchanged (Appendix A); Algorithm 2 equals direct encryption.
+  * Algorithm 1: equals the ring product sum_g c_g W_{i,g} (schoolbook), and
+    decrypting its masked, extracted output minus the mask equals the plain
+    convolution mod t, which is pinned to scipy's correlate2d.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.signal
+
+from oracle import bfv, calg1, conv, layout, params, ring
+from paper_2401_16732_amd import workloads as W
+
+
+def _ctx(n=64, L=2, t=2 ** 8):
+    return params.rns_primes(n, L), t
+
+
+def test_fresh_noise_is_the_error_and_decrypt_inverts():
+    n = 64
+    primes, t = _ctx(n)
+    g = W.rng(11)
+    for _ in range(5):
+        m = g.integers(-(t // 2) + 1, t // 2 + 1, size=n)
+        s, a, e = bfv.sample_secret(g, n), bfv.sample_a(g, primes, n), bfv.sample_error(g, n)
+        ct = bfv.encrypt_sk(m, s, a, e, primes, t)
+        assert bfv.noise_inf(ct, s, m, primes, t) == int(np.abs(e).max())
+        assert bfv.decrypt(ct, s, primes, t) == [int(v) % t for v in m]
+
+
+def test_hadd_cmult_drot_act_on_messages():
+    n = 64
+    primes, t = _ctx(n)
+    g = W.rng(12)
+    s = bfv.sample_secret(g, n)
+    m1 = g.integers(-20, 20, size=n)
+    m2 = g.integers(-20, 20, size=n)
+    c1 = bfv.encrypt_sk(m1, s, bfv.sample_a(g, primes, n), bfv.sample_error(g, n), primes, t).astype(np.int64)
+    c2 = bfv.encrypt_sk(m2, s, bfv.sample_a(g, primes, n), bfv.sample_error(g, n), primes, t).astype(np.int64)
+    qv = np.array(primes, dtype=np.int64)[None, :, None]
+    hadd = (c1 + c2) % qv
+    assert bfv.decrypt(hadd, s, primes, t) == [int(v) % t for v in m1 + m2]
+    cm = (c1 * 5) % qv
+    assert bfv.decrypt(cm, s, primes, t) == [int(v) % t for v in 5 * m1]
+    for step in (0, 3, 17, 63):
+        rot = np.stack([np.stack([ring.drot(c1[p, l], step, primes[l]) for l in range(len(primes))]) for p in range(2)])
+        assert bfv.decrypt(rot, s, primes, t) == [int(v) % t for v in ring.drot(m1, step)]
+        # DRot adds no noise (Appendix A): the noise norm is unchanged
+        assert bfv.noise_inf(rot, s, ring.drot(m1, step), primes, t) == bfv.noise_inf(c1, s, m1, primes, t)
+
+
+def test_algorithm2_online_encryption_equals_direct_encryption():
+    n = 64
+    primes, t = _ctx(n)
+    g = W.rng(13)
+    s, a, e = bfv.sample_secret(g, n), bfv.sample_a(g, primes, n), bfv.sample_error(g, n)
+    m = g.integers(-(t // 2) + 1, t // 2 + 1, size=n)
+    z = bfv.encrypt_zero(s, a, e, primes)
+    assert (bfv.online_encrypt(z, m, primes, t) == bfv.encrypt_sk(m, s, a, e, primes, t)).all()
+
+
+SHAPES = [  # (n, c_i, c_o, h, w, f_w, stride)
+    (64, 3, 2, 4, 4, 3, 1),
+    (64, 5, 3, 3, 3, 1, 1),
+    (64, 2, 2, 5, 5, 3, 2),
+    (64, 2, 2, 6, 6, 1, 2),
+    (64, 2, 3, 9, 9, 3, 1),     # tiled: F = 121 > 64
+    (64, 1, 2, 12, 10, 3, 2),   # tiled with stride
+    (128, 2, 2, 9, 9, 5, 1),
+    (128, 3, 2, 14, 12, 5, 2),  # tiled, 5x5, stride 2, ragged last tile
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_layout_is_a_valid_direct_encoding(shape):
+    n, ci, co, h, w, fw, s = shape
+    P = layout.plan(n, ci, co, h, w, fw, s)
+    # every (channel, tile) occupies distinct in-range coefficients
+    seen = {}
+    rows = P.r_o + P.f_w - 1 if P.tiled else P.hp
+    for j, tau in itertools.product(range(P.c_i), range(P.T)):
+        for y in range(tau * P.r_o, min(tau * P.r_o + rows, P.hp)):
+            for x in range(P.wp):
+                k = P.chan_off(j) + (y - tau * P.r_o) * P.wp + x
+                key = (P.in_ct(j, tau), k)
+                assert 0 <= k < n and key not in seen
+                seen[key] = (j, y, x)
+    # every output pixel maps to one (tile, coefficient) and its taps never wrap
+    maxtap = P.tap_off(P.f_w - 1, P.f_w - 1)
+    hit = set()
+    for oy, ox in itertools.product(range(P.ho), range(P.wo)):
+        tau, e = P.out_pos(oy, ox)
+        assert 0 <= tau < P.T and (tau, e) not in hit
+        hit.add((tau, e))
+        for j in range(P.c_i):
+            assert P.chan_off(j) + e + maxtap < n
+    assert (P.ho, P.wo) == ((h - 1) // s + 1, (w - 1) // s + 1)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_alg1_equals_ring_product_and_c_version(shape):
+    n, ci, co, h, w, fw, s = shape
+    primes, t = _ctx(n, 2)
+    P = layout.plan(n, ci, co, h, w, fw, s)
+    g = W.rng(hash(shape) % 2 ** 32)
+    f = W.gen_filters(g, W.ConvSpec(ci, co, h, w, fw, s))
+    x = W.gen_ct_limbs(g, (P.G, 2), primes, n)
+    y = conv.alg1_conv(x, f, P, primes)
+    assert (y == conv.ring_conv(x, f, P, primes)).all()
+    assert (y == calg1.alg1_layer(x, f, P, primes)).all()
+    # closed-form points agree with the full computation
+    pts = g.integers(0, [co, P.T, 2, len(primes), n], size=(40, 5))
+    v = calg1.alg1_points(x, f, P, primes, pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3], pts[:, 4])
+    assert (v == y[pts[:, 0] * P.T + pts[:, 1], pts[:, 2], pts[:, 3], pts[:, 4]]).all()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_decrypt_of_masked_conv_minus_mask_is_plain_conv(shape):
+    n, ci, co, h, w, fw, s = shape
+    primes, t = _ctx(n, 2, 2 ** 10)
+    P = layout.plan(n, ci, co, h, w, fw, s)
+    g = W.rng(1 + hash(shape) % 2 ** 32)
+    spec = W.ConvSpec(ci, co, h, w, fw, s)
+    f = W.gen_filters(g, spec)
+    a = W.gen_activations(g, spec, -128, 128)[0]
+    m = layout.encode_input(a, P)
+    sk = bfv.sample_secret(g, n)
+    x = np.stack([bfv.encrypt_sk(m[k], sk, bfv.sample_a(g, primes, n), bfv.sample_error(g, n), primes, t)
+                  for k in range(P.G)])
+    r = W.gen_mask(g, (co, P.ho, P.wo), t)
+    y = calg1.alg1_layer(x, f, P, primes)
+    c0e, c1o = conv.mask_extract(y, r, P, primes, t)
+    md = conv.decrypt_extracted(c0e, c1o, sk, P, primes, t)
+    z = conv.plain_conv_mod_t(a, f, s, t)
+    assert ((md - r.astype(np.int64)) % t == z).all()
+
+
+def test_plain_conv_matches_scipy_correlate():
+    g = W.rng(21)
+    for (ci, co, h, w, fw, s) in [(3, 2, 7, 6, 3, 1), (2, 3, 8, 8, 5, 2), (4, 2, 6, 6, 1, 2), (1, 1, 9, 9, 7, 2)]:
+        a = g.integers(-50, 50, size=(ci, h, w))
+        f = g.integers(-9, 9, size=(co, ci, fw, fw))
+        t = 2 ** 12
+        z = conv.plain_conv_mod_t(a, f, s, t)
+        for i in range(co):
+            full = sum(scipy.signal.correlate2d(a[j], f[i, j], mode="same", boundary="fill") for j in range(ci))
+            assert (z[i] == full[::s, ::s] % t).all()
+
+
+def test_identity_filter_returns_rotated_input_and_zero_filter_zero():
+    n = 64
+    primes, t = _ctx(n)
+    P = layout.plan(n, 4, 4, 3, 3, 1, 1)   # 1x1, c_n = 7: all channels in one ciphertext
+    g = W.rng(31)
+    x = W.gen_ct_limbs(g, (P.G, 2), primes, n)
+    f = np.zeros((4, 4, 1, 1), dtype=np.int8)
+    for i in range(4):
+        f[i, i, 0, 0] = 1
+    y = calg1.alg1_layer(x, f, P, primes)
+    for i in range(4):
+        for p, l in itertools.product(range(2), range(2)):
+            assert (y[i, p, l] == ring.drot(x[P.in_ct(i, 0), p, l], P.chan_off(i), primes[l])).all()
+    assert not calg1.alg1_layer(x, np.zeros_like(f), P, primes).any()
+
+
+def test_alg1_is_linear_in_inputs_and_filters():
+    n = 64
+    primes, t = _ctx(n)
+    P = layout.plan(n, 3, 2, 4, 4, 3, 1)
+    g = W.rng(41)
+    spec = W.ConvSpec(3, 2, 4, 4, 3, 1)
+    f1, f2 = W.gen_filters(g, spec) // 2, W.gen_filters(g, spec) // 2
+    x1 = W.gen_ct_limbs(g, (P.G, 2), primes, n)
+    x2 = W.gen_ct_limbs(g, (P.G, 2), primes, n)
+    qv = np.array(primes, dtype=np.int64)[None, None, :, None]
+    y = lambda x, f: calg1.alg1_layer(x, f, P, primes).astype(np.int64)
+    assert (y(x1, (f1 + f2).astype(np.int8)) == (y(x1, f1) + y(x1, f2)) % qv).all()
+    xs = ((x1.astype(np.int64) + x2) % qv).astype(np.uint32)
+    assert (y(xs, f1) == (y(x1, f1) + y(x2, f1)) % qv).all()
+
+
+@pytest.mark.parametrize("shape", SHAPES[:6])
+def test_freivalds_combination(shape):
+    n, ci, co, h, w, fw, s = shape
+    primes, t = _ctx(n, 2)
+    P = layout.plan(n, ci, co, h, w, fw, s)
+    g = W.rng(51)
+    f = W.gen_filters(g, W.ConvSpec(ci, co, h, w, fw, s))
+    x = W.gen_ct_limbs(g, (P.G, 2), primes, n)
+    rho = [g.integers(0, q, size=co) for q in primes]
+    y = calg1.alg1_layer(x, f, P, primes)
+    assert (conv.freivalds_lhs(y, rho, P, primes) == conv.freivalds_rhs(x, f, rho, P, primes)).all()
+    y_bad = y.copy()
+    y_bad[0, 1, 0, 3] = (int(y_bad[0, 1, 0, 3]) + 1) % primes[0]
+    assert not (conv.freivalds_lhs(y_bad, rho, P, primes) == conv.freivalds_rhs(x, f, rho, P, primes)).all()
+
+
+def test_lazy_int64_accumulation_cannot_overflow_at_the_largest_layer():
+    # |c| < 2^30, |f| <= 128, 49 taps (7x7), up to 2048 input channels
+    assert (2 ** 30) * 128 * 49 * 2048 < 2 ** 63
+
+
+@pytest.mark.parametrize("n,L,t,ci,fw", [(4096, 2, 2 ** 17, 16, 3), (8192, 3, 2 ** 20, 2048, 3),
+                                         (16384, 4, 2 ** 24, 512, 7)])
+def test_noise_budget_of_the_workloads(n, L, t, ci, fw):
+    """||v_out|| <= B_e ||f||_1 + (q mod t) ||f||_1 / 2 + (q mod t) stays below Delta / 2
+    (correctness condition of eq. bfv_dec); B_e = 6 sigma, ||f||_1 <= c_i f_w^2 128."""
+    q = params.modulus(params.rns_primes(n, L))
+    D = params.delta(q, t)
+    f1 = ci * fw * fw * 128
+    bound = 20 * f1 + (q % t) * f1 // 2 + (q % t)
+    assert bound < D // 2
