@@ -1,0 +1,195 @@
+/*
+ * hc.h - C ABI of the MI355X homomorphic-convolution library (libhconv.so).
+ *
+ * The library computes the homomorphic convolution of Flash (arXiv 2401.16732,
+ * section "Convolution with Direct Encoding", Algorithm 1) on one gfx950 GPU:
+ * a server holding integer filters receives BFV ciphertexts of direct-encoded
+ * (eq. de), zero-padded, channel-packed activations and returns one ciphertext
+ * per output channel (Algorithm 1's output vector y), masked with its own random
+ * share r (HAdd([[a]], [[r]]) in "Proposed Secure Computation of Polynomial
+ * Activation Function").
+ *
+ * Algorithm 1 is a ring computation: DRot is multiplication by x^(-step) in
+ * R_q = Z_q[x]/(x^n + 1) (eq. drot) and CMult is multiplication by a scalar, so
+ * for output channel i its result is y_i = sum_g c_g * W_{i,g} with the sparse
+ * weight polynomial W_{i,g}(x) = sum_{j in g} sum_taps f[i][j][tap] x^(-(o_j + s_tap)).
+ * The library evaluates that same product as a negacyclic NTT of the inputs,
+ * a pointwise multiply-accumulate over input ciphertexts against resident
+ * NTT-domain weights, and an inverse NTT. Results are the canonical residues
+ * of Algorithm 1's output, coefficient for coefficient.
+ *
+ * Arithmetic: RNS, q = prod_l q_l with L <= 4 primes q_l < 2^30, q_l = 1 mod 2n;
+ * plaintext modulus t <= 2^30 (the paper's p); Delta = floor(q / t) (Notation
+ * table). All values are uint32 residues; nothing is floating point.
+ *
+ * Layout of one convolution (fixed by hc_plan, public like the architecture):
+ *   padding p = (f - 1) / 2, padded image h' x w' = (h + 2p) x (w + 2p), F = h' w'.
+ *   F <= n: c_n = floor(n / F) channels per ciphertext; channel j sits in input
+ *           ciphertext floor(j / c_n) at offset (j mod c_n) F, padded pixel (y, x)
+ *           at that offset + y w' + x; one output ciphertext per output channel.
+ *   F >  n: row tiles: tile tau of channel j holds padded rows
+ *           [tau R_o, tau R_o + R_o + f - 1) at coefficient (y - tau R_o) w' + x,
+ *           where R_o = stride * floor((floor(n / w') - f + 1) / stride);
+ *           input ciphertext j T + tau, output ciphertext i T + tau.
+ *   stride s > 1, f > 1: the stride-1 grid is computed; output pixel (oy, ox)
+ *           is at coefficient (s oy - tau R_o) w' + s ox of output ciphertext (i, tau).
+ *   f = 1, s > 1: the client encodes the subsampled input a[j][s y][s x] and the
+ *           layer is the 1x1 stride-1 layer on the ceil(h/s) x ceil(w/s) grid.
+ *
+ * Device buffers (all uint32, contiguous, row-major, owned by the caller):
+ *   ciphertexts      [B][cts][2][L][n]   (poly 0 = c0, poly 1 = c1; limb-major)
+ *   mask r           [B][c_out][ho][wo]  values in [0, t)
+ *   c0_ext           [B][c_out][L][ho][wo]
+ *   c1_out           [B][out_cts][L][n]
+ * Inputs must be canonical residues (in [0, q_l)); outputs always are.
+ *
+ * Errors: every call returns hc_status. Argument and shape errors are
+ * synchronous (HC_EINVAL / HC_EUNSUPPORTED); kernel faults are asynchronous and
+ * surface from a later call or hc_sync as HC_EDEVICE. Nothing throws across
+ * the ABI. A context and its layers are immutable after creation; calls on
+ * different streams may run concurrently as long as their output and
+ * workspace buffers are distinct.
+ */
+#ifndef HC_H
+#define HC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HC_OK = 0,
+    HC_EINVAL = -1,        /* bad argument (null pointer, size, value out of range) */
+    HC_EUNSUPPORTED = -2,  /* valid request outside the supported shapes */
+    HC_ENOMEM = -3,        /* device or host allocation failed */
+    HC_EDEVICE = -4,       /* HIP runtime error, including an earlier asynchronous fault */
+    HC_ESTATE = -5         /* object used in the wrong state (e.g. mismatched context) */
+} hc_status;
+
+typedef struct hc_ctx hc_ctx;
+typedef struct hc_layer hc_layer;
+typedef struct hc_batch hc_batch;
+
+/* One convolution: c_in -> c_out channels on an h x w input, odd filter
+ * width f, stride, 'same' zero padding (f - 1) / 2. */
+typedef struct {
+    uint32_t c_in, c_out, h, w, f, stride;
+} hc_conv_shape;
+
+/* The direct-encoding layout of one convolution (see the header comment). */
+typedef struct {
+    uint32_t sub;               /* client-side subsampling factor (f = 1, stride > 1), else 1 */
+    uint32_t s;                 /* stride applied on the encoded grid */
+    uint32_t h_enc, w_enc;      /* encoded input size (after subsampling) */
+    uint32_t pad;               /* (f - 1) / 2 */
+    uint32_t h_pad, w_pad;      /* h_enc + 2 pad, w_enc + 2 pad */
+    uint32_t footprint;         /* F = h_pad * w_pad */
+    uint32_t tiled;             /* 1 when F > n */
+    uint32_t cn;                /* channels per input ciphertext */
+    uint32_t tiles;             /* T: row tiles per channel (1 when untiled) */
+    uint32_t rows_out_per_tile; /* R_o: stride-1 output rows per tile */
+    uint32_t in_cts;            /* G: input ciphertexts per image */
+    uint32_t w_cts;             /* weight polynomials per output channel (G, or c_in when tiled) */
+    uint32_t out_cts;           /* O = c_out * T output ciphertexts per image */
+    uint32_t ho, wo;            /* output size */
+} hc_layout;
+
+/* Create a context on HIP device `hip_device`: ring degree N (power of two,
+ * 1024..16384), L RNS primes (1..4), plaintext modulus t (2..2^30).
+ * primes: L distinct primes < 2^30 with q = 1 mod 2N, or NULL to choose the
+ * L largest such primes, in descending order. Builds the NTT twiddle tables
+ * on the device. The caller destroys it with hc_ctx_destroy. */
+hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t t, int hip_device,
+                        hc_ctx **out);
+
+/* Copy out the primes (L values) and Delta mod q_l (L values); either pointer may be NULL. */
+hc_status hc_ctx_info(const hc_ctx *ctx, uint32_t *primes_out, uint32_t *delta_mod_q_out);
+void hc_ctx_destroy(hc_ctx *ctx);
+
+/* The layout of `shape` in this context (pure host computation). */
+hc_status hc_plan(const hc_ctx *ctx, const hc_conv_shape *shape, hc_layout *out);
+
+/* Host-only forms (no device needed): the layout for ring degree N, and the
+ * parameters hc_ctx_create would choose (primes == NULL): the L largest primes
+ * < 2^30 with q = 1 mod 2N in descending order, and Delta mod q_l. */
+hc_status hc_plan_ring(uint32_t N, const hc_conv_shape *shape, hc_layout *out);
+hc_status hc_ring_params(uint32_t N, uint32_t L, uint64_t t, uint32_t *primes_out, uint32_t *delta_mod_q_out);
+
+/* Offline weight encoding (Algorithm 1's filters as W_{i,g}, then the forward
+ * NTT). filters_host: int8 [c_out][c_in][f][f] in host memory, read during
+ * the call. The NTT-domain weights stay resident in device memory owned by the
+ * layer until hc_layer_destroy. `stream` is a hipStream_t (NULL = default);
+ * the call returns after the encoding has been enqueued and the filters copied. */
+hc_status hc_layer_create(hc_ctx *ctx, const hc_conv_shape *shape, const int8_t *filters_host, void *stream,
+                          hc_layer **out);
+void hc_layer_destroy(hc_layer *layer);
+hc_status hc_layer_plan(const hc_layer *layer, hc_layout *out);
+
+/* Bytes of device workspace hc_conv (masked = 0) or hc_conv_masked (masked = 1)
+ * needs for a batch of B images. */
+hc_status hc_workspace_size(const hc_layer *layer, uint32_t B, int masked, size_t *bytes);
+
+/* Algorithm 1 for B images: ct_in [B][in_cts][2][L][N] -> ct_out
+ * [B][out_cts][2][L][N], coefficient domain, canonical. ws: device workspace of
+ * at least hc_workspace_size(layer, B, 0) bytes. Asynchronous on `stream`. */
+hc_status hc_conv(const hc_layer *layer, const uint32_t *ct_in, uint32_t *ct_out, uint32_t B, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* Share conversion and extraction of hc_conv's output: for every output pixel
+ * (b, i, oy, ox) at coefficient e of output ciphertext (i, tau):
+ *   c0_ext[b][i][l][oy][ox] = ct_out[b][(i,tau)][0][l][e] + (Delta mod q_l) * (r_c mod q_l)  mod q_l
+ * where r_c is mask[b][i][oy][ox] lifted to (-t/2, t/2]; and
+ *   c1_out[b][o][l][:] = ct_out[b][o][1][l][:].
+ * This adds the trivial ciphertext (Delta r, 0): the server cannot encrypt
+ * (it has no key), so HAdd with [[r]] is a plaintext add to c0.
+ * ct_out and c1_out must be 16-byte aligned. */
+hc_status hc_mask_extract(const hc_layer *layer, const uint32_t *ct_out, const uint32_t *mask, uint32_t *c0_ext,
+                          uint32_t *c1_out, uint32_t B, void *stream);
+
+/* hc_conv followed by hc_mask_extract, fused into the inverse-NTT epilogue;
+ * the full c0 of each output ciphertext is never written. ws: at least
+ * hc_workspace_size(layer, B, 1) bytes. */
+hc_status hc_conv_masked(const hc_layer *layer, const uint32_t *ct_in, const uint32_t *mask, uint32_t *c0_ext,
+                         uint32_t *c1_out, uint32_t B, void *ws, size_t ws_bytes, void *stream);
+
+/* Batched execution of several layers on B images each (all layers of a
+ * network): the per-layer work (forward NTT, multiply-accumulate, inverse NTT
+ * with mask and extraction) is recorded once into a HIP graph and replayed by
+ * hc_batch_run. The layers must outlive the batch. The batch owns its
+ * workspace (allocated here). */
+hc_status hc_batch_create(hc_ctx *ctx, const hc_layer *const *layers, uint32_t n_layers, uint32_t B,
+                          hc_batch **out);
+hc_status hc_batch_workspace_bytes(const hc_batch *batch, size_t *bytes);
+
+/* Run the batch: per layer k, ct_in[k], mask[k], c0_ext[k], c1_out[k] have
+ * the hc_conv_masked shapes for B images. The graph is re-recorded when the
+ * pointers differ from the previous call's. Asynchronous on `stream`. */
+hc_status hc_batch_run(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                       uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream);
+
+/* Same work as hc_batch_run but launched kernel by kernel in stream order
+ * (no graph); the reference for the graph path. */
+hc_status hc_batch_run_eager(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                             uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream);
+void hc_batch_destroy(hc_batch *batch);
+
+/* Negacyclic products c_k = a_k * b_k mod (x^N + 1, q_l) of `count` pairs of
+ * polynomials laid out [count][L][N] (canonical residues), through the same
+ * forward NTT, pointwise product and inverse NTT kernels as the convolution.
+ * ws: at least 2 * count * L * N * 4 bytes. Exposes the NTT for testing. */
+hc_status hc_poly_mul(const hc_ctx *ctx, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t count,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Wait for all work on the context's device; reports earlier asynchronous faults. */
+hc_status hc_sync(hc_ctx *ctx);
+const char *hc_status_string(hc_status s);
+/* Text of the last error on the calling thread (empty if none). */
+const char *hc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HC_H */

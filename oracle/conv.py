@@ -217,3 +217,10 @@ def decrypt_extracted(c0_ext, c1_out, s, P: Plan, primes: Sequence[int], t: int)
                 v = crt(res, primes)
                 m[i, oy, ox] = ((t * v + q // 2) // q) % t
     return m
+
+
+def mask_add(y_coeff: int, r: int, l: int, primes: Sequence[int], t: int) -> int:
+    """One masked coefficient: y + Delta_l * (r_centred mod q_l) mod q_l (see mask_extract)."""
+    ql = primes[l]
+    D = delta(modulus(primes), t)
+    return (int(y_coeff) + (D % ql) * (centred(int(r), t) % ql)) % ql

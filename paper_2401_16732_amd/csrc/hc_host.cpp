@@ -1,0 +1,665 @@
+// Host side of libhconv: the C ABI declared in include/hc.h.
+//
+// Parameters (RNS primes, roots of unity, twiddle and Shoup tables, Delta),
+// the direct-encoding layout planner, resident weight encoding, the per-layer
+// launch sequences and the graph-recorded batch. Kernels live in
+// hc_kernels.hip.
+#include "../../include/hc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hc_internal.h"
+
+using hc::ConvGeom;
+using hc::LimbConsts;
+using hc::Twiddles;
+using u128 = unsigned __int128;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hc_status fail(hc_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+hc_status hip_fail(hipError_t e, const char *where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return HC_EDEVICE;
+}
+#define HC_HIP(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+// ------------------------------------------------------------- number theory
+uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  while (e) {
+    if (e & 1) r = mulmod64(r, a, m);
+    a = mulmod64(a, a, m);
+    e >>= 1;
+  }
+  return r;
+}
+// Deterministic Miller-Rabin for n < 3.3e24 with the first 13 prime bases.
+bool is_prime(uint64_t n) {
+  if (n < 2) return false;
+  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41};
+  for (uint64_t p : bases) {
+    if (n % p == 0) return n == p;
+  }
+  uint64_t d = n - 1;
+  int r = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++r;
+  }
+  for (uint64_t a : bases) {
+    uint64_t x = powmod64(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < r; ++i) {
+      x = mulmod64(x, x, n);
+      if (x == n - 1) {
+        comp = false;
+        break;
+      }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+uint32_t shoup_of(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
+uint32_t bitrev(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- objects
+struct hc_ctx {
+  uint32_t N = 0, logn = 0, L = 0;
+  uint64_t t = 0;
+  uint32_t q[hc::kMaxLimbs] = {};
+  uint32_t psi[hc::kMaxLimbs] = {};
+  uint32_t delta[hc::kMaxLimbs] = {};
+  int device = 0;
+  LimbConsts consts{};
+  uint2 *d_tw = nullptr;  // [2][L][N]: forward then inverse
+  Twiddles tw{};
+};
+
+struct hc_layer {
+  hc_ctx *ctx = nullptr;
+  hc_conv_shape shape{};
+  hc_layout lay{};
+  ConvGeom geom{};
+  uint32_t *d_w = nullptr;  // [c_out][w_cts][L][N], NTT domain
+  size_t w_elems = 0;
+};
+
+struct hc_batch {
+  hc_ctx *ctx = nullptr;
+  std::vector<const hc_layer *> layers;
+  uint32_t B = 0;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<size_t> ws_off;  // per layer: X-hat offset; Y-hat follows
+  hipStream_t side[4] = {};
+  hipEvent_t fork = nullptr, join[4] = {};
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void *> key;  // pointers the graph was recorded with
+};
+
+namespace {
+
+bool valid_ring(uint32_t N) { return N >= 1024 && N <= 16384 && (N & (N - 1)) == 0; }
+
+// The L largest primes < 2^30 with q = 1 mod 2N, descending.
+bool auto_primes(uint32_t N, uint32_t L, uint32_t *q) {
+  const uint64_t two_n = 2ull * N;
+  uint64_t cand = (((1ull << 30) - 2) / two_n) * two_n + 1;
+  for (uint32_t l = 0; l < L; cand -= two_n) {
+    if (cand < two_n) return false;
+    if (is_prime(cand)) q[l++] = (uint32_t)cand;
+  }
+  return true;
+}
+
+hc_status plan_impl(uint32_t N, const hc_conv_shape &s, hc_layout &o) {
+  if (s.c_in == 0 || s.c_out == 0 || s.h == 0 || s.w == 0 || s.stride == 0)
+    return fail(HC_EINVAL, "empty convolution shape");
+  if (s.f % 2 == 0) return fail(HC_EUNSUPPORTED, "filter width must be odd");
+  std::memset(&o, 0, sizeof(o));
+  if (s.f == 1 && s.stride > 1) {
+    o.sub = s.stride;
+    o.s = 1;
+    o.h_enc = (s.h + s.stride - 1) / s.stride;
+    o.w_enc = (s.w + s.stride - 1) / s.stride;
+  } else {
+    o.sub = 1;
+    o.s = s.stride;
+    o.h_enc = s.h;
+    o.w_enc = s.w;
+  }
+  o.pad = (s.f - 1) / 2;
+  o.h_pad = o.h_enc + 2 * o.pad;
+  o.w_pad = o.w_enc + 2 * o.pad;
+  const uint64_t F = (uint64_t)o.h_pad * o.w_pad;
+  const uint32_t grid_rows = o.h_pad - s.f + 1;
+  if ((uint64_t)s.f * o.w_pad > N) return fail(HC_EUNSUPPORTED, "f * padded width exceeds the ring degree");
+  if (F <= N) {
+    o.footprint = (uint32_t)F;
+    o.tiled = 0;
+    o.cn = N / (uint32_t)F;
+    o.tiles = 1;
+    o.rows_out_per_tile = grid_rows;
+    o.in_cts = (s.c_in + o.cn - 1) / o.cn;
+    o.w_cts = o.in_cts;
+  } else {
+    const uint32_t R = N / o.w_pad;
+    const uint32_t ro = ((R - s.f + 1) / o.s) * o.s;
+    if (ro == 0) return fail(HC_EUNSUPPORTED, "no output row fits one ciphertext");
+    if (F > 0xffffffffu) return fail(HC_EUNSUPPORTED, "input too large");
+    o.footprint = (uint32_t)F;
+    o.tiled = 1;
+    o.cn = 1;
+    o.rows_out_per_tile = ro;
+    o.tiles = (grid_rows + ro - 1) / ro;
+    o.in_cts = s.c_in * o.tiles;
+    o.w_cts = s.c_in;
+  }
+  o.out_cts = s.c_out * o.tiles;
+  o.ho = (o.h_pad - s.f) / o.s + 1;
+  o.wo = (o.w_pad - s.f) / o.s + 1;
+  return HC_OK;
+}
+
+ConvGeom geom_of(const hc_ctx &c, const hc_conv_shape &s, const hc_layout &o) {
+  ConvGeom g{};
+  g.N = c.N;
+  g.L = c.L;
+  g.c_in = s.c_in;
+  g.c_out = s.c_out;
+  g.f = s.f;
+  g.s = o.s;
+  g.cn = o.cn;
+  g.tiled = o.tiled;
+  g.T = o.tiles;
+  g.r_o = o.rows_out_per_tile;
+  g.G = o.in_cts;
+  g.G_w = o.w_cts;
+  g.O = o.out_cts;
+  g.w_pad = o.w_pad;
+  g.F = o.footprint;
+  g.ho = o.ho;
+  g.wo = o.wo;
+  return g;
+}
+
+size_t ct_words(const hc_ctx &c) { return (size_t)2 * c.L * c.N; }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// A2 -> A4 (+A5 when masked) for one layer on B images.
+hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_out, const uint32_t *mask,
+                       uint32_t *c0_ext, uint32_t *c1_out, uint32_t B, void *ws, bool masked, hipStream_t st) {
+  const hc_ctx &c = *ly->ctx;
+  const ConvGeom &g = ly->geom;
+  uint32_t *xhat = (uint32_t *)ws;
+  const size_t npin = (size_t)B * g.G * 2 * c.L;
+  HC_HIP(hc::launch_ntt_fwd(c.logn, ct_in, xhat, npin, c.consts, c.tw, st));
+  if (!masked) {
+    HC_HIP(hc::launch_mac(g, xhat, ly->d_w, ct_out, B, c.consts, st));
+    HC_HIP(hc::launch_intt_full(c.logn, ct_out, ct_out, (size_t)B * g.O * 2 * c.L, c.consts, c.tw, st));
+  } else {
+    uint32_t *yhat = xhat + npin * c.N;
+    HC_HIP(hc::launch_mac(g, xhat, ly->d_w, yhat, B, c.consts, st));
+    HC_HIP(hc::launch_intt_masked(g, c.logn, yhat, mask, c0_ext, c1_out, B, c.consts, c.tw, st));
+  }
+  return HC_OK;
+}
+
+size_t ws_bytes_for(const hc_layer *ly, uint32_t B, bool masked) {
+  const hc_ctx &c = *ly->ctx;
+  size_t w = (size_t)B * ly->geom.G * ct_words(c);
+  if (masked) w += (size_t)B * ly->geom.O * ct_words(c);
+  return w * sizeof(uint32_t);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- ABI
+extern "C" {
+
+const char *hc_status_string(hc_status s) {
+  switch (s) {
+    case HC_OK: return "ok";
+    case HC_EINVAL: return "invalid argument";
+    case HC_EUNSUPPORTED: return "unsupported";
+    case HC_ENOMEM: return "out of memory";
+    case HC_EDEVICE: return "device error";
+    case HC_ESTATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char *hc_last_error(void) { return g_last_error.c_str(); }
+
+hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t t, int hip_device, hc_ctx **out) {
+  if (!out) return fail(HC_EINVAL, "out is null");
+  *out = nullptr;
+  if (!valid_ring(N)) return fail(HC_EUNSUPPORTED, "N must be a power of two in [1024, 16384]");
+  if (L < 1 || L > (uint32_t)hc::kMaxLimbs) return fail(HC_EUNSUPPORTED, "L must be in [1, 4]");
+  if (t < 2 || t > (1ull << 30)) return fail(HC_EUNSUPPORTED, "t must be in [2, 2^30]");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+    return fail(HC_EDEVICE, "no such HIP device");
+  hc_ctx *c = new (std::nothrow) hc_ctx;
+  if (!c) return fail(HC_ENOMEM, "host allocation");
+  c->N = N;
+  c->L = L;
+  c->t = t;
+  c->device = hip_device;
+  while ((1u << c->logn) < N) ++c->logn;
+  const uint64_t two_n = 2ull * N;
+  if (primes) {
+    for (uint32_t l = 0; l < L; ++l) {
+      const uint32_t q = primes[l];
+      if (q >= (1u << 30) || q % two_n != 1 || !is_prime(q)) {
+        delete c;
+        return fail(HC_EINVAL, "prime " + std::to_string(q) + " is not a prime < 2^30 with q = 1 mod 2N");
+      }
+      for (uint32_t k = 0; k < l; ++k)
+        if (primes[k] == q) {
+          delete c;
+          return fail(HC_EINVAL, "primes must be distinct");
+        }
+      c->q[l] = q;
+    }
+  } else if (!auto_primes(N, L, c->q)) {
+    delete c;
+    return fail(HC_EUNSUPPORTED, "not enough primes");
+  }
+  // Delta = floor(q / t), q = prod q_l < 2^120 (Notation table)
+  u128 Q = 1;
+  for (uint32_t l = 0; l < L; ++l) Q *= c->q[l];
+  const u128 D = Q / t;
+  LimbConsts &k = c->consts;
+  std::memset(&k, 0, sizeof(k));
+  k.t = (uint32_t)t;
+  k.L = L;
+  std::vector<uint2> tw((size_t)2 * L * N);
+  for (uint32_t l = 0; l < L; ++l) {
+    const uint32_t q = c->q[l];
+    c->delta[l] = (uint32_t)(D % q);
+    // psi: a primitive 2N-th root of unity (psi^N = -1), smallest base first
+    uint64_t psi = 0;
+    for (uint64_t x = 2; x < q; ++x) {
+      const uint64_t cand = powmod64(x, (q - 1) / two_n, q);
+      if (powmod64(cand, N, q) == q - 1) {
+        psi = cand;
+        break;
+      }
+    }
+    if (!psi) {
+      delete c;
+      return fail(HC_EINVAL, "no primitive 2N-th root of unity");
+    }
+    c->psi[l] = (uint32_t)psi;
+    const uint64_t ipsi = powmod64(psi, q - 2, q);
+    uint2 *fw = tw.data() + (size_t)l * N;
+    uint2 *iw = tw.data() + ((size_t)L + l) * N;
+    for (uint32_t i = 0; i < N; ++i) {
+      const uint32_t e = bitrev(i, (int)c->logn);
+      const uint32_t a = (uint32_t)powmod64(psi, e, q);
+      const uint32_t b = (uint32_t)powmod64(ipsi, e, q);
+      fw[i] = make_uint2(a, shoup_of(a, q));
+      iw[i] = make_uint2(b, shoup_of(b, q));
+    }
+    const uint32_t ninv = (uint32_t)powmod64(N, q - 2, q);
+    const uint32_t ninvw = (uint32_t)mulmod64(ninv, iw[1].x, q);
+    k.q[l] = q;
+    k.ninv[l] = ninv;
+    k.ninv_p[l] = shoup_of(ninv, q);
+    k.ninvw[l] = ninvw;
+    k.ninvw_p[l] = shoup_of(ninvw, q);
+    k.r2[l] = (uint32_t)((1ull << 32) % q);
+    k.r2_p[l] = shoup_of(k.r2[l], q);
+    k.one_p[l] = shoup_of(1, q);
+    k.delta[l] = c->delta[l];
+    k.delta_p[l] = shoup_of(c->delta[l], q);
+    // terms that fit between folds: fold leaves acc < 2^32 * r2 + 2^32; each
+    // term adds at most (q-1)^2; keep the total below 2^64
+    const u128 lim = ((u128)1 << 64) - 1;
+    const u128 base = ((u128)1 << 32) * k.r2[l] + ((u128)1 << 32);
+    const u128 term = (u128)(q - 1) * (q - 1);
+    u128 n_terms = (lim - base) / term;
+    k.fold[l] = (uint32_t)std::min<u128>(n_terms, 64);
+    if (k.fold[l] < 1) {
+      delete c;
+      return fail(HC_EINVAL, "prime too large for 64-bit accumulation");
+    }
+  }
+  DeviceGuard dg(hip_device);
+  const size_t bytes = tw.size() * sizeof(uint2);
+  hipError_t e = hipMalloc((void **)&c->d_tw, bytes);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(HC_ENOMEM, "twiddle allocation");
+  }
+  e = hipMemcpy(c->d_tw, tw.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(c->d_tw);
+    delete c;
+    return hip_fail(e, "twiddle upload");
+  }
+  c->tw.fwd = c->d_tw;
+  c->tw.inv = c->d_tw + (size_t)L * N;
+  *out = c;
+  return HC_OK;
+}
+
+hc_status hc_ctx_info(const hc_ctx *c, uint32_t *primes_out, uint32_t *delta_out) {
+  if (!c) return fail(HC_EINVAL, "ctx is null");
+  for (uint32_t l = 0; l < c->L; ++l) {
+    if (primes_out) primes_out[l] = c->q[l];
+    if (delta_out) delta_out[l] = c->delta[l];
+  }
+  return HC_OK;
+}
+
+void hc_ctx_destroy(hc_ctx *c) {
+  if (!c) return;
+  DeviceGuard dg(c->device);
+  if (c->d_tw) (void)hipFree(c->d_tw);
+  delete c;
+}
+
+hc_status hc_plan(const hc_ctx *c, const hc_conv_shape *s, hc_layout *o) {
+  if (!c || !s || !o) return fail(HC_EINVAL, "null argument");
+  return plan_impl(c->N, *s, *o);
+}
+
+hc_status hc_plan_ring(uint32_t N, const hc_conv_shape *s, hc_layout *o) {
+  if (!s || !o) return fail(HC_EINVAL, "null argument");
+  if (!valid_ring(N)) return fail(HC_EUNSUPPORTED, "N must be a power of two in [1024, 16384]");
+  return plan_impl(N, *s, *o);
+}
+
+hc_status hc_ring_params(uint32_t N, uint32_t L, uint64_t t, uint32_t *primes_out, uint32_t *delta_out) {
+  if (!valid_ring(N)) return fail(HC_EUNSUPPORTED, "N must be a power of two in [1024, 16384]");
+  if (L < 1 || L > (uint32_t)hc::kMaxLimbs) return fail(HC_EUNSUPPORTED, "L must be in [1, 4]");
+  if (t < 2 || t > (1ull << 30)) return fail(HC_EUNSUPPORTED, "t must be in [2, 2^30]");
+  uint32_t q[hc::kMaxLimbs];
+  if (!auto_primes(N, L, q)) return fail(HC_EUNSUPPORTED, "not enough primes");
+  u128 Q = 1;
+  for (uint32_t l = 0; l < L; ++l) Q *= q[l];
+  const u128 D = Q / t;
+  for (uint32_t l = 0; l < L; ++l) {
+    if (primes_out) primes_out[l] = q[l];
+    if (delta_out) delta_out[l] = (uint32_t)(D % q[l]);
+  }
+  return HC_OK;
+}
+
+hc_status hc_layer_create(hc_ctx *c, const hc_conv_shape *s, const int8_t *filters, void *stream, hc_layer **out) {
+  if (!c || !s || !filters || !out) return fail(HC_EINVAL, "null argument");
+  *out = nullptr;
+  hc_layout lay;
+  hc_status st = plan_impl(c->N, *s, lay);
+  if (st != HC_OK) return st;
+  DeviceGuard dg(c->device);
+  hc_layer *ly = new (std::nothrow) hc_layer;
+  if (!ly) return fail(HC_ENOMEM, "host allocation");
+  ly->ctx = c;
+  ly->shape = *s;
+  ly->lay = lay;
+  ly->geom = geom_of(*c, *s, lay);
+  ly->w_elems = (size_t)s->c_out * lay.w_cts * c->L * c->N;
+  hipStream_t hs = (hipStream_t)stream;
+  if (hipMalloc((void **)&ly->d_w, ly->w_elems * sizeof(uint32_t)) != hipSuccess) {
+    delete ly;
+    return fail(HC_ENOMEM, "weight allocation");
+  }
+  const size_t fbytes = (size_t)s->c_out * s->c_in * s->f * s->f;
+  int8_t *d_f = nullptr;
+  hipError_t e = hipMalloc((void **)&d_f, fbytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_f, filters, fbytes, hipMemcpyHostToDevice, hs);
+  if (e == hipSuccess) e = hc::launch_fill_zero(ly->d_w, ly->w_elems, hs);
+  if (e == hipSuccess) e = hc::launch_weight_scatter(ly->geom, d_f, ly->d_w, c->consts, hs);
+  if (e == hipSuccess)
+    e = hc::launch_ntt_fwd(c->logn, ly->d_w, ly->d_w, (size_t)s->c_out * lay.w_cts * c->L, c->consts, c->tw, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  if (d_f) (void)hipFree(d_f);
+  if (e != hipSuccess) {
+    (void)hipFree(ly->d_w);
+    delete ly;
+    return hip_fail(e, "weight encoding");
+  }
+  *out = ly;
+  return HC_OK;
+}
+
+void hc_layer_destroy(hc_layer *ly) {
+  if (!ly) return;
+  DeviceGuard dg(ly->ctx->device);
+  if (ly->d_w) (void)hipFree(ly->d_w);
+  delete ly;
+}
+
+hc_status hc_layer_plan(const hc_layer *ly, hc_layout *out) {
+  if (!ly || !out) return fail(HC_EINVAL, "null argument");
+  *out = ly->lay;
+  return HC_OK;
+}
+
+hc_status hc_workspace_size(const hc_layer *ly, uint32_t B, int masked, size_t *bytes) {
+  if (!ly || !bytes) return fail(HC_EINVAL, "null argument");
+  *bytes = ws_bytes_for(ly, B, masked != 0);
+  return HC_OK;
+}
+
+hc_status hc_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_out, uint32_t B, void *ws, size_t ws_bytes,
+                  void *stream) {
+  if (!ly || (B && (!ct_in || !ct_out || !ws))) return fail(HC_EINVAL, "null argument");
+  if (B == 0) return HC_OK;
+  if (ws_bytes < ws_bytes_for(ly, B, false)) return fail(HC_EINVAL, "workspace too small");
+  DeviceGuard dg(ly->ctx->device);
+  return enqueue_conv(ly, ct_in, ct_out, nullptr, nullptr, nullptr, B, ws, false, (hipStream_t)stream);
+}
+
+hc_status hc_mask_extract(const hc_layer *ly, const uint32_t *ct_out, const uint32_t *mask, uint32_t *c0_ext,
+                          uint32_t *c1_out, uint32_t B, void *stream) {
+  if (!ly || (B && (!ct_out || !mask || !c0_ext || !c1_out))) return fail(HC_EINVAL, "null argument");
+  if (B == 0) return HC_OK;
+  if (((uintptr_t)ct_out | (uintptr_t)c1_out) & 15u) return fail(HC_EINVAL, "ct_out and c1_out must be 16-byte aligned");
+  DeviceGuard dg(ly->ctx->device);
+  HC_HIP(hc::launch_mask_extract(ly->geom, ct_out, mask, c0_ext, c1_out, B, ly->ctx->consts, (hipStream_t)stream));
+  return HC_OK;
+}
+
+hc_status hc_conv_masked(const hc_layer *ly, const uint32_t *ct_in, const uint32_t *mask, uint32_t *c0_ext,
+                         uint32_t *c1_out, uint32_t B, void *ws, size_t ws_bytes, void *stream) {
+  if (!ly || (B && (!ct_in || !mask || !c0_ext || !c1_out || !ws))) return fail(HC_EINVAL, "null argument");
+  if (B == 0) return HC_OK;
+  if (ws_bytes < ws_bytes_for(ly, B, true)) return fail(HC_EINVAL, "workspace too small");
+  DeviceGuard dg(ly->ctx->device);
+  return enqueue_conv(ly, ct_in, nullptr, mask, c0_ext, c1_out, B, ws, true, (hipStream_t)stream);
+}
+
+hc_status hc_poly_mul(const hc_ctx *c, const uint32_t *a, const uint32_t *b, uint32_t *out, uint32_t count, void *ws,
+                      size_t ws_bytes, void *stream) {
+  if (!c || (count && (!a || !b || !out || !ws))) return fail(HC_EINVAL, "null argument");
+  if (count == 0) return HC_OK;
+  const size_t np = (size_t)count * c->L;
+  if (ws_bytes < 2 * np * c->N * sizeof(uint32_t)) return fail(HC_EINVAL, "workspace too small");
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t *wa = (uint32_t *)ws, *wb = wa + np * c->N;
+  HC_HIP(hc::launch_ntt_fwd(c->logn, a, wa, np, c->consts, c->tw, st));
+  HC_HIP(hc::launch_ntt_fwd(c->logn, b, wb, np, c->consts, c->tw, st));
+  HC_HIP(hc::launch_pointwise_mul(wa, wb, wa, np, c->N, c->consts, st));
+  HC_HIP(hc::launch_intt_full(c->logn, wa, out, np, c->consts, c->tw, st));
+  return HC_OK;
+}
+
+hc_status hc_sync(hc_ctx *c) {
+  if (!c) return fail(HC_EINVAL, "ctx is null");
+  DeviceGuard dg(c->device);
+  HC_HIP(hipDeviceSynchronize());
+  return HC_OK;
+}
+
+// ------------------------------------------------------------- batch (graph)
+hc_status hc_batch_create(hc_ctx *c, const hc_layer *const *layers, uint32_t n, uint32_t B, hc_batch **out) {
+  if (!c || !out || (n && !layers)) return fail(HC_EINVAL, "null argument");
+  *out = nullptr;
+  if (n == 0 || B == 0) return fail(HC_EINVAL, "empty batch");
+  for (uint32_t k = 0; k < n; ++k) {
+    if (!layers[k]) return fail(HC_EINVAL, "null layer");
+    if (layers[k]->ctx != c) return fail(HC_ESTATE, "layer belongs to another context");
+  }
+  DeviceGuard dg(c->device);
+  hc_batch *bt = new (std::nothrow) hc_batch;
+  if (!bt) return fail(HC_ENOMEM, "host allocation");
+  bt->ctx = c;
+  bt->B = B;
+  bt->layers.assign(layers, layers + n);
+  size_t off = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    bt->ws_off.push_back(off);
+    off += (ws_bytes_for(layers[k], B, true) + 255) & ~(size_t)255;
+  }
+  bt->ws_bytes = off;
+  if (hipMalloc(&bt->ws, off) != hipSuccess) {
+    delete bt;
+    return fail(HC_ENOMEM, "batch workspace allocation");
+  }
+  hipError_t e = hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming);
+  for (int s = 0; s < 4 && e == hipSuccess; ++s) {
+    e = hipStreamCreateWithFlags(&bt->side[s], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->join[s], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    hc_batch_destroy(bt);
+    return hip_fail(e, "batch streams");
+  }
+  *out = bt;
+  return HC_OK;
+}
+
+hc_status hc_batch_workspace_bytes(const hc_batch *bt, size_t *bytes) {
+  if (!bt || !bytes) return fail(HC_EINVAL, "null argument");
+  *bytes = bt->ws_bytes;
+  return HC_OK;
+}
+
+static hc_status batch_check(hc_batch *bt, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                             uint32_t *const *c0, uint32_t *const *c1) {
+  if (!bt || !ct_in || !mask || !c0 || !c1) return fail(HC_EINVAL, "null argument");
+  for (size_t k = 0; k < bt->layers.size(); ++k)
+    if (!ct_in[k] || !mask[k] || !c0[k] || !c1[k]) return fail(HC_EINVAL, "null buffer for a layer");
+  return HC_OK;
+}
+
+hc_status hc_batch_run_eager(hc_batch *bt, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                             uint32_t *const *c0, uint32_t *const *c1, void *stream) {
+  hc_status s = batch_check(bt, ct_in, mask, c0, c1);
+  if (s != HC_OK) return s;
+  DeviceGuard dg(bt->ctx->device);
+  for (size_t k = 0; k < bt->layers.size(); ++k) {
+    s = enqueue_conv(bt->layers[k], ct_in[k], nullptr, mask[k], c0[k], c1[k], bt->B,
+                     (char *)bt->ws + bt->ws_off[k], true, (hipStream_t)stream);
+    if (s != HC_OK) return s;
+  }
+  return HC_OK;
+}
+
+hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_t *const *mask, uint32_t *const *c0,
+                       uint32_t *const *c1, void *stream) {
+  hc_status s = batch_check(bt, ct_in, mask, c0, c1);
+  if (s != HC_OK) return s;
+  DeviceGuard dg(bt->ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = bt->layers.size();
+  std::vector<const void *> key;
+  key.reserve(4 * n);
+  for (size_t k = 0; k < n; ++k) {
+    key.push_back(ct_in[k]);
+    key.push_back(mask[k]);
+    key.push_back(c0[k]);
+    key.push_back(c1[k]);
+  }
+  if (!bt->exec || key != bt->key) {
+    if (bt->exec) {
+      (void)hipGraphExecDestroy(bt->exec);
+      bt->exec = nullptr;
+    }
+    // Record: the layers are independent, so they are spread over 4 side
+    // streams forked from and joined back into the capturing stream; the
+    // graph then holds 4 concurrent chains.
+    hipStream_t cap = nullptr;
+    HC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipEventRecord(bt->fork, cap);
+    for (int sd = 0; sd < 4 && e == hipSuccess; ++sd) e = hipStreamWaitEvent(bt->side[sd], bt->fork, 0);
+    hc_status cs = HC_OK;
+    for (size_t k = 0; k < n && e == hipSuccess && cs == HC_OK; ++k)
+      cs = enqueue_conv(bt->layers[k], ct_in[k], nullptr, mask[k], c0[k], c1[k], bt->B,
+                        (char *)bt->ws + bt->ws_off[k], true, bt->side[k % 4]);
+    for (int sd = 0; sd < 4 && e == hipSuccess; ++sd) {
+      e = hipEventRecord(bt->join[sd], bt->side[sd]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(cap, bt->join[sd], 0);
+    }
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess && cs == HC_OK) e = hipGraphInstantiate(&bt->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (cs != HC_OK) return cs;
+    if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+    bt->key = key;
+  }
+  HC_HIP(hipGraphLaunch(bt->exec, st));
+  return HC_OK;
+}
+
+void hc_batch_destroy(hc_batch *bt) {
+  if (!bt) return;
+  DeviceGuard dg(bt->ctx->device);
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  for (int s = 0; s < 4; ++s) {
+    if (bt->side[s]) (void)hipStreamDestroy(bt->side[s]);
+    if (bt->join[s]) (void)hipEventDestroy(bt->join[s]);
+  }
+  if (bt->fork) (void)hipEventDestroy(bt->fork);
+  if (bt->ws) (void)hipFree(bt->ws);
+  delete bt;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Internal declarations shared by the host library (hc_host.cpp) and the
+// gfx950 kernels (hc_kernels.hip). Not part of the ABI.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace hc {
+
+constexpr int kMaxLimbs = 4;
+
+// Per-limb constants handed to every kernel by value (scalar registers).
+// Shoup pairs: for a constant w < q, wp = floor(w * 2^32 / q); then for any
+// a < 2^32, a*w - floor(a*wp / 2^32)*q lies in [0, 2q).
+struct LimbConsts {
+  uint32_t q[kMaxLimbs];
+  uint32_t ninv[kMaxLimbs], ninv_p[kMaxLimbs];     // N^-1
+  uint32_t ninvw[kMaxLimbs], ninvw_p[kMaxLimbs];   // N^-1 * psi^-brv(1): last inverse stage
+  uint32_t r2[kMaxLimbs];                          // 2^32 mod q (64-bit accumulator fold)
+  uint32_t r2_p[kMaxLimbs];
+  uint32_t one_p[kMaxLimbs];                       // floor(2^32 / q): Shoup constant of 1
+  uint32_t delta[kMaxLimbs], delta_p[kMaxLimbs];   // Delta mod q
+  uint32_t fold[kMaxLimbs];                        // MAC terms between two accumulator folds
+  uint32_t t;                                      // plaintext modulus
+  uint32_t L;
+};
+
+// Twiddles: per limb N entries {w, floor(w 2^32 / q)} in the order the
+// butterflies read them: fwd[k] = psi^brv(k), inv[k] = psi^-brv(k).
+struct Twiddles {
+  const uint2 *fwd;
+  const uint2 *inv;
+};
+
+// Geometry of one convolution as the kernels need it.
+struct ConvGeom {
+  uint32_t N, L;
+  uint32_t c_in, c_out, f, s;        // s: stride on the encoded grid
+  uint32_t cn, tiled, T, r_o;
+  uint32_t G, G_w, O;
+  uint32_t w_pad, F;
+  uint32_t ho, wo;
+};
+
+enum InttMode : int { kInttFull = 0, kInttMasked = 1 };
+
+// Launchers (hc_kernels.hip). Each enqueues on `st` and returns the launch status.
+hipError_t launch_ntt_fwd(uint32_t logn, const uint32_t *in, uint32_t *out, size_t npolys, const LimbConsts &c,
+                          const Twiddles &tw, hipStream_t st);
+// Full mode: in [P][N] -> out [P][N] (in place allowed).
+hipError_t launch_intt_full(uint32_t logn, const uint32_t *in, uint32_t *out, size_t npolys, const LimbConsts &c,
+                            const Twiddles &tw, hipStream_t st);
+// Masked mode: in = Yhat [B][O][2][L][N]; c1 polys go to c1_out [B][O][L][N],
+// c0 polys are extracted with the mask into c0_ext [B][c_out][L][ho][wo].
+hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, const uint32_t *yhat, const uint32_t *mask,
+                              uint32_t *c0_ext, uint32_t *c1_out, uint32_t B, const LimbConsts &c,
+                              const Twiddles &tw, hipStream_t st);
+hipError_t launch_mac(const ConvGeom &g, const uint32_t *xhat, const uint32_t *what, uint32_t *yhat, uint32_t B,
+                      const LimbConsts &c, hipStream_t st);
+hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *filters, uint32_t *w, const LimbConsts &c,
+                                 hipStream_t st);
+hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st);
+hipError_t launch_mask_extract(const ConvGeom &g, const uint32_t *ct_out, const uint32_t *mask, uint32_t *c0_ext,
+                               uint32_t *c1_out, uint32_t B, const LimbConsts &c, hipStream_t st);
+hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *c, size_t npolys, uint32_t N,
+                                const LimbConsts &k, hipStream_t st);
+
+}  // namespace hc

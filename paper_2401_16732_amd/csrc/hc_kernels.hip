@@ -1,0 +1,560 @@
+// gfx950 kernels of the homomorphic convolution (Flash, arXiv 2401.16732,
+// Algorithm 1 evaluated as y_i = sum_g c_g * W_{i,g} in R_q through the NTT).
+//
+// All arithmetic is exact 32-bit modular arithmetic on the vector ALUs:
+//  * Shoup multiplication by precomputed constants (twiddles, N^-1, Delta),
+//  * Harvey's lazy butterflies (forward values kept in [0, 4q), inverse in
+//    [0, 2q); q < 2^30 so 4q < 2^32),
+//  * the multiply-accumulate over input ciphertexts in 64-bit accumulators
+//    (v_mad_u64_u32), folded every few terms and reduced once per output: the
+//    GPU form of the paper's lazy reduction (Employing Lazy Reduction in
+//    Convolution).
+// No MFMA: nothing here is a floating-point contraction.
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "hc_internal.h"
+
+namespace hc {
+
+// ---------------------------------------------------------------- arithmetic
+__device__ __forceinline__ uint32_t shoup_lazy(uint32_t a, uint32_t w, uint32_t wp, uint32_t q) {
+  uint32_t Q = __umulhi(a, wp);
+  return a * w - Q * q;  // in [0, 2q) for any a < 2^32
+}
+__device__ __forceinline__ uint32_t csub(uint32_t a, uint32_t m) { return a >= m ? a - m : a; }
+
+// acc < 2^64 -> acc mod q, q < 2^30.
+__device__ __forceinline__ uint32_t reduce64(uint64_t acc, uint32_t q, uint32_t r2, uint32_t r2p, uint32_t onep) {
+  uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
+  uint32_t r = shoup_lazy(hi, r2, r2p, q) + shoup_lazy(lo, 1u, onep, q);  // [0, 4q)
+  r = csub(r, 2 * q);
+  return csub(r, q);
+}
+
+// ---------------------------------------------------------------- NTT shape
+// A polynomial of N = 2^LOGN coefficients is transformed by one workgroup of
+// 2^(LOGN - ELOG) threads; each thread holds E = 2^ELOG coefficients in
+// registers. The LOGN butterfly stages are split into passes of at most ELOG
+// consecutive index bits; within a pass every butterfly's pair lies in one
+// thread, and passes exchange data through LDS.
+__host__ __device__ constexpr int n_pass(int logn, int elog) { return (logn + elog - 1) / elog; }
+__host__ __device__ constexpr int pass_bits(int logn, int elog, int k) {
+  return logn / n_pass(logn, elog) + (k < logn % n_pass(logn, elog) ? 1 : 0);
+}
+// Forward passes walk the index bits from the top down (stage s touches bit
+// LOGN-1-s); inverse passes walk them from the bottom up.
+__host__ __device__ constexpr int pass_lo_fwd(int logn, int elog, int k) {
+  int lo = logn;
+  for (int i = 0; i <= k; ++i) lo -= pass_bits(logn, elog, i);
+  return lo;
+}
+__host__ __device__ constexpr int pass_lo_inv(int logn, int elog, int k) {
+  int lo = 0;
+  for (int i = 0; i < k; ++i) lo += pass_bits(logn, elog, i);
+  return lo;
+}
+
+// Coefficient index held in register u during a pass over bits [LO, LO+EP).
+// u = (grp << EP) | w: w walks the pass bits; the thread id and grp fill the
+// remaining bit positions, thread id lowest (so a pass with LO >= thread bits
+// reads consecutive words across the wave).
+template <int LOGN, int ELOG, int LO, int EP>
+__device__ __forceinline__ uint32_t gidx(uint32_t tid, int u) {
+  constexpr int TB = LOGN - ELOG;
+  const uint32_t w = (uint32_t)u & ((1u << EP) - 1u);
+  const uint32_t grp = (uint32_t)u >> EP;
+  const uint32_t v = tid | (grp << TB);
+  return (v & ((1u << LO) - 1u)) | (w << LO) | ((v >> LO) << (LO + EP));
+}
+// LDS word address: one pad word per 32 keeps strided passes off a single bank.
+__device__ __forceinline__ uint32_t lpad(uint32_t j) { return j + (j >> 5); }
+
+// Forward (Cooley-Tukey, natural -> bit-reversed) stages of one pass.
+// Stage s works on pairs (j, j + 2^(LOGN-1-s)) with twiddle psi^brv(2^s + j >> (LOGN - s)).
+template <int LOGN, int ELOG, int LO, int EP>
+__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
+                                         uint32_t q) {
+  constexpr int E = 1 << ELOG;
+  const uint32_t q2 = 2 * q;
+#pragma unroll
+  for (int bb = EP - 1; bb >= 0; --bb) {
+    const int b = LO + bb;
+    const int s = LOGN - 1 - b;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      if (u & (1 << bb)) continue;
+      const int u2 = u | (1 << bb);
+      const uint32_t j = gidx<LOGN, ELOG, LO, EP>(tid, u);
+      const uint2 w = tw[(1u << s) + (j >> (b + 1))];
+      uint32_t X = v[u], Y = v[u2];
+      X = csub(X, q2);
+      const uint32_t T = shoup_lazy(Y, w.x, w.y, q);
+      v[u] = X + T;
+      v[u2] = X - T + q2;
+    }
+  }
+}
+
+// Inverse (Gentleman-Sande, bit-reversed -> natural) stages of one pass; the
+// last stage (s = 0) also multiplies by N^-1.
+template <int LOGN, int ELOG, int LO, int EP>
+__device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
+                                         uint32_t q, uint32_t ninv, uint32_t ninvp, uint32_t ninvw,
+                                         uint32_t ninvwp) {
+  constexpr int E = 1 << ELOG;
+  const uint32_t q2 = 2 * q;
+#pragma unroll
+  for (int bb = 0; bb < EP; ++bb) {
+    const int b = LO + bb;
+    const int s = LOGN - 1 - b;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      if (u & (1 << bb)) continue;
+      const int u2 = u | (1 << bb);
+      const uint32_t X = v[u], Y = v[u2];
+      if (s == 0) {
+        v[u] = shoup_lazy(X + Y, ninv, ninvp, q);
+        v[u2] = shoup_lazy(X - Y + q2, ninvw, ninvwp, q);
+      } else {
+        const uint32_t j = gidx<LOGN, ELOG, LO, EP>(tid, u);
+        const uint2 w = tw[(1u << s) + (j >> (b + 1))];
+        v[u] = csub(X + Y, q2);
+        v[u2] = shoup_lazy(X - Y + q2, w.x, w.y, q);
+      }
+    }
+  }
+}
+
+template <int LOGN, int ELOG, int LO, int EP>
+__device__ __forceinline__ void regs_to_lds(const uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid) {
+#pragma unroll
+  for (int u = 0; u < (1 << ELOG); ++u) lds[lpad(gidx<LOGN, ELOG, LO, EP>(tid, u))] = v[u];
+}
+template <int LOGN, int ELOG, int LO, int EP>
+__device__ __forceinline__ void lds_to_regs(uint32_t (&v)[1 << ELOG], const uint32_t *lds, uint32_t tid) {
+#pragma unroll
+  for (int u = 0; u < (1 << ELOG); ++u) v[u] = lds[lpad(gidx<LOGN, ELOG, LO, EP>(tid, u))];
+}
+
+template <int LOGN, int ELOG, int K>
+struct FwdPasses {
+  // pass K reads from LDS (K > 0) and leaves its result in registers
+  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid,
+                                             const uint2 *tw, uint32_t q) {
+    constexpr int LO = pass_lo_fwd(LOGN, ELOG, K), EP = pass_bits(LOGN, ELOG, K);
+    constexpr int PLO = pass_lo_fwd(LOGN, ELOG, K - 1), PEP = pass_bits(LOGN, ELOG, K - 1);
+    FwdPasses<LOGN, ELOG, K - 1>::run(v, lds, tid, tw, q);
+    regs_to_lds<LOGN, ELOG, PLO, PEP>(v, lds, tid);
+    __syncthreads();
+    lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
+    fwd_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q);
+  }
+};
+template <int LOGN, int ELOG>
+struct FwdPasses<LOGN, ELOG, 0> {
+  // pass 0 expects its inputs already in registers (loaded from global)
+  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *, uint32_t tid, const uint2 *tw,
+                                             uint32_t q) {
+    constexpr int LO = pass_lo_fwd(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
+    fwd_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q);
+  }
+};
+
+template <int LOGN, int ELOG, int K>
+struct InvPasses {
+  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid,
+                                             const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
+                                             uint32_t bp) {
+    constexpr int LO = pass_lo_inv(LOGN, ELOG, K), EP = pass_bits(LOGN, ELOG, K);
+    constexpr int PLO = pass_lo_inv(LOGN, ELOG, K - 1), PEP = pass_bits(LOGN, ELOG, K - 1);
+    InvPasses<LOGN, ELOG, K - 1>::run(v, lds, tid, tw, q, a, ap, b, bp);
+    regs_to_lds<LOGN, ELOG, PLO, PEP>(v, lds, tid);
+    __syncthreads();
+    lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
+    inv_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q, a, ap, b, bp);
+  }
+};
+template <int LOGN, int ELOG>
+struct InvPasses<LOGN, ELOG, 0> {
+  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid,
+                                             const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
+                                             uint32_t bp) {
+    constexpr int LO = pass_lo_inv(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
+    // pass 0 (bits [0, EP)) reads a strided pattern: fetch it from LDS, which
+    // the caller filled with a coalesced copy of the polynomial
+    lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
+    inv_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q, a, ap, b, bp);
+  }
+};
+
+// ---------------------------------------------------------------- forward NTT kernel
+// One workgroup per polynomial of in/out [P][N] (limb = poly mod L). Input
+// canonical; output canonical, in bit-reversed evaluation order.
+template <int LOGN, int ELOG>
+__global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *in, uint32_t *out, LimbConsts c,
+                                                                 Twiddles tws) {
+  constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
+  __shared__ uint32_t lds[N + N / 32];
+  const uint32_t tid = threadIdx.x;
+  const size_t poly = blockIdx.x;
+  const uint32_t l = (uint32_t)(poly % c.L);
+  const uint32_t q = c.q[l];
+  const uint2 *tw = tws.fwd + (size_t)l * N;
+  const uint32_t *src = in + poly * N;
+  uint32_t v[E];
+  {
+    constexpr int LO = pass_lo_fwd(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
+#pragma unroll
+    for (int u = 0; u < E; ++u) v[u] = __builtin_nontemporal_load(src + gidx<LOGN, ELOG, LO, EP>(tid, u));
+  }
+  FwdPasses<LOGN, ELOG, NP - 1>::run(v, lds, tid, tw, q);
+  // the last pass (bits [0, EP)) holds strided indices: transpose through LDS
+  {
+    constexpr int LO = pass_lo_fwd(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
+    __syncthreads();
+    regs_to_lds<LOGN, ELOG, LO, EP>(v, lds, tid);
+    __syncthreads();
+  }
+  uint32_t *dst = out + poly * N;
+  const uint32_t q2 = 2 * q;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const uint32_t j = tid + (uint32_t)k * NT;
+    dst[j] = csub(csub(lds[lpad(j)], q2), q);
+  }
+}
+
+// ---------------------------------------------------------------- inverse NTT kernels
+template <int LOGN, int ELOG>
+__device__ __forceinline__ void intt_core(const uint32_t *src, uint32_t (&v)[1 << ELOG], uint32_t *lds,
+                                          uint32_t tid, const LimbConsts &c, const uint2 *tw, uint32_t l) {
+  constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const uint32_t j = tid + (uint32_t)k * NT;
+    lds[lpad(j)] = __builtin_nontemporal_load(src + j);
+  }
+  __syncthreads();
+  InvPasses<LOGN, ELOG, NP - 1>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l], c.ninvw_p[l]);
+  (void)N;
+}
+
+// Full mode: [P][N] -> [P][N] canonical (in place allowed).
+template <int LOGN, int ELOG>
+__global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t *in, uint32_t *out, LimbConsts c,
+                                                                   Twiddles tws) {
+  constexpr int N = 1 << LOGN, E = 1 << ELOG, NP = n_pass(LOGN, ELOG);
+  __shared__ uint32_t lds[N + N / 32];
+  const uint32_t tid = threadIdx.x;
+  const size_t poly = blockIdx.x;
+  const uint32_t l = (uint32_t)(poly % c.L);
+  uint32_t v[E];
+  intt_core<LOGN, ELOG>(in + poly * N, v, lds, tid, c, tws.inv + (size_t)l * N, l);
+  constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
+  uint32_t *dst = out + poly * N;
+  const uint32_t q = c.q[l];
+#pragma unroll
+  for (int u = 0; u < E; ++u) dst[gidx<LOGN, ELOG, LO, EP>(tid, u)] = csub(v[u], q);
+}
+
+// Masked mode over Yhat [B][O][2][L][N]: c1 polynomials are written whole to
+// c1_out [B][O][L][N]; c0 polynomials get the server mask added at the valid
+// output coefficients, which are gathered into c0_ext [B][c_out][L][ho][wo].
+template <int LOGN, int ELOG>
+__global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32_t *yhat, const uint32_t *mask,
+                                                                     uint32_t *c0_ext, uint32_t *c1_out, ConvGeom g,
+                                                                     LimbConsts c, Twiddles tws) {
+  constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
+  __shared__ uint32_t lds[N + N / 32];
+  const uint32_t tid = threadIdx.x;
+  const size_t poly = blockIdx.x;  // ((b O + o) 2 + p) L + l
+  const uint32_t l = (uint32_t)(poly % g.L);
+  const uint32_t p = (uint32_t)((poly / g.L) % 2);
+  const size_t bo = poly / (2 * (size_t)g.L);  // b O + o
+  const uint32_t o = (uint32_t)(bo % g.O);
+  const size_t b = bo / g.O;
+  const uint32_t q = c.q[l];
+  uint32_t v[E];
+  intt_core<LOGN, ELOG>(yhat + poly * N, v, lds, tid, c, tws.inv + (size_t)l * N, l);
+  constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
+  if (p == 1) {
+    uint32_t *dst = c1_out + (bo * g.L + l) * (size_t)N;
+#pragma unroll
+    for (int u = 0; u < E; ++u) dst[gidx<LOGN, ELOG, LO, EP>(tid, u)] = csub(v[u], q);
+    return;
+  }
+  __syncthreads();
+  regs_to_lds<LOGN, ELOG, LO, EP>(v, lds, tid);
+  __syncthreads();
+  const uint32_t i = o / g.T, tau = o % g.T;
+  // output rows of this tile: s*oy in [tau r_o, (tau+1) r_o)  (r_o is a multiple of s)
+  const uint32_t oy0 = tau * g.r_o / g.s;
+  const uint32_t oy1 = min(g.ho, (tau + 1) * g.r_o / g.s);
+  const uint32_t count = (oy1 > oy0 ? oy1 - oy0 : 0) * g.wo;
+  const uint32_t t = c.t, half = c.t / 2;
+  const uint32_t dl = c.delta[l], dlp = c.delta_p[l];
+  const uint32_t *mrow = mask + (b * g.c_out + i) * (size_t)g.ho * g.wo;
+  uint32_t *orow = c0_ext + ((b * g.c_out + i) * g.L + l) * (size_t)g.ho * g.wo;
+  for (uint32_t idx = tid; idx < count; idx += NT) {
+    const uint32_t oy = oy0 + idx / g.wo, ox = idx % g.wo;
+    const uint32_t e = (g.s * oy - tau * g.r_o) * g.w_pad + g.s * ox;
+    const uint32_t r = mrow[oy * g.wo + ox];
+    const uint32_t rc = r > half ? r - t + q : r;  // centred lift of r, taken mod q
+    const uint32_t add = csub(shoup_lazy(rc, dl, dlp, q), q);
+    orow[oy * g.wo + ox] = csub(csub(lds[lpad(e)], q) + add, q);
+  }
+}
+
+// ---------------------------------------------------------------- multiply-accumulate
+// Yhat[b][o][p][l][k] = sum_{gw < G_w} What[i][gw][l][k] * Xhat[b][gw T + tau][p][l][k]  mod q_l,
+// o = i T + tau. One thread per (coefficient k, output ciphertext o, limb l,
+// BT images): the weight is loaded once and used for 2 BT products.
+template <int BT>
+__global__ __launch_bounds__(256) void k_mac(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Wt,
+                                             uint32_t *__restrict__ Y, ConvGeom g, uint32_t B, uint32_t nkb,
+                                             uint32_t nbt, LimbConsts c) {
+  // XCD-aware order: the hardware deals workgroups round-robin over 8 XCDs;
+  // give each XCD a contiguous range of logical ids so that the output
+  // ciphertexts sharing an input tile also share an L2.
+  const uint32_t nwg = gridDim.x;
+  uint32_t wg = blockIdx.x;
+  if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
+  const uint32_t o = wg % g.O;
+  uint32_t r = wg / g.O;
+  const uint32_t kb = r % nkb;
+  r /= nkb;
+  const uint32_t l = r % g.L;
+  const uint32_t bt = r / g.L;
+  const uint32_t k = kb * 256 + threadIdx.x;
+  const uint32_t i = o / g.T, tau = o % g.T;
+  const uint32_t b0 = bt * BT;
+  const uint32_t nb = min((uint32_t)BT, B - b0);
+  const size_t LN = (size_t)g.L * g.N;
+  const size_t ct_stride = 2 * LN;  // one ciphertext
+  const uint32_t *wp = Wt + ((size_t)i * g.G_w) * LN + (size_t)l * g.N + k;
+  const uint32_t *xp = X + (size_t)l * g.N + k;
+  const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
+  uint64_t acc[BT][2];
+#pragma unroll
+  for (int bb = 0; bb < BT; ++bb) acc[bb][0] = acc[bb][1] = 0;
+  uint32_t since = 0;
+  for (uint32_t gw = 0; gw < g.G_w; ++gw) {
+    const uint32_t w = wp[(size_t)gw * LN];
+    const size_t ct = (size_t)gw * g.T + tau;
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) {
+      if ((uint32_t)bb < nb) {
+        const uint32_t *x = xp + ((size_t)(b0 + bb) * g.G + ct) * ct_stride;
+        acc[bb][0] += (uint64_t)w * x[0];
+        acc[bb][1] += (uint64_t)w * x[LN];
+      }
+    }
+    if (++since == fold) {
+      since = 0;
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+        for (int pp = 0; pp < 2; ++pp)
+          acc[bb][pp] = (uint64_t)(uint32_t)(acc[bb][pp] >> 32) * r2 + (uint32_t)acc[bb][pp];
+    }
+  }
+#pragma unroll
+  for (int bb = 0; bb < BT; ++bb) {
+    if ((uint32_t)bb < nb) {
+      uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + k;
+      y[0] = reduce64(acc[bb][0], q, r2, c.r2_p[l], c.one_p[l]);
+      y[LN] = reduce64(acc[bb][1], q, r2, c.r2_p[l], c.one_p[l]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- weight encoding
+// What[i][gw][l][idx] = sign * f[i][j][ky][kx] mod q_l with x^(-e) = sign x^idx,
+// e = o_j + ky w' + kx (x^0 = 1; x^(-e) = -x^(N-e) for e > 0). The e values of
+// one (i, gw) are pairwise distinct, so every slot is written at most once.
+__global__ void k_weight_scatter(const int8_t *__restrict__ f, uint32_t *__restrict__ Wt, ConvGeom g,
+                                 LimbConsts c) {
+  const size_t ff = (size_t)g.f * g.f;
+  const size_t total = (size_t)g.c_out * g.c_in * ff;
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const uint32_t tap = (uint32_t)(id % ff);
+  const uint32_t j = (uint32_t)((id / ff) % g.c_in);
+  const uint32_t i = (uint32_t)(id / (ff * g.c_in));
+  const uint32_t ky = tap / g.f, kx = tap % g.f;
+  const uint32_t gw = g.tiled ? j : j / g.cn;
+  const uint32_t oj = g.tiled ? 0u : (j % g.cn) * g.F;
+  const uint32_t e = oj + ky * g.w_pad + kx;
+  const uint32_t idx = e == 0 ? 0u : g.N - e;
+  const bool neg = e != 0;
+  const int32_t val = f[id];
+  for (uint32_t l = 0; l < g.L; ++l) {
+    const uint32_t q = c.q[l];
+    int32_t sv = neg ? -val : val;
+    const uint32_t res = sv >= 0 ? (uint32_t)sv : q - (uint32_t)(-sv);
+    Wt[(((size_t)i * g.G_w + gw) * g.L + l) * g.N + idx] = res;
+  }
+}
+
+__global__ void k_fill_zero(uint32_t *p, size_t n) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = id; k < n; k += stride) p[k] = 0u;
+}
+
+// ---------------------------------------------------------------- unfused mask + extract
+// c0_ext[b][i][l][oy][ox] = ct_out[b][(i,tau)][0][l][e] + Delta_l (r_c mod q_l) mod q_l
+__global__ void k_mask_extract(const uint32_t *__restrict__ ct, const uint32_t *__restrict__ mask,
+                               uint32_t *__restrict__ c0_ext, ConvGeom g, uint32_t B, LimbConsts c) {
+  const size_t total = (size_t)B * g.c_out * g.ho * g.wo;
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const uint32_t ox = (uint32_t)(id % g.wo);
+  const uint32_t oy = (uint32_t)((id / g.wo) % g.ho);
+  const uint32_t i = (uint32_t)((id / ((size_t)g.wo * g.ho)) % g.c_out);
+  const size_t b = id / ((size_t)g.wo * g.ho * g.c_out);
+  const uint32_t Y = g.s * oy;
+  const uint32_t tau = Y / g.r_o;
+  const uint32_t e = (Y - tau * g.r_o) * g.w_pad + g.s * ox;
+  const uint32_t o = i * g.T + tau;
+  const uint32_t r = mask[id];
+  const uint32_t t = c.t, half = c.t / 2;
+  for (uint32_t l = 0; l < g.L; ++l) {
+    const uint32_t q = c.q[l];
+    const uint32_t rc = r > half ? r - t + q : r;
+    const uint32_t add = csub(shoup_lazy(rc, c.delta[l], c.delta_p[l], q), q);
+    const uint32_t y = ct[(((b * g.O + o) * 2 + 0) * g.L + l) * (size_t)g.N + e];
+    c0_ext[((b * g.c_out + i) * g.L + l) * (size_t)g.ho * g.wo + (size_t)oy * g.wo + ox] = csub(y + add, q);
+  }
+}
+
+// c1_out[b][o][l][:] = ct[b][o][1][l][:], 16-byte copies.
+__global__ void k_copy_c1(const uint4 *__restrict__ ct, uint4 *__restrict__ c1, size_t n_ct, size_t ln4) {
+  const size_t total = n_ct * ln4;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+    const size_t ctn = id / ln4, k = id % ln4;
+    c1[id] = ct[(2 * ctn + 1) * ln4 + k];
+  }
+}
+
+// c[j] = a[j] * b[j] mod q over [P][N] (both operands variable).
+__global__ void k_pointwise_mul(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                                uint32_t *__restrict__ cc, size_t total, uint32_t N, LimbConsts c) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+    const uint32_t l = (uint32_t)((id / N) % c.L);
+    cc[id] = reduce64((uint64_t)a[id] * b[id], c.q[l], c.r2[l], c.r2_p[l], c.one_p[l]);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int LOGN, int ELOG>
+static hipError_t fwd_t(const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c, const Twiddles &tw,
+                        hipStream_t st) {
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_ntt_fwd<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c, tw);
+  return hipGetLastError();
+}
+template <int LOGN, int ELOG>
+static hipError_t inv_t(const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c, const Twiddles &tw,
+                        hipStream_t st) {
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_intt_full<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c,
+                     tw);
+  return hipGetLastError();
+}
+template <int LOGN, int ELOG>
+static hipError_t invm_t(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
+                         uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  const size_t np = (size_t)B * g.O * 2 * g.L;
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, y, m, c0,
+                     c1, g, c, tw);
+  return hipGetLastError();
+}
+
+// Thread-count choice per ring size: 2^(LOGN - ELOG) threads per polynomial.
+#define HC_NTT_DISPATCH(FN, ...)                 \
+  switch (logn) {                                \
+    case 10: return FN<10, 4>(__VA_ARGS__);      \
+    case 11: return FN<11, 4>(__VA_ARGS__);      \
+    case 12: return FN<12, 4>(__VA_ARGS__);      \
+    case 13: return FN<13, 5>(__VA_ARGS__);      \
+    case 14: return FN<14, 5>(__VA_ARGS__);      \
+    default: return hipErrorInvalidValue;        \
+  }
+
+hipError_t launch_ntt_fwd(uint32_t logn, const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c,
+                          const Twiddles &tw, hipStream_t st) {
+  HC_NTT_DISPATCH(fwd_t, in, out, np, c, tw, st)
+}
+hipError_t launch_intt_full(uint32_t logn, const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c,
+                            const Twiddles &tw, hipStream_t st) {
+  HC_NTT_DISPATCH(inv_t, in, out, np, c, tw, st)
+}
+hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, const uint32_t *y, const uint32_t *m, uint32_t *c0,
+                              uint32_t *c1, uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  HC_NTT_DISPATCH(invm_t, g, y, m, c0, c1, B, c, tw, st)
+}
+
+template <int BT>
+static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
+                        const LimbConsts &c, hipStream_t st) {
+  const uint32_t nkb = g.N / 256;
+  const uint32_t nbt = (B + BT - 1) / BT;
+  const size_t nwg = (size_t)g.O * nkb * g.L * nbt;
+  if (nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_mac<BT>), dim3((uint32_t)nwg), dim3(256), 0, st, x, w, y, g, B, nkb, nbt, c);
+  return hipGetLastError();
+}
+hipError_t launch_mac(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
+                      const LimbConsts &c, hipStream_t st) {
+  if (B >= 16) return mac_t<16>(g, x, w, y, B, c, st);
+  if (B >= 8) return mac_t<8>(g, x, w, y, B, c, st);
+  if (B >= 4) return mac_t<4>(g, x, w, y, B, c, st);
+  if (B >= 2) return mac_t<2>(g, x, w, y, B, c, st);
+  return mac_t<1>(g, x, w, y, B, c, st);
+}
+
+hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *f, uint32_t *w, const LimbConsts &c,
+                                 hipStream_t st) {
+  const size_t total = (size_t)g.c_out * g.c_in * g.f * g.f;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_weight_scatter, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, f, w, g, c);
+  return hipGetLastError();
+}
+hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_mask_extract(const ConvGeom &g, const uint32_t *ct, const uint32_t *mask, uint32_t *c0,
+                               uint32_t *c1, uint32_t B, const LimbConsts &c, hipStream_t st) {
+  const size_t total = (size_t)B * g.c_out * g.ho * g.wo;
+  if (total) {
+    hipLaunchKernelGGL(k_mask_extract, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, ct, mask, c0, g, B,
+                       c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const size_t n_ct = (size_t)B * g.O, ln4 = (size_t)g.L * g.N / 4;
+  if (n_ct == 0) return hipSuccess;
+  size_t blocks = (n_ct * ln4 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_copy_c1, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint4 *)ct, (uint4 *)c1, n_ct, ln4);
+  return hipGetLastError();
+}
+hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *cc, size_t np, uint32_t N,
+                                const LimbConsts &k, hipStream_t st) {
+  const size_t total = np * N;
+  if (total == 0) return hipSuccess;
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_pointwise_mul, dim3((uint32_t)blocks), dim3(256), 0, st, a, b, cc, total, N, k);
+  return hipGetLastError();
+}
+
+}  // namespace hc

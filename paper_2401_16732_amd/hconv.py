@@ -1,0 +1,325 @@
+"""Python binding of libhconv (include/hc.h): argument marshalling only.
+
+Device buffers are torch tensors (dtype int32 holding the uint32 residues,
+contiguous, on the library's HIP device); streams are torch.cuda streams.
+Every step of the convolution runs in the library's HIP kernels; when the
+library is missing this module raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhconv.so")
+
+HC_OK = 0
+_STATUS = {0: "HC_OK", -1: "HC_EINVAL", -2: "HC_EUNSUPPORTED", -3: "HC_ENOMEM", -4: "HC_EDEVICE", -5: "HC_ESTATE"}
+
+SYMBOLS = [
+    "hc_ctx_create", "hc_ctx_info", "hc_ctx_destroy", "hc_plan", "hc_layer_create", "hc_layer_destroy",
+    "hc_layer_plan", "hc_workspace_size", "hc_conv", "hc_mask_extract", "hc_conv_masked", "hc_batch_create",
+    "hc_batch_workspace_bytes", "hc_batch_run", "hc_batch_run_eager", "hc_batch_destroy", "hc_poly_mul",
+    "hc_sync", "hc_status_string", "hc_last_error", "hc_plan_ring", "hc_ring_params",
+]
+
+
+class HcError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {_STATUS.get(status, status)} ({detail})")
+        self.status = status
+
+
+class ConvShape(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in ("c_in", "c_out", "h", "w", "f", "stride")]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "sub", "s", "h_enc", "w_enc", "pad", "h_pad", "w_pad", "footprint", "tiled", "cn", "tiles",
+        "rows_out_per_tile", "in_cts", "w_cts", "out_cts", "ho", "wo")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhconv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2401_16732_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, u32, u64, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    I = ctypes.c_int
+    sig = {
+        "hc_ctx_create": (I, [u32, u32, P, u64, I, P]),
+        "hc_ctx_info": (I, [P, P, P]),
+        "hc_ctx_destroy": (None, [P]),
+        "hc_plan": (I, [P, P, P]),
+        "hc_layer_create": (I, [P, P, P, P, P]),
+        "hc_layer_destroy": (None, [P]),
+        "hc_layer_plan": (I, [P, P]),
+        "hc_workspace_size": (I, [P, u32, I, P]),
+        "hc_conv": (I, [P, P, P, u32, P, sz, P]),
+        "hc_mask_extract": (I, [P, P, P, P, P, u32, P]),
+        "hc_conv_masked": (I, [P, P, P, P, P, u32, P, sz, P]),
+        "hc_batch_create": (I, [P, P, u32, u32, P]),
+        "hc_batch_workspace_bytes": (I, [P, P]),
+        "hc_batch_run": (I, [P, P, P, P, P, P]),
+        "hc_batch_run_eager": (I, [P, P, P, P, P, P]),
+        "hc_batch_destroy": (None, [P]),
+        "hc_poly_mul": (I, [P, P, P, P, u32, P, sz, P]),
+        "hc_sync": (I, [P]),
+        "hc_status_string": (ctypes.c_char_p, [I]),
+        "hc_last_error": (ctypes.c_char_p, []),
+        "hc_plan_ring": (I, [u32, P, P]),
+        "hc_ring_params": (I, [u32, u32, u64, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != HC_OK:
+        raise HcError(status, where, _lib.hc_last_error().decode())
+
+
+def _dptr(t, name: str, device=None):
+    """Device pointer of a contiguous int32 CUDA/HIP tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int32 device tensor")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on device {t.device.index}, the context on {device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def plan_ring(N, c_in, c_out, h, w, f, stride=1) -> Layout:
+    """Layout of a convolution for ring degree N (host only)."""
+    load()
+    lay = Layout()
+    sh = ConvShape(c_in, c_out, h, w, f, stride)
+    _check(_lib.hc_plan_ring(N, ctypes.byref(sh), ctypes.byref(lay)), "hc_plan_ring")
+    return lay
+
+
+def ring_params(N: int, L: int, t: int):
+    """(primes, Delta mod q_l) that a context would use (host only)."""
+    load()
+    p = (ctypes.c_uint32 * L)()
+    d = (ctypes.c_uint32 * L)()
+    _check(_lib.hc_ring_params(N, L, t, p, d), "hc_ring_params")
+    return list(p), list(d)
+
+
+class Context:
+    """RNS ring context: N, L primes (largest < 2^30 with q = 1 mod 2N unless
+    given), plaintext modulus t; twiddle tables live on `device`."""
+
+    def __init__(self, N: int, L: int, t: int, device: int = 0, primes: Optional[Sequence[int]] = None):
+        lib = load()
+        self.N, self.L, self.t, self.device = N, L, t, device
+        h = ctypes.c_void_p()
+        pr = None
+        if primes is not None:
+            self._pr = (ctypes.c_uint32 * L)(*primes)
+            pr = ctypes.cast(self._pr, ctypes.c_void_p)
+        _check(lib.hc_ctx_create(N, L, pr, t, device, ctypes.byref(h)), "hc_ctx_create")
+        self.h = h
+        p = (ctypes.c_uint32 * L)()
+        d = (ctypes.c_uint32 * L)()
+        _check(lib.hc_ctx_info(h, p, d), "hc_ctx_info")
+        self.primes: List[int] = list(p)
+        self.delta_mod_q: List[int] = list(d)
+
+    def plan(self, c_in, c_out, h, w, f, stride=1) -> Layout:
+        lay = Layout()
+        sh = ConvShape(c_in, c_out, h, w, f, stride)
+        _check(_lib.hc_plan(self.h, ctypes.byref(sh), ctypes.byref(lay)), "hc_plan")
+        return lay
+
+    def poly_mul(self, a, b, out, ws, stream=None):
+        count = a.numel() // (self.L * self.N)
+        if a.numel() != count * self.L * self.N or b.numel() != a.numel() or out.numel() < a.numel():
+            raise ValueError("a, b, out must hold count * L * N words")
+        if ws.numel() < 2 * a.numel():
+            raise ValueError("ws must hold 2 * count * L * N words")
+        _check(_lib.hc_poly_mul(self.h, _dptr(a, "a", self.device), _dptr(b, "b", self.device),
+                                _dptr(out, "out", self.device), count, _dptr(ws, "ws", self.device),
+                                ws.numel() * 4, _stream(stream)), "hc_poly_mul")
+
+    def sync(self):
+        _check(_lib.hc_sync(self.h), "hc_sync")
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.hc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Layer:
+    """One convolution with its NTT-domain weights resident on the device
+    (hc_layer_create: the offline weight encoding)."""
+
+    def __init__(self, ctx: Context, c_in, c_out, h, w, f, stride, filters: np.ndarray, stream=None):
+        filters = np.ascontiguousarray(filters, dtype=np.int8)
+        if filters.shape != (c_out, c_in, f, f):
+            raise ValueError("filters must be int8 [c_out][c_in][f][f]")
+        self.ctx = ctx
+        self.shape = (c_in, c_out, h, w, f, stride)
+        sh = ConvShape(c_in, c_out, h, w, f, stride)
+        hdl = ctypes.c_void_p()
+        _check(_lib.hc_layer_create(ctx.h, ctypes.byref(sh), filters.ctypes.data_as(ctypes.c_void_p),
+                                    _stream(stream), ctypes.byref(hdl)), "hc_layer_create")
+        self.h = hdl
+        lay = Layout()
+        _check(_lib.hc_layer_plan(hdl, ctypes.byref(lay)), "hc_layer_plan")
+        self.layout = lay
+
+    def workspace_words(self, B: int, masked: bool) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.hc_workspace_size(self.h, B, 1 if masked else 0, ctypes.byref(n)), "hc_workspace_size")
+        return (n.value + 3) // 4
+
+    def _need(self, t, shape, name):
+        n = 1
+        for v in shape:
+            n *= v
+        if t.numel() < n:
+            raise ValueError(f"{name} holds {t.numel()} words, the layout needs {n} ({tuple(shape)})")
+
+    def conv(self, ct_in, ct_out, B: int, ws, stream=None):
+        d = self.ctx.device
+        self._need(ct_in, self.in_shape(B), "ct_in")
+        self._need(ct_out, self.out_shape(B), "ct_out")
+        self._need(ws, (self.workspace_words(B, False),), "ws")
+        _check(_lib.hc_conv(self.h, _dptr(ct_in, "ct_in", d), _dptr(ct_out, "ct_out", d), B, _dptr(ws, "ws", d),
+                            ws.numel() * 4, _stream(stream)), "hc_conv")
+
+    def mask_extract(self, ct_out, mask, c0_ext, c1_out, B: int, stream=None):
+        d = self.ctx.device
+        self._need(ct_out, self.out_shape(B), "ct_out")
+        self._need(mask, self.mask_shape(B), "mask")
+        self._need(c0_ext, self.c0_shape(B), "c0_ext")
+        self._need(c1_out, self.c1_shape(B), "c1_out")
+        _check(_lib.hc_mask_extract(self.h, _dptr(ct_out, "ct_out", d), _dptr(mask, "mask", d),
+                                    _dptr(c0_ext, "c0_ext", d), _dptr(c1_out, "c1_out", d), B, _stream(stream)),
+               "hc_mask_extract")
+
+    def conv_masked(self, ct_in, mask, c0_ext, c1_out, B: int, ws, stream=None):
+        d = self.ctx.device
+        self._need(ct_in, self.in_shape(B), "ct_in")
+        self._need(mask, self.mask_shape(B), "mask")
+        self._need(c0_ext, self.c0_shape(B), "c0_ext")
+        self._need(c1_out, self.c1_shape(B), "c1_out")
+        self._need(ws, (self.workspace_words(B, True),), "ws")
+        _check(_lib.hc_conv_masked(self.h, _dptr(ct_in, "ct_in", d), _dptr(mask, "mask", d),
+                                   _dptr(c0_ext, "c0_ext", d), _dptr(c1_out, "c1_out", d), B, _dptr(ws, "ws", d),
+                                   ws.numel() * 4, _stream(stream)), "hc_conv_masked")
+
+    # shapes of the device buffers for B images
+    def in_shape(self, B):
+        return (B, self.layout.in_cts, 2, self.ctx.L, self.ctx.N)
+
+    def out_shape(self, B):
+        return (B, self.layout.out_cts, 2, self.ctx.L, self.ctx.N)
+
+    def mask_shape(self, B):
+        return (B, self.shape[1], self.layout.ho, self.layout.wo)
+
+    def c0_shape(self, B):
+        return (B, self.shape[1], self.ctx.L, self.layout.ho, self.layout.wo)
+
+    def c1_shape(self, B):
+        return (B, self.layout.out_cts, self.ctx.L, self.ctx.N)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.hc_layer_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(ts, name, device):
+    arr = (ctypes.c_void_p * len(ts))()
+    for k, t in enumerate(ts):
+        arr[k] = _dptr(t, f"{name}[{k}]", device).value
+    return arr
+
+
+class Batch:
+    """All layers of a network on B images, recorded once into a HIP graph
+    (hc_batch_create / hc_batch_run)."""
+
+    def __init__(self, ctx: Context, layers: Sequence[Layer], B: int):
+        self.ctx, self.layers, self.B = ctx, list(layers), B
+        arr = (ctypes.c_void_p * len(layers))(*[ly.h.value for ly in layers])
+        h = ctypes.c_void_p()
+        _check(_lib.hc_batch_create(ctx.h, arr, len(layers), B, ctypes.byref(h)), "hc_batch_create")
+        self.h = h
+        n = ctypes.c_size_t()
+        _check(_lib.hc_batch_workspace_bytes(h, ctypes.byref(n)), "hc_batch_workspace_bytes")
+        self.workspace_bytes = n.value
+
+    def _args(self, ct_in, mask, c0, c1):
+        d = self.ctx.device
+        if not (len(ct_in) == len(mask) == len(c0) == len(c1) == len(self.layers)):
+            raise ValueError("one buffer per layer is required")
+        for k, ly in enumerate(self.layers):
+            ly._need(ct_in[k], ly.in_shape(self.B), f"ct_in[{k}]")
+            ly._need(mask[k], ly.mask_shape(self.B), f"mask[{k}]")
+            ly._need(c0[k], ly.c0_shape(self.B), f"c0_ext[{k}]")
+            ly._need(c1[k], ly.c1_shape(self.B), f"c1_out[{k}]")
+        return (_ptr_array(ct_in, "ct_in", d), _ptr_array(mask, "mask", d), _ptr_array(c0, "c0_ext", d),
+                _ptr_array(c1, "c1_out", d))
+
+    def run(self, ct_in, mask, c0, c1, stream=None):
+        self._keep = self._args(ct_in, mask, c0, c1)
+        _check(_lib.hc_batch_run(self.h, *self._keep, _stream(stream)), "hc_batch_run")
+
+    def run_eager(self, ct_in, mask, c0, c1, stream=None):
+        a = self._args(ct_in, mask, c0, c1)
+        _check(_lib.hc_batch_run_eager(self.h, *a, _stream(stream)), "hc_batch_run_eager")
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.hc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

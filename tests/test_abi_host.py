@@ -1,0 +1,95 @@
+"""The C-ABI library on the CPU: it loads, exports every declared entry point,
+and its host-only logic (layout planner, ring parameters) agrees with the
+oracle's independent implementation. No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import layout as olayout
+from oracle import params as oparams
+from paper_2401_16732_amd import hconv
+from paper_2401_16732_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "hc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:hc_status|void|const char\s*\*)\s*(hc_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hconv.load()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(hconv.SYMBOLS)
+
+
+def test_status_strings():
+    lib = hconv.load()
+    for s, text in [(0, b"ok"), (-1, b"invalid argument"), (-2, b"unsupported"), (-4, b"device error")]:
+        assert lib.hc_status_string(s) == text
+
+
+@pytest.mark.parametrize("N,L,t", [(4096, 2, 2 ** 17), (8192, 3, 2 ** 20), (16384, 4, 2 ** 24), (1024, 1, 3),
+                                   (2048, 4, 2 ** 30)])
+def test_ring_params_match_oracle(N, L, t):
+    primes, deltas = hconv.ring_params(N, L, t)
+    assert primes == oparams.rns_primes(N, L)
+    assert deltas == oparams.delta_limbs(primes, t)
+
+
+def _same_plan(N, spec):
+    lay = hconv.plan_ring(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+    P = olayout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+    got = (lay.sub, lay.s, lay.h_enc, lay.w_enc, lay.pad, lay.h_pad, lay.w_pad, lay.footprint, lay.tiled, lay.cn,
+           lay.tiles, lay.rows_out_per_tile, lay.in_cts, lay.w_cts, lay.out_cts, lay.ho, lay.wo)
+    exp = (P.sub, P.s, P.he, P.we, P.pad, P.hp, P.wp, P.F, int(P.tiled), P.c_n, P.T, P.r_o, P.G, P.G_w, P.O,
+           P.ho, P.wo)
+    assert got == exp, (spec, got, exp)
+
+
+@pytest.mark.parametrize("net,N", [("resnet18_cifar", 8192), ("resnet50_224", 8192), ("resnet18_224", 16384),
+                                   ("resnet18_cifar", 1024), ("resnet50_224", 4096)])
+def test_planner_matches_oracle_on_network_layers(net, N):
+    for spec in W.NETS[net]():
+        try:
+            olayout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+        except ValueError:
+            with pytest.raises(hconv.HcError):
+                hconv.plan_ring(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+            continue
+        _same_plan(N, spec)
+
+
+def test_planner_matches_oracle_on_odd_shapes():
+    g = W.rng(77)
+    for _ in range(300):
+        N = int(2 ** g.integers(10, 15))
+        f = int(g.choice([1, 3, 5, 7]))
+        spec = W.ConvSpec(int(g.integers(1, 40)), int(g.integers(1, 9)), int(g.integers(1, 150)),
+                          int(g.integers(1, 150)), f, int(g.integers(1, 4)))
+        try:
+            olayout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+        except ValueError:
+            with pytest.raises(hconv.HcError):
+                hconv.plan_ring(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+            continue
+        _same_plan(N, spec)
+
+
+def test_planner_rejects_bad_shapes():
+    with pytest.raises(hconv.HcError) as e:
+        hconv.plan_ring(4096, 4, 4, 8, 8, 2, 1)
+    assert e.value.status == -2
+    with pytest.raises(hconv.HcError) as e:
+        hconv.plan_ring(3000, 4, 4, 8, 8, 3, 1)
+    assert e.value.status == -2
+    with pytest.raises(hconv.HcError) as e:
+        hconv.plan_ring(4096, 0, 4, 8, 8, 3, 1)
+    assert e.value.status == -1

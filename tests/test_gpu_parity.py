@@ -1,0 +1,179 @@
+"""GPU parity: every output of the HIP path equals the CPU oracle bit for bit.
+
+The oracle is Algorithm 1 (C, int64 lazy accumulation) plus the mask/extract
+definition; the NTT is checked through negacyclic products against the
+schoolbook product. Inputs come from the seeded generators only.
+"""
+import numpy as np
+import pytest
+
+from oracle import bfv, calg1, conv, layout, params, ring
+from paper_2401_16732_amd import workloads as W
+
+from gpu_util import check_layer_points, dev, host, zeros
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_16732_amd import hconv
+    hconv.load()
+    return hconv
+
+
+def _ctx(hc, N, L, t):
+    c = hc.Context(N, L, t)
+    assert c.primes == params.rns_primes(N, L)
+    assert c.delta_mod_q == params.delta_limbs(c.primes, t)
+    return c
+
+
+@pytest.mark.parametrize("N", [1024, 2048, 4096, 8192, 16384])
+def test_ntt_negacyclic_product(hc, N):
+    print(f"poly_mul N={N}", flush=True)
+    L = 2
+    c = _ctx(hc, N, L, 2 ** 17)
+    g = W.rng(N)
+    count = 2
+    a = W.gen_ct_limbs(g, (count,), c.primes, N)
+    b = W.gen_ct_limbs(g, (count,), c.primes, N)
+    # edge operands: the constant 1 and the monomial x^(N-1)
+    a[1, 0] = 0
+    a[1, 0, 0] = 1
+    a[1, 1] = 0
+    a[1, 1, N - 1] = 1
+    out = zeros((count, L, N))
+    ws = zeros((2 * count * L * N,))
+    c.poly_mul(dev(a), dev(b), out, ws)
+    got = host(out)
+    for k in range(count):
+        for l, q in enumerate(c.primes):
+            assert (got[k, l] == ring.negacyclic_mul(a[k, l], b[k, l], q)).all(), (k, l)
+
+
+SMALL = [  # (N, c_i, c_o, h, w, f, stride)
+    (1024, 5, 3, 14, 14, 3, 1),     # c_n = 4, ragged second ciphertext
+    (1024, 3, 4, 40, 40, 7, 2),     # tiled (F > N), stride 2, ragged last tile
+    (1024, 6, 5, 20, 20, 1, 2),     # 1x1 stride 2: client subsampling
+    (2048, 9, 2, 9, 9, 5, 1),       # f = 5, c_n = 11
+    (2048, 1, 1, 30, 30, 3, 1),     # single channel
+    (1024, 2, 3, 60, 30, 3, 1),     # tiled, stride 1
+    (2048, 33, 7, 6, 6, 3, 2),      # many channels per ciphertext, stride 2
+]
+
+
+def _layer_case(hc, shape, B, seed):
+    N, ci, co, h, w, fw, s = shape
+    L, t = 2, 2 ** 17
+    c = _ctx(hc, N, L, t)
+    P = layout.plan(N, ci, co, h, w, fw, s)
+    g = W.rng(seed)
+    f = W.gen_filters(g, W.ConvSpec(ci, co, h, w, fw, s))
+    x = W.gen_ct_limbs(g, (B, P.G, 2), c.primes, N)
+    r = W.gen_mask(g, (B, co, P.ho, P.wo), t)
+    ly = hc.Layer(c, ci, co, h, w, fw, s, f)
+    assert (ly.layout.in_cts, ly.layout.out_cts, ly.layout.ho, ly.layout.wo) == (P.G, P.O, P.ho, P.wo)
+    return c, P, f, x, r, ly
+
+
+@pytest.mark.parametrize("shape", SMALL)
+@pytest.mark.parametrize("B", [1, 3, 17])
+def test_layer_bit_exact(hc, shape, B):
+    print(f"layer {shape} B={B}", flush=True)
+    c, P, f, x, r, ly = _layer_case(hc, shape, B, 1000 + B)
+    dx, dr = dev(x), dev(r)
+    # unfused: conv -> full ciphertexts; then mask + extract
+    ct_out = zeros(ly.out_shape(B))
+    ly.conv(dx, ct_out, B, zeros((ly.workspace_words(B, False),)))
+    c0a, c1a = zeros(ly.c0_shape(B)), zeros(ly.c1_shape(B))
+    ly.mask_extract(ct_out, dr, c0a, c1a, B)
+    # fused
+    c0b, c1b = zeros(ly.c0_shape(B)), zeros(ly.c1_shape(B))
+    ly.conv_masked(dx, dr, c0b, c1b, B, zeros((ly.workspace_words(B, True),)))
+    y_gpu = host(ct_out)
+    c0a, c1a, c0b, c1b = host(c0a), host(c1a), host(c0b), host(c1b)
+    for b in range(B):
+        y = calg1.alg1_layer(x[b], f, P, c.primes)
+        assert (y_gpu[b] == y).all(), f"image {b}: conv output differs"
+        e0, e1 = conv.mask_extract(y, r[b], P, c.primes, c.t)
+        assert (c0a[b] == e0).all() and (c1a[b] == e1).all(), f"image {b}: mask_extract differs"
+    assert (c0b == c0a).all() and (c1b == c1a).all(), "fused path differs from unfused"
+
+
+def test_config1_decrypt_invariant(hc):
+    """Single layer, N=4096, 2 primes, t=2^17, 16->16, 16x16, 3x3: real toy-BFV
+    encryptions; decrypt(HE-conv) - mask == plain conv mod t, and every output
+    bit-exact against the oracle."""
+    N, L, t = 4096, 2, 2 ** 17
+    spec = W.ConvSpec(16, 16, 16, 16, 3, 1)
+    c = _ctx(hc, N, L, t)
+    P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+    g = W.rng(2401)
+    f = W.gen_filters(g, spec)
+    a = W.gen_activations(g, spec, -128, 128)[0]
+    sk = bfv.sample_secret(g, N)
+    m = layout.encode_input(a, P)
+    x = np.stack([bfv.encrypt_sk(m[k], sk, bfv.sample_a(g, c.primes, N), bfv.sample_error(g, N), c.primes, t)
+                  for k in range(P.G)])[None]
+    r = W.gen_mask(g, (1, spec.c_o, P.ho, P.wo), t)
+    ly = hc.Layer(c, *[spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride], f)
+    c0, c1 = zeros(ly.c0_shape(1)), zeros(ly.c1_shape(1))
+    print("config1 conv_masked", flush=True)
+    ly.conv_masked(dev(x), dev(r), c0, c1, 1, zeros((ly.workspace_words(1, True),)))
+    c0, c1 = host(c0)[0], host(c1)[0]
+    y = calg1.alg1_layer(x[0], f, P, c.primes)
+    e0, e1 = conv.mask_extract(y, r[0], P, c.primes, t)
+    assert (c0 == e0).all() and (c1 == e1).all()
+    md = conv.decrypt_extracted(c0, c1, sk, P, c.primes, t)
+    z = conv.plain_conv_mod_t(a, f, spec.stride, t)
+    assert ((md.astype(np.int64) - r[0]) % t == z).all()
+
+
+def test_resnet18_cifar_layers_sampled(hc):
+    """ResNet-18/CIFAR conv stack at N=8192, 3 primes, t=2^20, one image, one
+    launch sequence per layer: sampled outputs of every layer vs the oracle,
+    plus a Freivalds check over all output channels of three layers."""
+    N, L, t = 8192, 3, 2 ** 20
+    c = _ctx(hc, N, L, t)
+    g = W.rng(18)
+    for k, spec in enumerate(W.resnet18_cifar()):
+        print(f"r18-cifar layer {k} {spec}", flush=True)
+        P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+        f = W.gen_filters(g, spec)
+        x = W.gen_ct_limbs(g, (1, P.G, 2), c.primes, N)
+        r = W.gen_mask(g, (1, spec.c_o, P.ho, P.wo), t)
+        ly = hc.Layer(c, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride, f)
+        c0, c1 = zeros(ly.c0_shape(1)), zeros(ly.c1_shape(1))
+        ly.conv_masked(dev(x), dev(r), c0, c1, 1, zeros((ly.workspace_words(1, True),)))
+        check_layer_points(P, c.primes, t, x[0], f, r[0], host(c0)[0], host(c1)[0], g, npts=48)
+        if k in (0, 7, 19):
+            ct = zeros(ly.out_shape(1))
+            ly.conv(dev(x), ct, 1, zeros((ly.workspace_words(1, False),)))
+            rho = [g.integers(0, q, size=spec.c_o) for q in c.primes]
+            lhs = conv.freivalds_lhs(host(ct)[0], rho, P, c.primes)
+            rhs = conv.freivalds_rhs(x[0], f, rho, P, c.primes)
+            assert (lhs == rhs).all(), f"Freivalds check failed on layer {k}"
+        ly.close()
+
+
+def test_error_paths(hc):
+    c = _ctx(hc, 1024, 2, 2 ** 17)
+    f = np.zeros((2, 2, 3, 3), dtype=np.int8)
+    ly = hc.Layer(c, 2, 2, 8, 8, 3, 1, f)
+    with pytest.raises(ValueError):
+        ly.conv(zeros((1,)), zeros(ly.out_shape(1)), 1, zeros((ly.workspace_words(1, False),)))
+    with pytest.raises(hc.HcError) as e:
+        hc.Layer(c, 2, 2, 8, 8, 2, 1, np.zeros((2, 2, 2, 2), dtype=np.int8))
+    assert e.value.status == -2
+    with pytest.raises(hc.HcError) as e:
+        hc.Context(1000, 2, 2 ** 17)
+    assert e.value.status == -2
+    with pytest.raises(hc.HcError) as e:
+        hc.Context(1024, 1, 2 ** 17, primes=[1073692673 + 2])
+    assert e.value.status == -1
+    # B = 0 is a no-op
+    ly.conv(zeros((1,)), zeros((1,)), 0, zeros((1,)))
