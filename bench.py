@@ -1,0 +1,289 @@
+#!/usr/bin/env python3
+"""Benchmark: HE convolution of a whole ResNet-50 (224x224) on one MI355X.
+
+One step = every convolution layer of the network (53 layers) on a batch of B
+images, each layer computed as forward NTT -> multiply-accumulate against
+resident NTT-domain weights -> inverse NTT with the server mask added and the
+output coefficients extracted, replayed as one HIP graph. Inputs (ciphertexts,
+masks) are resident in HBM before the timed region. Reported:
+
+  value                ms of HE convolution per ResNet-50 image (batched graph)
+  plain_ms_per_image   the same work per image with one launch sequence per
+                       layer at B = 1 (stream order, no graph)
+  speedup_vs_plain     plain / batched
+  modmul_per_s         algorithmic modular multiplies (NTT butterflies + MAC)
+                       per second, batched
+  roofline             the dominant kernel against the VALU / HBM ceiling
+  cpu_baseline         the CPU oracle (Algorithm 1 in C, OpenMP) on a sample
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK = 8.0e12                     # bytes/s, MI355X HBM3E
+CUS, CLK = 256, 2.4e9                 # compute units, peak engine clock
+SIMPLE_LANES, MUL_LANES = 128, 64     # 32-bit lane-ops per clock per CU: add/sub/cmp, and integer multiply
+# Ideal Harvey butterfly: 3 multiplies (mul_hi, 2 mul_lo: Shoup) + 5 simple ops.
+BFLY_PEAK = CUS * CLK / (3.0 / MUL_LANES + 5.0 / SIMPLE_LANES)
+# Ideal MAC term: one v_mad_u64_u32.
+MAC_PEAK = CUS * CLK * MUL_LANES
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--net", default="resnet50_224", choices=["resnet50_224", "resnet18_cifar", "resnet18_224"])
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--N", type=int, default=8192)
+    ap.add_argument("--L", type=int, default=3)
+    ap.add_argument("--t", type=int, default=2 ** 20)
+    ap.add_argument("--plain-images", type=int, default=2)
+    ap.add_argument("--cpu-fraction", type=float, default=1.0 / 16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--seed", type=int, default=50)
+    ap.add_argument("--stage-passes", type=int, default=3, help="eager passes timed per kernel for the roofline")
+    ap.add_argument("--copy-gib", type=float, default=4.0, help="size of the HBM stream-copy calibration")
+    return ap.parse_args()
+
+
+def hbm_copy(torch, dev, gib, reps=5):
+    """Achievable HBM bandwidth: a plain device-to-device copy of `gib` GiB
+    (read + write counted), timed with events on the current stream."""
+    n = int(gib * 2 ** 30) // 4
+    a = torch.empty(n, dtype=torch.int32, device=dev)
+    b = torch.empty(n, dtype=torch.int32, device=dev)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * n * 4, "ms": round(ms, 3), "GBps": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
+
+
+def layer_counts(ly, B, N, L):
+    """Algorithmic work of one layer on B images (no scratch round trips)."""
+    lay = ly.layout
+    c_out = ly.shape[1]
+    logn = int(math.log2(N))
+    pin = B * lay.in_cts * 2 * L
+    pout = B * lay.out_cts * 2 * L
+    return {
+        "bfly_fwd": pin * (N // 2) * logn,
+        "bfly_inv": pout * (N // 2) * logn,
+        "mac": B * lay.out_cts * lay.w_cts * 2 * L * N,
+        "mask": B * c_out * lay.ho * lay.wo * L,
+        # bytes each kernel must move through its interface
+        "bytes_fwd": pin * N * 4 * 2,
+        "bytes_mac": (c_out * lay.w_cts * L * N + B * lay.in_cts * 2 * L * N + B * lay.out_cts * 2 * L * N) * 4,
+        "bytes_inv": (B * lay.out_cts * 2 * L * N + B * lay.out_cts * L * N + B * c_out * L * lay.ho * lay.wo
+                      + B * c_out * lay.ho * lay.wo) * 4,
+        # whole-path algorithmic bytes: weights once + inputs + c1 out + c0_ext out + mask
+        "bytes_path": (B * (lay.in_cts * 2 * L * N + lay.out_cts * L * N + c_out * L * lay.ho * lay.wo
+                            + c_out * lay.ho * lay.wo)) * 4,
+        "bytes_w": c_out * lay.w_cts * L * N * 4,
+    }
+
+
+def cpu_baseline(specs, N, L, t, frac, seed):
+    """The oracle (Algorithm 1 in C, OpenMP) on every layer for one image over
+    the first ceil(frac * c_out) output channels; Algorithm 1's work is the same
+    for every output channel, so the time scales by c_out / sampled."""
+    import numpy as np
+    from oracle import calg1, layout, params
+    from paper_2401_16732_amd import workloads as W
+    primes = params.rns_primes(N, L)
+    g = W.rng(seed + 1)
+    total_s, sampled, full = 0.0, 0, 0
+    for spec in specs:
+        P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+        f = W.gen_filters(g, spec)
+        x = W.gen_ct_limbs(g, (P.G, 2), primes, N)
+        n = max(1, math.ceil(frac * spec.c_o))
+        t0 = time.perf_counter()
+        calg1.alg1_layer(x, f, P, primes, outputs=np.arange(n))
+        dt = time.perf_counter() - t0
+        total_s += dt * spec.c_o / n
+        sampled += n
+        full += spec.c_o
+    return {"value": round(total_s * 1e3, 1), "unit": "ms/image", "cores": calg1.threads(), "kind": "oracle",
+            "sample": f"1 image, every layer, first {sampled} of {full} output channels "
+                      f"(~{frac:.4f} of the Algorithm 1 work), scaled by c_out/sampled per layer"}
+
+
+def main():
+    a = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (each image is independent; "
+              "see the design notes on sharding). Use --gpus 1.", file=sys.stderr)
+        return 2
+    import torch
+    from paper_2401_16732_amd import hconv
+    from paper_2401_16732_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    N, L, t, B = a.N, a.L, a.t, a.batch
+    ctx = hconv.Context(N, L, t)
+    specs = W.NETS[a.net]()
+    g = W.rng(a.seed)
+
+    # offline: resident NTT-domain weights (timed apart, like the paper's offline phase)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    layers = [hconv.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, W.gen_filters(g, s)) for s in specs]
+    torch.cuda.synchronize()
+    encode_ms = (time.perf_counter() - t0) * 1e3
+    print(f"[bench] {a.net}: {len(layers)} layers encoded in {encode_ms:.0f} ms", file=sys.stderr, flush=True)
+
+    tg = torch.Generator(device=dev)
+    tg.manual_seed(a.seed)
+    ct_in = [W.gen_ct_limbs_torch(tg, ly.in_shape(B)[:3], ctx.primes, N, dev) for ly in layers]
+    mask = [torch.randint(0, t, ly.mask_shape(B), generator=tg, device=dev, dtype=torch.int32) for ly in layers]
+    c0 = [torch.empty(ly.c0_shape(B), dtype=torch.int32, device=dev) for ly in layers]
+    c1 = [torch.empty(ly.c1_shape(B), dtype=torch.int32, device=dev) for ly in layers]
+    bt = hconv.Batch(ctx, layers, B)
+    torch.cuda.synchronize()
+    print(f"[bench] inputs resident; batch workspace {bt.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr,
+          flush=True)
+
+    for _ in range(a.warmup):
+        bt.run(ct_in, mask, c0, c1)
+    torch.cuda.synchronize()
+    ms_step = float("nan")
+    if a.steps > 0:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record()
+        for _ in range(a.steps):
+            bt.run(ct_in, mask, c0, c1)
+        e1.record()
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - w0) * 1e3 / a.steps
+        ms_step = e0.elapsed_time(e1) / a.steps
+        print(f"[bench] batched: {ms_step:.2f} ms/step ({ms_step / B:.3f} ms/image), wall {wall_ms:.2f}",
+              file=sys.stderr, flush=True)
+
+    # per-kernel stage times (eager, events around every launch on its stream)
+    acc = [0.0, 0.0, 0.0]
+    for _ in range(max(1, a.stage_passes)):
+        st = bt.run_timed(ct_in, mask, c0, c1)
+        acc = [x + y for x, y in zip(acc, st)]
+    stage = [x / max(1, a.stage_passes) for x in acc]
+    torch.cuda.synchronize()
+    print(f"[bench] stages (eager, ms): fwd {stage[0]:.2f} mac {stage[1]:.2f} inv {stage[2]:.2f}",
+          file=sys.stderr, flush=True)
+    copy = hbm_copy(torch, dev, a.copy_gib)
+    print(f"[bench] HBM copy: {copy['GBps']} GB/s", file=sys.stderr, flush=True)
+
+    tot = {}
+    for ly in layers:
+        for k, v in layer_counts(ly, B, N, L).items():
+            tot[k] = tot.get(k, 0) + v
+    modmul = tot["bfly_fwd"] + tot["bfly_inv"] + tot["mac"] + tot["mask"]
+
+    # plain path: one launch sequence per layer, one image at a time
+    plain_ms = None
+    if not a.no_plain:
+        wsw = max(ly.workspace_words(1, True) for ly in layers)
+        ws = torch.empty((wsw,), dtype=torch.int32, device=dev)
+
+        def one_image(b):
+            for k, ly in enumerate(layers):
+                ly.conv_masked(ct_in[k][b], mask[k][b], c0[k][b], c1[k][b], 1, ws)
+
+        one_image(0)
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record()
+        for b in range(a.plain_images):
+            one_image(b % B)
+        p1.record()
+        torch.cuda.synchronize()
+        plain_ms = p0.elapsed_time(p1) / a.plain_images
+        print(f"[bench] plain: {plain_ms:.3f} ms/image", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel (largest stage time)
+    names = [("ntt_fwd", stage[0], tot["bfly_fwd"], tot["bytes_fwd"]),
+             ("mac", stage[1], tot["mac"], tot["bytes_mac"]),
+             ("intt_mask_extract", stage[2], tot["bfly_inv"], tot["bytes_inv"])]
+    kname, kms, kops, kbytes = max(names, key=lambda r: r[1])
+    ops_peak = MAC_PEAK if kname == "mac" else BFLY_PEAK
+    t_alu, t_hbm = kops / ops_peak, kbytes / HBM_PEAK
+    if t_alu >= t_hbm:
+        ach = kops / (kms * 1e-3)
+        roof = {"bound": "alu", "achieved": round(ach / 1e12, 4), "peak": round(ops_peak / 1e12, 4),
+                "unit": "Tmac/s" if kname == "mac" else "Tbutterfly/s"}
+    else:
+        ach = kbytes / (kms * 1e-3)
+        roof = {"bound": "hbm", "achieved": round(ach / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = None
+    roof["kernel"] = kname
+    roof["launches"] = len(layers)
+    roof["ms_total"] = round(kms, 3)
+    roof["algorithmic_ops"] = kops
+    roof["algorithmic_bytes"] = kbytes
+    roof["alu_frac"] = round(kops / (kms * 1e-3) / ops_peak, 4)
+    roof["hbm_frac"] = round(kbytes / (kms * 1e-3) / HBM_PEAK, 4)
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(specs, N, L, t, a.cpu_fraction, a.seed)
+
+    per_img = ms_step / B
+    if a.steps == 0:
+        print(json.dumps({"profile_pass": True, "stage_ms_eager": stage, "hbm_copy": copy}), flush=True)
+        return 0
+    out = {
+        "metric": "HE-conv ms per ResNet-50 image + NTT modmul/s vs roofline, batched vs plain",
+        "value": round(per_img, 4),
+        "unit": "ms/image",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.net} HE convolution, all {len(layers)} conv layers, batched HIP graph",
+                   "N": N, "L": L, "primes": ctx.primes, "t": t, "batch": B, "layers": len(layers),
+                   "parallelism": "single GPU"},
+        "images_per_s": round(1e3 / per_img, 2),
+        "modmul_per_s": round(modmul / (ms_step * 1e-3), 1),
+        "plain_ms_per_image": None if plain_ms is None else round(plain_ms, 4),
+        "speedup_vs_plain": None if plain_ms is None else round(plain_ms / per_img, 3),
+        "weight_encode_ms": round(encode_ms, 1),
+        "stage_ms_eager": [round(v, 3) for v in stage],
+        "path_bytes_per_step": tot["bytes_path"] + tot["bytes_w"],
+        "path_hbm_frac": round((tot["bytes_path"] + tot["bytes_w"]) / (ms_step * 1e-3) / HBM_PEAK, 4),
+        "hbm_copy": copy,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -97,6 +97,18 @@ typedef struct {
     uint32_t ho, wo;            /* output size */
 } hc_layout;
 
+/* Launch-shape choices of a context (the autotuner's knobs). They change
+ * speed only, never results: every supported value produces the same bits.
+ * 0 selects the library default for that field. */
+typedef struct {
+    uint32_t fwd_elog;   /* forward NTT: 2^fwd_elog coefficients per thread */
+    uint32_t inv_elog;   /* inverse NTT: 2^inv_elog coefficients per thread */
+    uint32_t mac_rows;   /* multiply-accumulate: images per thread */
+    uint32_t mac_cols;   /* multiply-accumulate: output channels per thread */
+    uint32_t mac_row_groups;  /* waves per workgroup along images */
+    uint32_t mac_col_groups;  /* waves per workgroup along output channels */
+} hc_tuning;
+
 /* Create a context on HIP device `hip_device`: ring degree N (power of two,
  * 1024..16384), L RNS primes (1..4), plaintext modulus t (2..2^30).
  * primes: L distinct primes < 2^30 with q = 1 mod 2N, or NULL to choose the
@@ -108,6 +120,12 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
 /* Copy out the primes (L values) and Delta mod q_l (L values); either pointer may be NULL. */
 hc_status hc_ctx_info(const hc_ctx *ctx, uint32_t *primes_out, uint32_t *delta_mod_q_out);
 void hc_ctx_destroy(hc_ctx *ctx);
+
+/* Set / read the context's launch shapes. Unsupported combinations return
+ * HC_EUNSUPPORTED and leave the tuning unchanged. Not thread-safe against
+ * calls in flight on the same context from other host threads. */
+hc_status hc_ctx_set_tuning(hc_ctx *ctx, const hc_tuning *tuning);
+hc_status hc_ctx_get_tuning(const hc_ctx *ctx, hc_tuning *out);
 
 /* The layout of `shape` in this context (pure host computation). */
 hc_status hc_plan(const hc_ctx *ctx, const hc_conv_shape *shape, hc_layout *out);
@@ -175,6 +193,14 @@ hc_status hc_batch_run(hc_batch *batch, const uint32_t *const *ct_in, const uint
 hc_status hc_batch_run_eager(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
                              uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream);
 void hc_batch_destroy(hc_batch *batch);
+
+/* hc_batch_run_eager with a HIP event recorded on `stream` before and after
+ * every kernel launch; waits for completion and adds the elapsed milliseconds
+ * of each stage to stage_ms[0] (forward NTT of the inputs), stage_ms[1]
+ * (multiply-accumulate) and stage_ms[2] (inverse NTT with mask and
+ * extraction). For measurement; the events serialise the launches. */
+hc_status hc_batch_run_timed(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                             uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream, double *stage_ms);
 
 /* Negacyclic products c_k = a_k * b_k mod (x^N + 1, q_l) of `count` pairs of
  * polynomials laid out [count][L][N] (canonical residues), through the same

@@ -25,6 +25,19 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the OpenMP loops below will use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* dst += DRot(src, step) * w  (w = 1 for the channel alignment). */
 static void drot_axpy(int64_t *dst, const int64_t *src, uint32_t n, uint32_t step, int64_t w)

@@ -38,11 +38,17 @@ def load():
     u32 = ctypes.c_uint32
     lib.oracle_alg1_layer.restype = ctypes.c_int
     lib.oracle_alg1_layer.argtypes = [u32, u32, P, u32, u32, u32, P, P, P, P, P, u32, P, P]
+    lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_threads.argtypes = []
     lib.oracle_alg1_points.restype = None
     lib.oracle_alg1_points.argtypes = [u32, u32, P, u32, u32, u32, P, P, P, P, P, ctypes.c_uint64,
                                        P, P, P, P, P, P]
     _lib = lib
     return lib
+
+
+def threads() -> int:
+    return int(load().oracle_threads())
 
 
 def _ptr(a: np.ndarray):

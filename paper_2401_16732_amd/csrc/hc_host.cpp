@@ -101,6 +101,7 @@ struct hc_ctx {
   LimbConsts consts{};
   uint2 *d_tw = nullptr;  // [2][L][N]: forward then inverse
   Twiddles tw{};
+  hc_tuning tune{};        // 0 fields = defaults
 };
 
 struct hc_layer {
@@ -224,21 +225,61 @@ struct DeviceGuard {
   }
 };
 
+// Launch shapes in effect for B images.
+struct Shapes {
+  uint32_t fe, ie, bt, ct, rg, cg;
+};
+// Defaults measured on MI355X (ResNet-50 layer mix, N = 8192).
+uint32_t default_fwd_elog(uint32_t logn) { return logn >= 13 ? 5 : 4; }
+uint32_t default_inv_elog(uint32_t logn) { return logn >= 10 ? 4 : 3; }
+Shapes shapes_for(const hc_ctx &c, uint32_t B) {
+  Shapes s{};
+  s.fe = c.tune.fwd_elog ? c.tune.fwd_elog : default_fwd_elog(c.logn);
+  s.ie = c.tune.inv_elog ? c.tune.inv_elog : default_inv_elog(c.logn);
+  if (c.tune.mac_rows) {
+    s.bt = c.tune.mac_rows, s.ct = c.tune.mac_cols, s.rg = c.tune.mac_row_groups, s.cg = c.tune.mac_col_groups;
+  } else if (B >= 16) {
+    s.bt = 4, s.ct = 4, s.rg = 4, s.cg = 2;
+  } else if (B >= 4) {
+    s.bt = 4, s.ct = 4, s.rg = 1, s.cg = 4;
+  } else if (B >= 2) {
+    s.bt = 2, s.ct = 4, s.rg = 1, s.cg = 4;
+  } else {
+    s.bt = 1, s.ct = 8, s.rg = 1, s.cg = 4;
+  }
+  return s;
+}
+
+// Optional per-stage timing: events recorded on the launch stream around each kernel.
+struct StageTimer {
+  hipEvent_t ev[6] = {};
+  bool on = false;
+};
+
 // A2 -> A4 (+A5 when masked) for one layer on B images.
 hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_out, const uint32_t *mask,
-                       uint32_t *c0_ext, uint32_t *c1_out, uint32_t B, void *ws, bool masked, hipStream_t st) {
+                       uint32_t *c0_ext, uint32_t *c1_out, uint32_t B, void *ws, bool masked, hipStream_t st,
+                       StageTimer *tm = nullptr) {
   const hc_ctx &c = *ly->ctx;
   const ConvGeom &g = ly->geom;
+  const bool timed = tm && tm->on;
+  const Shapes sh = shapes_for(c, B);
   uint32_t *xhat = (uint32_t *)ws;
   const size_t npin = (size_t)B * g.G * 2 * c.L;
-  HC_HIP(hc::launch_ntt_fwd(c.logn, ct_in, xhat, npin, c.consts, c.tw, st));
+  if (timed) HC_HIP(hipEventRecord(tm->ev[0], st));
+  HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, ct_in, xhat, npin, c.consts, c.tw, st));
+  if (timed) HC_HIP(hipEventRecord(tm->ev[1], st));
   if (!masked) {
-    HC_HIP(hc::launch_mac(g, xhat, ly->d_w, ct_out, B, c.consts, st));
-    HC_HIP(hc::launch_intt_full(c.logn, ct_out, ct_out, (size_t)B * g.O * 2 * c.L, c.consts, c.tw, st));
+    HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, xhat, ly->d_w, ct_out, B, c.consts, st));
+    HC_HIP(hc::launch_intt_full(c.logn, sh.ie, ct_out, ct_out, (size_t)B * g.O * 2 * c.L, c.consts, c.tw, st));
   } else {
     uint32_t *yhat = xhat + npin * c.N;
-    HC_HIP(hc::launch_mac(g, xhat, ly->d_w, yhat, B, c.consts, st));
-    HC_HIP(hc::launch_intt_masked(g, c.logn, yhat, mask, c0_ext, c1_out, B, c.consts, c.tw, st));
+    if (timed) HC_HIP(hipEventRecord(tm->ev[2], st));
+    HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, xhat, ly->d_w, yhat, B, c.consts, st));
+    if (timed) HC_HIP(hipEventRecord(tm->ev[3], st));
+    if (timed) HC_HIP(hipEventRecord(tm->ev[4], st));
+    HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, yhat, mask, c0_ext, c1_out, B, c.consts, c.tw, st));
+    if (timed) HC_HIP(hipEventRecord(tm->ev[5], st));
   }
   return HC_OK;
 }
@@ -399,6 +440,27 @@ void hc_ctx_destroy(hc_ctx *c) {
   delete c;
 }
 
+hc_status hc_ctx_set_tuning(hc_ctx *c, const hc_tuning *t) {
+  if (!c || !t) return fail(HC_EINVAL, "null argument");
+  if (t->fwd_elog && !hc::ntt_variant_ok(c->logn, t->fwd_elog))
+    return fail(HC_EUNSUPPORTED, "forward NTT shape not available for this N");
+  if (t->inv_elog && !hc::ntt_variant_ok(c->logn, t->inv_elog))
+    return fail(HC_EUNSUPPORTED, "inverse NTT shape not available for this N");
+  const bool any = t->mac_rows || t->mac_cols || t->mac_row_groups || t->mac_col_groups;
+  const bool all = t->mac_rows && t->mac_cols && t->mac_row_groups && t->mac_col_groups;
+  if (any && !all) return fail(HC_EINVAL, "set all four MAC fields or none");
+  if (all && !hc::mac_variant_ok(t->mac_rows, t->mac_cols, t->mac_row_groups, t->mac_col_groups))
+    return fail(HC_EUNSUPPORTED, "MAC tile not available");
+  c->tune = *t;
+  return HC_OK;
+}
+
+hc_status hc_ctx_get_tuning(const hc_ctx *c, hc_tuning *out) {
+  if (!c || !out) return fail(HC_EINVAL, "null argument");
+  *out = c->tune;
+  return HC_OK;
+}
+
 hc_status hc_plan(const hc_ctx *c, const hc_conv_shape *s, hc_layout *o) {
   if (!c || !s || !o) return fail(HC_EINVAL, "null argument");
   return plan_impl(c->N, *s, *o);
@@ -452,7 +514,8 @@ hc_status hc_layer_create(hc_ctx *c, const hc_conv_shape *s, const int8_t *filte
   if (e == hipSuccess) e = hc::launch_fill_zero(ly->d_w, ly->w_elems, hs);
   if (e == hipSuccess) e = hc::launch_weight_scatter(ly->geom, d_f, ly->d_w, c->consts, hs);
   if (e == hipSuccess)
-    e = hc::launch_ntt_fwd(c->logn, ly->d_w, ly->d_w, (size_t)s->c_out * lay.w_cts * c->L, c->consts, c->tw, hs);
+    e = hc::launch_ntt_fwd(c->logn, shapes_for(*c, 1).fe, ly->d_w, ly->d_w, (size_t)s->c_out * lay.w_cts * c->L,
+                           c->consts, c->tw, hs);
   if (e == hipSuccess) e = hipStreamSynchronize(hs);
   if (d_f) (void)hipFree(d_f);
   if (e != hipSuccess) {
@@ -520,10 +583,11 @@ hc_status hc_poly_mul(const hc_ctx *c, const uint32_t *a, const uint32_t *b, uin
   DeviceGuard dg(c->device);
   hipStream_t st = (hipStream_t)stream;
   uint32_t *wa = (uint32_t *)ws, *wb = wa + np * c->N;
-  HC_HIP(hc::launch_ntt_fwd(c->logn, a, wa, np, c->consts, c->tw, st));
-  HC_HIP(hc::launch_ntt_fwd(c->logn, b, wb, np, c->consts, c->tw, st));
+  const Shapes sh = shapes_for(*c, 1);
+  HC_HIP(hc::launch_ntt_fwd(c->logn, sh.fe, a, wa, np, c->consts, c->tw, st));
+  HC_HIP(hc::launch_ntt_fwd(c->logn, sh.fe, b, wb, np, c->consts, c->tw, st));
   HC_HIP(hc::launch_pointwise_mul(wa, wb, wa, np, c->N, c->consts, st));
-  HC_HIP(hc::launch_intt_full(c->logn, wa, out, np, c->consts, c->tw, st));
+  HC_HIP(hc::launch_intt_full(c->logn, sh.ie, wa, out, np, c->consts, c->tw, st));
   return HC_OK;
 }
 
@@ -607,7 +671,13 @@ hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_
   hipStream_t st = (hipStream_t)stream;
   const size_t n = bt->layers.size();
   std::vector<const void *> key;
-  key.reserve(4 * n);
+  key.reserve(4 * n + 4);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.fwd_elog);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.inv_elog);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_rows);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_cols);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_row_groups);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_col_groups);
   for (size_t k = 0; k < n; ++k) {
     key.push_back(ct_in[k]);
     key.push_back(mask[k]);
@@ -647,6 +717,35 @@ hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_
   }
   HC_HIP(hipGraphLaunch(bt->exec, st));
   return HC_OK;
+}
+
+hc_status hc_batch_run_timed(hc_batch *bt, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                             uint32_t *const *c0, uint32_t *const *c1, void *stream, double *stage_ms) {
+  hc_status s = batch_check(bt, ct_in, mask, c0, c1);
+  if (s != HC_OK) return s;
+  if (!stage_ms) return fail(HC_EINVAL, "stage_ms is null");
+  DeviceGuard dg(bt->ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+  StageTimer tm;
+  tm.on = true;
+  for (int k = 0; k < 6; ++k) HC_HIP(hipEventCreate(&tm.ev[k]));
+  hc_status out = HC_OK;
+  for (size_t k = 0; k < bt->layers.size() && out == HC_OK; ++k) {
+    out = enqueue_conv(bt->layers[k], ct_in[k], nullptr, mask[k], c0[k], c1[k], bt->B,
+                       (char *)bt->ws + bt->ws_off[k], true, st, &tm);
+    if (out != HC_OK) break;
+    hipError_t e = hipEventSynchronize(tm.ev[5]);
+    float a = 0, b = 0, c = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&a, tm.ev[0], tm.ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, tm.ev[2], tm.ev[3]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&c, tm.ev[4], tm.ev[5]);
+    if (e != hipSuccess) out = hip_fail(e, "stage timing");
+    stage_ms[0] += a;
+    stage_ms[1] += b;
+    stage_ms[2] += c;
+  }
+  for (int k = 0; k < 6; ++k) (void)hipEventDestroy(tm.ev[k]);
+  return out;
 }
 
 void hc_batch_destroy(hc_batch *bt) {

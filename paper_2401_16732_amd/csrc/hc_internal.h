@@ -45,18 +45,24 @@ struct ConvGeom {
 enum InttMode : int { kInttFull = 0, kInttMasked = 1 };
 
 // Launchers (hc_kernels.hip). Each enqueues on `st` and returns the launch status.
-hipError_t launch_ntt_fwd(uint32_t logn, const uint32_t *in, uint32_t *out, size_t npolys, const LimbConsts &c,
-                          const Twiddles &tw, hipStream_t st);
+// Launch-shape variants: an NTT uses 2^(logn - elog) threads per polynomial;
+// the MAC gives each thread bt images x ct output channels, and a workgroup
+// rg x cg such threads per coefficient (image groups x channel groups).
+bool ntt_variant_ok(uint32_t logn, uint32_t elog);
+bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg);
+
+hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
+                          const LimbConsts &c, const Twiddles &tw, hipStream_t st);
 // Full mode: in [P][N] -> out [P][N] (in place allowed).
-hipError_t launch_intt_full(uint32_t logn, const uint32_t *in, uint32_t *out, size_t npolys, const LimbConsts &c,
-                            const Twiddles &tw, hipStream_t st);
+hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
+                            const LimbConsts &c, const Twiddles &tw, hipStream_t st);
 // Masked mode: in = Yhat [B][O][2][L][N]; c1 polys go to c1_out [B][O][L][N],
 // c0 polys are extracted with the mask into c0_ext [B][c_out][L][ho][wo].
-hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, const uint32_t *yhat, const uint32_t *mask,
-                              uint32_t *c0_ext, uint32_t *c1_out, uint32_t B, const LimbConsts &c,
-                              const Twiddles &tw, hipStream_t st);
-hipError_t launch_mac(const ConvGeom &g, const uint32_t *xhat, const uint32_t *what, uint32_t *yhat, uint32_t B,
-                      const LimbConsts &c, hipStream_t st);
+hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, const uint32_t *yhat,
+                              const uint32_t *mask, uint32_t *c0_ext, uint32_t *c1_out, uint32_t B,
+                              const LimbConsts &c, const Twiddles &tw, hipStream_t st);
+hipError_t launch_mac(const ConvGeom &g, uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, const uint32_t *xhat,
+                      const uint32_t *what, uint32_t *yhat, uint32_t B, const LimbConsts &c, hipStream_t st);
 hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *filters, uint32_t *w, const LimbConsts &c,
                                  hipStream_t st);
 hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st);

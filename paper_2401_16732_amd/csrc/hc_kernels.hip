@@ -176,16 +176,28 @@ struct InvPasses {
 };
 template <int LOGN, int ELOG>
 struct InvPasses<LOGN, ELOG, 0> {
-  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid,
-                                             const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
-                                             uint32_t bp) {
+  // pass 0 (bits [0, EP)) expects its inputs already in registers
+  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *, uint32_t tid, const uint2 *tw,
+                                             uint32_t q, uint32_t a, uint32_t ap, uint32_t b, uint32_t bp) {
     constexpr int LO = pass_lo_inv(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
-    // pass 0 (bits [0, EP)) reads a strided pattern: fetch it from LDS, which
-    // the caller filled with a coalesced copy of the polynomial
-    lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
     inv_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q, a, ap, b, bp);
   }
 };
+
+// A pass over bits [0, EP) holds 2^EP consecutive coefficients per group in
+// registers: move them with 16-byte accesses.
+template <int LOGN, int ELOG, int EP>
+__device__ __forceinline__ void load_low_pass(uint32_t (&v)[1 << ELOG], const uint32_t *src, uint32_t tid) {
+  static_assert(EP >= 2, "vector access needs 4 consecutive words");
+#pragma unroll
+  for (int u = 0; u < (1 << ELOG); u += 4) {
+    const uint4 t4 = *reinterpret_cast<const uint4 *>(src + gidx<LOGN, ELOG, 0, EP>(tid, u));
+    v[u] = t4.x;
+    v[u + 1] = t4.y;
+    v[u + 2] = t4.z;
+    v[u + 3] = t4.w;
+  }
+}
 
 // ---------------------------------------------------------------- forward NTT kernel
 // One workgroup per polynomial of in/out [P][N] (limb = poly mod L). Input
@@ -208,35 +220,31 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
     for (int u = 0; u < E; ++u) v[u] = __builtin_nontemporal_load(src + gidx<LOGN, ELOG, LO, EP>(tid, u));
   }
   FwdPasses<LOGN, ELOG, NP - 1>::run(v, lds, tid, tw, q);
-  // the last pass (bits [0, EP)) holds strided indices: transpose through LDS
-  {
-    constexpr int LO = pass_lo_fwd(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
-    __syncthreads();
-    regs_to_lds<LOGN, ELOG, LO, EP>(v, lds, tid);
-    __syncthreads();
-  }
+  // the last pass (bits [0, EP)) leaves runs of 2^EP consecutive coefficients
+  // in each thread: canonicalise and store them 16 bytes at a time
+  constexpr int EPL = pass_bits(LOGN, ELOG, NP - 1);
+  static_assert(pass_lo_fwd(LOGN, ELOG, NP - 1) == 0 && EPL >= 2, "last forward pass covers the low bits");
   uint32_t *dst = out + poly * N;
   const uint32_t q2 = 2 * q;
 #pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const uint32_t j = tid + (uint32_t)k * NT;
-    dst[j] = csub(csub(lds[lpad(j)], q2), q);
+  for (int u = 0; u < E; u += 4) {
+    uint4 t4;
+    t4.x = csub(csub(v[u], q2), q);
+    t4.y = csub(csub(v[u + 1], q2), q);
+    t4.z = csub(csub(v[u + 2], q2), q);
+    t4.w = csub(csub(v[u + 3], q2), q);
+    *reinterpret_cast<uint4 *>(dst + gidx<LOGN, ELOG, 0, EPL>(tid, u)) = t4;
   }
+  (void)NT;
 }
 
 // ---------------------------------------------------------------- inverse NTT kernels
 template <int LOGN, int ELOG>
 __device__ __forceinline__ void intt_core(const uint32_t *src, uint32_t (&v)[1 << ELOG], uint32_t *lds,
                                           uint32_t tid, const LimbConsts &c, const uint2 *tw, uint32_t l) {
-  constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
-#pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const uint32_t j = tid + (uint32_t)k * NT;
-    lds[lpad(j)] = __builtin_nontemporal_load(src + j);
-  }
-  __syncthreads();
+  constexpr int NP = n_pass(LOGN, ELOG);
+  load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v, src, tid);
   InvPasses<LOGN, ELOG, NP - 1>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l], c.ninvw_p[l]);
-  (void)N;
 }
 
 // Full mode: [P][N] -> [P][N] canonical (in place allowed).
@@ -307,63 +315,108 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
 
 // ---------------------------------------------------------------- multiply-accumulate
 // Yhat[b][o][p][l][k] = sum_{gw < G_w} What[i][gw][l][k] * Xhat[b][gw T + tau][p][l][k]  mod q_l,
-// o = i T + tau. One thread per (coefficient k, output ciphertext o, limb l,
-// BT images): the weight is loaded once and used for 2 BT products.
-template <int BT>
-__global__ __launch_bounds__(256) void k_mac(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Wt,
-                                             uint32_t *__restrict__ Y, ConvGeom g, uint32_t B, uint32_t nkb,
-                                             uint32_t nbt, LimbConsts c) {
-  // XCD-aware order: the hardware deals workgroups round-robin over 8 XCDs;
-  // give each XCD a contiguous range of logical ids so that the output
-  // ciphertexts sharing an input tile also share an L2.
+// o = i T + tau.
+// Register-tiled form: one thread owns coefficient k and CT output channels
+// (same row tile tau) for BT images x 2 polynomials, so each input value it
+// loads is used CT times and each weight 2 BT times. A workgroup is RG x CG
+// waves over the same 64 coefficients: RG groups of images times CG groups of
+// output channels. Waves of one channel group read the same weights and
+// waves of one image group the same inputs, which L1 then serves once.
+// Loads of the next input ciphertext are issued before the current one's
+// multiply-accumulates.
+template <int BT, int CT, int RG, int CG>
+__global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__restrict__ X,
+                                                            const uint32_t *__restrict__ Wt,
+                                                            uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
+                                                            uint32_t nib, uint32_t nkb, LimbConsts c) {
   const uint32_t nwg = gridDim.x;
   uint32_t wg = blockIdx.x;
   if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
-  const uint32_t o = wg % g.O;
-  uint32_t r = wg / g.O;
+  const uint32_t ib = wg % nib;
+  uint32_t r = wg / nib;
+  const uint32_t tau = r % g.T;
+  r /= g.T;
   const uint32_t kb = r % nkb;
   r /= nkb;
   const uint32_t l = r % g.L;
   const uint32_t bt = r / g.L;
-  const uint32_t k = kb * 256 + threadIdx.x;
-  const uint32_t i = o / g.T, tau = o % g.T;
-  const uint32_t b0 = bt * BT;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t rg = wave % RG, cg = wave / RG;
+  const uint32_t k = kb * 64 + lane;
+  const uint32_t i0 = (ib * CG + cg) * CT;
+  const uint32_t b0 = (bt * RG + rg) * BT;
+  if (i0 >= g.c_out || b0 >= B) return;
+  const uint32_t nc = min((uint32_t)CT, g.c_out - i0);
   const uint32_t nb = min((uint32_t)BT, B - b0);
   const size_t LN = (size_t)g.L * g.N;
-  const size_t ct_stride = 2 * LN;  // one ciphertext
-  const uint32_t *wp = Wt + ((size_t)i * g.G_w) * LN + (size_t)l * g.N + k;
-  const uint32_t *xp = X + (size_t)l * g.N + k;
+  const size_t xstride = 2 * LN * g.T;  // next input ciphertext of the same tile
+  const uint32_t *xp = X + ((size_t)b0 * g.G + tau) * 2 * LN + (size_t)l * g.N + k;
+  const size_t ximg = (size_t)g.G * 2 * LN;
+  const uint32_t *wp = Wt + (size_t)i0 * g.G_w * LN + (size_t)l * g.N + k;
+  const size_t wch = (size_t)g.G_w * LN;
   const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
-  uint64_t acc[BT][2];
+  uint64_t acc[CT][BT][2];
 #pragma unroll
-  for (int bb = 0; bb < BT; ++bb) acc[bb][0] = acc[bb][1] = 0;
+  for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+  uint32_t wv[CT], xv[BT][2];
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc) wv[cc] = (uint32_t)cc < nc ? wp[cc * wch] : 0u;
+#pragma unroll
+  for (int bb = 0; bb < BT; ++bb) {
+    xv[bb][0] = (uint32_t)bb < nb ? xp[bb * ximg] : 0u;
+    xv[bb][1] = (uint32_t)bb < nb ? xp[bb * ximg + LN] : 0u;
+  }
   uint32_t since = 0;
   for (uint32_t gw = 0; gw < g.G_w; ++gw) {
-    const uint32_t w = wp[(size_t)gw * LN];
-    const size_t ct = (size_t)gw * g.T + tau;
+    uint32_t wn[CT], xn[BT][2];
+    const bool more = gw + 1 < g.G_w;
+    const uint32_t *xq = xp + (size_t)(gw + 1) * xstride;
+    const uint32_t *wq = wp + (size_t)(gw + 1) * LN;
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc) wn[cc] = (more && (uint32_t)cc < nc) ? wq[cc * wch] : 0u;
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb) {
-      if ((uint32_t)bb < nb) {
-        const uint32_t *x = xp + ((size_t)(b0 + bb) * g.G + ct) * ct_stride;
-        acc[bb][0] += (uint64_t)w * x[0];
-        acc[bb][1] += (uint64_t)w * x[LN];
-      }
+      xn[bb][0] = (more && (uint32_t)bb < nb) ? xq[bb * ximg] : 0u;
+      xn[bb][1] = (more && (uint32_t)bb < nb) ? xq[bb * ximg + LN] : 0u;
     }
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) {
+        acc[cc][bb][0] += (uint64_t)wv[cc] * xv[bb][0];
+        acc[cc][bb][1] += (uint64_t)wv[cc] * xv[bb][1];
+      }
     if (++since == fold) {
       since = 0;
 #pragma unroll
-      for (int bb = 0; bb < BT; ++bb)
+      for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-        for (int pp = 0; pp < 2; ++pp)
-          acc[bb][pp] = (uint64_t)(uint32_t)(acc[bb][pp] >> 32) * r2 + (uint32_t)acc[bb][pp];
+        for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+          for (int pp = 0; pp < 2; ++pp)
+            acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+    }
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc) wv[cc] = wn[cc];
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) {
+      xv[bb][0] = xn[bb][0];
+      xv[bb][1] = xn[bb][1];
     }
   }
+  const uint32_t r2p = c.r2_p[l], onep = c.one_p[l];
 #pragma unroll
-  for (int bb = 0; bb < BT; ++bb) {
-    if ((uint32_t)bb < nb) {
+  for (int cc = 0; cc < CT; ++cc) {
+    if ((uint32_t)cc >= nc) continue;
+    const uint32_t o = (i0 + cc) * g.T + tau;
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) {
+      if ((uint32_t)bb >= nb) continue;
       uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + k;
-      y[0] = reduce64(acc[bb][0], q, r2, c.r2_p[l], c.one_p[l]);
-      y[LN] = reduce64(acc[bb][1], q, r2, c.r2_p[l], c.one_p[l]);
+      y[0] = reduce64(acc[cc][bb][0], q, r2, r2p, onep);
+      y[LN] = reduce64(acc[cc][bb][1], q, r2, r2p, onep);
     }
   }
 }
@@ -474,47 +527,74 @@ static hipError_t invm_t(const ConvGeom &g, const uint32_t *y, const uint32_t *m
   return hipGetLastError();
 }
 
-// Thread-count choice per ring size: 2^(LOGN - ELOG) threads per polynomial.
-#define HC_NTT_DISPATCH(FN, ...)                 \
-  switch (logn) {                                \
-    case 10: return FN<10, 4>(__VA_ARGS__);      \
-    case 11: return FN<11, 4>(__VA_ARGS__);      \
-    case 12: return FN<12, 4>(__VA_ARGS__);      \
-    case 13: return FN<13, 5>(__VA_ARGS__);      \
-    case 14: return FN<14, 5>(__VA_ARGS__);      \
-    default: return hipErrorInvalidValue;        \
-  }
+// (LOGN, ELOG) instances: 2^(LOGN - ELOG) threads per polynomial.
+#define HC_NTT_CASE(L, E, FN, ...) \
+  if (logn == L && elog == E) return FN<L, E>(__VA_ARGS__);
+#define HC_NTT_DISPATCH(FN, ...)                                                             \
+  HC_NTT_CASE(10, 3, FN, __VA_ARGS__) HC_NTT_CASE(10, 4, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(11, 3, FN, __VA_ARGS__) HC_NTT_CASE(11, 4, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(12, 3, FN, __VA_ARGS__) HC_NTT_CASE(12, 4, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(12, 5, FN, __VA_ARGS__) HC_NTT_CASE(13, 3, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(13, 4, FN, __VA_ARGS__) HC_NTT_CASE(13, 5, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(14, 4, FN, __VA_ARGS__) HC_NTT_CASE(14, 5, FN, __VA_ARGS__)                    \
+  return hipErrorInvalidValue;
 
-hipError_t launch_ntt_fwd(uint32_t logn, const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c,
-                          const Twiddles &tw, hipStream_t st) {
+bool ntt_variant_ok(uint32_t logn, uint32_t elog) {
+  switch (logn) {
+    case 10: case 11: return elog == 3 || elog == 4;
+    case 12: case 13: return elog >= 3 && elog <= 5;
+    case 14: return elog == 4 || elog == 5;
+  }
+  return false;
+}
+
+hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
+                          const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
   HC_NTT_DISPATCH(fwd_t, in, out, np, c, tw, st)
 }
-hipError_t launch_intt_full(uint32_t logn, const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c,
-                            const Twiddles &tw, hipStream_t st) {
+hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
+                            const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
   HC_NTT_DISPATCH(inv_t, in, out, np, c, tw, st)
 }
-hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, const uint32_t *y, const uint32_t *m, uint32_t *c0,
-                              uint32_t *c1, uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, const uint32_t *y, const uint32_t *m,
+                              uint32_t *c0, uint32_t *c1, uint32_t B, const LimbConsts &c, const Twiddles &tw,
+                              hipStream_t st) {
   HC_NTT_DISPATCH(invm_t, g, y, m, c0, c1, B, c, tw, st)
 }
 
-template <int BT>
+template <int BT, int CT, int RG, int CG>
 static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
                         const LimbConsts &c, hipStream_t st) {
-  const uint32_t nkb = g.N / 256;
-  const uint32_t nbt = (B + BT - 1) / BT;
-  const size_t nwg = (size_t)g.O * nkb * g.L * nbt;
+  const uint32_t nkb = g.N / 64;
+  const uint32_t nib = (g.c_out + CG * CT - 1) / (CG * CT);
+  const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
+  const size_t nwg = (size_t)nib * g.T * nkb * g.L * nbt;
   if (nwg == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_mac<BT>), dim3((uint32_t)nwg), dim3(256), 0, st, x, w, y, g, B, nkb, nbt, c);
+  hipLaunchKernelGGL((k_mac_tiled<BT, CT, RG, CG>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y, g, B,
+                     nib, nkb, c);
   return hipGetLastError();
 }
-hipError_t launch_mac(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
-                      const LimbConsts &c, hipStream_t st) {
-  if (B >= 16) return mac_t<16>(g, x, w, y, B, c, st);
-  if (B >= 8) return mac_t<8>(g, x, w, y, B, c, st);
-  if (B >= 4) return mac_t<4>(g, x, w, y, B, c, st);
-  if (B >= 2) return mac_t<2>(g, x, w, y, B, c, st);
-  return mac_t<1>(g, x, w, y, B, c, st);
+
+// (images per thread, channels per thread, image groups, channel groups)
+#define HC_MAC_VARIANTS(X)                                                                              \
+  X(1, 8, 1, 4) X(1, 4, 1, 4) X(2, 4, 1, 4) X(4, 4, 1, 4) X(4, 2, 1, 4) X(8, 2, 1, 4) X(16, 2, 1, 4)   \
+  X(4, 4, 4, 2) X(4, 8, 4, 2) X(2, 8, 4, 2) X(4, 4, 2, 4) X(8, 4, 2, 2) X(2, 4, 4, 4) X(1, 8, 2, 4)
+
+bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg) {
+#define HC_MAC_OK(B_, C_, R_, G_) \
+  if (bt == B_ && ct == C_ && rg == R_ && cg == G_) return true;
+  HC_MAC_VARIANTS(HC_MAC_OK)
+#undef HC_MAC_OK
+  return false;
+}
+
+hipError_t launch_mac(const ConvGeom &g, uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, const uint32_t *x,
+                      const uint32_t *w, uint32_t *y, uint32_t B, const LimbConsts &c, hipStream_t st) {
+#define HC_MAC_CASE(B_, C_, R_, G_) \
+  if (bt == B_ && ct == C_ && rg == R_ && cg == G_) return mac_t<B_, C_, R_, G_>(g, x, w, y, B, c, st);
+  HC_MAC_VARIANTS(HC_MAC_CASE)
+#undef HC_MAC_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *f, uint32_t *w, const LimbConsts &c,

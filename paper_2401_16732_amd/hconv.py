@@ -25,6 +25,7 @@ SYMBOLS = [
     "hc_layer_plan", "hc_workspace_size", "hc_conv", "hc_mask_extract", "hc_conv_masked", "hc_batch_create",
     "hc_batch_workspace_bytes", "hc_batch_run", "hc_batch_run_eager", "hc_batch_destroy", "hc_poly_mul",
     "hc_sync", "hc_status_string", "hc_last_error", "hc_plan_ring", "hc_ring_params",
+    "hc_batch_run_timed", "hc_ctx_set_tuning", "hc_ctx_get_tuning",
 ]
 
 
@@ -36,6 +37,11 @@ class HcError(RuntimeError):
 
 class ConvShape(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("c_in", "c_out", "h", "w", "f", "stride")]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in ("fwd_elog", "inv_elog", "mac_rows", "mac_cols", "mac_row_groups",
+                                               "mac_col_groups")]
 
 
 class Layout(ctypes.Structure):
@@ -83,6 +89,9 @@ def load(path: str = LIB_PATH):
         "hc_last_error": (ctypes.c_char_p, []),
         "hc_plan_ring": (I, [u32, P, P]),
         "hc_ring_params": (I, [u32, u32, u64, P, P]),
+        "hc_batch_run_timed": (I, [P, P, P, P, P, P, P]),
+        "hc_ctx_set_tuning": (I, [P, P]),
+        "hc_ctx_get_tuning": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -171,6 +180,15 @@ class Context:
 
     def sync(self):
         _check(_lib.hc_sync(self.h), "hc_sync")
+
+    def set_tuning(self, fwd_elog=0, inv_elog=0, mac_rows=0, mac_cols=0, mac_row_groups=0, mac_col_groups=0):
+        t = Tuning(fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups)
+        _check(_lib.hc_ctx_set_tuning(self.h, ctypes.byref(t)), "hc_ctx_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(_lib.hc_ctx_get_tuning(self.h, ctypes.byref(t)), "hc_ctx_get_tuning")
+        return (t.fwd_elog, t.inv_elog, t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups)
 
     def close(self):
         if getattr(self, "h", None):
@@ -312,6 +330,14 @@ class Batch:
     def run_eager(self, ct_in, mask, c0, c1, stream=None):
         a = self._args(ct_in, mask, c0, c1)
         _check(_lib.hc_batch_run_eager(self.h, *a, _stream(stream)), "hc_batch_run_eager")
+
+    def run_timed(self, ct_in, mask, c0, c1, stream=None):
+        """Eager run with HIP events around every kernel; returns milliseconds
+        per stage: (forward NTT, multiply-accumulate, inverse NTT + mask + extract)."""
+        a = self._args(ct_in, mask, c0, c1)
+        ms = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+        _check(_lib.hc_batch_run_timed(self.h, *a, _stream(stream), ms), "hc_batch_run_timed")
+        return tuple(ms)
 
     def close(self):
         if getattr(self, "h", None):

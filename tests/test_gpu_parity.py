@@ -177,3 +177,39 @@ def test_error_paths(hc):
     assert e.value.status == -1
     # B = 0 is a no-op
     ly.conv(zeros((1,)), zeros((1,)), 0, zeros((1,)))
+
+
+MAC_VARIANTS = [(1, 8, 1, 4), (1, 4, 1, 4), (2, 4, 1, 4), (4, 4, 1, 4), (4, 2, 1, 4), (8, 2, 1, 4), (16, 2, 1, 4),
+                (4, 4, 4, 2), (4, 8, 4, 2), (2, 8, 4, 2), (4, 4, 2, 4), (8, 4, 2, 2), (2, 4, 4, 4), (1, 8, 2, 4)]
+
+
+@pytest.mark.parametrize("N,elogs", [(8192, (3, 4, 5)), (16384, (4, 5)), (4096, (3, 4, 5)), (1024, (3, 4))])
+def test_every_launch_shape_gives_the_same_bits(hc, N, elogs):
+    """Autotuner candidates: every NTT thread shape and MAC tile produces the oracle's bits."""
+    L, t, B = 2, 2 ** 17, 3
+    c = _ctx(hc, N, L, t)
+    spec = W.ConvSpec(20, 13, 12, 12, 3, 1)
+    P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+    g = W.rng(N + 5)
+    f = W.gen_filters(g, spec)
+    x = W.gen_ct_limbs(g, (B, P.G, 2), c.primes, N)
+    r = W.gen_mask(g, (B, spec.c_o, P.ho, P.wo), t)
+    ly = hc.Layer(c, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride, f)
+    exp = [conv.mask_extract(calg1.alg1_layer(x[b], f, P, c.primes), r[b], P, c.primes, t) for b in range(B)]
+    dx, dr = dev(x), dev(r)
+    ws = zeros((ly.workspace_words(B, True),))
+    cases = [(fe, ie, 0, 0, 0, 0) for fe in elogs for ie in elogs] + [(0, 0) + v for v in MAC_VARIANTS]
+    for tune in cases:
+        print(f"N={N} tuning {tune}", flush=True)
+        c.set_tuning(*tune)
+        c0, c1 = zeros(ly.c0_shape(B)), zeros(ly.c1_shape(B))
+        ly.conv_masked(dx, dr, c0, c1, B, ws)
+        c0, c1 = host(c0), host(c1)
+        for b in range(B):
+            assert (c0[b] == exp[b][0]).all() and (c1[b] == exp[b][1]).all(), (tune, b)
+    with pytest.raises(hc.HcError):
+        c.set_tuning(7, 0, 0, 0)
+    with pytest.raises(hc.HcError):
+        c.set_tuning(0, 0, 3, 3, 1, 1)
+    with pytest.raises(hc.HcError):
+        c.set_tuning(0, 0, 4, 4, 0, 0)
