@@ -77,6 +77,31 @@ def hbm_copy(torch, dev, gib, reps=5):
     return {"bytes_per_copy": 2 * n * 4, "ms": round(ms, 3), "GBps": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
 
 
+KERNEL_KEYS = {"ntt_fwd": "k_ntt_fwd", "mac": "k_mac_tiled", "intt_mask_extract": "k_intt_masked"}
+
+
+def measured_traffic(kernel: str, tag: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    summary is missing or was taken on a different kernel source."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"hbm_traffic_{tag}.md")
+    src = os.path.join(here, "paper_2401_16732_amd", "csrc", "hc_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    got, val = None, None
+    for line in open(path):
+        if line.startswith("source_sha256_16:"):
+            got = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch:"):
+            k, v = line.split(":", 1)[1].split("=")
+            if k.strip() == KERNEL_KEYS.get(kernel):
+                val = float(v)
+    return val if got == cur else None
+
+
 def layer_counts(ly, B, N, L):
     """Algorithmic work of one layer on B images (no scratch round trips)."""
     lay = ly.layout
@@ -235,7 +260,10 @@ def main():
         ach = kbytes / (kms * 1e-3)
         roof = {"bound": "hbm", "achieved": round(ach / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = None
+    traffic = measured_traffic(kname, f"resnet50_b{B}") if a.net == "resnet50_224" else None
+    roof["traffic"] = None if traffic is None else round(traffic)
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roof["algorithmic_bytes_per_launch"] = round(kbytes / len(layers))
     roof["kernel"] = kname
     roof["launches"] = len(layers)
     roof["ms_total"] = round(kms, 3)

@@ -239,7 +239,7 @@ Shapes shapes_for(const hc_ctx &c, uint32_t B) {
   if (c.tune.mac_rows) {
     s.bt = c.tune.mac_rows, s.ct = c.tune.mac_cols, s.rg = c.tune.mac_row_groups, s.cg = c.tune.mac_col_groups;
   } else if (B >= 16) {
-    s.bt = 4, s.ct = 4, s.rg = 4, s.cg = 2;
+    s.bt = 4, s.ct = 8, s.rg = 4, s.cg = 2;
   } else if (B >= 4) {
     s.bt = 4, s.ct = 4, s.rg = 1, s.cg = 4;
   } else if (B >= 2) {
@@ -264,6 +264,8 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
   const ConvGeom &g = ly->geom;
   const bool timed = tm && tm->on;
   const Shapes sh = shapes_for(c, B);
+  if (!hc::mac_offsets_fit(g, sh.bt, sh.ct))
+    return fail(HC_EUNSUPPORTED, "layer too large for the selected MAC tile (32-bit offsets); use smaller mac_rows");
   uint32_t *xhat = (uint32_t *)ws;
   const size_t npin = (size_t)B * g.G * 2 * c.L;
   if (timed) HC_HIP(hipEventRecord(tm->ev[0], st));
@@ -399,8 +401,8 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
     const u128 base = ((u128)1 << 32) * k.r2[l] + ((u128)1 << 32);
     const u128 term = (u128)(q - 1) * (q - 1);
     u128 n_terms = (lim - base) / term;
-    k.fold[l] = (uint32_t)std::min<u128>(n_terms, 64);
-    if (k.fold[l] < 1) {
+    k.fold[l] = (uint32_t)std::min<u128>(n_terms, 64) & ~1u;  // even: the MAC consumes ciphertexts in pairs
+    if (k.fold[l] < 2) {
       delete c;
       return fail(HC_EINVAL, "prime too large for 64-bit accumulation");
     }

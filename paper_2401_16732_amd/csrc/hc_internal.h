@@ -50,6 +50,8 @@ enum InttMode : int { kInttFull = 0, kInttMasked = 1 };
 // rg x cg such threads per coefficient (image groups x channel groups).
 bool ntt_variant_ok(uint32_t logn, uint32_t elog);
 bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg);
+// The MAC addresses one image tile and one channel tile with 32-bit byte offsets.
+bool mac_offsets_fit(const ConvGeom &g, uint32_t bt, uint32_t ct);
 
 hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                           const LimbConsts &c, const Twiddles &tw, hipStream_t st);

@@ -340,73 +340,95 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
   r /= nkb;
   const uint32_t l = r % g.L;
   const uint32_t bt = r / g.L;
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  // wave-uniform indices (readfirstlane keeps the bases in scalar registers)
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
   const uint32_t rg = wave % RG, cg = wave / RG;
-  const uint32_t k = kb * 64 + lane;
   const uint32_t i0 = (ib * CG + cg) * CT;
   const uint32_t b0 = (bt * RG + rg) * BT;
   if (i0 >= g.c_out || b0 >= B) return;
   const uint32_t nc = min((uint32_t)CT, g.c_out - i0);
   const uint32_t nb = min((uint32_t)BT, B - b0);
-  const size_t LN = (size_t)g.L * g.N;
-  const size_t xstride = 2 * LN * g.T;  // next input ciphertext of the same tile
-  const uint32_t *xp = X + ((size_t)b0 * g.G + tau) * 2 * LN + (size_t)l * g.N + k;
-  const size_t ximg = (size_t)g.G * 2 * LN;
-  const uint32_t *wp = Wt + (size_t)i0 * g.G_w * LN + (size_t)l * g.N + k;
-  const size_t wch = (size_t)g.G_w * LN;
+  const uint32_t LN = g.L * g.N;
+  // Scalar bases advance by one input ciphertext per step; per-thread offsets
+  // (32-bit, fixed for the whole loop) select image, polynomial and channel.
+  const uint32_t *xbase = X + ((size_t)b0 * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64;
+  const uint32_t *wbase = Wt + (size_t)i0 * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64;
+  const size_t xstep = (size_t)2 * LN * g.T, wstep = LN;
+  // byte offsets; the host guarantees BT*G*2*L*N*4 and CT*G_w*L*N*4 < 2^32
+  uint32_t xo[BT][2], wo[CT];
+#pragma unroll
+  for (int bb = 0; bb < BT; ++bb) {
+    const uint32_t b = (uint32_t)bb < nb ? (uint32_t)bb : 0u;  // clamp: loads of absent images are discarded
+    xo[bb][0] = (b * g.G * 2 * LN + lane) * 4u;
+    xo[bb][1] = xo[bb][0] + LN * 4u;
+  }
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc) wo[cc] = (((uint32_t)cc < nc ? (uint32_t)cc : 0u) * g.G_w * LN + lane) * 4u;
   const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
   uint64_t acc[CT][BT][2];
 #pragma unroll
   for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
-  uint32_t wv[CT], xv[BT][2];
+  const uint32_t G_w = g.G_w;
+  auto load = [&](uint32_t gw, uint32_t (&w)[CT], uint32_t (&x)[BT][2]) {
+    const char *xb = (const char *)(xbase + gw * xstep), *wb = (const char *)(wbase + gw * wstep);
 #pragma unroll
-  for (int cc = 0; cc < CT; ++cc) wv[cc] = (uint32_t)cc < nc ? wp[cc * wch] : 0u;
-#pragma unroll
-  for (int bb = 0; bb < BT; ++bb) {
-    xv[bb][0] = (uint32_t)bb < nb ? xp[bb * ximg] : 0u;
-    xv[bb][1] = (uint32_t)bb < nb ? xp[bb * ximg + LN] : 0u;
-  }
-  uint32_t since = 0;
-  for (uint32_t gw = 0; gw < g.G_w; ++gw) {
-    uint32_t wn[CT], xn[BT][2];
-    const bool more = gw + 1 < g.G_w;
-    const uint32_t *xq = xp + (size_t)(gw + 1) * xstride;
-    const uint32_t *wq = wp + (size_t)(gw + 1) * LN;
-#pragma unroll
-    for (int cc = 0; cc < CT; ++cc) wn[cc] = (more && (uint32_t)cc < nc) ? wq[cc * wch] : 0u;
+    for (int cc = 0; cc < CT; ++cc) w[cc] = *(const uint32_t *)(wb + wo[cc]);
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb) {
-      xn[bb][0] = (more && (uint32_t)bb < nb) ? xq[bb * ximg] : 0u;
-      xn[bb][1] = (more && (uint32_t)bb < nb) ? xq[bb * ximg + LN] : 0u;
+      x[bb][0] = *(const uint32_t *)(xb + xo[bb][0]);
+      x[bb][1] = *(const uint32_t *)(xb + xo[bb][1]);
     }
+  };
+  auto mac = [&](const uint32_t (&w)[CT], const uint32_t (&x)[BT][2]) {
 #pragma unroll
     for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
       for (int bb = 0; bb < BT; ++bb) {
-        acc[cc][bb][0] += (uint64_t)wv[cc] * xv[bb][0];
-        acc[cc][bb][1] += (uint64_t)wv[cc] * xv[bb][1];
+        acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
+        acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
       }
-    if (++since == fold) {
-      since = 0;
+  };
+  // Two register sets A and B alternate: while one set is multiplied, the
+  // other's loads (two input ciphertexts ahead) are in flight. The loop body
+  // has no branches, so the compiler keeps that order: loads past the end
+  // re-read the last ciphertext, and the odd tail's second set gets zero
+  // weights. Folding is exact mod q, so it runs after every chunk.
+  uint32_t wa[CT], xa[BT][2], wb2[CT], xb2[BT][2];
+  const uint32_t last = G_w - 1;
+  load(0, wa, xa);
+  load(min(1u, last), wb2, xb2);
+  for (uint32_t base = 0; base < G_w; base += fold) {
+    const uint32_t end = min(G_w, base + fold);
+    for (uint32_t gw = base; gw < end; gw += 2) {
+      // sched_barrier keeps each group in place: set A's loads must all be
+      // issued before set B's, so that waiting for A never waits for B
+      mac(wa, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      load(min(gw + 2, last), wa, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      const bool tail = gw + 1 >= end;
 #pragma unroll
-      for (int cc = 0; cc < CT; ++cc)
-#pragma unroll
-        for (int bb = 0; bb < BT; ++bb)
-#pragma unroll
-          for (int pp = 0; pp < 2; ++pp)
-            acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+      for (int cc = 0; cc < CT; ++cc) wb2[cc] = tail ? 0u : wb2[cc];
+      mac(wb2, xb2);
+      __builtin_amdgcn_sched_barrier(0);
+      // on a tail the zeroed set held ciphertext end, which the next chunk
+      // still needs: reload it instead of gw + 3
+      load(min(tail ? gw + 1 : gw + 3, last), wb2, xb2);
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int cc = 0; cc < CT; ++cc) wv[cc] = wn[cc];
+    for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-    for (int bb = 0; bb < BT; ++bb) {
-      xv[bb][0] = xn[bb][0];
-      xv[bb][1] = xn[bb][1];
-    }
+      for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+        for (int pp = 0; pp < 2; ++pp)
+          acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
   }
   const uint32_t r2p = c.r2_p[l], onep = c.one_p[l];
+  const uint32_t k = kb * 64 + lane;
 #pragma unroll
   for (int cc = 0; cc < CT; ++cc) {
     if ((uint32_t)cc >= nc) continue;
@@ -565,6 +587,7 @@ hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, c
 template <int BT, int CT, int RG, int CG>
 static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
                         const LimbConsts &c, hipStream_t st) {
+  if (!mac_offsets_fit(g, BT, CT)) return hipErrorInvalidValue;
   const uint32_t nkb = g.N / 64;
   const uint32_t nib = (g.c_out + CG * CT - 1) / (CG * CT);
   const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
@@ -573,6 +596,11 @@ static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w,
   hipLaunchKernelGGL((k_mac_tiled<BT, CT, RG, CG>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y, g, B,
                      nib, nkb, c);
   return hipGetLastError();
+}
+
+bool mac_offsets_fit(const ConvGeom &g, uint32_t bt, uint32_t ct) {
+  const uint64_t ln = (uint64_t)g.L * g.N * 4;
+  return (uint64_t)bt * g.G * 2 * ln < (1ull << 32) && (uint64_t)ct * g.G_w * ln < (1ull << 32);
 }
 
 // (images per thread, channels per thread, image groups, channel groups)
