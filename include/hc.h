@@ -202,6 +202,53 @@ void hc_batch_destroy(hc_batch *batch);
 hc_status hc_batch_run_timed(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
                              uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream, double *stage_ms);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of requests. A request is one image through every
+ * convolution layer of one registered network. The server owns an HBM arena
+ * of arena_bytes; a request is admitted, first come first served, when its
+ * footprint (per layer: input ciphertexts, mask, c0_ext, c1_out of one image)
+ * fits, and its inputs are then copied into the arena (from device or host
+ * memory, which must stay valid until the request completes). Each
+ * hc_server_step groups the next layer of every admitted request whose
+ * previous layer has finished by (network, layer) and launches every group of
+ * at most max_batch images as one batched forward NTT -> multiply-accumulate
+ * -> masked inverse NTT, round robin over `streams` streams. Layers of one
+ * request run in order. Steps never block. The results of a request do not
+ * depend on which other requests it was grouped with. The server is not
+ * thread-safe; drive it from one host thread. */
+typedef struct hc_server hc_server;
+typedef struct {
+    uint64_t arena_bytes;  /* HBM for admitted requests */
+    uint32_t max_batch;    /* images per launch group, 1..16 */
+    uint32_t streams;      /* concurrent launch streams, 1..8 */
+} hc_server_config;
+typedef struct {
+    uint64_t submitted, admitted, completed, groups, images;  /* cumulative */
+    uint64_t queued;       /* waiting for arena space */
+    uint64_t arena_used, arena_bytes;
+} hc_server_stats;
+
+hc_status hc_server_create(hc_ctx *ctx, const hc_server_config *cfg, hc_server **out);
+/* Register a network (its layers must outlive the server); call before submitting. */
+hc_status hc_server_add_net(hc_server *s, const hc_layer *const *layers, uint32_t n_layers, uint32_t *net_id);
+hc_status hc_server_request_bytes(const hc_server *s, uint32_t net_id, size_t *bytes);
+/* Queue a request: ct_in[k] / mask[k] are layer k's inputs for one image
+ * ([in_cts][2][L][N] and [c_out][ho][wo]). */
+hc_status hc_server_submit(hc_server *s, uint32_t net_id, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                           uint64_t *req_id);
+hc_status hc_server_step(hc_server *s);
+/* Ids of requests completed since the last poll (at most cap; *n returned). */
+hc_status hc_server_poll(hc_server *s, uint64_t *ids, uint32_t cap, uint32_t *n);
+/* Device pointers of a completed (or admitted) request's outputs for one layer:
+ * c0_ext [c_out][L][ho][wo], c1_out [out_cts][L][N]; valid until release. */
+hc_status hc_server_outputs(const hc_server *s, uint64_t req_id, uint32_t layer, uint32_t **c0_ext, uint32_t **c1_out);
+/* Return a completed request's arena space. */
+hc_status hc_server_release(hc_server *s, uint64_t req_id);
+hc_status hc_server_get_stats(const hc_server *s, hc_server_stats *out);
+/* Wait for all launched work. */
+hc_status hc_server_sync(hc_server *s);
+void hc_server_destroy(hc_server *s);
+
 /* Negacyclic products c_k = a_k * b_k mod (x^N + 1, q_l) of `count` pairs of
  * polynomials laid out [count][L][N] (canonical residues), through the same
  * forward NTT, pointwise product and inverse NTT kernels as the convolution.

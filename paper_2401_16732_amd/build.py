@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhconv.so")
-SOURCES = [os.path.join(CSRC, "hc_host.cpp"), os.path.join(CSRC, "hc_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "hc_host.cpp"), os.path.join(CSRC, "hc_server.cpp"), os.path.join(CSRC, "hc_kernels.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -42,7 +42,8 @@ def stale() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    deps = SOURCES + [os.path.join(CSRC, "hc_internal.h"), os.path.join(HERE, "..", "include", "hc.h")]
+    deps = SOURCES + [os.path.join(CSRC, "hc_internal.h"), os.path.join(CSRC, "hc_objects.h"),
+                      os.path.join(HERE, "..", "include", "hc.h")]
     return any(os.path.getmtime(d) > t for d in deps)
 
 

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "hc_internal.h"
+#include "hc_objects.h"
 
 using hc::ConvGeom;
 using hc::LimbConsts;
@@ -24,9 +25,10 @@ using hc::Twiddles;
 using u128 = unsigned __int128;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
+namespace hc {
 hc_status fail(hc_status s, const std::string &msg) {
   g_last_error = msg;
   return s;
@@ -35,6 +37,13 @@ hc_status hip_fail(hipError_t e, const char *where) {
   g_last_error = std::string(where) + ": " + hipGetErrorString(e);
   return HC_EDEVICE;
 }
+}  // namespace hc
+using hc::fail;
+using hc::hip_fail;
+using hc::Shapes;
+using hc::DeviceGuard;
+
+namespace {
 #define HC_HIP(call)                                  \
   do {                                                \
     hipError_t e_ = (call);                           \
@@ -89,29 +98,6 @@ uint32_t bitrev(uint32_t x, int bits) {
 }
 
 }  // namespace
-
-// ------------------------------------------------------------- objects
-struct hc_ctx {
-  uint32_t N = 0, logn = 0, L = 0;
-  uint64_t t = 0;
-  uint32_t q[hc::kMaxLimbs] = {};
-  uint32_t psi[hc::kMaxLimbs] = {};
-  uint32_t delta[hc::kMaxLimbs] = {};
-  int device = 0;
-  LimbConsts consts{};
-  uint2 *d_tw = nullptr;  // [2][L][N]: forward then inverse
-  Twiddles tw{};
-  hc_tuning tune{};        // 0 fields = defaults
-};
-
-struct hc_layer {
-  hc_ctx *ctx = nullptr;
-  hc_conv_shape shape{};
-  hc_layout lay{};
-  ConvGeom geom{};
-  uint32_t *d_w = nullptr;  // [c_out][w_cts][L][N], NTT domain
-  size_t w_elems = 0;
-};
 
 struct hc_batch {
   hc_ctx *ctx = nullptr;
@@ -214,25 +200,13 @@ ConvGeom geom_of(const hc_ctx &c, const hc_conv_shape &s, const hc_layout &o) {
 
 size_t ct_words(const hc_ctx &c) { return (size_t)2 * c.L * c.N; }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
-// Launch shapes in effect for B images.
-struct Shapes {
-  uint32_t fe, ie, bt, ct, rg, cg;
-};
 // Defaults measured on MI355X (ResNet-50 layer mix, N = 8192).
 uint32_t default_fwd_elog(uint32_t logn) { return logn >= 13 ? 5 : 4; }
 uint32_t default_inv_elog(uint32_t logn) { return logn >= 10 ? 4 : 3; }
-Shapes shapes_for(const hc_ctx &c, uint32_t B) {
+}  // namespace
+
+hc::Shapes hc::shapes_for(const hc_ctx &c, uint32_t B) {
   Shapes s{};
   s.fe = c.tune.fwd_elog ? c.tune.fwd_elog : default_fwd_elog(c.logn);
   s.ie = c.tune.inv_elog ? c.tune.inv_elog : default_inv_elog(c.logn);
@@ -249,6 +223,9 @@ Shapes shapes_for(const hc_ctx &c, uint32_t B) {
   }
   return s;
 }
+
+namespace {
+using hc::shapes_for;
 
 // Optional per-stage timing: events recorded on the launch stream around each kernel.
 struct StageTimer {
@@ -286,14 +263,42 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
   return HC_OK;
 }
 
-size_t ws_bytes_for(const hc_layer *ly, uint32_t B, bool masked) {
+}  // namespace
+
+size_t hc::ws_bytes_for(const hc_layer *ly, uint32_t B, bool masked) {
   const hc_ctx &c = *ly->ctx;
   size_t w = (size_t)B * ly->geom.G * ct_words(c);
   if (masked) w += (size_t)B * ly->geom.O * ct_words(c);
   return w * sizeof(uint32_t);
 }
+using hc::ws_bytes_for;
 
-}  // namespace
+hc_status hc::enqueue_conv_gather(const hc_layer *ly, uint32_t B, const uint32_t *const *ct_in,
+                                  const uint32_t *const *mask, uint32_t *const *c0, uint32_t *const *c1, void *ws,
+                                  hipStream_t st) {
+  const hc_ctx &c = *ly->ctx;
+  const ConvGeom &g = ly->geom;
+  if (B == 0 || B > hc::kMaxTab) return fail(HC_EINVAL, "group size out of range");
+  const Shapes sh = shapes_for(c, B);
+  if (!hc::mac_offsets_fit(g, sh.bt, sh.ct)) return fail(HC_EUNSUPPORTED, "layer too large for the MAC tile");
+  hc::ImgPtrs in{};
+  hc::OutPtrs out{};
+  in.n = out.n = B;
+  for (uint32_t b = 0; b < B; ++b) {
+    in.p[b] = (uint64_t)(uintptr_t)ct_in[b];
+    out.mask[b] = (uint64_t)(uintptr_t)mask[b];
+    out.c0[b] = (uint64_t)(uintptr_t)c0[b];
+    out.c1[b] = (uint64_t)(uintptr_t)c1[b];
+  }
+  uint32_t *xhat = (uint32_t *)ws;
+  const uint32_t ppi = g.G * 2 * c.L;
+  const size_t npin = (size_t)B * ppi;
+  HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, nullptr, xhat, npin, c.consts, c.tw, st, &in, ppi));
+  uint32_t *yhat = xhat + npin * c.N;
+  HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, xhat, ly->d_w, yhat, B, c.consts, st));
+  HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, yhat, nullptr, nullptr, nullptr, B, c.consts, c.tw, st, &out));
+  return HC_OK;
+}
 
 // ------------------------------------------------------------- ABI
 extern "C" {

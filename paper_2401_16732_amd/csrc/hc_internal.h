@@ -42,7 +42,17 @@ struct ConvGeom {
   uint32_t ho, wo;
 };
 
-enum InttMode : int { kInttFull = 0, kInttMasked = 1 };
+// Per-image buffer tables (kernel arguments by value) for groups of up to
+// kMaxTab images whose buffers are not one strided array (the server).
+constexpr uint32_t kMaxTab = 16;
+struct ImgPtrs {
+  uint64_t p[kMaxTab];
+  uint32_t n;  // 0: not used
+};
+struct OutPtrs {
+  uint64_t mask[kMaxTab], c0[kMaxTab], c1[kMaxTab];
+  uint32_t n;  // 0: not used
+};
 
 // Launchers (hc_kernels.hip). Each enqueues on `st` and returns the launch status.
 // Launch-shape variants: an NTT uses 2^(logn - elog) threads per polynomial;
@@ -53,16 +63,20 @@ bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg);
 // The MAC addresses one image tile and one channel tile with 32-bit byte offsets.
 bool mac_offsets_fit(const ConvGeom &g, uint32_t bt, uint32_t ct);
 
+// tab: optional input table (npolys == tab->n * ppi); input polynomials then
+// come from tab->p[poly / ppi] + (poly % ppi) * N.
 hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
-                          const LimbConsts &c, const Twiddles &tw, hipStream_t st);
+                          const LimbConsts &c, const Twiddles &tw, hipStream_t st, const ImgPtrs *tab = nullptr,
+                          uint32_t ppi = 0);
 // Full mode: in [P][N] -> out [P][N] (in place allowed).
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st);
 // Masked mode: in = Yhat [B][O][2][L][N]; c1 polys go to c1_out [B][O][L][N],
 // c0 polys are extracted with the mask into c0_ext [B][c_out][L][ho][wo].
+// tab: optional per-image output tables (tab->n == B).
 hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, const uint32_t *yhat,
                               const uint32_t *mask, uint32_t *c0_ext, uint32_t *c1_out, uint32_t B,
-                              const LimbConsts &c, const Twiddles &tw, hipStream_t st);
+                              const LimbConsts &c, const Twiddles &tw, hipStream_t st, const OutPtrs *tab = nullptr);
 hipError_t launch_mac(const ConvGeom &g, uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, const uint32_t *xhat,
                       const uint32_t *what, uint32_t *yhat, uint32_t B, const LimbConsts &c, hipStream_t st);
 hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *filters, uint32_t *w, const LimbConsts &c,

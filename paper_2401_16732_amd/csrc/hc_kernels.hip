@@ -202,9 +202,11 @@ __device__ __forceinline__ void load_low_pass(uint32_t (&v)[1 << ELOG], const ui
 // ---------------------------------------------------------------- forward NTT kernel
 // One workgroup per polynomial of in/out [P][N] (limb = poly mod L). Input
 // canonical; output canonical, in bit-reversed evaluation order.
+// With a pointer table (tab.n > 0) polynomial `poly` is read from image
+// poly / ppi at polynomial poly % ppi of that image's buffer instead.
 template <int LOGN, int ELOG>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *in, uint32_t *out, LimbConsts c,
-                                                                 Twiddles tws) {
+                                                                 Twiddles tws, ImgPtrs tab, uint32_t ppi) {
   constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
   __shared__ uint32_t lds[N + N / 32];
   const uint32_t tid = threadIdx.x;
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
   const uint32_t l = (uint32_t)(poly % c.L);
   const uint32_t q = c.q[l];
   const uint2 *tw = tws.fwd + (size_t)l * N;
-  const uint32_t *src = in + poly * N;
+  const uint32_t *src = tab.n ? (const uint32_t *)tab.p[poly / ppi] + (poly % ppi) * N : in + poly * N;
   uint32_t v[E];
   {
     constexpr int LO = pass_lo_fwd(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
@@ -268,10 +270,12 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
 // Masked mode over Yhat [B][O][2][L][N]: c1 polynomials are written whole to
 // c1_out [B][O][L][N]; c0 polynomials get the server mask added at the valid
 // output coefficients, which are gathered into c0_ext [B][c_out][L][ho][wo].
+// With pointer tables (out.n > 0) image b's mask, c0_ext and c1_out are
+// separate buffers (out.mask[b], out.c0[b], out.c1[b]) laid out as for B = 1.
 template <int LOGN, int ELOG>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32_t *yhat, const uint32_t *mask,
                                                                      uint32_t *c0_ext, uint32_t *c1_out, ConvGeom g,
-                                                                     LimbConsts c, Twiddles tws) {
+                                                                     LimbConsts c, Twiddles tws, OutPtrs out) {
   constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
   __shared__ uint32_t lds[N + N / 32];
   const uint32_t tid = threadIdx.x;
@@ -286,7 +290,7 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
   intt_core<LOGN, ELOG>(yhat + poly * N, v, lds, tid, c, tws.inv + (size_t)l * N, l);
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
   if (p == 1) {
-    uint32_t *dst = c1_out + (bo * g.L + l) * (size_t)N;
+    uint32_t *dst = out.n ? (uint32_t *)out.c1[b] + ((size_t)o * g.L + l) * N : c1_out + (bo * g.L + l) * (size_t)N;
 #pragma unroll
     for (int u = 0; u < E; ++u) dst[gidx<LOGN, ELOG, LO, EP>(tid, u)] = csub(v[u], q);
     return;
@@ -301,8 +305,10 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
   const uint32_t count = (oy1 > oy0 ? oy1 - oy0 : 0) * g.wo;
   const uint32_t t = c.t, half = c.t / 2;
   const uint32_t dl = c.delta[l], dlp = c.delta_p[l];
-  const uint32_t *mrow = mask + (b * g.c_out + i) * (size_t)g.ho * g.wo;
-  uint32_t *orow = c0_ext + ((b * g.c_out + i) * g.L + l) * (size_t)g.ho * g.wo;
+  const size_t hw = (size_t)g.ho * g.wo;
+  const uint32_t *mrow = out.n ? (const uint32_t *)out.mask[b] + i * hw : mask + (b * g.c_out + i) * hw;
+  uint32_t *orow = out.n ? (uint32_t *)out.c0[b] + ((size_t)i * g.L + l) * hw
+                         : c0_ext + ((b * g.c_out + i) * g.L + l) * hw;
   for (uint32_t idx = tid; idx < count; idx += NT) {
     const uint32_t oy = oy0 + idx / g.wo, ox = idx % g.wo;
     const uint32_t e = (g.s * oy - tau * g.r_o) * g.w_pad + g.s * ox;
@@ -526,9 +532,10 @@ __global__ void k_pointwise_mul(const uint32_t *__restrict__ a, const uint32_t *
 // ---------------------------------------------------------------- launchers
 template <int LOGN, int ELOG>
 static hipError_t fwd_t(const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c, const Twiddles &tw,
-                        hipStream_t st) {
+                        const ImgPtrs &tab, uint32_t ppi, hipStream_t st) {
   if (np == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_ntt_fwd<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c, tw);
+  hipLaunchKernelGGL((k_ntt_fwd<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c, tw,
+                     tab, ppi);
   return hipGetLastError();
 }
 template <int LOGN, int ELOG>
@@ -541,11 +548,11 @@ static hipError_t inv_t(const uint32_t *in, uint32_t *out, size_t np, const Limb
 }
 template <int LOGN, int ELOG>
 static hipError_t invm_t(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
-                         uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+                         uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
   const size_t np = (size_t)B * g.O * 2 * g.L;
   if (np == 0) return hipSuccess;
   hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, y, m, c0,
-                     c1, g, c, tw);
+                     c1, g, c, tw, out);
   return hipGetLastError();
 }
 
@@ -571,8 +578,12 @@ bool ntt_variant_ok(uint32_t logn, uint32_t elog) {
 }
 
 hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
-                          const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
-  HC_NTT_DISPATCH(fwd_t, in, out, np, c, tw, st)
+                          const LimbConsts &c, const Twiddles &tw, hipStream_t st, const ImgPtrs *tab,
+                          uint32_t ppi) {
+  ImgPtrs none{};
+  if (tab && (tab->n == 0 || tab->n > kMaxTab || ppi == 0 || np != (size_t)tab->n * ppi)) return hipErrorInvalidValue;
+  const ImgPtrs &t = tab ? *tab : none;
+  HC_NTT_DISPATCH(fwd_t, in, out, np, c, tw, t, ppi, st)
 }
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
@@ -580,8 +591,11 @@ hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, ui
 }
 hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, const uint32_t *y, const uint32_t *m,
                               uint32_t *c0, uint32_t *c1, uint32_t B, const LimbConsts &c, const Twiddles &tw,
-                              hipStream_t st) {
-  HC_NTT_DISPATCH(invm_t, g, y, m, c0, c1, B, c, tw, st)
+                              hipStream_t st, const OutPtrs *tab) {
+  OutPtrs none{};
+  if (tab && (tab->n != B || B > kMaxTab)) return hipErrorInvalidValue;
+  const OutPtrs &t = tab ? *tab : none;
+  HC_NTT_DISPATCH(invm_t, g, y, m, c0, c1, B, c, tw, t, st)
 }
 
 template <int BT, int CT, int RG, int CG>

@@ -1,0 +1,64 @@
+// Library-private definitions shared by hc_host.cpp and hc_server.cpp.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/hc.h"
+#include "hc_internal.h"
+
+struct hc_ctx {
+  uint32_t N = 0, logn = 0, L = 0;
+  uint64_t t = 0;
+  uint32_t q[hc::kMaxLimbs] = {};
+  uint32_t psi[hc::kMaxLimbs] = {};
+  uint32_t delta[hc::kMaxLimbs] = {};
+  int device = 0;
+  hc::LimbConsts consts{};
+  uint2 *d_tw = nullptr;  // [2][L][N]: forward then inverse
+  hc::Twiddles tw{};
+  hc_tuning tune{};        // 0 fields = defaults
+};
+
+struct hc_layer {
+  hc_ctx *ctx = nullptr;
+  hc_conv_shape shape{};
+  hc_layout lay{};
+  hc::ConvGeom geom{};
+  uint32_t *d_w = nullptr;  // [c_out][w_cts][L][N], NTT domain
+  size_t w_elems = 0;
+};
+
+
+namespace hc {
+
+hc_status fail(hc_status s, const std::string &msg);
+hc_status hip_fail(hipError_t e, const char *where);
+
+// Launch shapes in effect for B images.
+struct Shapes {
+  uint32_t fe, ie, bt, ct, rg, cg;
+};
+Shapes shapes_for(const hc_ctx &c, uint32_t B);
+
+// Device workspace of one layer's conv for B images (X-hat, plus Y-hat when masked).
+size_t ws_bytes_for(const hc_layer *ly, uint32_t B, bool masked);
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Forward NTT, MAC and masked inverse NTT of one layer for a group of images
+// whose buffers are given per image (at most kMaxTab).
+hc_status enqueue_conv_gather(const hc_layer *ly, uint32_t B, const uint32_t *const *ct_in,
+                              const uint32_t *const *mask, uint32_t *const *c0, uint32_t *const *c1, void *ws,
+                              hipStream_t st);
+
+}  // namespace hc

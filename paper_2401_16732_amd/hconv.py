@@ -26,6 +26,9 @@ SYMBOLS = [
     "hc_batch_workspace_bytes", "hc_batch_run", "hc_batch_run_eager", "hc_batch_destroy", "hc_poly_mul",
     "hc_sync", "hc_status_string", "hc_last_error", "hc_plan_ring", "hc_ring_params",
     "hc_batch_run_timed", "hc_ctx_set_tuning", "hc_ctx_get_tuning",
+    "hc_server_create", "hc_server_add_net", "hc_server_request_bytes", "hc_server_submit", "hc_server_step",
+    "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
+    "hc_server_destroy",
 ]
 
 
@@ -92,6 +95,17 @@ def load(path: str = LIB_PATH):
         "hc_batch_run_timed": (I, [P, P, P, P, P, P, P]),
         "hc_ctx_set_tuning": (I, [P, P]),
         "hc_ctx_get_tuning": (I, [P, P]),
+        "hc_server_create": (I, [P, P, P]),
+        "hc_server_add_net": (I, [P, P, u32, P]),
+        "hc_server_request_bytes": (I, [P, u32, P]),
+        "hc_server_submit": (I, [P, u32, P, P, P]),
+        "hc_server_step": (I, [P]),
+        "hc_server_poll": (I, [P, P, u32, P]),
+        "hc_server_outputs": (I, [P, ctypes.c_uint64, u32, P, P]),
+        "hc_server_release": (I, [P, ctypes.c_uint64]),
+        "hc_server_get_stats": (I, [P, P]),
+        "hc_server_sync": (I, [P]),
+        "hc_server_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -349,3 +363,121 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32), ("streams", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "admitted", "completed", "groups", "images", "queued",
+                                               "arena_used", "arena_bytes")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Server:
+    """Continuous-batching request loop over resident layers (hc_server_*)."""
+
+    def __init__(self, ctx: Context, arena_bytes: int, max_batch: int = 16, streams: int = 4):
+        self.ctx = ctx
+        cfg = ServerConfig(arena_bytes, max_batch, streams)
+        h = ctypes.c_void_p()
+        _check(_lib.hc_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)), "hc_server_create")
+        self.h = h
+        self.nets = []
+
+    def add_net(self, layers: Sequence[Layer]) -> int:
+        arr = (ctypes.c_void_p * len(layers))(*[ly.h.value for ly in layers])
+        nid = ctypes.c_uint32()
+        _check(_lib.hc_server_add_net(self.h, arr, len(layers), ctypes.byref(nid)), "hc_server_add_net")
+        self.nets.append(list(layers))
+        return nid.value
+
+    def request_bytes(self, net: int) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.hc_server_request_bytes(self.h, net, ctypes.byref(n)), "hc_server_request_bytes")
+        return n.value
+
+    def submit(self, net: int, ct_in, mask) -> int:
+        """ct_in[k], mask[k]: layer k's inputs for one image (device tensors, B = 1 shapes);
+        they must stay alive until the request completes."""
+        layers = self.nets[net]
+        if len(ct_in) != len(layers) or len(mask) != len(layers):
+            raise ValueError("one input and one mask per layer")
+        d = self.ctx.device
+        for k, ly in enumerate(layers):
+            ly._need(ct_in[k], ly.in_shape(1), f"ct_in[{k}]")
+            ly._need(mask[k], ly.mask_shape(1), f"mask[{k}]")
+        a = _ptr_array(ct_in, "ct_in", d)
+        m = _ptr_array(mask, "mask", d)
+        rid = ctypes.c_uint64()
+        _check(_lib.hc_server_submit(self.h, net, a, m, ctypes.byref(rid)), "hc_server_submit")
+        return rid.value
+
+    def step(self):
+        _check(_lib.hc_server_step(self.h), "hc_server_step")
+
+    def poll(self, cap: int = 1024):
+        ids = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_uint32()
+        _check(_lib.hc_server_poll(self.h, ids, cap, ctypes.byref(n)), "hc_server_poll")
+        return list(ids[: n.value])
+
+    def outputs(self, rid: int, layer: int, net: int):
+        """(c0_ext, c1_out) of a completed request's layer, copied to new device tensors."""
+        import torch
+        ly = self.nets[net][layer]
+        c0p, c1p = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(_lib.hc_server_outputs(self.h, rid, layer, ctypes.byref(c0p), ctypes.byref(c1p)), "hc_server_outputs")
+        c0 = torch.empty(ly.c0_shape(1)[1:], dtype=torch.int32, device=f"cuda:{self.ctx.device}")
+        c1 = torch.empty(ly.c1_shape(1)[1:], dtype=torch.int32, device=f"cuda:{self.ctx.device}")
+        _copy_from_ptr(c0, c0p.value)
+        _copy_from_ptr(c1, c1p.value)
+        return c0, c1
+
+    def release(self, rid: int):
+        _check(_lib.hc_server_release(self.h, rid), "hc_server_release")
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib.hc_server_get_stats(self.h, ctypes.byref(st)), "hc_server_get_stats")
+        return st.as_dict()
+
+    def sync(self):
+        _check(_lib.hc_server_sync(self.h), "hc_server_sync")
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.hc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _copy_from_ptr(dst, src_ptr: int):
+    """Device-to-device copy of dst.numel() words from a raw device address (HIP runtime)."""
+    import torch
+    hip = _hip_runtime()
+    torch.cuda.synchronize(dst.device)
+    rc = hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src_ptr), ctypes.c_size_t(dst.numel() * 4),
+                       ctypes.c_int(3))  # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed: {rc}")
+
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return _hip
