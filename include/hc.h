@@ -221,6 +221,9 @@ typedef struct {
     uint64_t arena_bytes;  /* HBM for admitted requests */
     uint32_t max_batch;    /* images per launch group, 1..16 */
     uint32_t streams;      /* concurrent launch streams, 1..8 */
+    uint32_t max_inflight; /* launch groups queued on the GPU at once (0: no limit). While the
+                              limit is reached, ready requests wait and can join larger groups;
+                              the largest ready group (then the oldest) launches first. */
 } hc_server_config;
 typedef struct {
     uint64_t submitted, admitted, completed, groups, images;  /* cumulative */

@@ -99,15 +99,17 @@ uint32_t bitrev(uint32_t x, int bits) {
 
 }  // namespace
 
+constexpr int kChains = 4;  // concurrent chains of layers in a batch graph
+
 struct hc_batch {
   hc_ctx *ctx = nullptr;
   std::vector<const hc_layer *> layers;
   uint32_t B = 0;
   void *ws = nullptr;
   size_t ws_bytes = 0;
-  std::vector<size_t> ws_off;  // per layer: X-hat offset; Y-hat follows
-  hipStream_t side[4] = {};
-  hipEvent_t fork = nullptr, join[4] = {};
+  std::vector<size_t> ws_off;  // per layer: start of its workspace region (shared within a chain)
+  hipStream_t side[kChains] = {};
+  hipEvent_t fork = nullptr, join[kChains] = {};
   hipGraphExec_t exec = nullptr;
   std::vector<const void *> key;  // pointers the graph was recorded with
 };
@@ -620,18 +622,22 @@ hc_status hc_batch_create(hc_ctx *c, const hc_layer *const *layers, uint32_t n, 
   bt->ctx = c;
   bt->B = B;
   bt->layers.assign(layers, layers + n);
-  size_t off = 0;
-  for (uint32_t k = 0; k < n; ++k) {
-    bt->ws_off.push_back(off);
-    off += (ws_bytes_for(layers[k], B, true) + 255) & ~(size_t)255;
-  }
+  // Layer k runs in chain k % kChains of the recorded graph; layers of one
+  // chain run one after another, so each chain needs one region, sized for
+  // its largest layer.
+  size_t region[kChains] = {};
+  for (uint32_t k = 0; k < n; ++k)
+    region[k % kChains] = std::max(region[k % kChains], (ws_bytes_for(layers[k], B, true) + 255) & ~(size_t)255);
+  size_t start[kChains], off = 0;
+  for (int c = 0; c < kChains; ++c) start[c] = off, off += region[c];
+  for (uint32_t k = 0; k < n; ++k) bt->ws_off.push_back(start[k % kChains]);
   bt->ws_bytes = off;
   if (hipMalloc(&bt->ws, off) != hipSuccess) {
     delete bt;
     return fail(HC_ENOMEM, "batch workspace allocation");
   }
   hipError_t e = hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming);
-  for (int s = 0; s < 4 && e == hipSuccess; ++s) {
+  for (int s = 0; s < kChains && e == hipSuccess; ++s) {
     e = hipStreamCreateWithFlags(&bt->side[s], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->join[s], hipEventDisableTiming);
   }
@@ -704,12 +710,12 @@ hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = hipEventRecord(bt->fork, cap);
-    for (int sd = 0; sd < 4 && e == hipSuccess; ++sd) e = hipStreamWaitEvent(bt->side[sd], bt->fork, 0);
+    for (int sd = 0; sd < kChains && e == hipSuccess; ++sd) e = hipStreamWaitEvent(bt->side[sd], bt->fork, 0);
     hc_status cs = HC_OK;
     for (size_t k = 0; k < n && e == hipSuccess && cs == HC_OK; ++k)
       cs = enqueue_conv(bt->layers[k], ct_in[k], nullptr, mask[k], c0[k], c1[k], bt->B,
-                        (char *)bt->ws + bt->ws_off[k], true, bt->side[k % 4]);
-    for (int sd = 0; sd < 4 && e == hipSuccess; ++sd) {
+                        (char *)bt->ws + bt->ws_off[k], true, bt->side[k % kChains]);
+    for (int sd = 0; sd < kChains && e == hipSuccess; ++sd) {
       e = hipEventRecord(bt->join[sd], bt->side[sd]);
       if (e == hipSuccess) e = hipStreamWaitEvent(cap, bt->join[sd], 0);
     }
@@ -759,7 +765,7 @@ void hc_batch_destroy(hc_batch *bt) {
   if (!bt) return;
   DeviceGuard dg(bt->ctx->device);
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < kChains; ++s) {
     if (bt->side[s]) (void)hipStreamDestroy(bt->side[s]);
     if (bt->join[s]) (void)hipEventDestroy(bt->join[s]);
   }

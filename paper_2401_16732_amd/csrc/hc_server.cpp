@@ -125,6 +125,7 @@ struct hc_server {
   std::vector<int> ev_refs;
   std::vector<int> ev_free;
   std::vector<uint64_t> completed;
+  std::vector<int> inflight;  // event slots of launched groups not yet seen complete
   hc_server_stats st{};
 };
 
@@ -189,6 +190,8 @@ hc_status hc_server_create(hc_ctx *ctx, const hc_server_config *cfg, hc_server *
   *out = nullptr;
   if (cfg->max_batch < 1 || cfg->max_batch > hc::kMaxTab) return fail(HC_EUNSUPPORTED, "max_batch must be in [1, 16]");
   if (cfg->streams < 1 || cfg->streams > 8) return fail(HC_EUNSUPPORTED, "streams must be in [1, 8]");
+  if (cfg->max_inflight && cfg->max_inflight < cfg->streams)
+    return fail(HC_EINVAL, "max_inflight must be 0 or at least the number of streams");
   if (cfg->arena_bytes < kAlign) return fail(HC_EINVAL, "arena too small");
   hc::DeviceGuard dg(ctx->device);
   hc_server *s = new (std::nothrow) hc_server;
@@ -305,6 +308,18 @@ hc_status hc_server_step(hc_server *s) {
       }
     }
   }
+  for (size_t k = 0; k < s->inflight.size();) {
+    hipError_t q = hipEventQuery(s->events[s->inflight[k]]);
+    if (q == hipSuccess) {
+      ev_unref(s, s->inflight[k]);
+      s->inflight[k] = s->inflight.back();
+      s->inflight.pop_back();
+    } else if (q != hipErrorNotReady) {
+      return hip_fail(q, "layer group");
+    } else {
+      ++k;
+    }
+  }
   // 2. admission, first come first served
   while (!s->queue.empty()) {
     Request &r = s->reqs.at(s->queue.front());
@@ -313,43 +328,59 @@ hc_status hc_server_step(hc_server *s) {
     if (a != HC_OK) return a;
     s->queue.pop_front();
   }
-  // 3. group the next layer of every ready request by (network, layer)
+  // 3. group the next layer of every ready request by (network, layer); chunks
+  // of at most max_batch images, largest first, then the oldest request first
   std::map<std::pair<uint32_t, uint32_t>, std::vector<Request *>> groups;
   for (auto &kv : s->reqs) {
     Request &r = kv.second;
     if (!r.admitted || r.done || r.group >= 0 || r.ready >= 0) continue;
     groups[{r.net, r.next}].push_back(&r);
   }
+  struct Chunk {
+    uint32_t net, layer;
+    std::vector<Request *> reqs;
+  };
+  std::vector<Chunk> chunks;
   for (auto &g : groups) {
     std::vector<Request *> &v = g.second;
     std::sort(v.begin(), v.end(), [](const Request *a, const Request *b) { return a->id < b->id; });
-    const NetPlan &np = s->nets[g.first.first];
-    const uint32_t k = g.first.second;
-    const hc_layer *ly = np.layers[k];
     for (size_t at = 0; at < v.size(); at += s->cfg.max_batch) {
-      const uint32_t B = (uint32_t)std::min<size_t>(s->cfg.max_batch, v.size() - at);
-      const uint32_t *in[hc::kMaxTab];
-      const uint32_t *mk[hc::kMaxTab];
-      uint32_t *c0[hc::kMaxTab];
-      uint32_t *c1[hc::kMaxTab];
-      for (uint32_t b = 0; b < B; ++b) {
-        char *base = s->arena + v[at + b]->off;
-        in[b] = (const uint32_t *)(base + np.off_in[k]);
-        mk[b] = (const uint32_t *)(base + np.off_mask[k]);
-        c0[b] = (uint32_t *)(base + np.off_c0[k]);
-        c1[b] = (uint32_t *)(base + np.off_c1[k]);
-      }
-      const uint32_t si = s->rr++ % (uint32_t)s->streams.size();
-      hc_status cs = hc::enqueue_conv_gather(ly, B, in, mk, c0, c1, s->ws[si], s->streams[si]);
-      if (cs != HC_OK) return cs;
-      int ev = ev_get(s);
-      if (ev < 0) return fail(HC_EDEVICE, "event creation");
-      SV_HIP(hipEventRecord(s->events[ev], s->streams[si]));
-      s->ev_refs[ev] = (int)B;
-      for (uint32_t b = 0; b < B; ++b) v[at + b]->group = ev;
-      s->st.groups++;
-      s->st.images += B;
+      const size_t B = std::min<size_t>(s->cfg.max_batch, v.size() - at);
+      chunks.push_back({g.first.first, g.first.second, std::vector<Request *>(v.begin() + at, v.begin() + at + B)});
     }
+  }
+  std::sort(chunks.begin(), chunks.end(), [](const Chunk &a, const Chunk &b) {
+    if (a.reqs.size() != b.reqs.size()) return a.reqs.size() > b.reqs.size();
+    return a.reqs.front()->id < b.reqs.front()->id;
+  });
+  for (Chunk &ch : chunks) {
+    if (s->cfg.max_inflight && s->inflight.size() >= s->cfg.max_inflight) break;
+    const NetPlan &np = s->nets[ch.net];
+    const uint32_t k = ch.layer;
+    const hc_layer *ly = np.layers[k];
+    const uint32_t B = (uint32_t)ch.reqs.size();
+    const uint32_t *in[hc::kMaxTab];
+    const uint32_t *mk[hc::kMaxTab];
+    uint32_t *c0[hc::kMaxTab];
+    uint32_t *c1[hc::kMaxTab];
+    for (uint32_t b = 0; b < B; ++b) {
+      char *base = s->arena + ch.reqs[b]->off;
+      in[b] = (const uint32_t *)(base + np.off_in[k]);
+      mk[b] = (const uint32_t *)(base + np.off_mask[k]);
+      c0[b] = (uint32_t *)(base + np.off_c0[k]);
+      c1[b] = (uint32_t *)(base + np.off_c1[k]);
+    }
+    const uint32_t si = s->rr++ % (uint32_t)s->streams.size();
+    hc_status cs = hc::enqueue_conv_gather(ly, B, in, mk, c0, c1, s->ws[si], s->streams[si]);
+    if (cs != HC_OK) return cs;
+    int ev = ev_get(s);
+    if (ev < 0) return fail(HC_EDEVICE, "event creation");
+    SV_HIP(hipEventRecord(s->events[ev], s->streams[si]));
+    s->ev_refs[ev] = (int)B + 1;  // the group's requests and the in-flight list
+    s->inflight.push_back(ev);
+    for (uint32_t b = 0; b < B; ++b) ch.reqs[b]->group = ev;
+    s->st.groups++;
+    s->st.images += B;
   }
   return HC_OK;
 }

@@ -366,7 +366,8 @@ class Batch:
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32), ("streams", ctypes.c_uint32)]
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("max_inflight", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -380,9 +381,9 @@ class ServerStats(ctypes.Structure):
 class Server:
     """Continuous-batching request loop over resident layers (hc_server_*)."""
 
-    def __init__(self, ctx: Context, arena_bytes: int, max_batch: int = 16, streams: int = 4):
+    def __init__(self, ctx: Context, arena_bytes: int, max_batch: int = 16, streams: int = 4, max_inflight: int = 0):
         self.ctx = ctx
-        cfg = ServerConfig(arena_bytes, max_batch, streams)
+        cfg = ServerConfig(arena_bytes, max_batch, streams, max_inflight)
         h = ctypes.c_void_p()
         _check(_lib.hc_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)), "hc_server_create")
         self.h = h

@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--arena-gib", type=float, default=160.0)
     ap.add_argument("--max-batch", type=int, default=16)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--max-inflight", type=int, default=8, help="launch groups on the GPU at once (0: no limit)")
     ap.add_argument("--burst", type=int, default=64, help="requests in the saturation burst")
     ap.add_argument("--sets", type=int, default=2, help="distinct input sets per network")
     ap.add_argument("--seed", type=int, default=4)
@@ -58,7 +59,7 @@ def main():
         nets[name] = [hconv.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, W.gen_filters(g, s)) for s in specs]
     torch.cuda.synchronize()
     enc_ms = (time.perf_counter() - t0) * 1e3
-    srv = hconv.Server(ctx, int(a.arena_gib * 2 ** 30), a.max_batch, a.streams)
+    srv = hconv.Server(ctx, int(a.arena_gib * 2 ** 30), a.max_batch, a.streams, a.max_inflight)
     nid = {name: srv.add_net(layers) for name, layers in nets.items()}
     tg = torch.Generator(device=dev)
     tg.manual_seed(a.seed)
@@ -73,7 +74,7 @@ def main():
     torch.cuda.synchronize()
     info = {"networks": {k: {"layers": len(v), "request_bytes": srv.request_bytes(nid[k])} for k, v in nets.items()},
             "weight_encode_ms": round(enc_ms, 1), "arena_gib": a.arena_gib, "max_batch": a.max_batch,
-            "streams": a.streams, "mix_resnet50": a.mix}
+            "streams": a.streams, "max_inflight": a.max_inflight, "mix_resnet50": a.mix}
     print(json.dumps({"serving_setup": info}), flush=True)
     rng = np.random.default_rng(a.seed)
 

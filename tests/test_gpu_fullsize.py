@@ -1,0 +1,124 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (all 53 ResNet-50 layers, 16 images, one HIP graph), and at the large
+ring (ResNet-18 224x224, N = 16384, 4 primes, 64 images): sampled outputs of
+every layer against the oracle's closed form (bit-exact), and graph replays
+against eager runs."""
+import numpy as np
+import pytest
+
+from oracle import layout
+from paper_2401_16732_amd import workloads as W
+
+from gpu_util import check_layer_points, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_16732_amd import hconv
+    hconv.load()
+    return hconv
+
+
+def _net_batch(hc, net, N, L, t, B, seed):
+    import torch
+    ctx = hc.Context(N, L, t)
+    specs = W.NETS[net]()
+    g = W.rng(seed)
+    filters = [W.gen_filters(g, s) for s in specs]
+    layers = [hc.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, f) for s, f in zip(specs, filters)]
+    tg = torch.Generator(device="cuda")
+    tg.manual_seed(seed)
+    ct_in = [W.gen_ct_limbs_torch(tg, ly.in_shape(B)[:3], ctx.primes, N, "cuda") for ly in layers]
+    mask = [torch.randint(0, t, ly.mask_shape(B), generator=tg, device="cuda", dtype=torch.int32) for ly in layers]
+    c0 = [torch.zeros(ly.c0_shape(B), dtype=torch.int32, device="cuda") for ly in layers]
+    c1 = [torch.zeros(ly.c1_shape(B), dtype=torch.int32, device="cuda") for ly in layers]
+    return ctx, specs, filters, layers, ct_in, mask, c0, c1
+
+
+def _check_net(ctx, specs, filters, ct_in, mask, c0, c1, images, t, g, npts):
+    for k, (s, f) in enumerate(zip(specs, filters)):
+        P = layout.plan(ctx.N, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride)
+        for b in images:
+            print(f"  layer {k} {s.name} image {b}", flush=True)
+            check_layer_points(P, ctx.primes, t, host(ct_in[k][b]), f, host(mask[k][b]), host(c0[k][b]),
+                               host(c1[k][b]), g, npts=npts)
+
+
+def _free(*objs):
+    import torch
+    for o in objs:
+        if isinstance(o, list):
+            for x in o:
+                if hasattr(x, "close"):
+                    x.close()
+        elif hasattr(o, "close"):
+            o.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_resnet50_batch16_graph_matches_oracle(hc):
+    import torch
+    N, L, t, B = 8192, 3, 2 ** 20, 16
+    print("resnet50_224 B=16 graph", flush=True)
+    ctx, specs, filters, layers, ct_in, mask, c0, c1 = _net_batch(hc, "resnet50_224", N, L, t, B, 50)
+    bt = hc.Batch(ctx, layers, B)
+    bt.run(ct_in, mask, c0, c1)
+    torch.cuda.synchronize()
+    _check_net(ctx, specs, filters, ct_in, mask, c0, c1, (0, B - 1), t, W.rng(7), npts=8)
+    del ct_in, mask, c0, c1
+    _free(bt, layers)
+
+
+def test_graph_replays_match_eager(hc):
+    """Replay the recorded graph several times with eager work and syncs in
+    between; every replay must equal the eager (stream-ordered) result."""
+    import torch
+    N, L, t, B = 8192, 3, 2 ** 20, 16
+    ctx = hc.Context(N, L, t)
+    specs = [s for s in W.resnet50_224() if s.name in ("stem", "s1.b0.c2", "s2.b0.proj", "s3.b1.c1", "s4.b0.c3",
+                                                         "s4.b2.c2")]
+    g = W.rng(3)
+    layers = [hc.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, W.gen_filters(g, s)) for s in specs]
+    tg = torch.Generator(device="cuda")
+    tg.manual_seed(3)
+    ct_in = [W.gen_ct_limbs_torch(tg, ly.in_shape(B)[:3], ctx.primes, N, "cuda") for ly in layers]
+    mask = [torch.randint(0, t, ly.mask_shape(B), generator=tg, device="cuda", dtype=torch.int32) for ly in layers]
+    outs = lambda: ([torch.zeros(ly.c0_shape(B), dtype=torch.int32, device="cuda") for ly in layers],
+                    [torch.zeros(ly.c1_shape(B), dtype=torch.int32, device="cuda") for ly in layers])
+    bt = hc.Batch(ctx, layers, B)
+    e0, e1 = outs()
+    bt.run_eager(ct_in, mask, e0, e1)
+    torch.cuda.synchronize()
+    g0, g1 = outs()
+    x0, x1 = outs()
+    for rep in range(3):
+        print(f"graph replay {rep}", flush=True)
+        for v in g0 + g1:
+            v.zero_()
+        bt.run(ct_in, mask, g0, g1)
+        bt.run_eager(ct_in, mask, x0, x1)  # eager work between replays
+        torch.cuda.synchronize()
+        for k in range(len(layers)):
+            assert torch.equal(g0[k], e0[k]) and torch.equal(g1[k], e1[k]), (rep, k)
+            assert torch.equal(x0[k], e0[k]) and torch.equal(x1[k], e1[k]), (rep, k)
+    del ct_in, mask, e0, e1, g0, g1, x0, x1
+    _free(bt, layers)
+
+
+def test_resnet18_224_large_ring_batch64_matches_oracle(hc):
+    import torch
+    N, L, t, B = 16384, 4, 2 ** 24, 64
+    print("resnet18_224 N=16384 L=4 B=64 graph", flush=True)
+    ctx, specs, filters, layers, ct_in, mask, c0, c1 = _net_batch(hc, "resnet18_224", N, L, t, B, 18)
+    bt = hc.Batch(ctx, layers, B)
+    bt.run(ct_in, mask, c0, c1)
+    torch.cuda.synchronize()
+    _check_net(ctx, specs, filters, ct_in, mask, c0, c1, (0, 37, B - 1), t, W.rng(8), npts=8)
+    del ct_in, mask, c0, c1
+    _free(bt, layers)

@@ -87,7 +87,7 @@ def test_request_alone_equals_request_in_mix(setup):
         others.append((net, [dev(v) for v in x], [dev(v) for v in m]))
         plan.append((k // 2, net, others[-1][1], others[-1][2]))
     plan.insert(4, (1, na, dxa, dma))
-    srv = hconv.Server(ctx, arena_bytes=8 << 30, max_batch=16, streams=3)
+    srv = hconv.Server(ctx, arena_bytes=8 << 30, max_batch=16, streams=3, max_inflight=3)
     assert srv.add_net(layers_a) == na and srv.add_net(layers_b) == nb
     ids = _run(srv, plan)
     st = srv.stats()
