@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=50)
     ap.add_argument("--stage-passes", type=int, default=3, help="eager passes timed per kernel for the roofline")
     ap.add_argument("--copy-gib", type=float, default=4.0, help="size of the HBM stream-copy calibration")
+    ap.add_argument("--no-autotune", action="store_true", help="use the context's default launch shapes")
     return ap.parse_args()
 
 
@@ -188,6 +189,12 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] inputs resident; batch workspace {bt.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr,
           flush=True)
+    tune_ms = None
+    if not a.no_autotune:
+        t1 = time.perf_counter()
+        bt.autotune(ct_in, mask, c0, c1)
+        tune_ms = (time.perf_counter() - t1) * 1e3
+        print(f"[bench] autotuned {len(layers)} layers in {tune_ms:.0f} ms", file=sys.stderr, flush=True)
 
     for _ in range(a.warmup):
         bt.run(ct_in, mask, c0, c1)
@@ -302,6 +309,7 @@ def main():
         "plain_ms_per_image": None if plain_ms is None else round(plain_ms, 4),
         "speedup_vs_plain": None if plain_ms is None else round(plain_ms / per_img, 3),
         "weight_encode_ms": round(encode_ms, 1),
+        "autotune_ms": None if tune_ms is None else round(tune_ms, 1),
         "stage_ms_eager": [round(v, 3) for v in stage],
         "path_bytes_per_step": tot["bytes_path"] + tot["bytes_w"],
         "path_hbm_frac": round((tot["bytes_path"] + tot["bytes_w"]) / (ms_step * 1e-3) / HBM_PEAK, 4),

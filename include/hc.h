@@ -194,6 +194,21 @@ hc_status hc_batch_run_eager(hc_batch *batch, const uint32_t *const *ct_in, cons
                              uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream);
 void hc_batch_destroy(hc_batch *batch);
 
+/* Autotuner: for every layer of the batch, time each supported launch shape
+ * of each stage (forward NTT threads per polynomial, MAC tile, inverse NTT
+ * threads per polynomial) on the batch's own buffers (B images) and keep the
+ * fastest per stage as the layer's shapes for B images. Results never change
+ * (every shape gives the same bits). cache_path (may be NULL): a text file of
+ * earlier results keyed by device, ring, B and layer shape; hits skip the
+ * timing and new results are appended. Synchronous; the next hc_batch_run
+ * re-records its graph. The buffers are overwritten. */
+hc_status hc_batch_autotune(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                            uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream, const char *cache_path);
+/* A layer's autotuned shapes and the batch size they apply to (0: none); clearing
+ * returns the layer to the context's shapes. */
+hc_status hc_layer_get_tuning(const hc_layer *layer, uint32_t *batch_size, hc_tuning *out);
+hc_status hc_layer_clear_tuning(hc_layer *layer);
+
 /* hc_batch_run_eager with a HIP event recorded on `stream` before and after
  * every kernel launch; waits for completion and adds the elapsed milliseconds
  * of each stage to stage_ms[0] (forward NTT of the inputs), stage_ms[1]

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <map>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -197,6 +198,13 @@ ConvGeom geom_of(const hc_ctx &c, const hc_conv_shape &s, const hc_layout &o) {
   g.F = o.footprint;
   g.ho = o.ho;
   g.wo = o.wo;
+  // largest extracted coefficient: output row s*oy - tau*r_o < r_o (and below the
+  // stride-1 grid), column s*(wo-1)
+  const uint32_t rows = std::min(o.rows_out_per_tile, o.h_pad - s.f + 1);
+  const uint64_t e_max = (uint64_t)(((rows - 1) / o.s) * o.s) * o.w_pad + (uint64_t)o.s * (o.wo - 1);
+  uint32_t pb = 0;
+  while ((1ull << pb) <= e_max) ++pb;
+  g.prune_bits = std::min(pb, c.logn);
   return g;
 }
 
@@ -226,6 +234,17 @@ hc::Shapes hc::shapes_for(const hc_ctx &c, uint32_t B) {
   return s;
 }
 
+hc::Shapes hc::layer_shapes(const hc_layer *ly, uint32_t B) {
+  hc::Shapes s = shapes_for(*ly->ctx, B);
+  if (ly->tune_B == B) {
+    const hc_tuning &t = ly->tune;
+    if (t.fwd_elog) s.fe = t.fwd_elog;
+    if (t.inv_elog) s.ie = t.inv_elog;
+    if (t.mac_rows) s.bt = t.mac_rows, s.ct = t.mac_cols, s.rg = t.mac_row_groups, s.cg = t.mac_col_groups;
+  }
+  return s;
+}
+
 namespace {
 using hc::shapes_for;
 
@@ -242,7 +261,7 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
   const hc_ctx &c = *ly->ctx;
   const ConvGeom &g = ly->geom;
   const bool timed = tm && tm->on;
-  const Shapes sh = shapes_for(c, B);
+  const Shapes sh = hc::layer_shapes(ly, B);
   if (!hc::mac_offsets_fit(g, sh.bt, sh.ct))
     return fail(HC_EUNSUPPORTED, "layer too large for the selected MAC tile (32-bit offsets); use smaller mac_rows");
   uint32_t *xhat = (uint32_t *)ws;
@@ -281,7 +300,7 @@ hc_status hc::enqueue_conv_gather(const hc_layer *ly, uint32_t B, const uint32_t
   const hc_ctx &c = *ly->ctx;
   const ConvGeom &g = ly->geom;
   if (B == 0 || B > hc::kMaxTab) return fail(HC_EINVAL, "group size out of range");
-  const Shapes sh = shapes_for(c, B);
+  const Shapes sh = hc::layer_shapes(ly, B);
   if (!hc::mac_offsets_fit(g, sh.bt, sh.ct)) return fail(HC_EUNSUPPORTED, "layer too large for the MAC tile");
   hc::ImgPtrs in{};
   hc::OutPtrs out{};
@@ -759,6 +778,162 @@ hc_status hc_batch_run_timed(hc_batch *bt, const uint32_t *const *ct_in, const u
   }
   for (int k = 0; k < 6; ++k) (void)hipEventDestroy(tm.ev[k]);
   return out;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- autotuner
+namespace {
+
+std::string tune_key(const hc_layer *ly, uint32_t B, const char *arch) {
+  const hc_conv_shape &s = ly->shape;
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s N=%u L=%u B=%u %u-%u %ux%u f%u s%u", arch, ly->ctx->N, ly->ctx->L, B, s.c_in,
+                s.c_out, s.h, s.w, s.f, s.stride);
+  return buf;
+}
+
+// Mean milliseconds of `reps` launches of fn on stream st (after one warm-up).
+template <class F>
+hc_status time_it(F fn, hipStream_t st, int reps, float *ms) {
+  hipEvent_t a, b;
+  HC_HIP(hipEventCreate(&a));
+  HC_HIP(hipEventCreate(&b));
+  hipError_t e = fn();
+  if (e == hipSuccess) e = hipEventRecord(a, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = fn();
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return hip_fail(e, "autotune timing");
+  *ms /= reps;
+  return HC_OK;
+}
+
+const uint32_t kMacCand[][4] = {{1, 8, 1, 4}, {1, 4, 1, 4}, {2, 4, 1, 4}, {4, 4, 1, 4}, {4, 2, 1, 4},
+                                {8, 2, 1, 4}, {16, 2, 1, 4}, {4, 4, 4, 2}, {4, 8, 4, 2}, {2, 8, 4, 2},
+                                {4, 4, 2, 4}, {8, 4, 2, 2}, {2, 4, 4, 4}, {1, 8, 2, 4}};
+
+}  // namespace
+
+extern "C" {
+
+hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                            uint32_t *const *c0, uint32_t *const *c1, void *stream, const char *cache_path) {
+  hc_status s = batch_check(bt, ct_in, mask, c0, c1);
+  if (s != HC_OK) return s;
+  DeviceGuard dg(bt->ctx->device);
+  hipDeviceProp_t prop;
+  HC_HIP(hipGetDeviceProperties(&prop, bt->ctx->device));
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  std::map<std::string, hc_tuning> cache;
+  if (cache_path) {
+    FILE *f = std::fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      while (std::fgets(line, sizeof(line), f)) {
+        char *bar = std::strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        hc_tuning t{};
+        if (std::sscanf(bar + 1, "%u %u %u %u %u %u", &t.fwd_elog, &t.inv_elog, &t.mac_rows, &t.mac_cols,
+                        &t.mac_row_groups, &t.mac_col_groups) == 6)
+          cache[line] = t;
+      }
+      std::fclose(f);
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const hc_ctx &c = *bt->ctx;
+  const uint32_t B = bt->B;
+  const int reps = 3;
+  std::string appended;
+  for (size_t k = 0; k < bt->layers.size(); ++k) {
+    hc_layer *ly = const_cast<hc_layer *>(bt->layers[k]);
+    const std::string key = tune_key(ly, B, arch.c_str());
+    auto hit = cache.find(key);
+    if (hit != cache.end()) {
+      const hc_tuning &t = hit->second;
+      if (hc::ntt_variant_ok(c.logn, t.fwd_elog) && hc::ntt_variant_ok(c.logn, t.inv_elog) &&
+          hc::mac_variant_ok(t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups) &&
+          hc::mac_offsets_fit(ly->geom, t.mac_rows, t.mac_cols)) {
+        ly->tune = t;
+        ly->tune_B = B;
+        continue;
+      }
+    }
+    const hc::ConvGeom &g = ly->geom;
+    uint32_t *xhat = (uint32_t *)((char *)bt->ws + bt->ws_off[k]);
+    const size_t npin = (size_t)B * g.G * 2 * c.L;
+    uint32_t *yhat = xhat + npin * c.N;
+    hc_tuning best{};
+    float best_ms = 1e30f;
+    for (uint32_t e = 3; e <= 6; ++e) {
+      if (!hc::ntt_variant_ok(c.logn, e)) continue;
+      float ms;
+      s = time_it([&] { return hc::launch_ntt_fwd(c.logn, e, ct_in[k], xhat, npin, c.consts, c.tw, st); }, st, reps,
+                  &ms);
+      if (s != HC_OK) return s;
+      if (ms < best_ms) best_ms = ms, best.fwd_elog = e;
+    }
+    best_ms = 1e30f;
+    for (const auto &m : kMacCand) {
+      if (!hc::mac_variant_ok(m[0], m[1], m[2], m[3]) || !hc::mac_offsets_fit(g, m[0], m[1])) continue;
+      float ms;
+      s = time_it([&] { return hc::launch_mac(g, m[0], m[1], m[2], m[3], xhat, ly->d_w, yhat, B, c.consts, st); },
+                  st, reps, &ms);
+      if (s != HC_OK) return s;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best.mac_rows = m[0], best.mac_cols = m[1], best.mac_row_groups = m[2], best.mac_col_groups = m[3];
+      }
+    }
+    best_ms = 1e30f;
+    for (uint32_t e = 3; e <= 6; ++e) {
+      if (!hc::ntt_variant_ok(c.logn, e)) continue;
+      float ms;
+      s = time_it([&] {
+        return hc::launch_intt_masked(g, c.logn, e, yhat, mask[k], c0[k], c1[k], B, c.consts, c.tw, st);
+      }, st, reps, &ms);
+      if (s != HC_OK) return s;
+      if (ms < best_ms) best_ms = ms, best.inv_elog = e;
+    }
+    ly->tune = best;
+    ly->tune_B = B;
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog, best.mac_rows,
+                  best.mac_cols, best.mac_row_groups, best.mac_col_groups);
+    appended += key + buf;
+  }
+  if (cache_path && !appended.empty()) {
+    FILE *f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fputs(appended.c_str(), f);
+      std::fclose(f);
+    }
+  }
+  if (bt->exec) {
+    (void)hipGraphExecDestroy(bt->exec);
+    bt->exec = nullptr;
+  }
+  return HC_OK;
+}
+
+hc_status hc_layer_get_tuning(const hc_layer *ly, uint32_t *B, hc_tuning *out) {
+  if (!ly || !B || !out) return fail(HC_EINVAL, "null argument");
+  *B = ly->tune_B;
+  *out = ly->tune;
+  return HC_OK;
+}
+
+hc_status hc_layer_clear_tuning(hc_layer *ly) {
+  if (!ly) return fail(HC_EINVAL, "null argument");
+  ly->tune = hc_tuning{};
+  ly->tune_B = 0;
+  return HC_OK;
 }
 
 void hc_batch_destroy(hc_batch *bt) {

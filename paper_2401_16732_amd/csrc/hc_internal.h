@@ -40,6 +40,7 @@ struct ConvGeom {
   uint32_t G, G_w, O;
   uint32_t w_pad, F;
   uint32_t ho, wo;
+  uint32_t prune_bits;  // every extracted c0 coefficient index is below 2^prune_bits
 };
 
 // Per-image buffer tables (kernel arguments by value) for groups of up to

@@ -67,7 +67,10 @@ __device__ __forceinline__ uint32_t gidx(uint32_t tid, int u) {
   return (v & ((1u << LO) - 1u)) | (w << LO) | ((v >> LO) << (LO + EP));
 }
 // LDS word address: one pad word per 32 keeps strided passes off a single bank.
-__device__ __forceinline__ uint32_t lpad(uint32_t j) { return j + (j >> 5); }
+// gidx(tid, u) is the OR of a thread part gidx(tid, 0) and a register part
+// gidx(0, u) over disjoint bits, so lpad(gidx(tid, u)) = lpad(gidx(tid, 0)) +
+// lpad(gidx(0, u)): one base per thread and compile-time offsets per register.
+__host__ __device__ constexpr uint32_t lpad(uint32_t j) { return j + (j >> 5); }
 
 // Forward (Cooley-Tukey, natural -> bit-reversed) stages of one pass.
 // Stage s works on pairs (j, j + 2^(LOGN-1-s)) with twiddle psi^brv(2^s + j >> (LOGN - s)).
@@ -80,12 +83,13 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
   for (int bb = EP - 1; bb >= 0; --bb) {
     const int b = LO + bb;
     const int s = LOGN - 1 - b;
+    // twiddle index 2^s + (j >> (b + 1)), split into thread and register parts
+    const uint2 *tws = tw + (1u << s) + (gidx<LOGN, ELOG, LO, EP>(tid, 0) >> (b + 1));
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       if (u & (1 << bb)) continue;
       const int u2 = u | (1 << bb);
-      const uint32_t j = gidx<LOGN, ELOG, LO, EP>(tid, u);
-      const uint2 w = tw[(1u << s) + (j >> (b + 1))];
+      const uint2 w = tws[gidx<LOGN, ELOG, LO, EP>(0, u) >> (b + 1)];
       uint32_t X = v[u], Y = v[u2];
       X = csub(X, q2);
       const uint32_t T = shoup_lazy(Y, w.x, w.y, q);
@@ -97,16 +101,31 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
 
 // Inverse (Gentleman-Sande, bit-reversed -> natural) stages of one pass; the
 // last stage (s = 0) also multiplies by N^-1.
+// Pruning: when only outputs below 2^pb are wanted, every stage on a bit
+// b >= pb feeds wanted outputs from its lower (sum) half only - all wanted
+// indices have bits pb.. clear - so the difference half, with its twiddle
+// multiply, is skipped there. pb = LOGN computes the full transform.
 template <int LOGN, int ELOG, int LO, int EP>
 __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
                                          uint32_t q, uint32_t ninv, uint32_t ninvp, uint32_t ninvw,
-                                         uint32_t ninvwp) {
+                                         uint32_t ninvwp, uint32_t pb) {
   constexpr int E = 1 << ELOG;
   const uint32_t q2 = 2 * q;
 #pragma unroll
   for (int bb = 0; bb < EP; ++bb) {
     const int b = LO + bb;
     const int s = LOGN - 1 - b;
+    const bool sum_only = (uint32_t)b >= pb;  // uniform
+    const uint2 *tws = tw + (1u << s) + (gidx<LOGN, ELOG, LO, EP>(tid, 0) >> (b + 1));
+    if (sum_only) {
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        if (u & (1 << bb)) continue;
+        const int u2 = u | (1 << bb);
+        v[u] = s == 0 ? shoup_lazy(v[u] + v[u2], ninv, ninvp, q) : csub(v[u] + v[u2], q2);
+      }
+      continue;
+    }
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       if (u & (1 << bb)) continue;
@@ -116,8 +135,7 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
         v[u] = shoup_lazy(X + Y, ninv, ninvp, q);
         v[u2] = shoup_lazy(X - Y + q2, ninvw, ninvwp, q);
       } else {
-        const uint32_t j = gidx<LOGN, ELOG, LO, EP>(tid, u);
-        const uint2 w = tw[(1u << s) + (j >> (b + 1))];
+        const uint2 w = tws[gidx<LOGN, ELOG, LO, EP>(0, u) >> (b + 1)];
         v[u] = csub(X + Y, q2);
         v[u2] = shoup_lazy(X - Y + q2, w.x, w.y, q);
       }
@@ -127,13 +145,15 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
 
 template <int LOGN, int ELOG, int LO, int EP>
 __device__ __forceinline__ void regs_to_lds(const uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid) {
+  uint32_t *p = lds + lpad(gidx<LOGN, ELOG, LO, EP>(tid, 0));
 #pragma unroll
-  for (int u = 0; u < (1 << ELOG); ++u) lds[lpad(gidx<LOGN, ELOG, LO, EP>(tid, u))] = v[u];
+  for (int u = 0; u < (1 << ELOG); ++u) p[lpad(gidx<LOGN, ELOG, LO, EP>(0, u))] = v[u];
 }
 template <int LOGN, int ELOG, int LO, int EP>
 __device__ __forceinline__ void lds_to_regs(uint32_t (&v)[1 << ELOG], const uint32_t *lds, uint32_t tid) {
+  const uint32_t *p = lds + lpad(gidx<LOGN, ELOG, LO, EP>(tid, 0));
 #pragma unroll
-  for (int u = 0; u < (1 << ELOG); ++u) v[u] = lds[lpad(gidx<LOGN, ELOG, LO, EP>(tid, u))];
+  for (int u = 0; u < (1 << ELOG); ++u) v[u] = p[lpad(gidx<LOGN, ELOG, LO, EP>(0, u))];
 }
 
 template <int LOGN, int ELOG, int K>
@@ -164,23 +184,24 @@ template <int LOGN, int ELOG, int K>
 struct InvPasses {
   static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid,
                                              const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
-                                             uint32_t bp) {
+                                             uint32_t bp, uint32_t pb) {
     constexpr int LO = pass_lo_inv(LOGN, ELOG, K), EP = pass_bits(LOGN, ELOG, K);
     constexpr int PLO = pass_lo_inv(LOGN, ELOG, K - 1), PEP = pass_bits(LOGN, ELOG, K - 1);
-    InvPasses<LOGN, ELOG, K - 1>::run(v, lds, tid, tw, q, a, ap, b, bp);
+    InvPasses<LOGN, ELOG, K - 1>::run(v, lds, tid, tw, q, a, ap, b, bp, pb);
     regs_to_lds<LOGN, ELOG, PLO, PEP>(v, lds, tid);
     __syncthreads();
     lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
-    inv_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q, a, ap, b, bp);
+    inv_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q, a, ap, b, bp, pb);
   }
 };
 template <int LOGN, int ELOG>
 struct InvPasses<LOGN, ELOG, 0> {
   // pass 0 (bits [0, EP)) expects its inputs already in registers
   static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *, uint32_t tid, const uint2 *tw,
-                                             uint32_t q, uint32_t a, uint32_t ap, uint32_t b, uint32_t bp) {
+                                             uint32_t q, uint32_t a, uint32_t ap, uint32_t b, uint32_t bp,
+                                             uint32_t pb) {
     constexpr int LO = pass_lo_inv(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
-    inv_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q, a, ap, b, bp);
+    inv_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q, a, ap, b, bp, pb);
   }
 };
 
@@ -189,9 +210,10 @@ struct InvPasses<LOGN, ELOG, 0> {
 template <int LOGN, int ELOG, int EP>
 __device__ __forceinline__ void load_low_pass(uint32_t (&v)[1 << ELOG], const uint32_t *src, uint32_t tid) {
   static_assert(EP >= 2, "vector access needs 4 consecutive words");
+  const uint32_t *sb = src + gidx<LOGN, ELOG, 0, EP>(tid, 0);
 #pragma unroll
   for (int u = 0; u < (1 << ELOG); u += 4) {
-    const uint4 t4 = *reinterpret_cast<const uint4 *>(src + gidx<LOGN, ELOG, 0, EP>(tid, u));
+    const uint4 t4 = *reinterpret_cast<const uint4 *>(sb + gidx<LOGN, ELOG, 0, EP>(0, u));
     v[u] = t4.x;
     v[u + 1] = t4.y;
     v[u + 2] = t4.z;
@@ -218,8 +240,9 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
   uint32_t v[E];
   {
     constexpr int LO = pass_lo_fwd(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
+    const uint32_t *sb = src + gidx<LOGN, ELOG, LO, EP>(tid, 0);
 #pragma unroll
-    for (int u = 0; u < E; ++u) v[u] = __builtin_nontemporal_load(src + gidx<LOGN, ELOG, LO, EP>(tid, u));
+    for (int u = 0; u < E; ++u) v[u] = __builtin_nontemporal_load(sb + gidx<LOGN, ELOG, LO, EP>(0, u));
   }
   FwdPasses<LOGN, ELOG, NP - 1>::run(v, lds, tid, tw, q);
   // the last pass (bits [0, EP)) leaves runs of 2^EP consecutive coefficients
@@ -235,18 +258,20 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
     t4.y = csub(csub(v[u + 1], q2), q);
     t4.z = csub(csub(v[u + 2], q2), q);
     t4.w = csub(csub(v[u + 3], q2), q);
-    *reinterpret_cast<uint4 *>(dst + gidx<LOGN, ELOG, 0, EPL>(tid, u)) = t4;
+    *reinterpret_cast<uint4 *>(dst + gidx<LOGN, ELOG, 0, EPL>(tid, 0) + gidx<LOGN, ELOG, 0, EPL>(0, u)) = t4;
   }
   (void)NT;
 }
 
 // ---------------------------------------------------------------- inverse NTT kernels
+// pb: prune bit (see inv_pass); LOGN for the whole transform.
 template <int LOGN, int ELOG>
 __device__ __forceinline__ void intt_core(const uint32_t *src, uint32_t (&v)[1 << ELOG], uint32_t *lds,
-                                          uint32_t tid, const LimbConsts &c, const uint2 *tw, uint32_t l) {
+                                          uint32_t tid, const LimbConsts &c, const uint2 *tw, uint32_t l,
+                                          uint32_t pb = LOGN) {
   constexpr int NP = n_pass(LOGN, ELOG);
   load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v, src, tid);
-  InvPasses<LOGN, ELOG, NP - 1>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l], c.ninvw_p[l]);
+  InvPasses<LOGN, ELOG, NP - 1>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l], c.ninvw_p[l], pb);
 }
 
 // Full mode: [P][N] -> [P][N] canonical (in place allowed).
@@ -263,8 +288,9 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
   uint32_t *dst = out + poly * N;
   const uint32_t q = c.q[l];
+  uint32_t *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
 #pragma unroll
-  for (int u = 0; u < E; ++u) dst[gidx<LOGN, ELOG, LO, EP>(tid, u)] = csub(v[u], q);
+  for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[u], q);
 }
 
 // Masked mode over Yhat [B][O][2][L][N]: c1 polynomials are written whole to
@@ -287,12 +313,15 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
   const size_t b = bo / g.O;
   const uint32_t q = c.q[l];
   uint32_t v[E];
-  intt_core<LOGN, ELOG>(yhat + poly * N, v, lds, tid, c, tws.inv + (size_t)l * N, l);
+  // c0 needs only its extracted coefficients, all below 2^g.prune_bits
+  intt_core<LOGN, ELOG>(yhat + poly * N, v, lds, tid, c, tws.inv + (size_t)l * N, l,
+                        p == 0 ? g.prune_bits : (uint32_t)LOGN);
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
   if (p == 1) {
     uint32_t *dst = out.n ? (uint32_t *)out.c1[b] + ((size_t)o * g.L + l) * N : c1_out + (bo * g.L + l) * (size_t)N;
+    uint32_t *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
 #pragma unroll
-    for (int u = 0; u < E; ++u) dst[gidx<LOGN, ELOG, LO, EP>(tid, u)] = csub(v[u], q);
+    for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[u], q);
     return;
   }
   __syncthreads();

@@ -27,6 +27,8 @@ struct hc_layer {
   hc::ConvGeom geom{};
   uint32_t *d_w = nullptr;  // [c_out][w_cts][L][N], NTT domain
   size_t w_elems = 0;
+  hc_tuning tune{};         // per-layer launch shapes chosen by the autotuner ...
+  uint32_t tune_B = 0;      // ... for this batch size (0: none)
 };
 
 
@@ -40,6 +42,8 @@ struct Shapes {
   uint32_t fe, ie, bt, ct, rg, cg;
 };
 Shapes shapes_for(const hc_ctx &c, uint32_t B);
+// The layer's autotuned shapes when tuned for B images, else the context's.
+Shapes layer_shapes(const hc_layer *ly, uint32_t B);
 
 // Device workspace of one layer's conv for B images (X-hat, plus Y-hat when masked).
 size_t ws_bytes_for(const hc_layer *ly, uint32_t B, bool masked);

@@ -28,7 +28,7 @@ SYMBOLS = [
     "hc_batch_run_timed", "hc_ctx_set_tuning", "hc_ctx_get_tuning",
     "hc_server_create", "hc_server_add_net", "hc_server_request_bytes", "hc_server_submit", "hc_server_step",
     "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
-    "hc_server_destroy",
+    "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
 ]
 
 
@@ -106,6 +106,9 @@ def load(path: str = LIB_PATH):
         "hc_server_get_stats": (I, [P, P]),
         "hc_server_sync": (I, [P]),
         "hc_server_destroy": (None, [P]),
+        "hc_batch_autotune": (I, [P, P, P, P, P, P, ctypes.c_char_p]),
+        "hc_layer_get_tuning": (I, [P, P, P]),
+        "hc_layer_clear_tuning": (I, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -276,6 +279,16 @@ class Layer:
                                    _dptr(c0_ext, "c0_ext", d), _dptr(c1_out, "c1_out", d), B, _dptr(ws, "ws", d),
                                    ws.numel() * 4, _stream(stream)), "hc_conv_masked")
 
+    def tuning(self):
+        """(batch size, (fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups)) or (0, ...)."""
+        B = ctypes.c_uint32()
+        t = Tuning()
+        _check(_lib.hc_layer_get_tuning(self.h, ctypes.byref(B), ctypes.byref(t)), "hc_layer_get_tuning")
+        return B.value, (t.fwd_elog, t.inv_elog, t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups)
+
+    def clear_tuning(self):
+        _check(_lib.hc_layer_clear_tuning(self.h), "hc_layer_clear_tuning")
+
     # shapes of the device buffers for B images
     def in_shape(self, B):
         return (B, self.layout.in_cts, 2, self.ctx.L, self.ctx.N)
@@ -344,6 +357,12 @@ class Batch:
     def run_eager(self, ct_in, mask, c0, c1, stream=None):
         a = self._args(ct_in, mask, c0, c1)
         _check(_lib.hc_batch_run_eager(self.h, *a, _stream(stream)), "hc_batch_run_eager")
+
+    def autotune(self, ct_in, mask, c0, c1, cache_path=None, stream=None):
+        """Pick each layer's launch shapes by timing every candidate on these buffers."""
+        a = self._args(ct_in, mask, c0, c1)
+        cp = None if cache_path is None else str(cache_path).encode()
+        _check(_lib.hc_batch_autotune(self.h, *a, _stream(stream), cp), "hc_batch_autotune")
 
     def run_timed(self, ct_in, mask, c0, c1, stream=None):
         """Eager run with HIP events around every kernel; returns milliseconds

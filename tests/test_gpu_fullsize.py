@@ -122,3 +122,42 @@ def test_resnet18_224_large_ring_batch64_matches_oracle(hc):
     _check_net(ctx, specs, filters, ct_in, mask, c0, c1, (0, 37, B - 1), t, W.rng(8), npts=8)
     del ct_in, mask, c0, c1
     _free(bt, layers)
+
+
+def test_autotuner_keeps_results_and_caches(hc, tmp_path):
+    import torch
+    N, L, t, B = 8192, 3, 2 ** 20, 16
+    ctx = hc.Context(N, L, t)
+    specs = [s for s in W.resnet50_224() if s.name in ("s1.b0.c2", "s3.b1.c1", "s4.b0.c3")]
+    g = W.rng(5)
+    layers = [hc.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, W.gen_filters(g, s)) for s in specs]
+    tg = torch.Generator(device="cuda")
+    tg.manual_seed(5)
+    ct_in = [W.gen_ct_limbs_torch(tg, ly.in_shape(B)[:3], ctx.primes, N, "cuda") for ly in layers]
+    mask = [torch.randint(0, t, ly.mask_shape(B), generator=tg, device="cuda", dtype=torch.int32) for ly in layers]
+    outs = lambda: ([torch.zeros(ly.c0_shape(B), dtype=torch.int32, device="cuda") for ly in layers],
+                    [torch.zeros(ly.c1_shape(B), dtype=torch.int32, device="cuda") for ly in layers])
+    bt = hc.Batch(ctx, layers, B)
+    r0, r1 = outs()
+    bt.run(ct_in, mask, r0, r1)
+    cache = tmp_path / "tune.txt"
+    s0, s1 = outs()
+    print("autotune (timing)", flush=True)
+    bt.autotune(ct_in, mask, s0, s1, cache_path=cache)
+    tuned = [ly.tuning() for ly in layers]
+    assert all(tb == B and all(v > 0 for v in tv) for tb, tv in tuned), tuned
+    assert len(cache.read_text().strip().splitlines()) == len(layers)
+    a0, a1 = outs()
+    bt.run(ct_in, mask, a0, a1)  # graph re-recorded with the tuned shapes
+    torch.cuda.synchronize()
+    for k in range(len(layers)):
+        assert torch.equal(a0[k], r0[k]) and torch.equal(a1[k], r1[k]), k
+    for ly in layers:
+        ly.clear_tuning()
+        assert ly.tuning()[0] == 0
+    print("autotune (cache)", flush=True)
+    bt.autotune(ct_in, mask, s0, s1, cache_path=cache)
+    assert [ly.tuning() for ly in layers] == tuned
+    assert len(cache.read_text().strip().splitlines()) == len(layers)  # nothing re-timed
+    del ct_in, mask, r0, r1, s0, s1, a0, a1
+    _free(bt, layers)
