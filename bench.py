@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--stage-passes", type=int, default=3, help="eager passes timed per kernel for the roofline")
     ap.add_argument("--copy-gib", type=float, default=4.0, help="size of the HBM stream-copy calibration")
     ap.add_argument("--no-autotune", action="store_true", help="use the context's default launch shapes")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: layers found there are not re-timed, new results are appended")
     return ap.parse_args()
 
 
@@ -192,7 +194,7 @@ def main():
     tune_ms = None
     if not a.no_autotune:
         t1 = time.perf_counter()
-        bt.autotune(ct_in, mask, c0, c1)
+        bt.autotune(ct_in, mask, c0, c1, cache_path=a.tune_cache)
         tune_ms = (time.perf_counter() - t1) * 1e3
         print(f"[bench] autotuned {len(layers)} layers in {tune_ms:.0f} ms", file=sys.stderr, flush=True)
 
