@@ -101,37 +101,31 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
 
 // Inverse (Gentleman-Sande, bit-reversed -> natural) stages of one pass; the
 // last stage (s = 0) also multiplies by N^-1.
-// Pruning: when only outputs below 2^pb are wanted, every stage on a bit
-// b >= pb feeds wanted outputs from its lower (sum) half only - all wanted
-// indices have bits pb.. clear - so the difference half, with its twiddle
-// multiply, is skipped there. pb = LOGN computes the full transform.
-template <int LOGN, int ELOG, int LO, int EP>
+// Pruning: when only outputs below 2^(LOGN - PS) are wanted, every stage on a
+// bit b >= LOGN - PS feeds wanted outputs from its lower (sum) half only - all
+// wanted indices have those bits clear - so the difference half, with its
+// twiddle multiply, is skipped there. PS = 0 computes the full transform. PS
+// is a compile-time constant, so no stage carries a run-time branch.
+template <int LOGN, int ELOG, int LO, int EP, int PS>
 __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
                                          uint32_t q, uint32_t ninv, uint32_t ninvp, uint32_t ninvw,
-                                         uint32_t ninvwp, uint32_t pb) {
+                                         uint32_t ninvwp) {
   constexpr int E = 1 << ELOG;
   const uint32_t q2 = 2 * q;
 #pragma unroll
   for (int bb = 0; bb < EP; ++bb) {
     const int b = LO + bb;
     const int s = LOGN - 1 - b;
-    const bool sum_only = (uint32_t)b >= pb;  // uniform
+    const bool sum_only = b >= LOGN - PS;
     const uint2 *tws = tw + (1u << s) + (gidx<LOGN, ELOG, LO, EP>(tid, 0) >> (b + 1));
-    if (sum_only) {
-#pragma unroll
-      for (int u = 0; u < E; ++u) {
-        if (u & (1 << bb)) continue;
-        const int u2 = u | (1 << bb);
-        v[u] = s == 0 ? shoup_lazy(v[u] + v[u2], ninv, ninvp, q) : csub(v[u] + v[u2], q2);
-      }
-      continue;
-    }
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       if (u & (1 << bb)) continue;
       const int u2 = u | (1 << bb);
       const uint32_t X = v[u], Y = v[u2];
-      if (s == 0) {
+      if (sum_only) {
+        v[u] = s == 0 ? shoup_lazy(X + Y, ninv, ninvp, q) : csub(X + Y, q2);
+      } else if (s == 0) {
         v[u] = shoup_lazy(X + Y, ninv, ninvp, q);
         v[u2] = shoup_lazy(X - Y + q2, ninvw, ninvwp, q);
       } else {
@@ -180,28 +174,27 @@ struct FwdPasses<LOGN, ELOG, 0> {
   }
 };
 
-template <int LOGN, int ELOG, int K>
+template <int LOGN, int ELOG, int K, int PS>
 struct InvPasses {
   static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid,
                                              const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
-                                             uint32_t bp, uint32_t pb) {
+                                             uint32_t bp) {
     constexpr int LO = pass_lo_inv(LOGN, ELOG, K), EP = pass_bits(LOGN, ELOG, K);
     constexpr int PLO = pass_lo_inv(LOGN, ELOG, K - 1), PEP = pass_bits(LOGN, ELOG, K - 1);
-    InvPasses<LOGN, ELOG, K - 1>::run(v, lds, tid, tw, q, a, ap, b, bp, pb);
+    InvPasses<LOGN, ELOG, K - 1, PS>::run(v, lds, tid, tw, q, a, ap, b, bp);
     regs_to_lds<LOGN, ELOG, PLO, PEP>(v, lds, tid);
     __syncthreads();
     lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
-    inv_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q, a, ap, b, bp, pb);
+    inv_pass<LOGN, ELOG, LO, EP, PS>(v, tid, tw, q, a, ap, b, bp);
   }
 };
-template <int LOGN, int ELOG>
-struct InvPasses<LOGN, ELOG, 0> {
+template <int LOGN, int ELOG, int PS>
+struct InvPasses<LOGN, ELOG, 0, PS> {
   // pass 0 (bits [0, EP)) expects its inputs already in registers
   static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *, uint32_t tid, const uint2 *tw,
-                                             uint32_t q, uint32_t a, uint32_t ap, uint32_t b, uint32_t bp,
-                                             uint32_t pb) {
+                                             uint32_t q, uint32_t a, uint32_t ap, uint32_t b, uint32_t bp) {
     constexpr int LO = pass_lo_inv(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
-    inv_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q, a, ap, b, bp, pb);
+    inv_pass<LOGN, ELOG, LO, EP, PS>(v, tid, tw, q, a, ap, b, bp);
   }
 };
 
@@ -264,14 +257,13 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
 }
 
 // ---------------------------------------------------------------- inverse NTT kernels
-// pb: prune bit (see inv_pass); LOGN for the whole transform.
-template <int LOGN, int ELOG>
+// PS: top stages pruned (see inv_pass); 0 for the whole transform.
+template <int LOGN, int ELOG, int PS = 0>
 __device__ __forceinline__ void intt_core(const uint32_t *src, uint32_t (&v)[1 << ELOG], uint32_t *lds,
-                                          uint32_t tid, const LimbConsts &c, const uint2 *tw, uint32_t l,
-                                          uint32_t pb = LOGN) {
+                                          uint32_t tid, const LimbConsts &c, const uint2 *tw, uint32_t l) {
   constexpr int NP = n_pass(LOGN, ELOG);
   load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v, src, tid);
-  InvPasses<LOGN, ELOG, NP - 1>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l], c.ninvw_p[l], pb);
+  InvPasses<LOGN, ELOG, NP - 1, PS>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l], c.ninvw_p[l]);
 }
 
 // Full mode: [P][N] -> [P][N] canonical (in place allowed).
@@ -298,7 +290,9 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
 // output coefficients, which are gathered into c0_ext [B][c_out][L][ho][wo].
 // With pointer tables (out.n > 0) image b's mask, c0_ext and c1_out are
 // separate buffers (out.mask[b], out.c0[b], out.c1[b]) laid out as for B = 1.
-template <int LOGN, int ELOG>
+// PS: top stages of the c0 transform that are pruned (2^(LOGN - PS) must
+// exceed every extracted coefficient index); c1 is always transformed whole.
+template <int LOGN, int ELOG, int PS>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32_t *yhat, const uint32_t *mask,
                                                                      uint32_t *c0_ext, uint32_t *c1_out, ConvGeom g,
                                                                      LimbConsts c, Twiddles tws, OutPtrs out) {
@@ -313,17 +307,18 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
   const size_t b = bo / g.O;
   const uint32_t q = c.q[l];
   uint32_t v[E];
-  // c0 needs only its extracted coefficients, all below 2^g.prune_bits
-  intt_core<LOGN, ELOG>(yhat + poly * N, v, lds, tid, c, tws.inv + (size_t)l * N, l,
-                        p == 0 ? g.prune_bits : (uint32_t)LOGN);
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
+  const uint2 *tw = tws.inv + (size_t)l * N;
   if (p == 1) {
+    intt_core<LOGN, ELOG, 0>(yhat + poly * N, v, lds, tid, c, tw, l);
     uint32_t *dst = out.n ? (uint32_t *)out.c1[b] + ((size_t)o * g.L + l) * N : c1_out + (bo * g.L + l) * (size_t)N;
     uint32_t *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
 #pragma unroll
     for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[u], q);
     return;
   }
+  // c0 needs only its extracted coefficients
+  intt_core<LOGN, ELOG, PS>(yhat + poly * N, v, lds, tid, c, tw, l);
   __syncthreads();
   regs_to_lds<LOGN, ELOG, LO, EP>(v, lds, tid);
   __syncthreads();
@@ -575,14 +570,27 @@ static hipError_t inv_t(const uint32_t *in, uint32_t *out, size_t np, const Limb
                      tw);
   return hipGetLastError();
 }
+template <int LOGN, int ELOG, int PS>
+static hipError_t invm_ps(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
+                          uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
+  const size_t np = (size_t)B * g.O * 2 * g.L;
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG, PS>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, y, m, c0,
+                     c1, g, c, tw, out);
+  return hipGetLastError();
+}
+// Pruning fewer stages than allowed is always exact: take the largest
+// instantiated count not above LOGN - prune_bits.
 template <int LOGN, int ELOG>
 static hipError_t invm_t(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
                          uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
-  const size_t np = (size_t)B * g.O * 2 * g.L;
-  if (np == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, y, m, c0,
-                     c1, g, c, tw, out);
-  return hipGetLastError();
+  const int ps = LOGN - (int)g.prune_bits;
+  if (ps >= 7) return invm_ps<LOGN, ELOG, 7>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 5) return invm_ps<LOGN, ELOG, 5>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 3) return invm_ps<LOGN, ELOG, 3>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 2) return invm_ps<LOGN, ELOG, 2>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 1) return invm_ps<LOGN, ELOG, 1>(g, y, m, c0, c1, B, c, tw, out, st);
+  return invm_ps<LOGN, ELOG, 0>(g, y, m, c0, c1, B, c, tw, out, st);
 }
 
 // (LOGN, ELOG) instances: 2^(LOGN - ELOG) threads per polynomial.
