@@ -222,14 +222,15 @@ hc::Shapes hc::shapes_for(const hc_ctx &c, uint32_t B) {
   s.ie = c.tune.inv_elog ? c.tune.inv_elog : default_inv_elog(c.logn);
   if (c.tune.mac_rows) {
     s.bt = c.tune.mac_rows, s.ct = c.tune.mac_cols, s.rg = c.tune.mac_row_groups, s.cg = c.tune.mac_col_groups;
+    s.ns = c.tune.mac_depth ? c.tune.mac_depth : 2;
   } else if (B >= 16) {
-    s.bt = 4, s.ct = 8, s.rg = 4, s.cg = 2;
+    s.bt = 4, s.ct = 8, s.rg = 4, s.cg = 2, s.ns = 2;
   } else if (B >= 4) {
-    s.bt = 4, s.ct = 4, s.rg = 1, s.cg = 4;
+    s.bt = 4, s.ct = 4, s.rg = 1, s.cg = 4, s.ns = 2;
   } else if (B >= 2) {
-    s.bt = 2, s.ct = 4, s.rg = 1, s.cg = 4;
+    s.bt = 2, s.ct = 4, s.rg = 1, s.cg = 4, s.ns = 2;
   } else {
-    s.bt = 1, s.ct = 8, s.rg = 1, s.cg = 4;
+    s.bt = 1, s.ct = 8, s.rg = 1, s.cg = 4, s.ns = 2;
   }
   return s;
 }
@@ -240,7 +241,10 @@ hc::Shapes hc::layer_shapes(const hc_layer *ly, uint32_t B) {
     const hc_tuning &t = ly->tune;
     if (t.fwd_elog) s.fe = t.fwd_elog;
     if (t.inv_elog) s.ie = t.inv_elog;
-    if (t.mac_rows) s.bt = t.mac_rows, s.ct = t.mac_cols, s.rg = t.mac_row_groups, s.cg = t.mac_col_groups;
+    if (t.mac_rows) {
+      s.bt = t.mac_rows, s.ct = t.mac_cols, s.rg = t.mac_row_groups, s.cg = t.mac_col_groups;
+      s.ns = t.mac_depth ? t.mac_depth : 2;
+    }
   }
   return s;
 }
@@ -270,12 +274,12 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
   HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, ct_in, xhat, npin, c.consts, c.tw, st));
   if (timed) HC_HIP(hipEventRecord(tm->ev[1], st));
   if (!masked) {
-    HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, xhat, ly->d_w, ct_out, B, c.consts, st));
+    HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, sh.ns, xhat, ly->d_w, ct_out, B, c.consts, st));
     HC_HIP(hc::launch_intt_full(c.logn, sh.ie, ct_out, ct_out, (size_t)B * g.O * 2 * c.L, c.consts, c.tw, st));
   } else {
     uint32_t *yhat = xhat + npin * c.N;
     if (timed) HC_HIP(hipEventRecord(tm->ev[2], st));
-    HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, xhat, ly->d_w, yhat, B, c.consts, st));
+    HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, sh.ns, xhat, ly->d_w, yhat, B, c.consts, st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[3], st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[4], st));
     HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, yhat, mask, c0_ext, c1_out, B, c.consts, c.tw, st));
@@ -316,7 +320,7 @@ hc_status hc::enqueue_conv_gather(const hc_layer *ly, uint32_t B, const uint32_t
   const size_t npin = (size_t)B * ppi;
   HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, nullptr, xhat, npin, c.consts, c.tw, st, &in, ppi));
   uint32_t *yhat = xhat + npin * c.N;
-  HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, xhat, ly->d_w, yhat, B, c.consts, st));
+  HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, sh.ns, xhat, ly->d_w, yhat, B, c.consts, st));
   HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, yhat, nullptr, nullptr, nullptr, B, c.consts, c.tw, st, &out));
   return HC_OK;
 }
@@ -427,8 +431,10 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
     const u128 base = ((u128)1 << 32) * k.r2[l] + ((u128)1 << 32);
     const u128 term = (u128)(q - 1) * (q - 1);
     u128 n_terms = (lim - base) / term;
-    k.fold[l] = (uint32_t)std::min<u128>(n_terms, 64) & ~1u;  // even: the MAC consumes ciphertexts in pairs
-    if (k.fold[l] < 2) {
+    // a multiple of 4: the MAC's register ring (2 or 4 deep) turns a whole
+    // number of times per fold
+    k.fold[l] = (uint32_t)std::min<u128>(n_terms, 64) & ~3u;
+    if (k.fold[l] < 4) {
       delete c;
       return fail(HC_EINVAL, "prime too large for 64-bit accumulation");
     }
@@ -474,10 +480,11 @@ hc_status hc_ctx_set_tuning(hc_ctx *c, const hc_tuning *t) {
     return fail(HC_EUNSUPPORTED, "forward NTT shape not available for this N");
   if (t->inv_elog && !hc::ntt_variant_ok(c->logn, t->inv_elog))
     return fail(HC_EUNSUPPORTED, "inverse NTT shape not available for this N");
-  const bool any = t->mac_rows || t->mac_cols || t->mac_row_groups || t->mac_col_groups;
+  const bool any = t->mac_rows || t->mac_cols || t->mac_row_groups || t->mac_col_groups || t->mac_depth;
   const bool all = t->mac_rows && t->mac_cols && t->mac_row_groups && t->mac_col_groups;
   if (any && !all) return fail(HC_EINVAL, "set all four MAC fields or none");
-  if (all && !hc::mac_variant_ok(t->mac_rows, t->mac_cols, t->mac_row_groups, t->mac_col_groups))
+  if (all && !hc::mac_variant_ok(t->mac_rows, t->mac_cols, t->mac_row_groups, t->mac_col_groups,
+                                 t->mac_depth ? t->mac_depth : 2))
     return fail(HC_EUNSUPPORTED, "MAC tile not available");
   c->tune = *t;
   return HC_OK;
@@ -710,6 +717,7 @@ hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_cols);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_row_groups);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_col_groups);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_depth);
   for (size_t k = 0; k < n; ++k) {
     key.push_back(ct_in[k]);
     key.push_back(mask[k]);
@@ -812,9 +820,12 @@ hc_status time_it(F fn, hipStream_t st, int reps, float *ms) {
   return HC_OK;
 }
 
-const uint32_t kMacCand[][4] = {{1, 8, 1, 4}, {1, 4, 1, 4}, {2, 4, 1, 4}, {4, 4, 1, 4}, {4, 2, 1, 4},
-                                {8, 2, 1, 4}, {16, 2, 1, 4}, {4, 4, 4, 2}, {4, 8, 4, 2}, {2, 8, 4, 2},
-                                {4, 4, 2, 4}, {8, 4, 2, 2}, {2, 4, 4, 4}, {1, 8, 2, 4}};
+// (images, channels per thread; image, channel wave groups; register ring depth)
+const uint32_t kMacCand[][5] = {{1, 8, 1, 4, 2}, {1, 4, 1, 4, 2}, {2, 4, 1, 4, 2}, {4, 4, 1, 4, 2},
+                                {4, 2, 1, 4, 2}, {8, 2, 1, 4, 2}, {16, 2, 1, 4, 2}, {4, 4, 4, 2, 2},
+                                {4, 8, 4, 2, 2}, {2, 8, 4, 2, 2}, {4, 4, 2, 4, 2}, {8, 4, 2, 2, 2},
+                                {2, 4, 4, 4, 2}, {1, 8, 2, 4, 2}, {4, 8, 4, 2, 4}, {2, 8, 4, 2, 4},
+                                {4, 4, 4, 2, 4}, {4, 4, 2, 4, 4}, {1, 8, 2, 4, 4}, {2, 4, 4, 4, 4}};
 
 }  // namespace
 
@@ -839,8 +850,8 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
         if (!bar) continue;
         *bar = 0;
         hc_tuning t{};
-        if (std::sscanf(bar + 1, "%u %u %u %u %u %u", &t.fwd_elog, &t.inv_elog, &t.mac_rows, &t.mac_cols,
-                        &t.mac_row_groups, &t.mac_col_groups) == 6)
+        if (std::sscanf(bar + 1, "%u %u %u %u %u %u %u", &t.fwd_elog, &t.inv_elog, &t.mac_rows, &t.mac_cols,
+                        &t.mac_row_groups, &t.mac_col_groups, &t.mac_depth) >= 6)
           cache[line] = t;
       }
       std::fclose(f);
@@ -858,7 +869,8 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     if (hit != cache.end()) {
       const hc_tuning &t = hit->second;
       if (hc::ntt_variant_ok(c.logn, t.fwd_elog) && hc::ntt_variant_ok(c.logn, t.inv_elog) &&
-          hc::mac_variant_ok(t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups) &&
+          hc::mac_variant_ok(t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups,
+                             t.mac_depth ? t.mac_depth : 2) &&
           hc::mac_offsets_fit(ly->geom, t.mac_rows, t.mac_cols)) {
         ly->tune = t;
         ly->tune_B = B;
@@ -881,14 +893,17 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     }
     best_ms = 1e30f;
     for (const auto &m : kMacCand) {
-      if (!hc::mac_variant_ok(m[0], m[1], m[2], m[3]) || !hc::mac_offsets_fit(g, m[0], m[1])) continue;
+      if (!hc::mac_variant_ok(m[0], m[1], m[2], m[3], m[4]) || !hc::mac_offsets_fit(g, m[0], m[1])) continue;
       float ms;
-      s = time_it([&] { return hc::launch_mac(g, m[0], m[1], m[2], m[3], xhat, ly->d_w, yhat, B, c.consts, st); },
+      s = time_it([&] {
+        return hc::launch_mac(g, m[0], m[1], m[2], m[3], m[4], xhat, ly->d_w, yhat, B, c.consts, st);
+      },
                   st, reps, &ms);
       if (s != HC_OK) return s;
       if (ms < best_ms) {
         best_ms = ms;
         best.mac_rows = m[0], best.mac_cols = m[1], best.mac_row_groups = m[2], best.mac_col_groups = m[3];
+        best.mac_depth = m[4];
       }
     }
     best_ms = 1e30f;
@@ -903,9 +918,9 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     }
     ly->tune = best;
     ly->tune_B = B;
-    char buf[96];
-    std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog, best.mac_rows,
-                  best.mac_cols, best.mac_row_groups, best.mac_col_groups);
+    char buf[112];
+    std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog, best.mac_rows,
+                  best.mac_cols, best.mac_row_groups, best.mac_col_groups, best.mac_depth);
     appended += key + buf;
   }
   if (cache_path && !appended.empty()) {

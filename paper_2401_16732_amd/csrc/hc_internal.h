@@ -60,7 +60,7 @@ struct OutPtrs {
 // the MAC gives each thread bt images x ct output channels, and a workgroup
 // rg x cg such threads per coefficient (image groups x channel groups).
 bool ntt_variant_ok(uint32_t logn, uint32_t elog);
-bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg);
+bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, uint32_t ns);
 // The MAC addresses one image tile and one channel tile with 32-bit byte offsets.
 bool mac_offsets_fit(const ConvGeom &g, uint32_t bt, uint32_t ct);
 
@@ -78,7 +78,8 @@ hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, ui
 hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, const uint32_t *yhat,
                               const uint32_t *mask, uint32_t *c0_ext, uint32_t *c1_out, uint32_t B,
                               const LimbConsts &c, const Twiddles &tw, hipStream_t st, const OutPtrs *tab = nullptr);
-hipError_t launch_mac(const ConvGeom &g, uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, const uint32_t *xhat,
+hipError_t launch_mac(const ConvGeom &g, uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, uint32_t ns,
+                      const uint32_t *xhat,
                       const uint32_t *what, uint32_t *yhat, uint32_t B, const LimbConsts &c, hipStream_t st);
 hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *filters, uint32_t *w, const LimbConsts &c,
                                  hipStream_t st);

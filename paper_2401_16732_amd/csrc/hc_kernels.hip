@@ -352,9 +352,10 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
 // waves over the same 64 coefficients: RG groups of images times CG groups of
 // output channels. Waves of one channel group read the same weights and
 // waves of one image group the same inputs, which L1 then serves once.
-// Loads of the next input ciphertext are issued before the current one's
-// multiply-accumulates.
-template <int BT, int CT, int RG, int CG>
+// NS register sets form a ring: the loads of input ciphertext gw + NS are
+// issued right after gw's multiply-accumulates, so NS - 1 ciphertexts are in
+// flight while one is being multiplied.
+template <int BT, int CT, int RG, int CG, int NS>
 __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__restrict__ X,
                                                             const uint32_t *__restrict__ Wt,
                                                             uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
@@ -380,21 +381,24 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
   const uint32_t nc = min((uint32_t)CT, g.c_out - i0);
   const uint32_t nb = min((uint32_t)BT, B - b0);
   const uint32_t LN = g.L * g.N;
-  // Scalar bases advance by one input ciphertext per step; per-thread offsets
-  // (32-bit, fixed for the whole loop) select image, polynomial and channel.
-  const uint32_t *xbase = X + ((size_t)b0 * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64;
-  const uint32_t *wbase = Wt + (size_t)i0 * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64;
-  const size_t xstep = (size_t)2 * LN * g.T, wstep = LN;
-  // byte offsets; the host guarantees BT*G*2*L*N*4 and CT*G_w*L*N*4 < 2^32
+  // Scalar bases advance by one input ciphertext per step; each (image,
+  // polynomial) and each channel adds a wave-uniform byte offset (32-bit;
+  // the host guarantees BT*G*2*L*N*4 and CT*G_w*L*N*4 < 2^32), and every
+  // lane the same 4 * lane.
+  const char *xbase = (const char *)(X + ((size_t)b0 * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const char *wbase = (const char *)(Wt + (size_t)i0 * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
+  const uint32_t lane4 = lane * 4u;
   uint32_t xo[BT][2], wo[CT];
 #pragma unroll
   for (int bb = 0; bb < BT; ++bb) {
     const uint32_t b = (uint32_t)bb < nb ? (uint32_t)bb : 0u;  // clamp: loads of absent images are discarded
-    xo[bb][0] = (b * g.G * 2 * LN + lane) * 4u;
-    xo[bb][1] = xo[bb][0] + LN * 4u;
+    xo[bb][0] = __builtin_amdgcn_readfirstlane(b * g.G * 2 * LN * 4u);
+    xo[bb][1] = __builtin_amdgcn_readfirstlane(xo[bb][0] + LN * 4u);
   }
 #pragma unroll
-  for (int cc = 0; cc < CT; ++cc) wo[cc] = (((uint32_t)cc < nc ? (uint32_t)cc : 0u) * g.G_w * LN + lane) * 4u;
+  for (int cc = 0; cc < CT; ++cc)
+    wo[cc] = __builtin_amdgcn_readfirstlane(((uint32_t)cc < nc ? (uint32_t)cc : 0u) * g.G_w * LN * 4u);
   const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
   uint64_t acc[CT][BT][2];
 #pragma unroll
@@ -403,13 +407,13 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
     for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
   const uint32_t G_w = g.G_w;
   auto load = [&](uint32_t gw, uint32_t (&w)[CT], uint32_t (&x)[BT][2]) {
-    const char *xb = (const char *)(xbase + gw * xstep), *wb = (const char *)(wbase + gw * wstep);
+    const char *xb = xbase + gw * xstep, *wb = wbase + gw * wstep;
 #pragma unroll
-    for (int cc = 0; cc < CT; ++cc) w[cc] = *(const uint32_t *)(wb + wo[cc]);
+    for (int cc = 0; cc < CT; ++cc) w[cc] = *(const uint32_t *)(wb + wo[cc] + lane4);
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb) {
-      x[bb][0] = *(const uint32_t *)(xb + xo[bb][0]);
-      x[bb][1] = *(const uint32_t *)(xb + xo[bb][1]);
+      x[bb][0] = *(const uint32_t *)(xb + xo[bb][0] + lane4);
+      x[bb][1] = *(const uint32_t *)(xb + xo[bb][1] + lane4);
     }
   };
   auto mac = [&](const uint32_t (&w)[CT], const uint32_t (&x)[BT][2]) {
@@ -421,33 +425,32 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
         acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
       }
   };
-  // Two register sets A and B alternate: while one set is multiplied, the
-  // other's loads (two input ciphertexts ahead) are in flight. The loop body
-  // has no branches, so the compiler keeps that order: loads past the end
-  // re-read the last ciphertext, and the odd tail's second set gets zero
-  // weights. Folding is exact mod q, so it runs after every chunk.
-  uint32_t wa[CT], xa[BT][2], wb2[CT], xb2[BT][2];
+  // The loop body has no branches, so the compiler keeps the ring's order:
+  // loads past the end re-read the last ciphertext, and sets past the end of
+  // the last chunk get zero weights. fold is a multiple of NS, so only the
+  // last chunk can end inside a ring turn. Folding is exact mod q.
+  uint32_t ws[NS][CT], xs[NS][BT][2];
   const uint32_t last = G_w - 1;
-  load(0, wa, xa);
-  load(min(1u, last), wb2, xb2);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) load(min((uint32_t)j, last), ws[j], xs[j]);
   for (uint32_t base = 0; base < G_w; base += fold) {
     const uint32_t end = min(G_w, base + fold);
-    for (uint32_t gw = base; gw < end; gw += 2) {
-      // sched_barrier keeps each group in place: set A's loads must all be
-      // issued before set B's, so that waiting for A never waits for B
-      mac(wa, xa);
-      __builtin_amdgcn_sched_barrier(0);
-      load(min(gw + 2, last), wa, xa);
-      __builtin_amdgcn_sched_barrier(0);
-      const bool tail = gw + 1 >= end;
+    for (uint32_t gw = base; gw < end; gw += NS) {
 #pragma unroll
-      for (int cc = 0; cc < CT; ++cc) wb2[cc] = tail ? 0u : wb2[cc];
-      mac(wb2, xb2);
-      __builtin_amdgcn_sched_barrier(0);
-      // on a tail the zeroed set held ciphertext end, which the next chunk
-      // still needs: reload it instead of gw + 3
-      load(min(tail ? gw + 1 : gw + 3, last), wb2, xb2);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int j = 0; j < NS; ++j) {
+        // sched_barrier keeps each group in place: a set's loads are all
+        // issued before the next set's, so waiting for one never waits for
+        // a later one
+        if (j > 0) {
+          const bool tail = gw + j >= end;
+#pragma unroll
+          for (int cc = 0; cc < CT; ++cc) ws[j][cc] = tail ? 0u : ws[j][cc];
+        }
+        mac(ws[j], xs[j]);
+        __builtin_amdgcn_sched_barrier(0);
+        load(min(gw + NS + j, last), ws[j], xs[j]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
 #pragma unroll
     for (int cc = 0; cc < CT; ++cc)
@@ -635,7 +638,7 @@ hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, c
   HC_NTT_DISPATCH(invm_t, g, y, m, c0, c1, B, c, tw, t, st)
 }
 
-template <int BT, int CT, int RG, int CG>
+template <int BT, int CT, int RG, int CG, int NS>
 static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
                         const LimbConsts &c, hipStream_t st) {
   if (!mac_offsets_fit(g, BT, CT)) return hipErrorInvalidValue;
@@ -644,7 +647,7 @@ static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w,
   const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
   const size_t nwg = (size_t)nib * g.T * nkb * g.L * nbt;
   if (nwg == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_mac_tiled<BT, CT, RG, CG>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y, g, B,
+  hipLaunchKernelGGL((k_mac_tiled<BT, CT, RG, CG, NS>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y, g, B,
                      nib, nkb, c);
   return hipGetLastError();
 }
@@ -654,23 +657,26 @@ bool mac_offsets_fit(const ConvGeom &g, uint32_t bt, uint32_t ct) {
   return (uint64_t)bt * g.G * 2 * ln < (1ull << 32) && (uint64_t)ct * g.G_w * ln < (1ull << 32);
 }
 
-// (images per thread, channels per thread, image groups, channel groups)
-#define HC_MAC_VARIANTS(X)                                                                              \
-  X(1, 8, 1, 4) X(1, 4, 1, 4) X(2, 4, 1, 4) X(4, 4, 1, 4) X(4, 2, 1, 4) X(8, 2, 1, 4) X(16, 2, 1, 4)   \
-  X(4, 4, 4, 2) X(4, 8, 4, 2) X(2, 8, 4, 2) X(4, 4, 2, 4) X(8, 4, 2, 2) X(2, 4, 4, 4) X(1, 8, 2, 4)
+// (images per thread, channels per thread, image groups, channel groups, ring depth)
+#define HC_MAC_VARIANTS(X)                                                                                    \
+  X(1, 8, 1, 4, 2) X(1, 4, 1, 4, 2) X(2, 4, 1, 4, 2) X(4, 4, 1, 4, 2) X(4, 2, 1, 4, 2) X(8, 2, 1, 4, 2)       \
+  X(16, 2, 1, 4, 2) X(4, 4, 4, 2, 2) X(4, 8, 4, 2, 2) X(2, 8, 4, 2, 2) X(4, 4, 2, 4, 2) X(8, 4, 2, 2, 2)     \
+  X(2, 4, 4, 4, 2) X(1, 8, 2, 4, 2) X(4, 8, 4, 2, 4) X(2, 8, 4, 2, 4) X(4, 4, 4, 2, 4) X(4, 4, 2, 4, 4)     \
+  X(1, 8, 2, 4, 4) X(2, 4, 4, 4, 4)
 
-bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg) {
-#define HC_MAC_OK(B_, C_, R_, G_) \
-  if (bt == B_ && ct == C_ && rg == R_ && cg == G_) return true;
+bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, uint32_t ns) {
+#define HC_MAC_OK(B_, C_, R_, G_, S_) \
+  if (bt == B_ && ct == C_ && rg == R_ && cg == G_ && ns == S_) return true;
   HC_MAC_VARIANTS(HC_MAC_OK)
 #undef HC_MAC_OK
   return false;
 }
 
-hipError_t launch_mac(const ConvGeom &g, uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, const uint32_t *x,
-                      const uint32_t *w, uint32_t *y, uint32_t B, const LimbConsts &c, hipStream_t st) {
-#define HC_MAC_CASE(B_, C_, R_, G_) \
-  if (bt == B_ && ct == C_ && rg == R_ && cg == G_) return mac_t<B_, C_, R_, G_>(g, x, w, y, B, c, st);
+hipError_t launch_mac(const ConvGeom &g, uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, uint32_t ns,
+                      const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B, const LimbConsts &c,
+                      hipStream_t st) {
+#define HC_MAC_CASE(B_, C_, R_, G_, S_) \
+  if (bt == B_ && ct == C_ && rg == R_ && cg == G_ && ns == S_) return mac_t<B_, C_, R_, G_, S_>(g, x, w, y, B, c, st);
   HC_MAC_VARIANTS(HC_MAC_CASE)
 #undef HC_MAC_CASE
   return hipErrorInvalidValue;

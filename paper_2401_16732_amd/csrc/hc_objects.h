@@ -39,7 +39,7 @@ hc_status hip_fail(hipError_t e, const char *where);
 
 // Launch shapes in effect for B images.
 struct Shapes {
-  uint32_t fe, ie, bt, ct, rg, cg;
+  uint32_t fe, ie, bt, ct, rg, cg, ns;
 };
 Shapes shapes_for(const hc_ctx &c, uint32_t B);
 // The layer's autotuned shapes when tuned for B images, else the context's.

@@ -44,7 +44,10 @@ class ConvShape(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("fwd_elog", "inv_elog", "mac_rows", "mac_cols", "mac_row_groups",
-                                               "mac_col_groups")]
+                                               "mac_col_groups", "mac_depth")]
+
+    def as_tuple(self):
+        return tuple(getattr(self, k) for k, _ in self._fields_)
 
 
 class Layout(ctypes.Structure):
@@ -198,14 +201,15 @@ class Context:
     def sync(self):
         _check(_lib.hc_sync(self.h), "hc_sync")
 
-    def set_tuning(self, fwd_elog=0, inv_elog=0, mac_rows=0, mac_cols=0, mac_row_groups=0, mac_col_groups=0):
-        t = Tuning(fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups)
+    def set_tuning(self, fwd_elog=0, inv_elog=0, mac_rows=0, mac_cols=0, mac_row_groups=0, mac_col_groups=0,
+                   mac_depth=0):
+        t = Tuning(fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups, mac_depth)
         _check(_lib.hc_ctx_set_tuning(self.h, ctypes.byref(t)), "hc_ctx_set_tuning")
 
     def get_tuning(self):
         t = Tuning()
         _check(_lib.hc_ctx_get_tuning(self.h, ctypes.byref(t)), "hc_ctx_get_tuning")
-        return (t.fwd_elog, t.inv_elog, t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups)
+        return t.as_tuple()
 
     def close(self):
         if getattr(self, "h", None):
@@ -280,11 +284,12 @@ class Layer:
                                    ws.numel() * 4, _stream(stream)), "hc_conv_masked")
 
     def tuning(self):
-        """(batch size, (fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups)) or (0, ...)."""
+        """(batch size, (fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups, mac_depth))
+        or (0, ...)."""
         B = ctypes.c_uint32()
         t = Tuning()
         _check(_lib.hc_layer_get_tuning(self.h, ctypes.byref(B), ctypes.byref(t)), "hc_layer_get_tuning")
-        return B.value, (t.fwd_elog, t.inv_elog, t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups)
+        return B.value, t.as_tuple()
 
     def clear_tuning(self):
         _check(_lib.hc_layer_clear_tuning(self.h), "hc_layer_clear_tuning")

@@ -179,8 +179,11 @@ def test_error_paths(hc):
     ly.conv(zeros((1,)), zeros((1,)), 0, zeros((1,)))
 
 
-MAC_VARIANTS = [(1, 8, 1, 4), (1, 4, 1, 4), (2, 4, 1, 4), (4, 4, 1, 4), (4, 2, 1, 4), (8, 2, 1, 4), (16, 2, 1, 4),
-                (4, 4, 4, 2), (4, 8, 4, 2), (2, 8, 4, 2), (4, 4, 2, 4), (8, 4, 2, 2), (2, 4, 4, 4), (1, 8, 2, 4)]
+# (images, channels per thread, image groups, channel groups, register ring depth)
+MAC_VARIANTS = [(1, 8, 1, 4, 2), (1, 4, 1, 4, 2), (2, 4, 1, 4, 2), (4, 4, 1, 4, 2), (4, 2, 1, 4, 2),
+                (8, 2, 1, 4, 2), (16, 2, 1, 4, 2), (4, 4, 4, 2, 2), (4, 8, 4, 2, 2), (2, 8, 4, 2, 2),
+                (4, 4, 2, 4, 2), (8, 4, 2, 2, 2), (2, 4, 4, 4, 2), (1, 8, 2, 4, 2), (4, 8, 4, 2, 4),
+                (2, 8, 4, 2, 4), (4, 4, 4, 2, 4), (4, 4, 2, 4, 4), (1, 8, 2, 4, 4), (2, 4, 4, 4, 4)]
 
 
 @pytest.mark.parametrize("N,elogs", [(8192, (3, 4, 5)), (16384, (4, 5)), (4096, (3, 4, 5)), (1024, (3, 4))])
@@ -213,3 +216,34 @@ def test_every_launch_shape_gives_the_same_bits(hc, N, elogs):
         c.set_tuning(0, 0, 3, 3, 1, 1)
     with pytest.raises(hc.HcError):
         c.set_tuning(0, 0, 4, 4, 0, 0)
+    with pytest.raises(hc.HcError):  # ring depth 3 does not exist
+        c.set_tuning(0, 0, 4, 8, 4, 2, 3)
+    with pytest.raises(hc.HcError):  # a depth alone is not a tile
+        c.set_tuning(0, 0, 0, 0, 0, 0, 4)
+
+
+def test_mac_ring_over_many_input_ciphertexts(hc):
+    """37 input ciphertexts per output (one channel per ciphertext at N = 1024):
+    more than two accumulator folds and a ring turn cut short by the end, for
+    every MAC tile and ring depth, against the oracle."""
+    N, L, t, B = 1024, 2, 2 ** 17, 5
+    c = _ctx(hc, N, L, t)
+    spec = W.ConvSpec(37, 9, 28, 28, 3, 1)
+    P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+    assert P.G == 37 and not P.tiled
+    g = W.rng(37)
+    f = W.gen_filters(g, spec)
+    x = W.gen_ct_limbs(g, (B, P.G, 2), c.primes, N)
+    r = W.gen_mask(g, (B, spec.c_o, P.ho, P.wo), t)
+    ly = hc.Layer(c, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride, f)
+    exp = [conv.mask_extract(calg1.alg1_layer(x[b], f, P, c.primes), r[b], P, c.primes, t) for b in range(B)]
+    dx, dr = dev(x), dev(r)
+    ws = zeros((ly.workspace_words(B, True),))
+    for v in MAC_VARIANTS:
+        print(f"mac {v}", flush=True)
+        c.set_tuning(0, 0, *v)
+        c0, c1 = zeros(ly.c0_shape(B)), zeros(ly.c1_shape(B))
+        ly.conv_masked(dx, dr, c0, c1, B, ws)
+        c0, c1 = host(c0), host(c1)
+        for b in range(B):
+            assert (c0[b] == exp[b][0]).all() and (c1[b] == exp[b][1]).all(), (v, b)
