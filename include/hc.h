@@ -108,7 +108,7 @@ typedef struct {
     uint32_t mac_row_groups;  /* waves per workgroup along images */
     uint32_t mac_col_groups;  /* waves per workgroup along output channels */
     uint32_t mac_depth;       /* input ciphertexts whose loads are in flight per thread (register
-                                 ring depth, 2 or 4; 0 = 2) */
+                                 ring depth, 2..4 as the tile allows; 0 = 2) */
 } hc_tuning;
 
 /* Create a context on HIP device `hip_device`: ring degree N (power of two,

@@ -431,8 +431,8 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
     const u128 base = ((u128)1 << 32) * k.r2[l] + ((u128)1 << 32);
     const u128 term = (u128)(q - 1) * (q - 1);
     u128 n_terms = (lim - base) / term;
-    // a multiple of 4: the MAC's register ring (2 or 4 deep) turns a whole
-    // number of times per fold
+    // at least 8 (n_terms >= 11 for q < 2^30), so the MAC's register ring
+    // (2..4 ciphertexts deep) completes at least two turns between folds
     k.fold[l] = (uint32_t)std::min<u128>(n_terms, 64) & ~3u;
     if (k.fold[l] < 4) {
       delete c;
@@ -822,10 +822,10 @@ hc_status time_it(F fn, hipStream_t st, int reps, float *ms) {
 
 // (images, channels per thread; image, channel wave groups; register ring depth)
 const uint32_t kMacCand[][5] = {{1, 8, 1, 4, 2}, {1, 4, 1, 4, 2}, {2, 4, 1, 4, 2}, {4, 4, 1, 4, 2},
-                                {4, 2, 1, 4, 2}, {8, 2, 1, 4, 2}, {16, 2, 1, 4, 2}, {4, 4, 4, 2, 2},
-                                {4, 8, 4, 2, 2}, {2, 8, 4, 2, 2}, {4, 4, 2, 4, 2}, {8, 4, 2, 2, 2},
-                                {2, 4, 4, 4, 2}, {1, 8, 2, 4, 2}, {4, 8, 4, 2, 4}, {2, 8, 4, 2, 4},
-                                {4, 4, 4, 2, 4}, {4, 4, 2, 4, 4}, {1, 8, 2, 4, 4}, {2, 4, 4, 4, 4}};
+                                {4, 2, 1, 4, 2}, {8, 2, 1, 4, 2}, {4, 4, 4, 2, 2}, {4, 8, 4, 2, 2},
+                                {2, 8, 4, 2, 2}, {4, 4, 2, 4, 2}, {2, 4, 4, 4, 2}, {1, 8, 2, 4, 2},
+                                {4, 8, 4, 2, 3}, {2, 8, 4, 2, 4}, {4, 4, 4, 2, 4}, {4, 4, 2, 4, 4},
+                                {1, 8, 2, 4, 4}, {2, 4, 4, 4, 4}, {1, 8, 1, 4, 4}};
 
 }  // namespace
 

@@ -16,6 +16,10 @@
 
 namespace hc {
 
+// Third word of a gfx9-family raw buffer descriptor (32-bit data, no swizzle,
+// no stride), as used for gfx908/90a/94x/950.
+constexpr uint32_t kBufferWord3 = 0x00020000u;
+
 // ---------------------------------------------------------------- arithmetic
 __device__ __forceinline__ uint32_t shoup_lazy(uint32_t a, uint32_t w, uint32_t wp, uint32_t q) {
   uint32_t Q = __umulhi(a, wp);
@@ -360,6 +364,7 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
                                                             const uint32_t *__restrict__ Wt,
                                                             uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
                                                             uint32_t nib, uint32_t nkb, LimbConsts c) {
+  static_assert(NS >= 2 && NS * (CT + 2 * BT) <= 63, "loads in flight beyond the vector memory counter");
   const uint32_t nwg = gridDim.x;
   uint32_t wg = blockIdx.x;
   if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
@@ -406,14 +411,20 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
   const uint32_t G_w = g.G_w;
+  // Raw buffer loads: the step's base in the descriptor, the uniform offset
+  // in soffset, the lane's in voffset - no vector address arithmetic. Every
+  // access is in bounds by construction; num_records is the maximum.
   auto load = [&](uint32_t gw, uint32_t (&w)[CT], uint32_t (&x)[BT][2]) {
-    const char *xb = xbase + gw * xstep, *wb = wbase + gw * wstep;
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(xbase + gw * xstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+    const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(wbase + gw * wstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
 #pragma unroll
-    for (int cc = 0; cc < CT; ++cc) w[cc] = *(const uint32_t *)(wb + wo[cc] + lane4);
+    for (int cc = 0; cc < CT; ++cc) w[cc] = __builtin_amdgcn_raw_buffer_load_b32(wr, lane4, wo[cc], 0);
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb) {
-      x[bb][0] = *(const uint32_t *)(xb + xo[bb][0] + lane4);
-      x[bb][1] = *(const uint32_t *)(xb + xo[bb][1] + lane4);
+      x[bb][0] = __builtin_amdgcn_raw_buffer_load_b32(xr, lane4, xo[bb][0], 0);
+      x[bb][1] = __builtin_amdgcn_raw_buffer_load_b32(xr, lane4, xo[bb][1], 0);
     }
   };
   auto mac = [&](const uint32_t (&w)[CT], const uint32_t (&x)[BT][2]) {
@@ -425,40 +436,55 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
         acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
       }
   };
-  // The loop body has no branches, so the compiler keeps the ring's order:
-  // loads past the end re-read the last ciphertext, and sets past the end of
-  // the last chunk get zero weights. fold is a multiple of NS, so only the
-  // last chunk can end inside a ring turn. Folding is exact mod q.
+  // One loop over ring turns. Its body has no data-dependent branches, so the
+  // compiler keeps the ring's order: loads past the end re-read the last
+  // ciphertext, and sets past the end get zero weights. Every fold / NS turns
+  // (at most fold terms) the accumulators are folded, exactly mod q; that
+  // branch is uniform and does no loads, so both of its paths leave the same
+  // loads in flight. The last partial chunk needs no fold: reduce64 takes any
+  // 64-bit value. NS * (CT + 2 BT) loads in flight must stay within the
+  // 63 that the vector memory counter can track.
   uint32_t ws[NS][CT], xs[NS][BT][2];
   const uint32_t last = G_w - 1;
+  const uint32_t turns_per_fold = fold / NS;
+  // the prologue issues the sets in ring order too: the loop's first wait
+  // is computed from the order on entry as well as around the loop
 #pragma unroll
-  for (int j = 0; j < NS; ++j) load(min((uint32_t)j, last), ws[j], xs[j]);
-  for (uint32_t base = 0; base < G_w; base += fold) {
-    const uint32_t end = min(G_w, base + fold);
-    for (uint32_t gw = base; gw < end; gw += NS) {
+  for (int j = 0; j < NS; ++j) {
+    asm volatile("" ::: "memory");
+    load(min((uint32_t)j, last), ws[j], xs[j]);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  uint32_t turn = 0;
+  for (uint32_t gw = 0; gw < G_w; gw += NS) {
 #pragma unroll
-      for (int j = 0; j < NS; ++j) {
-        // sched_barrier keeps each group in place: a set's loads are all
-        // issued before the next set's, so waiting for one never waits for
-        // a later one
-        if (j > 0) {
-          const bool tail = gw + j >= end;
+    for (int j = 0; j < NS; ++j) {
+      // sched_barrier keeps each group in place: a set's loads are all
+      // issued before the next set's, so waiting for one never waits for
+      // a later one
+      if (j > 0) {
+        const bool tail = gw + j >= G_w;
 #pragma unroll
-          for (int cc = 0; cc < CT; ++cc) ws[j][cc] = tail ? 0u : ws[j][cc];
-        }
-        mac(ws[j], xs[j]);
-        __builtin_amdgcn_sched_barrier(0);
-        load(min(gw + NS + j, last), ws[j], xs[j]);
-        __builtin_amdgcn_sched_barrier(0);
+        for (int cc = 0; cc < CT; ++cc) ws[j][cc] = tail ? 0u : ws[j][cc];
       }
+      mac(ws[j], xs[j]);
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("" ::: "memory");  // compiler-only barrier: loads stay in this slot
+      load(min(gw + NS + j, last), ws[j], xs[j]);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (++turn == turns_per_fold) {
+      turn = 0;
 #pragma unroll
-    for (int cc = 0; cc < CT; ++cc)
+      for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-      for (int bb = 0; bb < BT; ++bb)
+        for (int bb = 0; bb < BT; ++bb)
 #pragma unroll
-        for (int pp = 0; pp < 2; ++pp)
-          acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+          for (int pp = 0; pp < 2; ++pp)
+            acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+    }
   }
   const uint32_t r2p = c.r2_p[l], onep = c.one_p[l];
   const uint32_t k = kb * 64 + lane;
@@ -660,9 +686,9 @@ bool mac_offsets_fit(const ConvGeom &g, uint32_t bt, uint32_t ct) {
 // (images per thread, channels per thread, image groups, channel groups, ring depth)
 #define HC_MAC_VARIANTS(X)                                                                                    \
   X(1, 8, 1, 4, 2) X(1, 4, 1, 4, 2) X(2, 4, 1, 4, 2) X(4, 4, 1, 4, 2) X(4, 2, 1, 4, 2) X(8, 2, 1, 4, 2)       \
-  X(16, 2, 1, 4, 2) X(4, 4, 4, 2, 2) X(4, 8, 4, 2, 2) X(2, 8, 4, 2, 2) X(4, 4, 2, 4, 2) X(8, 4, 2, 2, 2)     \
-  X(2, 4, 4, 4, 2) X(1, 8, 2, 4, 2) X(4, 8, 4, 2, 4) X(2, 8, 4, 2, 4) X(4, 4, 4, 2, 4) X(4, 4, 2, 4, 4)     \
-  X(1, 8, 2, 4, 4) X(2, 4, 4, 4, 4)
+  X(4, 4, 4, 2, 2) X(4, 8, 4, 2, 2) X(2, 8, 4, 2, 2) X(4, 4, 2, 4, 2) X(2, 4, 4, 4, 2) X(1, 8, 2, 4, 2)       \
+  X(4, 8, 4, 2, 3) X(2, 8, 4, 2, 4) X(4, 4, 4, 2, 4) X(4, 4, 2, 4, 4) X(1, 8, 2, 4, 4) X(2, 4, 4, 4, 4)       \
+  X(1, 8, 1, 4, 4)
 
 bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, uint32_t ns) {
 #define HC_MAC_OK(B_, C_, R_, G_, S_) \
