@@ -107,8 +107,10 @@ typedef struct {
     uint32_t mac_cols;   /* multiply-accumulate: output channels per thread */
     uint32_t mac_row_groups;  /* waves per workgroup along images */
     uint32_t mac_col_groups;  /* waves per workgroup along output channels */
-    uint32_t mac_depth;       /* input ciphertexts whose loads are in flight per thread (register
-                                 ring depth, 2..4 as the tile allows; 0 = 2) */
+    uint32_t mac_depth;       /* input ciphertexts whose loads are in flight (2..4 as the tile
+                                 allows; 0 = 2) */
+    uint32_t mac_lds;         /* 1: the workgroup stages each input ciphertext's tile through LDS
+                                 with 16-byte loads; 0: every wave loads its operands itself */
 } hc_tuning;
 
 /* Create a context on HIP device `hip_device`: ring degree N (power of two,

@@ -221,16 +221,15 @@ hc::Shapes hc::shapes_for(const hc_ctx &c, uint32_t B) {
   s.fe = c.tune.fwd_elog ? c.tune.fwd_elog : default_fwd_elog(c.logn);
   s.ie = c.tune.inv_elog ? c.tune.inv_elog : default_inv_elog(c.logn);
   if (c.tune.mac_rows) {
-    s.bt = c.tune.mac_rows, s.ct = c.tune.mac_cols, s.rg = c.tune.mac_row_groups, s.cg = c.tune.mac_col_groups;
-    s.ns = c.tune.mac_depth ? c.tune.mac_depth : 2;
+    s.mac = mac_of(c.tune);
   } else if (B >= 16) {
-    s.bt = 4, s.ct = 8, s.rg = 4, s.cg = 2, s.ns = 2;
+    s.mac = {4, 8, 4, 2, 2, 0};
   } else if (B >= 4) {
-    s.bt = 4, s.ct = 4, s.rg = 1, s.cg = 4, s.ns = 2;
+    s.mac = {4, 4, 1, 4, 2, 0};
   } else if (B >= 2) {
-    s.bt = 2, s.ct = 4, s.rg = 1, s.cg = 4, s.ns = 2;
+    s.mac = {2, 4, 1, 4, 2, 0};
   } else {
-    s.bt = 1, s.ct = 8, s.rg = 1, s.cg = 4, s.ns = 2;
+    s.mac = {1, 8, 1, 4, 2, 0};
   }
   return s;
 }
@@ -241,10 +240,7 @@ hc::Shapes hc::layer_shapes(const hc_layer *ly, uint32_t B) {
     const hc_tuning &t = ly->tune;
     if (t.fwd_elog) s.fe = t.fwd_elog;
     if (t.inv_elog) s.ie = t.inv_elog;
-    if (t.mac_rows) {
-      s.bt = t.mac_rows, s.ct = t.mac_cols, s.rg = t.mac_row_groups, s.cg = t.mac_col_groups;
-      s.ns = t.mac_depth ? t.mac_depth : 2;
-    }
+    if (t.mac_rows) s.mac = mac_of(t);
   }
   return s;
 }
@@ -266,7 +262,7 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
   const ConvGeom &g = ly->geom;
   const bool timed = tm && tm->on;
   const Shapes sh = hc::layer_shapes(ly, B);
-  if (!hc::mac_offsets_fit(g, sh.bt, sh.ct))
+  if (!hc::mac_offsets_fit(g, sh.mac))
     return fail(HC_EUNSUPPORTED, "layer too large for the selected MAC tile (32-bit offsets); use smaller mac_rows");
   uint32_t *xhat = (uint32_t *)ws;
   const size_t npin = (size_t)B * g.G * 2 * c.L;
@@ -274,12 +270,12 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
   HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, ct_in, xhat, npin, c.consts, c.tw, st));
   if (timed) HC_HIP(hipEventRecord(tm->ev[1], st));
   if (!masked) {
-    HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, sh.ns, xhat, ly->d_w, ct_out, B, c.consts, st));
+    HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, ct_out, B, c.consts, st));
     HC_HIP(hc::launch_intt_full(c.logn, sh.ie, ct_out, ct_out, (size_t)B * g.O * 2 * c.L, c.consts, c.tw, st));
   } else {
     uint32_t *yhat = xhat + npin * c.N;
     if (timed) HC_HIP(hipEventRecord(tm->ev[2], st));
-    HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, sh.ns, xhat, ly->d_w, yhat, B, c.consts, st));
+    HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[3], st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[4], st));
     HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, yhat, mask, c0_ext, c1_out, B, c.consts, c.tw, st));
@@ -305,7 +301,7 @@ hc_status hc::enqueue_conv_gather(const hc_layer *ly, uint32_t B, const uint32_t
   const ConvGeom &g = ly->geom;
   if (B == 0 || B > hc::kMaxTab) return fail(HC_EINVAL, "group size out of range");
   const Shapes sh = hc::layer_shapes(ly, B);
-  if (!hc::mac_offsets_fit(g, sh.bt, sh.ct)) return fail(HC_EUNSUPPORTED, "layer too large for the MAC tile");
+  if (!hc::mac_offsets_fit(g, sh.mac)) return fail(HC_EUNSUPPORTED, "layer too large for the MAC tile");
   hc::ImgPtrs in{};
   hc::OutPtrs out{};
   in.n = out.n = B;
@@ -320,7 +316,7 @@ hc_status hc::enqueue_conv_gather(const hc_layer *ly, uint32_t B, const uint32_t
   const size_t npin = (size_t)B * ppi;
   HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, nullptr, xhat, npin, c.consts, c.tw, st, &in, ppi));
   uint32_t *yhat = xhat + npin * c.N;
-  HC_HIP(hc::launch_mac(g, sh.bt, sh.ct, sh.rg, sh.cg, sh.ns, xhat, ly->d_w, yhat, B, c.consts, st));
+  HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, st));
   HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, yhat, nullptr, nullptr, nullptr, B, c.consts, c.tw, st, &out));
   return HC_OK;
 }
@@ -480,11 +476,11 @@ hc_status hc_ctx_set_tuning(hc_ctx *c, const hc_tuning *t) {
     return fail(HC_EUNSUPPORTED, "forward NTT shape not available for this N");
   if (t->inv_elog && !hc::ntt_variant_ok(c->logn, t->inv_elog))
     return fail(HC_EUNSUPPORTED, "inverse NTT shape not available for this N");
-  const bool any = t->mac_rows || t->mac_cols || t->mac_row_groups || t->mac_col_groups || t->mac_depth;
+  const bool any =
+      t->mac_rows || t->mac_cols || t->mac_row_groups || t->mac_col_groups || t->mac_depth || t->mac_lds;
   const bool all = t->mac_rows && t->mac_cols && t->mac_row_groups && t->mac_col_groups;
   if (any && !all) return fail(HC_EINVAL, "set all four MAC fields or none");
-  if (all && !hc::mac_variant_ok(t->mac_rows, t->mac_cols, t->mac_row_groups, t->mac_col_groups,
-                                 t->mac_depth ? t->mac_depth : 2))
+  if (all && !hc::mac_variant_ok(hc::mac_of(*t)))
     return fail(HC_EUNSUPPORTED, "MAC tile not available");
   c->tune = *t;
   return HC_OK;
@@ -718,6 +714,7 @@ hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_row_groups);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_col_groups);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_depth);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_lds);
   for (size_t k = 0; k < n; ++k) {
     key.push_back(ct_in[k]);
     key.push_back(mask[k]);
@@ -820,12 +817,14 @@ hc_status time_it(F fn, hipStream_t st, int reps, float *ms) {
   return HC_OK;
 }
 
-// (images, channels per thread; image, channel wave groups; register ring depth)
-const uint32_t kMacCand[][5] = {{1, 8, 1, 4, 2}, {1, 4, 1, 4, 2}, {2, 4, 1, 4, 2}, {4, 4, 1, 4, 2},
-                                {4, 2, 1, 4, 2}, {8, 2, 1, 4, 2}, {4, 4, 4, 2, 2}, {4, 8, 4, 2, 2},
-                                {2, 8, 4, 2, 2}, {4, 4, 2, 4, 2}, {2, 4, 4, 4, 2}, {1, 8, 2, 4, 2},
-                                {4, 8, 4, 2, 3}, {2, 8, 4, 2, 4}, {4, 4, 4, 2, 4}, {4, 4, 2, 4, 4},
-                                {1, 8, 2, 4, 4}, {2, 4, 4, 4, 4}, {1, 8, 1, 4, 4}};
+// (images, channels per thread; image, channel wave groups; loads in flight; LDS-staged)
+const uint32_t kMacCand[][6] = {{1, 8, 1, 4, 2, 0}, {1, 4, 1, 4, 2, 0}, {2, 4, 1, 4, 2, 0}, {4, 4, 1, 4, 2, 0},
+                                {4, 2, 1, 4, 2, 0}, {8, 2, 1, 4, 2, 0}, {4, 4, 4, 2, 2, 0}, {4, 8, 4, 2, 2, 0},
+                                {2, 8, 4, 2, 2, 0}, {4, 4, 2, 4, 2, 0}, {2, 4, 4, 4, 2, 0}, {1, 8, 2, 4, 2, 0},
+                                {4, 8, 4, 2, 3, 0}, {2, 8, 4, 2, 4, 0}, {4, 4, 4, 2, 4, 0}, {4, 4, 2, 4, 4, 0},
+                                {1, 8, 2, 4, 4, 0}, {2, 4, 4, 4, 4, 0}, {1, 8, 1, 4, 4, 0}, {4, 8, 4, 2, 2, 1},
+                                {4, 8, 4, 2, 3, 1}, {4, 8, 2, 2, 2, 1}, {4, 8, 2, 2, 3, 1}, {2, 8, 4, 2, 3, 1},
+                                {4, 4, 4, 2, 3, 1}, {2, 8, 2, 2, 3, 1}};
 
 }  // namespace
 
@@ -850,8 +849,8 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
         if (!bar) continue;
         *bar = 0;
         hc_tuning t{};
-        if (std::sscanf(bar + 1, "%u %u %u %u %u %u %u", &t.fwd_elog, &t.inv_elog, &t.mac_rows, &t.mac_cols,
-                        &t.mac_row_groups, &t.mac_col_groups, &t.mac_depth) >= 6)
+        if (std::sscanf(bar + 1, "%u %u %u %u %u %u %u %u", &t.fwd_elog, &t.inv_elog, &t.mac_rows, &t.mac_cols,
+                        &t.mac_row_groups, &t.mac_col_groups, &t.mac_depth, &t.mac_lds) >= 6)
           cache[line] = t;
       }
       std::fclose(f);
@@ -869,9 +868,7 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     if (hit != cache.end()) {
       const hc_tuning &t = hit->second;
       if (hc::ntt_variant_ok(c.logn, t.fwd_elog) && hc::ntt_variant_ok(c.logn, t.inv_elog) &&
-          hc::mac_variant_ok(t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups,
-                             t.mac_depth ? t.mac_depth : 2) &&
-          hc::mac_offsets_fit(ly->geom, t.mac_rows, t.mac_cols)) {
+          hc::mac_variant_ok(hc::mac_of(t)) && hc::mac_offsets_fit(ly->geom, hc::mac_of(t))) {
         ly->tune = t;
         ly->tune_B = B;
         continue;
@@ -893,17 +890,18 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     }
     best_ms = 1e30f;
     for (const auto &m : kMacCand) {
-      if (!hc::mac_variant_ok(m[0], m[1], m[2], m[3], m[4]) || !hc::mac_offsets_fit(g, m[0], m[1])) continue;
+      const hc::MacShape shape{m[0], m[1], m[2], m[3], m[4], m[5]};
+      if (!hc::mac_variant_ok(shape) || !hc::mac_offsets_fit(g, shape)) continue;
       float ms;
       s = time_it([&] {
-        return hc::launch_mac(g, m[0], m[1], m[2], m[3], m[4], xhat, ly->d_w, yhat, B, c.consts, st);
+        return hc::launch_mac(g, shape, xhat, ly->d_w, yhat, B, c.consts, st);
       },
                   st, reps, &ms);
       if (s != HC_OK) return s;
       if (ms < best_ms) {
         best_ms = ms;
         best.mac_rows = m[0], best.mac_cols = m[1], best.mac_row_groups = m[2], best.mac_col_groups = m[3];
-        best.mac_depth = m[4];
+        best.mac_depth = m[4], best.mac_lds = m[5];
       }
     }
     best_ms = 1e30f;
@@ -918,9 +916,9 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     }
     ly->tune = best;
     ly->tune_B = B;
-    char buf[112];
-    std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog, best.mac_rows,
-                  best.mac_cols, best.mac_row_groups, best.mac_col_groups, best.mac_depth);
+    char buf[128];
+    std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog, best.mac_rows,
+                  best.mac_cols, best.mac_row_groups, best.mac_col_groups, best.mac_depth, best.mac_lds);
     appended += key + buf;
   }
   if (cache_path && !appended.empty()) {

@@ -58,11 +58,15 @@ struct OutPtrs {
 // Launchers (hc_kernels.hip). Each enqueues on `st` and returns the launch status.
 // Launch-shape variants: an NTT uses 2^(logn - elog) threads per polynomial;
 // the MAC gives each thread bt images x ct output channels, and a workgroup
-// rg x cg such threads per coefficient (image groups x channel groups).
+// rg x cg such threads per coefficient (image groups x channel groups); depth
+// input ciphertexts are in flight, in registers or (lds) staged through LDS.
+struct MacShape {
+  uint32_t bt, ct, rg, cg, depth, lds;
+};
 bool ntt_variant_ok(uint32_t logn, uint32_t elog);
-bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, uint32_t ns);
-// The MAC addresses one image tile and one channel tile with 32-bit byte offsets.
-bool mac_offsets_fit(const ConvGeom &g, uint32_t bt, uint32_t ct);
+bool mac_variant_ok(const MacShape &m);
+// The MAC addresses its image and channel tiles with 32-bit byte offsets.
+bool mac_offsets_fit(const ConvGeom &g, const MacShape &m);
 
 // tab: optional input table (npolys == tab->n * ppi); input polynomials then
 // come from tab->p[poly / ppi] + (poly % ppi) * N.
@@ -78,9 +82,8 @@ hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, ui
 hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, const uint32_t *yhat,
                               const uint32_t *mask, uint32_t *c0_ext, uint32_t *c1_out, uint32_t B,
                               const LimbConsts &c, const Twiddles &tw, hipStream_t st, const OutPtrs *tab = nullptr);
-hipError_t launch_mac(const ConvGeom &g, uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, uint32_t ns,
-                      const uint32_t *xhat,
-                      const uint32_t *what, uint32_t *yhat, uint32_t B, const LimbConsts &c, hipStream_t st);
+hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *xhat, const uint32_t *what,
+                      uint32_t *yhat, uint32_t B, const LimbConsts &c, hipStream_t st);
 hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *filters, uint32_t *w, const LimbConsts &c,
                                  hipStream_t st);
 hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st);

@@ -502,6 +502,202 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
   }
 }
 
+// LDS-staged form of the same register tile. Per input ciphertext ("step")
+// the workgroup needs NX = RG BT 2 input segments and NW = CG CT weight
+// segments of 64 coefficients (256 bytes). They are loaded once per
+// workgroup - every thread the same number of bytes of each, 16 at a time
+// where the share allows - into a ring of R register sets (R steps in
+// flight), written to one of two LDS buffers, and each wave reads its
+// operands from there. One barrier per step orders the LDS buffers: step g
+// is read from buffer g & 1 while step g + 1 is written to the other.
+template <int BYTES>
+struct Chunk;  // one thread's share of one operand per step
+template <>
+struct Chunk<4> {
+  uint32_t v;
+  __device__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off) { v = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0); }
+  __device__ void store(char *lds) const { *(uint32_t *)lds = v; }
+};
+template <>
+struct Chunk<8> {
+  uint2 v;
+  __device__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    v = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  __device__ void store(char *lds) const { *(uint2 *)lds = v; }
+};
+template <>
+struct Chunk<16> {
+  uint4 v;
+  __device__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  }
+  __device__ void store(char *lds) const { *(uint4 *)lds = v; }
+};
+
+template <int BT, int CT, int RG, int CG, int R>
+__global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__restrict__ X,
+                                                          const uint32_t *__restrict__ Wt,
+                                                          uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
+                                                          uint32_t nib, uint32_t nkb, LimbConsts c) {
+  constexpr int NT = 64 * RG * CG;
+  constexpr int NX = RG * BT * 2, NW = CG * CT;               // segments per step
+  constexpr int XB = NX * 256 / NT, WB = NW * 256 / NT;       // bytes per thread per step
+  static_assert(NX * 256 % NT == 0 && NW * 256 % NT == 0, "shares must be whole");
+  constexpr int XW = XB < 16 ? XB : 16, WWD = WB < 16 ? WB : 16;  // access widths
+  constexpr int KX = XB / XW, KW = WB / WWD;                      // accesses per thread per step
+  static_assert((XW == 4 || XW == 8 || XW == 16) && (WWD == 4 || WWD == 8 || WWD == 16), "access width");
+  static_assert(R >= 2 && R * (KX + KW) <= 63, "loads in flight beyond the vector memory counter");
+  constexpr uint32_t BUFB = (NX + NW) * 256;  // bytes per LDS buffer
+  __shared__ uint4 stage4[2 * BUFB / 16];
+  char *stage = (char *)stage4;
+  const uint32_t nwg = gridDim.x;
+  uint32_t wg = blockIdx.x;
+  if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
+  const uint32_t ib = wg % nib;
+  uint32_t r = wg / nib;
+  const uint32_t tau = r % g.T;
+  r /= g.T;
+  const uint32_t kb = r % nkb;
+  r /= nkb;
+  const uint32_t l = r % g.L;
+  const uint32_t bt = r / g.L;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t lane = tid & 63u;
+  const uint32_t rg = wave % RG, cg = wave / RG;
+  // workgroup tile: images [bw, bw + nbw), channels [iw, iw + ncw)
+  const uint32_t bw = bt * RG * BT, iw = ib * CG * CT;
+  if (bw >= B || iw >= g.c_out) return;  // uniform over the workgroup
+  const uint32_t nbw = min((uint32_t)(RG * BT), B - bw), ncw = min((uint32_t)(CG * CT), g.c_out - iw);
+  const uint32_t LN = g.L * g.N;
+  // Per-thread global byte offsets and LDS byte positions of its accesses
+  // (fixed for the whole loop). Byte e of the step's input share sits in
+  // segment e / 256 = 2 i + p; absent images and channels read image /
+  // channel 0 of the tile, whose results are never stored.
+  uint32_t xoff[KX], woff[KW];
+#pragma unroll
+  for (int k = 0; k < KX; ++k) {
+    const uint32_t e = (tid + k * NT) * XW, seg = e >> 8, i = seg >> 1;
+    xoff[k] = (((i < nbw ? i : 0u) * g.G * 2 + (seg & 1u)) * LN) * 4u + (e & 255u);
+  }
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const uint32_t e = (tid + k * NT) * WWD, cc = e >> 8;
+    woff[k] = ((cc < ncw ? cc : 0u) * g.G_w * LN) * 4u + (e & 255u);
+  }
+  const char *xbase = (const char *)(X + ((size_t)bw * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const char *wbase = (const char *)(Wt + (size_t)iw * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
+  const uint32_t G_w = g.G_w, last = G_w - 1;
+  using CX = Chunk<XW>;
+  using CW = Chunk<WWD>;
+  auto gload = [&](uint32_t gw, CX (&rx)[KX], CW (&rw)[KW]) {
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(xbase + gw * xstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+    const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(wbase + gw * wstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+#pragma unroll
+    for (int k = 0; k < KX; ++k) rx[k].load(xr, xoff[k]);
+#pragma unroll
+    for (int k = 0; k < KW; ++k) rw[k].load(wr, woff[k]);
+  };
+  auto lstore = [&](uint32_t buf, const CX (&rx)[KX], const CW (&rw)[KW]) {
+    char *sb = stage + buf * BUFB;
+#pragma unroll
+    for (int k = 0; k < KX; ++k) rx[k].store(sb + (tid + k * NT) * XW);
+#pragma unroll
+    for (int k = 0; k < KW; ++k) rw[k].store(sb + NX * 256 + (tid + k * NT) * WWD);
+  };
+  const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
+  uint64_t acc[CT][BT][2];
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+  // this wave's operands inside a stage buffer (words)
+  const uint32_t *xs0 = (const uint32_t *)stage + (rg * BT * 2) * 64 + lane;
+  const uint32_t *ws0 = (const uint32_t *)stage + (NX + cg * CT) * 64 + lane;
+  constexpr uint32_t BUFW = BUFB / 4;  // words per buffer
+  CX rx[R][KX];
+  CW rw[R][KW];
+  // prologue: steps 0 .. R-1 in flight, step 0 into buffer 0, step R into set 0
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    asm volatile("" ::: "memory");
+    gload(min((uint32_t)j, last), rx[j], rw[j]);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  lstore(0, rx[0], rw[0]);
+  asm volatile("" ::: "memory");
+  gload(min((uint32_t)R, last), rx[0], rw[0]);
+  asm volatile("" ::: "memory");
+  __syncthreads();
+  uint32_t since_fold = 0;
+  // step g: operands from buffer g & 1; set (g + 1) % R holds step g + 1 and
+  // goes to the other buffer, then reloads with step g + 1 + R
+  for (uint32_t g0 = 0; g0 < G_w; g0 += R) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint32_t gw = g0 + j;
+      if (gw >= G_w) break;  // uniform
+      const uint32_t *xs = xs0 + (gw & 1u) * BUFW, *wsp = ws0 + (gw & 1u) * BUFW;
+      uint32_t w[CT], x[BT][2];
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc) w[cc] = wsp[cc * 64];
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) {
+        x[bb][0] = xs[(bb * 2) * 64];
+        x[bb][1] = xs[(bb * 2 + 1) * 64];
+      }
+      const int jn = (j + 1) % R;
+      asm volatile("" ::: "memory");
+      lstore((gw + 1) & 1u, rx[jn], rw[jn]);
+      asm volatile("" ::: "memory");
+      gload(min(gw + 1 + R, last), rx[jn], rw[jn]);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+        for (int bb = 0; bb < BT; ++bb) {
+          acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
+          acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
+        }
+      if (++since_fold == fold) {
+        since_fold = 0;
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+          for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+            for (int pp = 0; pp < 2; ++pp)
+              acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+      }
+      __syncthreads();
+    }
+  }
+  // wave tile and its stores, as in k_mac_tiled
+  const uint32_t i0 = iw + cg * CT, b0 = bw + rg * BT;
+  if (i0 >= g.c_out || b0 >= B) return;
+  const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
+  const uint32_t r2p = c.r2_p[l], onep = c.one_p[l];
+  const uint32_t k = kb * 64 + lane;
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc) {
+    if ((uint32_t)cc >= nc) continue;
+    const uint32_t o = (i0 + cc) * g.T + tau;
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) {
+      if ((uint32_t)bb >= nb) continue;
+      uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + k;
+      y[0] = reduce64(acc[cc][bb][0], q, r2, r2p, onep);
+      y[LN] = reduce64(acc[cc][bb][1], q, r2, r2p, onep);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- weight encoding
 // What[i][gw][l][idx] = sign * f[i][j][ky][kx] mod q_l with x^(-e) = sign x^idx,
 // e = o_j + ky w' + kx (x^0 = 1; x^(-e) = -x^(N-e) for e > 0). The e values of
@@ -664,45 +860,55 @@ hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, c
   HC_NTT_DISPATCH(invm_t, g, y, m, c0, c1, B, c, tw, t, st)
 }
 
-template <int BT, int CT, int RG, int CG, int NS>
+template <int BT, int CT, int RG, int CG, int NS, int LDS>
 static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
                         const LimbConsts &c, hipStream_t st) {
-  if (!mac_offsets_fit(g, BT, CT)) return hipErrorInvalidValue;
+  if (!mac_offsets_fit(g, MacShape{BT, CT, RG, CG, NS, LDS})) return hipErrorInvalidValue;
   const uint32_t nkb = g.N / 64;
   const uint32_t nib = (g.c_out + CG * CT - 1) / (CG * CT);
   const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
   const size_t nwg = (size_t)nib * g.T * nkb * g.L * nbt;
   if (nwg == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_mac_tiled<BT, CT, RG, CG, NS>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y, g, B,
-                     nib, nkb, c);
+  if constexpr (LDS != 0)
+    hipLaunchKernelGGL((k_mac_lds<BT, CT, RG, CG, NS>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y, g,
+                       B, nib, nkb, c);
+  else
+    hipLaunchKernelGGL((k_mac_tiled<BT, CT, RG, CG, NS>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y,
+                       g, B, nib, nkb, c);
   return hipGetLastError();
 }
 
-bool mac_offsets_fit(const ConvGeom &g, uint32_t bt, uint32_t ct) {
+// The register tile's 32-bit offsets span BT images and CT channels; the
+// LDS-staged form's span the workgroup's RG BT images and CG CT channels.
+bool mac_offsets_fit(const ConvGeom &g, const MacShape &m) {
   const uint64_t ln = (uint64_t)g.L * g.N * 4;
-  return (uint64_t)bt * g.G * 2 * ln < (1ull << 32) && (uint64_t)ct * g.G_w * ln < (1ull << 32);
+  const uint64_t bi = m.lds ? (uint64_t)m.rg * m.bt : m.bt, ch = m.lds ? (uint64_t)m.cg * m.ct : m.ct;
+  return bi * g.G * 2 * ln < (1ull << 32) && ch * g.G_w * ln < (1ull << 32);
 }
 
-// (images per thread, channels per thread, image groups, channel groups, ring depth)
-#define HC_MAC_VARIANTS(X)                                                                                    \
-  X(1, 8, 1, 4, 2) X(1, 4, 1, 4, 2) X(2, 4, 1, 4, 2) X(4, 4, 1, 4, 2) X(4, 2, 1, 4, 2) X(8, 2, 1, 4, 2)       \
-  X(4, 4, 4, 2, 2) X(4, 8, 4, 2, 2) X(2, 8, 4, 2, 2) X(4, 4, 2, 4, 2) X(2, 4, 4, 4, 2) X(1, 8, 2, 4, 2)       \
-  X(4, 8, 4, 2, 3) X(2, 8, 4, 2, 4) X(4, 4, 4, 2, 4) X(4, 4, 2, 4, 4) X(1, 8, 2, 4, 4) X(2, 4, 4, 4, 4)       \
-  X(1, 8, 1, 4, 4)
+// (images per thread, channels per thread, image groups, channel groups,
+//  loads in flight (register sets), LDS-staged)
+#define HC_MAC_VARIANTS(X)                                                                                      \
+  X(1, 8, 1, 4, 2, 0) X(1, 4, 1, 4, 2, 0) X(2, 4, 1, 4, 2, 0) X(4, 4, 1, 4, 2, 0) X(4, 2, 1, 4, 2, 0)           \
+  X(8, 2, 1, 4, 2, 0) X(4, 4, 4, 2, 2, 0) X(4, 8, 4, 2, 2, 0) X(2, 8, 4, 2, 2, 0) X(4, 4, 2, 4, 2, 0)           \
+  X(2, 4, 4, 4, 2, 0) X(1, 8, 2, 4, 2, 0) X(4, 8, 4, 2, 3, 0) X(2, 8, 4, 2, 4, 0) X(4, 4, 4, 2, 4, 0)           \
+  X(4, 4, 2, 4, 4, 0) X(1, 8, 2, 4, 4, 0) X(2, 4, 4, 4, 4, 0) X(1, 8, 1, 4, 4, 0) X(4, 8, 4, 2, 2, 1)           \
+  X(4, 8, 4, 2, 3, 1) X(4, 8, 2, 2, 2, 1) X(4, 8, 2, 2, 3, 1) X(2, 8, 4, 2, 3, 1) X(4, 4, 4, 2, 3, 1)           \
+  X(2, 8, 2, 2, 3, 1)
 
-bool mac_variant_ok(uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, uint32_t ns) {
-#define HC_MAC_OK(B_, C_, R_, G_, S_) \
-  if (bt == B_ && ct == C_ && rg == R_ && cg == G_ && ns == S_) return true;
+bool mac_variant_ok(const MacShape &m) {
+#define HC_MAC_OK(B_, C_, R_, G_, S_, D_) \
+  if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_) return true;
   HC_MAC_VARIANTS(HC_MAC_OK)
 #undef HC_MAC_OK
   return false;
 }
 
-hipError_t launch_mac(const ConvGeom &g, uint32_t bt, uint32_t ct, uint32_t rg, uint32_t cg, uint32_t ns,
-                      const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B, const LimbConsts &c,
-                      hipStream_t st) {
-#define HC_MAC_CASE(B_, C_, R_, G_, S_) \
-  if (bt == B_ && ct == C_ && rg == R_ && cg == G_ && ns == S_) return mac_t<B_, C_, R_, G_, S_>(g, x, w, y, B, c, st);
+hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *x, const uint32_t *w, uint32_t *y,
+                      uint32_t B, const LimbConsts &c, hipStream_t st) {
+#define HC_MAC_CASE(B_, C_, R_, G_, S_, D_)                                                          \
+  if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_)          \
+    return mac_t<B_, C_, R_, G_, S_, D_>(g, x, w, y, B, c, st);
   HC_MAC_VARIANTS(HC_MAC_CASE)
 #undef HC_MAC_CASE
   return hipErrorInvalidValue;

@@ -39,9 +39,15 @@ hc_status hip_fail(hipError_t e, const char *where);
 
 // Launch shapes in effect for B images.
 struct Shapes {
-  uint32_t fe, ie, bt, ct, rg, cg, ns;
+  uint32_t fe, ie;
+  MacShape mac;
 };
 Shapes shapes_for(const hc_ctx &c, uint32_t B);
+// The MAC shape a tuning names (all four tile fields set); depth 0 means 2.
+inline MacShape mac_of(const hc_tuning &t) {
+  return MacShape{t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups, t.mac_depth ? t.mac_depth : 2u,
+                  t.mac_lds};
+}
 // The layer's autotuned shapes when tuned for B images, else the context's.
 Shapes layer_shapes(const hc_layer *ly, uint32_t B);
 

@@ -238,7 +238,7 @@ hc_status hc_server_add_net(hc_server *s, const hc_layer *const *layers, uint32_
     np.in_bytes.push_back(in_b);
     np.mask_bytes.push_back(mask_b);
     const hc::Shapes sh = hc::shapes_for(c, s->cfg.max_batch);
-    if (!hc::mac_offsets_fit(ly->geom, sh.bt, sh.ct)) return fail(HC_EUNSUPPORTED, "layer too large for the MAC tile");
+    if (!hc::mac_offsets_fit(ly->geom, sh.mac)) return fail(HC_EUNSUPPORTED, "layer too large for the MAC tile");
     ws = std::max(ws, hc::ws_bytes_for(ly, s->cfg.max_batch, true));
   }
   np.bytes = off;

@@ -179,11 +179,13 @@ def test_error_paths(hc):
     ly.conv(zeros((1,)), zeros((1,)), 0, zeros((1,)))
 
 
-# (images, channels per thread, image groups, channel groups, register ring depth)
-MAC_VARIANTS = [(1, 8, 1, 4, 2), (1, 4, 1, 4, 2), (2, 4, 1, 4, 2), (4, 4, 1, 4, 2), (4, 2, 1, 4, 2),
-                (8, 2, 1, 4, 2), (4, 4, 4, 2, 2), (4, 8, 4, 2, 2), (2, 8, 4, 2, 2), (4, 4, 2, 4, 2),
-                (2, 4, 4, 4, 2), (1, 8, 2, 4, 2), (4, 8, 4, 2, 3), (2, 8, 4, 2, 4), (4, 4, 4, 2, 4),
-                (4, 4, 2, 4, 4), (1, 8, 2, 4, 4), (2, 4, 4, 4, 4), (1, 8, 1, 4, 4)]
+# (images, channels per thread, image groups, channel groups, loads in flight, LDS-staged)
+MAC_VARIANTS = [(1, 8, 1, 4, 2, 0), (1, 4, 1, 4, 2, 0), (2, 4, 1, 4, 2, 0), (4, 4, 1, 4, 2, 0), (4, 2, 1, 4, 2, 0),
+                (8, 2, 1, 4, 2, 0), (4, 4, 4, 2, 2, 0), (4, 8, 4, 2, 2, 0), (2, 8, 4, 2, 2, 0), (4, 4, 2, 4, 2, 0),
+                (2, 4, 4, 4, 2, 0), (1, 8, 2, 4, 2, 0), (4, 8, 4, 2, 3, 0), (2, 8, 4, 2, 4, 0), (4, 4, 4, 2, 4, 0),
+                (4, 4, 2, 4, 4, 0), (1, 8, 2, 4, 4, 0), (2, 4, 4, 4, 4, 0), (1, 8, 1, 4, 4, 0), (4, 8, 4, 2, 2, 1),
+                (4, 8, 4, 2, 3, 1), (4, 8, 2, 2, 2, 1), (4, 8, 2, 2, 3, 1), (2, 8, 4, 2, 3, 1), (4, 4, 4, 2, 3, 1),
+                (2, 8, 2, 2, 3, 1)]
 
 
 @pytest.mark.parametrize("N,elogs", [(8192, (3, 4, 5)), (16384, (4, 5)), (4096, (3, 4, 5)), (1024, (3, 4))])
@@ -220,6 +222,8 @@ def test_every_launch_shape_gives_the_same_bits(hc, N, elogs):
         c.set_tuning(0, 0, 4, 8, 4, 2, 4)
     with pytest.raises(hc.HcError):  # a depth alone is not a tile
         c.set_tuning(0, 0, 0, 0, 0, 0, 4)
+    with pytest.raises(hc.HcError):  # nor is the LDS flag
+        c.set_tuning(0, 0, 0, 0, 0, 0, 0, 1)
 
 
 def test_mac_ring_over_many_input_ciphertexts(hc):
