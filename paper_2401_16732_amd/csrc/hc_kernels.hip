@@ -76,6 +76,41 @@ __device__ __forceinline__ uint32_t gidx(uint32_t tid, int u) {
 // lpad(gidx(0, u)): one base per thread and compile-time offsets per register.
 __host__ __device__ constexpr uint32_t lpad(uint32_t j) { return j + (j >> 5); }
 
+// Twiddles of stage bit b (s = LOGN - 1 - b) read at index 2^s + (j >> (b+1)).
+// In a pass over bits [LO, LO + EP) with LO >= 6 the thread's share of j above
+// bit b comes from tid >> LO, which is the same for all 64 lanes of a wave:
+// the base is then wave-uniform and read through the constant address space,
+// so the compiler can fetch those twiddles with scalar loads instead of one
+// vector load per lane.
+using const_u64 = __attribute__((address_space(4))) const uint64_t;
+template <int LOGN, int ELOG, int LO, int EP>
+struct StageTw {
+  static constexpr bool kUniform = LO >= 6;
+  const uint2 *vec;
+  const_u64 *uni;  // the same {w, w'} pairs as 64-bit words
+  __device__ __forceinline__ StageTw(const uint2 *tw, uint32_t tid, int b) {
+    const int s = LOGN - 1 - b;
+    if constexpr (kUniform) {
+      const uint32_t hi = __builtin_amdgcn_readfirstlane(tid >> LO);
+      uni = (const_u64 *)(tw + (1u << s) + (((size_t)hi << (LO + EP)) >> (b + 1)));
+      vec = nullptr;
+    } else {
+      vec = tw + (1u << s) + (gidx<LOGN, ELOG, LO, EP>(tid, 0) >> (b + 1));
+      uni = nullptr;
+    }
+  }
+  // twiddle of register slot u (the register part of j is gidx(0, u))
+  __device__ __forceinline__ uint2 operator()(int u, int b) const {
+    const uint32_t k = gidx<LOGN, ELOG, LO, EP>(0, u) >> (b + 1);
+    if constexpr (kUniform) {
+      const uint64_t t = uni[k];
+      return make_uint2((uint32_t)t, (uint32_t)(t >> 32));
+    } else {
+      return vec[k];
+    }
+  }
+};
+
 // Forward (Cooley-Tukey, natural -> bit-reversed) stages of one pass.
 // Stage s works on pairs (j, j + 2^(LOGN-1-s)) with twiddle psi^brv(2^s + j >> (LOGN - s)).
 template <int LOGN, int ELOG, int LO, int EP>
@@ -88,12 +123,13 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
     const int b = LO + bb;
     const int s = LOGN - 1 - b;
     // twiddle index 2^s + (j >> (b + 1)), split into thread and register parts
-    const uint2 *tws = tw + (1u << s) + (gidx<LOGN, ELOG, LO, EP>(tid, 0) >> (b + 1));
+    const StageTw<LOGN, ELOG, LO, EP> tws(tw, tid, b);
+    (void)s;
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       if (u & (1 << bb)) continue;
       const int u2 = u | (1 << bb);
-      const uint2 w = tws[gidx<LOGN, ELOG, LO, EP>(0, u) >> (b + 1)];
+      const uint2 w = tws(u, b);
       uint32_t X = v[u], Y = v[u2];
       X = csub(X, q2);
       const uint32_t T = shoup_lazy(Y, w.x, w.y, q);
@@ -121,7 +157,7 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
     const int b = LO + bb;
     const int s = LOGN - 1 - b;
     const bool sum_only = b >= LOGN - PS;
-    const uint2 *tws = tw + (1u << s) + (gidx<LOGN, ELOG, LO, EP>(tid, 0) >> (b + 1));
+    const StageTw<LOGN, ELOG, LO, EP> tws(tw, tid, b);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       if (u & (1 << bb)) continue;
@@ -133,7 +169,7 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
         v[u] = shoup_lazy(X + Y, ninv, ninvp, q);
         v[u2] = shoup_lazy(X - Y + q2, ninvw, ninvwp, q);
       } else {
-        const uint2 w = tws[gidx<LOGN, ELOG, LO, EP>(0, u) >> (b + 1)];
+        const uint2 w = tws(u, b);
         v[u] = csub(X + Y, q2);
         v[u2] = shoup_lazy(X - Y + q2, w.x, w.y, q);
       }
