@@ -111,6 +111,8 @@ typedef struct {
                                  allows; 0 = 2) */
     uint32_t mac_lds;         /* 1: the workgroup stages each input ciphertext's tile through LDS
                                  with 16-byte loads; 0: every wave loads its operands itself */
+    uint32_t inv_polys;       /* masked inverse NTT: polynomials per workgroup, sharing each twiddle
+                                 load (1, or 2 when inv_elog <= 4; 0 = 1) */
 } hc_tuning;
 
 /* Create a context on HIP device `hip_device`: ring degree N (power of two,

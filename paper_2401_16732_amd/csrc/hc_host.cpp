@@ -220,6 +220,7 @@ hc::Shapes hc::shapes_for(const hc_ctx &c, uint32_t B) {
   Shapes s{};
   s.fe = c.tune.fwd_elog ? c.tune.fwd_elog : default_fwd_elog(c.logn);
   s.ie = c.tune.inv_elog ? c.tune.inv_elog : default_inv_elog(c.logn);
+  s.ipw = c.tune.inv_polys ? c.tune.inv_polys : 1;
   if (c.tune.mac_rows) {
     s.mac = mac_of(c.tune);
   } else if (B >= 16) {
@@ -240,8 +241,10 @@ hc::Shapes hc::layer_shapes(const hc_layer *ly, uint32_t B) {
     const hc_tuning &t = ly->tune;
     if (t.fwd_elog) s.fe = t.fwd_elog;
     if (t.inv_elog) s.ie = t.inv_elog;
+    if (t.inv_polys) s.ipw = t.inv_polys;
     if (t.mac_rows) s.mac = mac_of(t);
   }
+  if (!hc::intt_masked_ok(ly->ctx->logn, s.ie, s.ipw)) s.ipw = 1;  // e.g. a tuned e = 5 under a context's 2
   return s;
 }
 
@@ -278,7 +281,7 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
     HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[3], st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[4], st));
-    HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, yhat, mask, c0_ext, c1_out, B, c.consts, c.tw, st));
+    HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, sh.ipw, yhat, mask, c0_ext, c1_out, B, c.consts, c.tw, st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[5], st));
   }
   return HC_OK;
@@ -317,7 +320,8 @@ hc_status hc::enqueue_conv_gather(const hc_layer *ly, uint32_t B, const uint32_t
   HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, nullptr, xhat, npin, c.consts, c.tw, st, &in, ppi));
   uint32_t *yhat = xhat + npin * c.N;
   HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, st));
-  HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, yhat, nullptr, nullptr, nullptr, B, c.consts, c.tw, st, &out));
+  HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, sh.ipw, yhat, nullptr, nullptr, nullptr, B, c.consts, c.tw, st,
+                                &out));
   return HC_OK;
 }
 
@@ -476,6 +480,9 @@ hc_status hc_ctx_set_tuning(hc_ctx *c, const hc_tuning *t) {
     return fail(HC_EUNSUPPORTED, "forward NTT shape not available for this N");
   if (t->inv_elog && !hc::ntt_variant_ok(c->logn, t->inv_elog))
     return fail(HC_EUNSUPPORTED, "inverse NTT shape not available for this N");
+  if (t->inv_polys &&
+      !hc::intt_masked_ok(c->logn, t->inv_elog ? t->inv_elog : default_inv_elog(c->logn), t->inv_polys))
+    return fail(HC_EUNSUPPORTED, "inverse NTT polynomials per workgroup not available for this shape");
   const bool any =
       t->mac_rows || t->mac_cols || t->mac_row_groups || t->mac_col_groups || t->mac_depth || t->mac_lds;
   const bool all = t->mac_rows && t->mac_cols && t->mac_row_groups && t->mac_col_groups;
@@ -715,6 +722,7 @@ hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_col_groups);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_depth);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_lds);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.inv_polys);
   for (size_t k = 0; k < n; ++k) {
     key.push_back(ct_in[k]);
     key.push_back(mask[k]);
@@ -849,8 +857,9 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
         if (!bar) continue;
         *bar = 0;
         hc_tuning t{};
-        if (std::sscanf(bar + 1, "%u %u %u %u %u %u %u %u", &t.fwd_elog, &t.inv_elog, &t.mac_rows, &t.mac_cols,
-                        &t.mac_row_groups, &t.mac_col_groups, &t.mac_depth, &t.mac_lds) >= 6)
+        if (std::sscanf(bar + 1, "%u %u %u %u %u %u %u %u %u", &t.fwd_elog, &t.inv_elog, &t.mac_rows,
+                        &t.mac_cols, &t.mac_row_groups, &t.mac_col_groups, &t.mac_depth, &t.mac_lds,
+                        &t.inv_polys) >= 6)
           cache[line] = t;
       }
       std::fclose(f);
@@ -867,7 +876,8 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     auto hit = cache.find(key);
     if (hit != cache.end()) {
       const hc_tuning &t = hit->second;
-      if (hc::ntt_variant_ok(c.logn, t.fwd_elog) && hc::ntt_variant_ok(c.logn, t.inv_elog) &&
+      if (hc::ntt_variant_ok(c.logn, t.fwd_elog) &&
+          hc::intt_masked_ok(c.logn, t.inv_elog, t.inv_polys ? t.inv_polys : 1) &&
           hc::mac_variant_ok(hc::mac_of(t)) && hc::mac_offsets_fit(ly->geom, hc::mac_of(t))) {
         ly->tune = t;
         ly->tune_B = B;
@@ -906,19 +916,22 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     }
     best_ms = 1e30f;
     for (uint32_t e = 3; e <= 6; ++e) {
-      if (!hc::ntt_variant_ok(c.logn, e)) continue;
-      float ms;
-      s = time_it([&] {
-        return hc::launch_intt_masked(g, c.logn, e, yhat, mask[k], c0[k], c1[k], B, c.consts, c.tw, st);
-      }, st, reps, &ms);
-      if (s != HC_OK) return s;
-      if (ms < best_ms) best_ms = ms, best.inv_elog = e;
+      for (uint32_t npw = 1; npw <= 2; ++npw) {
+        if (!hc::intt_masked_ok(c.logn, e, npw)) continue;
+        float ms;
+        s = time_it([&] {
+          return hc::launch_intt_masked(g, c.logn, e, npw, yhat, mask[k], c0[k], c1[k], B, c.consts, c.tw, st);
+        }, st, reps, &ms);
+        if (s != HC_OK) return s;
+        if (ms < best_ms) best_ms = ms, best.inv_elog = e, best.inv_polys = npw;
+      }
     }
     ly->tune = best;
     ly->tune_B = B;
     char buf[128];
-    std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog, best.mac_rows,
-                  best.mac_cols, best.mac_row_groups, best.mac_col_groups, best.mac_depth, best.mac_lds);
+    std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog, best.mac_rows,
+                  best.mac_cols, best.mac_row_groups, best.mac_col_groups, best.mac_depth, best.mac_lds,
+                  best.inv_polys);
     appended += key + buf;
   }
   if (cache_path && !appended.empty()) {

@@ -64,6 +64,8 @@ struct MacShape {
   uint32_t bt, ct, rg, cg, depth, lds;
 };
 bool ntt_variant_ok(uint32_t logn, uint32_t elog);
+// The masked inverse NTT with npw polynomials per workgroup (1, or 2 for elog <= 4).
+bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw);
 bool mac_variant_ok(const MacShape &m);
 // The MAC addresses its image and channel tiles with 32-bit byte offsets.
 bool mac_offsets_fit(const ConvGeom &g, const MacShape &m);
@@ -78,8 +80,8 @@ hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, ui
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st);
 // Masked mode: in = Yhat [B][O][2][L][N]; c1 polys go to c1_out [B][O][L][N],
 // c0 polys are extracted with the mask into c0_ext [B][c_out][L][ho][wo].
-// tab: optional per-image output tables (tab->n == B).
-hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, const uint32_t *yhat,
+// tab: optional per-image output tables (tab->n == B). npw: polynomials per workgroup.
+hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, uint32_t npw, const uint32_t *yhat,
                               const uint32_t *mask, uint32_t *c0_ext, uint32_t *c1_out, uint32_t B,
                               const LimbConsts &c, const Twiddles &tw, hipStream_t st, const OutPtrs *tab = nullptr);
 hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *xhat, const uint32_t *what,

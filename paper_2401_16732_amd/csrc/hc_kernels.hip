@@ -146,8 +146,10 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
 // wanted indices have those bits clear - so the difference half, with its
 // twiddle multiply, is skipped there. PS = 0 computes the full transform. PS
 // is a compile-time constant, so no stage carries a run-time branch.
-template <int LOGN, int ELOG, int LO, int EP, int PS>
-__device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
+// M polynomials of one limb go through the stages together (v[m]): each
+// twiddle is loaded once for all of them.
+template <int LOGN, int ELOG, int LO, int EP, int PS, int M>
+__device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
                                          uint32_t q, uint32_t ninv, uint32_t ninvp, uint32_t ninvw,
                                          uint32_t ninvwp) {
   constexpr int E = 1 << ELOG;
@@ -162,16 +164,25 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
     for (int u = 0; u < E; ++u) {
       if (u & (1 << bb)) continue;
       const int u2 = u | (1 << bb);
-      const uint32_t X = v[u], Y = v[u2];
       if (sum_only) {
-        v[u] = s == 0 ? shoup_lazy(X + Y, ninv, ninvp, q) : csub(X + Y, q2);
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+          v[m][u] = s == 0 ? shoup_lazy(v[m][u] + v[m][u2], ninv, ninvp, q) : csub(v[m][u] + v[m][u2], q2);
       } else if (s == 0) {
-        v[u] = shoup_lazy(X + Y, ninv, ninvp, q);
-        v[u2] = shoup_lazy(X - Y + q2, ninvw, ninvwp, q);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const uint32_t X = v[m][u], Y = v[m][u2];
+          v[m][u] = shoup_lazy(X + Y, ninv, ninvp, q);
+          v[m][u2] = shoup_lazy(X - Y + q2, ninvw, ninvwp, q);
+        }
       } else {
         const uint2 w = tws(u, b);
-        v[u] = csub(X + Y, q2);
-        v[u2] = shoup_lazy(X - Y + q2, w.x, w.y, q);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const uint32_t X = v[m][u], Y = v[m][u2];
+          v[m][u] = csub(X + Y, q2);
+          v[m][u2] = shoup_lazy(X - Y + q2, w.x, w.y, q);
+        }
       }
     }
   }
@@ -214,27 +225,33 @@ struct FwdPasses<LOGN, ELOG, 0> {
   }
 };
 
-template <int LOGN, int ELOG, int K, int PS>
+// Polynomial m exchanges through lds + m * lds_words(LOGN).
+__host__ __device__ constexpr uint32_t lds_words(int logn) { return (1u << logn) + (1u << logn) / 32; }
+
+template <int LOGN, int ELOG, int K, int PS, int M>
 struct InvPasses {
-  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid,
+  static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *lds, uint32_t tid,
                                              const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
                                              uint32_t bp) {
     constexpr int LO = pass_lo_inv(LOGN, ELOG, K), EP = pass_bits(LOGN, ELOG, K);
     constexpr int PLO = pass_lo_inv(LOGN, ELOG, K - 1), PEP = pass_bits(LOGN, ELOG, K - 1);
-    InvPasses<LOGN, ELOG, K - 1, PS>::run(v, lds, tid, tw, q, a, ap, b, bp);
-    regs_to_lds<LOGN, ELOG, PLO, PEP>(v, lds, tid);
+    InvPasses<LOGN, ELOG, K - 1, PS, M>::run(v, lds, tid, tw, q, a, ap, b, bp);
+#pragma unroll
+    for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, PLO, PEP>(v[m], lds + m * lds_words(LOGN), tid);
     __syncthreads();
-    lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
-    inv_pass<LOGN, ELOG, LO, EP, PS>(v, tid, tw, q, a, ap, b, bp);
+#pragma unroll
+    for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
+    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tid, tw, q, a, ap, b, bp);
   }
 };
-template <int LOGN, int ELOG, int PS>
-struct InvPasses<LOGN, ELOG, 0, PS> {
+template <int LOGN, int ELOG, int PS, int M>
+struct InvPasses<LOGN, ELOG, 0, PS, M> {
   // pass 0 (bits [0, EP)) expects its inputs already in registers
-  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *, uint32_t tid, const uint2 *tw,
-                                             uint32_t q, uint32_t a, uint32_t ap, uint32_t b, uint32_t bp) {
+  static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *, uint32_t tid,
+                                             const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
+                                             uint32_t bp) {
     constexpr int LO = pass_lo_inv(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
-    inv_pass<LOGN, ELOG, LO, EP, PS>(v, tid, tw, q, a, ap, b, bp);
+    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tid, tw, q, a, ap, b, bp);
   }
 };
 
@@ -297,13 +314,17 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
 }
 
 // ---------------------------------------------------------------- inverse NTT kernels
-// PS: top stages pruned (see inv_pass); 0 for the whole transform.
-template <int LOGN, int ELOG, int PS = 0>
-__device__ __forceinline__ void intt_core(const uint32_t *src, uint32_t (&v)[1 << ELOG], uint32_t *lds,
-                                          uint32_t tid, const LimbConsts &c, const uint2 *tw, uint32_t l) {
+// PS: top stages pruned (see inv_pass); 0 for the whole transform. M
+// polynomials src[m] of one limb, LDS of M * lds_words(LOGN) words.
+template <int LOGN, int ELOG, int PS, int M>
+__device__ __forceinline__ void intt_core(const uint32_t *const (&src)[M], uint32_t (&v)[M][1 << ELOG],
+                                          uint32_t *lds, uint32_t tid, const LimbConsts &c, const uint2 *tw,
+                                          uint32_t l) {
   constexpr int NP = n_pass(LOGN, ELOG);
-  load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v, src, tid);
-  InvPasses<LOGN, ELOG, NP - 1, PS>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l], c.ninvw_p[l]);
+#pragma unroll
+  for (int m = 0; m < M; ++m) load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v[m], src[m], tid);
+  InvPasses<LOGN, ELOG, NP - 1, PS, M>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l],
+                                            c.ninvw_p[l]);
 }
 
 // Full mode: [P][N] -> [P][N] canonical (in place allowed).
@@ -315,14 +336,15 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
   const uint32_t tid = threadIdx.x;
   const size_t poly = blockIdx.x;
   const uint32_t l = (uint32_t)(poly % c.L);
-  uint32_t v[E];
-  intt_core<LOGN, ELOG>(in + poly * N, v, lds, tid, c, tws.inv + (size_t)l * N, l);
+  uint32_t v[1][E];
+  const uint32_t *const src[1] = {in + poly * N};
+  intt_core<LOGN, ELOG, 0, 1>(src, v, lds, tid, c, tws.inv + (size_t)l * N, l);
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
   uint32_t *dst = out + poly * N;
   const uint32_t q = c.q[l];
   uint32_t *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
 #pragma unroll
-  for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[u], q);
+  for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[0][u], q);
 }
 
 // Masked mode over Yhat [B][O][2][L][N]: c1 polynomials are written whole to
@@ -332,54 +354,81 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
 // separate buffers (out.mask[b], out.c0[b], out.c1[b]) laid out as for B = 1.
 // PS: top stages of the c0 transform that are pruned (2^(LOGN - PS) must
 // exceed every extracted coefficient index); c1 is always transformed whole.
-template <int LOGN, int ELOG, int PS>
+// M: polynomials per workgroup, those of M consecutive (image, output
+// ciphertext) indices bo with the same half p and limb l; workgroup w is
+// ((pair 2 + p) L + l), bo = pair M + m. Slots past B O compute a copy of
+// slot 0 and store nothing.
+template <int LOGN, int ELOG, int PS, int M>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32_t *yhat, const uint32_t *mask,
                                                                      uint32_t *c0_ext, uint32_t *c1_out, ConvGeom g,
-                                                                     LimbConsts c, Twiddles tws, OutPtrs out) {
+                                                                     uint32_t B, LimbConsts c, Twiddles tws,
+                                                                     OutPtrs out) {
   constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
-  __shared__ uint32_t lds[N + N / 32];
+  __shared__ uint32_t lds[M * lds_words(LOGN)];
   const uint32_t tid = threadIdx.x;
-  const size_t poly = blockIdx.x;  // ((b O + o) 2 + p) L + l
-  const uint32_t l = (uint32_t)(poly % g.L);
-  const uint32_t p = (uint32_t)((poly / g.L) % 2);
-  const size_t bo = poly / (2 * (size_t)g.L);  // b O + o
-  const uint32_t o = (uint32_t)(bo % g.O);
-  const size_t b = bo / g.O;
+  const uint32_t wg = blockIdx.x;
+  const uint32_t l = wg % g.L;
+  const uint32_t p = (wg / g.L) % 2;
+  const size_t pair = wg / (2 * g.L);
+  const size_t nbo = (size_t)B * g.O;
+  size_t bo[M];
+  bool valid[M];
+  const uint32_t *src[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    bo[m] = pair * M + m;
+    valid[m] = bo[m] < nbo;  // uniform
+    src[m] = yhat + (((valid[m] ? bo[m] : bo[0]) * 2 + p) * g.L + l) * (size_t)N;
+  }
   const uint32_t q = c.q[l];
-  uint32_t v[E];
+  uint32_t v[M][E];
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
   const uint2 *tw = tws.inv + (size_t)l * N;
   if (p == 1) {
-    intt_core<LOGN, ELOG, 0>(yhat + poly * N, v, lds, tid, c, tw, l);
-    uint32_t *dst = out.n ? (uint32_t *)out.c1[b] + ((size_t)o * g.L + l) * N : c1_out + (bo * g.L + l) * (size_t)N;
-    uint32_t *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+    intt_core<LOGN, ELOG, 0, M>(src, v, lds, tid, c, tw, l);
 #pragma unroll
-    for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[u], q);
+    for (int m = 0; m < M; ++m) {
+      if (!valid[m]) continue;
+      const uint32_t o = (uint32_t)(bo[m] % g.O);
+      const size_t b = bo[m] / g.O;
+      uint32_t *dst = out.n ? (uint32_t *)out.c1[b] + ((size_t)o * g.L + l) * N : c1_out + (bo[m] * g.L + l) * (size_t)N;
+      uint32_t *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+#pragma unroll
+      for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[m][u], q);
+    }
     return;
   }
   // c0 needs only its extracted coefficients
-  intt_core<LOGN, ELOG, PS>(yhat + poly * N, v, lds, tid, c, tw, l);
+  intt_core<LOGN, ELOG, PS, M>(src, v, lds, tid, c, tw, l);
   __syncthreads();
-  regs_to_lds<LOGN, ELOG, LO, EP>(v, lds, tid);
+#pragma unroll
+  for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
   __syncthreads();
-  const uint32_t i = o / g.T, tau = o % g.T;
-  // output rows of this tile: s*oy in [tau r_o, (tau+1) r_o)  (r_o is a multiple of s)
-  const uint32_t oy0 = tau * g.r_o / g.s;
-  const uint32_t oy1 = min(g.ho, (tau + 1) * g.r_o / g.s);
-  const uint32_t count = (oy1 > oy0 ? oy1 - oy0 : 0) * g.wo;
   const uint32_t t = c.t, half = c.t / 2;
   const uint32_t dl = c.delta[l], dlp = c.delta_p[l];
   const size_t hw = (size_t)g.ho * g.wo;
-  const uint32_t *mrow = out.n ? (const uint32_t *)out.mask[b] + i * hw : mask + (b * g.c_out + i) * hw;
-  uint32_t *orow = out.n ? (uint32_t *)out.c0[b] + ((size_t)i * g.L + l) * hw
-                         : c0_ext + ((b * g.c_out + i) * g.L + l) * hw;
-  for (uint32_t idx = tid; idx < count; idx += NT) {
-    const uint32_t oy = oy0 + idx / g.wo, ox = idx % g.wo;
-    const uint32_t e = (g.s * oy - tau * g.r_o) * g.w_pad + g.s * ox;
-    const uint32_t r = mrow[oy * g.wo + ox];
-    const uint32_t rc = r > half ? r - t + q : r;  // centred lift of r, taken mod q
-    const uint32_t add = csub(shoup_lazy(rc, dl, dlp, q), q);
-    orow[oy * g.wo + ox] = csub(csub(lds[lpad(e)], q) + add, q);
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    if (!valid[m]) continue;
+    const uint32_t o = (uint32_t)(bo[m] % g.O);
+    const size_t b = bo[m] / g.O;
+    const uint32_t *lm = lds + m * lds_words(LOGN);
+    const uint32_t i = o / g.T, tau = o % g.T;
+    // output rows of this tile: s*oy in [tau r_o, (tau+1) r_o)  (r_o is a multiple of s)
+    const uint32_t oy0 = tau * g.r_o / g.s;
+    const uint32_t oy1 = min(g.ho, (tau + 1) * g.r_o / g.s);
+    const uint32_t count = (oy1 > oy0 ? oy1 - oy0 : 0) * g.wo;
+    const uint32_t *mrow = out.n ? (const uint32_t *)out.mask[b] + i * hw : mask + (b * g.c_out + i) * hw;
+    uint32_t *orow = out.n ? (uint32_t *)out.c0[b] + ((size_t)i * g.L + l) * hw
+                           : c0_ext + ((b * g.c_out + i) * g.L + l) * hw;
+    for (uint32_t idx = tid; idx < count; idx += NT) {
+      const uint32_t oy = oy0 + idx / g.wo, ox = idx % g.wo;
+      const uint32_t e = (g.s * oy - tau * g.r_o) * g.w_pad + g.s * ox;
+      const uint32_t r = mrow[oy * g.wo + ox];
+      const uint32_t rc = r > half ? r - t + q : r;  // centred lift of r, taken mod q
+      const uint32_t add = csub(shoup_lazy(rc, dl, dlp, q), q);
+      orow[oy * g.wo + ox] = csub(csub(lm[lpad(e)], q) + add, q);
+    }
   }
 }
 
@@ -831,27 +880,39 @@ static hipError_t inv_t(const uint32_t *in, uint32_t *out, size_t np, const Limb
                      tw);
   return hipGetLastError();
 }
-template <int LOGN, int ELOG, int PS>
+template <int LOGN, int ELOG, int PS, int M>
 static hipError_t invm_ps(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
                           uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
-  const size_t np = (size_t)B * g.O * 2 * g.L;
-  if (np == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG, PS>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, y, m, c0,
-                     c1, g, c, tw, out);
+  const size_t nbo = (size_t)B * g.O;
+  const size_t nwg = (nbo + M - 1) / M * 2 * g.L;
+  if (nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG, PS, M>), dim3((uint32_t)nwg), dim3(1 << (LOGN - ELOG)), 0, st, y, m,
+                     c0, c1, g, B, c, tw, out);
   return hipGetLastError();
 }
-// Pruning fewer stages than allowed is always exact: take the largest
-// instantiated count not above LOGN - prune_bits.
-template <int LOGN, int ELOG>
-static hipError_t invm_t(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
-                         uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
+template <int LOGN, int ELOG, int M>
+static hipError_t invm_pm(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
+                          uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
   const int ps = LOGN - (int)g.prune_bits;
-  if (ps >= 7) return invm_ps<LOGN, ELOG, 7>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 5) return invm_ps<LOGN, ELOG, 5>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 3) return invm_ps<LOGN, ELOG, 3>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 2) return invm_ps<LOGN, ELOG, 2>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 1) return invm_ps<LOGN, ELOG, 1>(g, y, m, c0, c1, B, c, tw, out, st);
-  return invm_ps<LOGN, ELOG, 0>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 7) return invm_ps<LOGN, ELOG, 7, M>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 5) return invm_ps<LOGN, ELOG, 5, M>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 3) return invm_ps<LOGN, ELOG, 3, M>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 2) return invm_ps<LOGN, ELOG, 2, M>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 1) return invm_ps<LOGN, ELOG, 1, M>(g, y, m, c0, c1, B, c, tw, out, st);
+  return invm_ps<LOGN, ELOG, 0, M>(g, y, m, c0, c1, B, c, tw, out, st);
+}
+// Pruning fewer stages than allowed is always exact: take the largest
+// instantiated count not above LOGN - prune_bits. Two polynomials per
+// workgroup exist for ELOG <= 4 (the register and LDS budgets of ELOG 5).
+template <int LOGN, int ELOG>
+static hipError_t invm_t(const ConvGeom &g, uint32_t npw, const uint32_t *y, const uint32_t *m, uint32_t *c0,
+                         uint32_t *c1, uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out,
+                         hipStream_t st) {
+  if (npw == 1) return invm_pm<LOGN, ELOG, 1>(g, y, m, c0, c1, B, c, tw, out, st);
+  if constexpr (ELOG <= 4) {
+    if (npw == 2) return invm_pm<LOGN, ELOG, 2>(g, y, m, c0, c1, B, c, tw, out, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 // (LOGN, ELOG) instances: 2^(LOGN - ELOG) threads per polynomial.
@@ -887,13 +948,17 @@ hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, ui
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
   HC_NTT_DISPATCH(inv_t, in, out, np, c, tw, st)
 }
-hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, const uint32_t *y, const uint32_t *m,
-                              uint32_t *c0, uint32_t *c1, uint32_t B, const LimbConsts &c, const Twiddles &tw,
-                              hipStream_t st, const OutPtrs *tab) {
+bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw) {
+  return ntt_variant_ok(logn, elog) && (npw == 1 || (npw == 2 && elog <= 4));
+}
+
+hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, uint32_t npw, const uint32_t *y,
+                              const uint32_t *m, uint32_t *c0, uint32_t *c1, uint32_t B, const LimbConsts &c,
+                              const Twiddles &tw, hipStream_t st, const OutPtrs *tab) {
   OutPtrs none{};
   if (tab && (tab->n != B || B > kMaxTab)) return hipErrorInvalidValue;
   const OutPtrs &t = tab ? *tab : none;
-  HC_NTT_DISPATCH(invm_t, g, y, m, c0, c1, B, c, tw, t, st)
+  HC_NTT_DISPATCH(invm_t, g, npw, y, m, c0, c1, B, c, tw, t, st)
 }
 
 template <int BT, int CT, int RG, int CG, int NS, int LDS>

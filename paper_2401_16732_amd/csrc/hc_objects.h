@@ -39,7 +39,7 @@ hc_status hip_fail(hipError_t e, const char *where);
 
 // Launch shapes in effect for B images.
 struct Shapes {
-  uint32_t fe, ie;
+  uint32_t fe, ie, ipw;  // ipw: polynomials per workgroup of the masked inverse NTT
   MacShape mac;
 };
 Shapes shapes_for(const hc_ctx &c, uint32_t B);

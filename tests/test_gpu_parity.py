@@ -204,6 +204,8 @@ def test_every_launch_shape_gives_the_same_bits(hc, N, elogs):
     dx, dr = dev(x), dev(r)
     ws = zeros((ly.workspace_words(B, True),))
     cases = [(fe, ie, 0, 0, 0, 0) for fe in elogs for ie in elogs] + [(0, 0) + v for v in MAC_VARIANTS]
+    # two inverse-NTT polynomials per workgroup; B * out_cts = 39 leaves the last pair half empty
+    cases += [(0, ie, 0, 0, 0, 0, 0, 0, 2) for ie in elogs if ie <= 4]
     for tune in cases:
         print(f"N={N} tuning {tune}", flush=True)
         c.set_tuning(*tune)
@@ -224,6 +226,9 @@ def test_every_launch_shape_gives_the_same_bits(hc, N, elogs):
         c.set_tuning(0, 0, 0, 0, 0, 0, 4)
     with pytest.raises(hc.HcError):  # nor is the LDS flag
         c.set_tuning(0, 0, 0, 0, 0, 0, 0, 1)
+    if 5 in elogs:
+        with pytest.raises(hc.HcError):  # two polynomials per workgroup need inv_elog <= 4
+            c.set_tuning(0, 5, 0, 0, 0, 0, 0, 0, 2)
 
 
 def test_mac_ring_over_many_input_ciphertexts(hc):
