@@ -80,13 +80,15 @@ def hbm_copy(torch, dev, gib, reps=5):
     return {"bytes_per_copy": 2 * n * 4, "ms": round(ms, 3), "GBps": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
 
 
-KERNEL_KEYS = {"ntt_fwd": "k_ntt_fwd", "mac": "k_mac_tiled", "intt_mask_extract": "k_intt_masked"}
+# stage -> kernels launched for it (the MAC has a register-tiled and an LDS-staged form)
+STAGE_KERNELS = {"ntt_fwd": ("k_ntt_fwd",), "mac": ("k_mac_tiled", "k_mac_lds"), "intt_mask_extract": ("k_intt_masked",)}
 
 
 def measured_traffic(kernel: str, tag: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
-    summary is missing or was taken on a different kernel source."""
+    """HBM bytes per launch of stage `kernel` (all kernels of the stage) from the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated), or None when the summary is missing or was taken on a
+    different kernel source."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", f"hbm_traffic_{tag}.md")
@@ -100,7 +102,7 @@ def measured_traffic(kernel: str, tag: str):
             got = line.split(":", 1)[1].strip()
         elif line.startswith("traffic_bytes_per_launch:"):
             k, v = line.split(":", 1)[1].split("=")
-            if k.strip() == KERNEL_KEYS.get(kernel):
+            if k.strip() == f"stage {kernel}":
                 val = float(v)
     return val if got == cur else None
 
