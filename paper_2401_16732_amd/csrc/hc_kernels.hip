@@ -453,14 +453,18 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
   const uint32_t nwg = gridDim.x;
   uint32_t wg = blockIdx.x;
   if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
-  const uint32_t ib = wg % nib;
-  uint32_t r = wg / nib;
+  // image tiles vary fastest: the workgroups that share one weight tile run
+  // next to each other (on one XCD, by the remap above), then channel tiles,
+  // which share input tiles
+  const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
+  const uint32_t bt = wg % nbt;
+  uint32_t r = wg / nbt;
+  const uint32_t ib = r % nib;
+  r /= nib;
   const uint32_t tau = r % g.T;
   r /= g.T;
   const uint32_t kb = r % nkb;
-  r /= nkb;
-  const uint32_t l = r % g.L;
-  const uint32_t bt = r / g.L;
+  const uint32_t l = r / nkb;
   // wave-uniform indices (readfirstlane keeps the bases in scalar registers)
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t lane = threadIdx.x & 63u;
@@ -639,14 +643,18 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__rest
   const uint32_t nwg = gridDim.x;
   uint32_t wg = blockIdx.x;
   if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
-  const uint32_t ib = wg % nib;
-  uint32_t r = wg / nib;
+  // image tiles vary fastest: the workgroups that share one weight tile run
+  // next to each other (on one XCD, by the remap above), then channel tiles,
+  // which share input tiles
+  const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
+  const uint32_t bt = wg % nbt;
+  uint32_t r = wg / nbt;
+  const uint32_t ib = r % nib;
+  r /= nib;
   const uint32_t tau = r % g.T;
   r /= g.T;
   const uint32_t kb = r % nkb;
-  r /= nkb;
-  const uint32_t l = r % g.L;
-  const uint32_t bt = r / g.L;
+  const uint32_t l = r / nkb;
   const uint32_t tid = threadIdx.x;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t lane = tid & 63u;
