@@ -113,6 +113,8 @@ typedef struct {
                                  with 16-byte loads; 0: every wave loads its operands itself */
     uint32_t inv_polys;       /* masked inverse NTT: polynomials per workgroup, sharing each twiddle
                                  load (1, or 2 when inv_elog <= 4; 0 = 1) */
+    uint32_t mac_pre;         /* masked conv: inverse NTT stages the LDS-staged MAC applies to its
+                                 outputs before storing them (0, or 5 for 4x8 tiles, N >= 4096) */
 } hc_tuning;
 
 /* Create a context on HIP device `hip_device`: ring degree N (power of two,

@@ -224,13 +224,13 @@ hc::Shapes hc::shapes_for(const hc_ctx &c, uint32_t B) {
   if (c.tune.mac_rows) {
     s.mac = mac_of(c.tune);
   } else if (B >= 16) {
-    s.mac = {4, 8, 4, 2, 2, 0};
+    s.mac = {4, 8, 4, 2, 2, 0, 0};
   } else if (B >= 4) {
-    s.mac = {4, 4, 1, 4, 2, 0};
+    s.mac = {4, 4, 1, 4, 2, 0, 0};
   } else if (B >= 2) {
-    s.mac = {2, 4, 1, 4, 2, 0};
+    s.mac = {2, 4, 1, 4, 2, 0, 0};
   } else {
-    s.mac = {1, 8, 1, 4, 2, 0};
+    s.mac = {1, 8, 1, 4, 2, 0, 0};
   }
   return s;
 }
@@ -244,7 +244,7 @@ hc::Shapes hc::layer_shapes(const hc_layer *ly, uint32_t B) {
     if (t.inv_polys) s.ipw = t.inv_polys;
     if (t.mac_rows) s.mac = mac_of(t);
   }
-  if (!hc::intt_masked_ok(ly->ctx->logn, s.ie, s.ipw)) s.ipw = 1;  // e.g. a tuned e = 5 under a context's 2
+  if (!hc::intt_masked_ok(ly->ctx->logn, s.ie, s.ipw, s.mac.pre)) s.ipw = 1;  // e.g. a tuned e = 5 under a context's 2
   return s;
 }
 
@@ -273,15 +273,18 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
   HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, ct_in, xhat, npin, c.consts, c.tw, st));
   if (timed) HC_HIP(hipEventRecord(tm->ev[1], st));
   if (!masked) {
-    HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, ct_out, B, c.consts, st));
+    hc::MacShape m = sh.mac;
+    m.pre = 0;  // the full inverse NTT runs every stage
+    HC_HIP(hc::launch_mac(g, m, xhat, ly->d_w, ct_out, B, c.consts, c.tw, st));
     HC_HIP(hc::launch_intt_full(c.logn, sh.ie, ct_out, ct_out, (size_t)B * g.O * 2 * c.L, c.consts, c.tw, st));
   } else {
     uint32_t *yhat = xhat + npin * c.N;
     if (timed) HC_HIP(hipEventRecord(tm->ev[2], st));
-    HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, st));
+    HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, c.tw, st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[3], st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[4], st));
-    HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, sh.ipw, yhat, mask, c0_ext, c1_out, B, c.consts, c.tw, st));
+    HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, sh.ipw, sh.mac.pre, yhat, mask, c0_ext, c1_out, B, c.consts,
+                                  c.tw, st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[5], st));
   }
   return HC_OK;
@@ -319,9 +322,9 @@ hc_status hc::enqueue_conv_gather(const hc_layer *ly, uint32_t B, const uint32_t
   const size_t npin = (size_t)B * ppi;
   HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, nullptr, xhat, npin, c.consts, c.tw, st, &in, ppi));
   uint32_t *yhat = xhat + npin * c.N;
-  HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, st));
-  HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, sh.ipw, yhat, nullptr, nullptr, nullptr, B, c.consts, c.tw, st,
-                                &out));
+  HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, c.tw, st));
+  HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, sh.ipw, sh.mac.pre, yhat, nullptr, nullptr, nullptr, B, c.consts,
+                                c.tw, st, &out));
   return HC_OK;
 }
 
@@ -481,10 +484,11 @@ hc_status hc_ctx_set_tuning(hc_ctx *c, const hc_tuning *t) {
   if (t->inv_elog && !hc::ntt_variant_ok(c->logn, t->inv_elog))
     return fail(HC_EUNSUPPORTED, "inverse NTT shape not available for this N");
   if (t->inv_polys &&
-      !hc::intt_masked_ok(c->logn, t->inv_elog ? t->inv_elog : default_inv_elog(c->logn), t->inv_polys))
+      !hc::intt_masked_ok(c->logn, t->inv_elog ? t->inv_elog : default_inv_elog(c->logn), t->inv_polys, 0))
     return fail(HC_EUNSUPPORTED, "inverse NTT polynomials per workgroup not available for this shape");
-  const bool any =
-      t->mac_rows || t->mac_cols || t->mac_row_groups || t->mac_col_groups || t->mac_depth || t->mac_lds;
+  if (t->mac_pre && c->logn < 12) return fail(HC_EUNSUPPORTED, "MAC epilogue stages need N >= 4096");
+  const bool any = t->mac_rows || t->mac_cols || t->mac_row_groups || t->mac_col_groups || t->mac_depth ||
+                   t->mac_lds || t->mac_pre;
   const bool all = t->mac_rows && t->mac_cols && t->mac_row_groups && t->mac_col_groups;
   if (any && !all) return fail(HC_EINVAL, "set all four MAC fields or none");
   if (all && !hc::mac_variant_ok(hc::mac_of(*t)))
@@ -723,6 +727,7 @@ hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_depth);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_lds);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.inv_polys);
+  key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_pre);
   for (size_t k = 0; k < n; ++k) {
     key.push_back(ct_in[k]);
     key.push_back(mask[k]);
@@ -825,14 +830,17 @@ hc_status time_it(F fn, hipStream_t st, int reps, float *ms) {
   return HC_OK;
 }
 
-// (images, channels per thread; image, channel wave groups; loads in flight; LDS-staged)
-const uint32_t kMacCand[][6] = {{1, 8, 1, 4, 2, 0}, {1, 4, 1, 4, 2, 0}, {2, 4, 1, 4, 2, 0}, {4, 4, 1, 4, 2, 0},
-                                {4, 2, 1, 4, 2, 0}, {8, 2, 1, 4, 2, 0}, {4, 4, 4, 2, 2, 0}, {4, 8, 4, 2, 2, 0},
-                                {2, 8, 4, 2, 2, 0}, {4, 4, 2, 4, 2, 0}, {2, 4, 4, 4, 2, 0}, {1, 8, 2, 4, 2, 0},
-                                {4, 8, 4, 2, 3, 0}, {2, 8, 4, 2, 4, 0}, {4, 4, 4, 2, 4, 0}, {4, 4, 2, 4, 4, 0},
-                                {1, 8, 2, 4, 4, 0}, {2, 4, 4, 4, 4, 0}, {1, 8, 1, 4, 4, 0}, {4, 8, 4, 2, 2, 1},
-                                {4, 8, 4, 2, 3, 1}, {4, 8, 2, 2, 2, 1}, {4, 8, 2, 2, 3, 1}, {2, 8, 4, 2, 3, 1},
-                                {4, 4, 4, 2, 3, 1}, {2, 8, 2, 2, 3, 1}};
+// (images, channels per thread; image, channel wave groups; loads in flight; LDS-staged;
+//  inverse NTT stages in the MAC's epilogue)
+const uint32_t kMacCand[][7] = {
+    {1, 8, 1, 4, 2, 0, 0}, {1, 4, 1, 4, 2, 0, 0}, {2, 4, 1, 4, 2, 0, 0}, {4, 4, 1, 4, 2, 0, 0},
+    {4, 2, 1, 4, 2, 0, 0}, {8, 2, 1, 4, 2, 0, 0}, {4, 4, 4, 2, 2, 0, 0}, {4, 8, 4, 2, 2, 0, 0},
+    {2, 8, 4, 2, 2, 0, 0}, {4, 4, 2, 4, 2, 0, 0}, {2, 4, 4, 4, 2, 0, 0}, {1, 8, 2, 4, 2, 0, 0},
+    {4, 8, 4, 2, 3, 0, 0}, {2, 8, 4, 2, 4, 0, 0}, {4, 4, 4, 2, 4, 0, 0}, {4, 4, 2, 4, 4, 0, 0},
+    {1, 8, 2, 4, 4, 0, 0}, {2, 4, 4, 4, 4, 0, 0}, {1, 8, 1, 4, 4, 0, 0}, {4, 8, 4, 2, 2, 1, 0},
+    {4, 8, 4, 2, 3, 1, 0}, {4, 8, 2, 2, 2, 1, 0}, {4, 8, 2, 2, 3, 1, 0}, {2, 8, 4, 2, 3, 1, 0},
+    {4, 4, 4, 2, 3, 1, 0}, {2, 8, 2, 2, 3, 1, 0}, {4, 8, 4, 2, 2, 1, 5}, {4, 8, 2, 2, 2, 1, 5},
+    {4, 8, 2, 2, 3, 1, 5}};
 
 }  // namespace
 
@@ -857,9 +865,9 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
         if (!bar) continue;
         *bar = 0;
         hc_tuning t{};
-        if (std::sscanf(bar + 1, "%u %u %u %u %u %u %u %u %u", &t.fwd_elog, &t.inv_elog, &t.mac_rows,
+        if (std::sscanf(bar + 1, "%u %u %u %u %u %u %u %u %u %u", &t.fwd_elog, &t.inv_elog, &t.mac_rows,
                         &t.mac_cols, &t.mac_row_groups, &t.mac_col_groups, &t.mac_depth, &t.mac_lds,
-                        &t.inv_polys) >= 6)
+                        &t.inv_polys, &t.mac_pre) >= 6)
           cache[line] = t;
       }
       std::fclose(f);
@@ -877,7 +885,7 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     if (hit != cache.end()) {
       const hc_tuning &t = hit->second;
       if (hc::ntt_variant_ok(c.logn, t.fwd_elog) &&
-          hc::intt_masked_ok(c.logn, t.inv_elog, t.inv_polys ? t.inv_polys : 1) &&
+          hc::intt_masked_ok(c.logn, t.inv_elog, t.inv_polys ? t.inv_polys : 1, t.mac_pre) &&
           hc::mac_variant_ok(hc::mac_of(t)) && hc::mac_offsets_fit(ly->geom, hc::mac_of(t))) {
         ly->tune = t;
         ly->tune_B = B;
@@ -898,40 +906,48 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
       if (s != HC_OK) return s;
       if (ms < best_ms) best_ms = ms, best.fwd_elog = e;
     }
-    best_ms = 1e30f;
-    for (const auto &m : kMacCand) {
-      const hc::MacShape shape{m[0], m[1], m[2], m[3], m[4], m[5]};
-      if (!hc::mac_variant_ok(shape) || !hc::mac_offsets_fit(g, shape)) continue;
-      float ms;
-      s = time_it([&] {
-        return hc::launch_mac(g, shape, xhat, ly->d_w, yhat, B, c.consts, st);
-      },
-                  st, reps, &ms);
-      if (s != HC_OK) return s;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best.mac_rows = m[0], best.mac_cols = m[1], best.mac_row_groups = m[2], best.mac_col_groups = m[3];
-        best.mac_depth = m[4], best.mac_lds = m[5];
-      }
-    }
-    best_ms = 1e30f;
-    for (uint32_t e = 3; e <= 6; ++e) {
-      for (uint32_t npw = 1; npw <= 2; ++npw) {
-        if (!hc::intt_masked_ok(c.logn, e, npw)) continue;
+    // MAC and inverse NTT are chosen together: with epilogue stages (pre) the
+    // MAC does part of the inverse transform, so compare MAC + inverse NTT
+    // totals of the best of each with and without them.
+    float best_total = 1e30f;
+    for (uint32_t pre : {0u, hc::kMacPre}) {
+      if (pre && c.logn < 12) continue;
+      float mac_ms = 1e30f, inv_ms = 1e30f;
+      hc_tuning t = best;
+      for (const auto &m : kMacCand) {
+        const hc::MacShape shape{m[0], m[1], m[2], m[3], m[4], m[5], m[6]};
+        if (shape.pre != pre || !hc::mac_variant_ok(shape) || !hc::mac_offsets_fit(g, shape)) continue;
         float ms;
-        s = time_it([&] {
-          return hc::launch_intt_masked(g, c.logn, e, npw, yhat, mask[k], c0[k], c1[k], B, c.consts, c.tw, st);
-        }, st, reps, &ms);
+        s = time_it([&] { return hc::launch_mac(g, shape, xhat, ly->d_w, yhat, B, c.consts, c.tw, st); }, st,
+                    reps, &ms);
         if (s != HC_OK) return s;
-        if (ms < best_ms) best_ms = ms, best.inv_elog = e, best.inv_polys = npw;
+        if (ms < mac_ms) {
+          mac_ms = ms;
+          t.mac_rows = m[0], t.mac_cols = m[1], t.mac_row_groups = m[2], t.mac_col_groups = m[3];
+          t.mac_depth = m[4], t.mac_lds = m[5], t.mac_pre = m[6];
+        }
       }
+      if (mac_ms >= 1e30f) continue;
+      for (uint32_t e = 3; e <= 6; ++e) {
+        for (uint32_t npw = 1; npw <= 2; ++npw) {
+          if (!hc::intt_masked_ok(c.logn, e, npw, pre)) continue;
+          float ms;
+          s = time_it([&] {
+            return hc::launch_intt_masked(g, c.logn, e, npw, pre, yhat, mask[k], c0[k], c1[k], B, c.consts, c.tw,
+                                          st);
+          }, st, reps, &ms);
+          if (s != HC_OK) return s;
+          if (ms < inv_ms) inv_ms = ms, t.inv_elog = e, t.inv_polys = npw;
+        }
+      }
+      if (mac_ms + inv_ms < best_total) best_total = mac_ms + inv_ms, best = t;
     }
     ly->tune = best;
     ly->tune_B = B;
     char buf[128];
-    std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog, best.mac_rows,
-                  best.mac_cols, best.mac_row_groups, best.mac_col_groups, best.mac_depth, best.mac_lds,
-                  best.inv_polys);
+    std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog,
+                  best.mac_rows, best.mac_cols, best.mac_row_groups, best.mac_col_groups, best.mac_depth,
+                  best.mac_lds, best.inv_polys, best.mac_pre);
     appended += key + buf;
   }
   if (cache_path && !appended.empty()) {

@@ -60,12 +60,18 @@ struct OutPtrs {
 // the MAC gives each thread bt images x ct output channels, and a workgroup
 // rg x cg such threads per coefficient (image groups x channel groups); depth
 // input ciphertexts are in flight, in registers or (lds) staged through LDS.
+// pre: inverse NTT stages (index bits 0 .. pre-1) applied by the MAC before
+// it stores (0, or kMacPre for LDS-staged tiles with 2 bt ct = 64).
 struct MacShape {
-  uint32_t bt, ct, rg, cg, depth, lds;
+  uint32_t bt, ct, rg, cg, depth, lds, pre;
 };
 bool ntt_variant_ok(uint32_t logn, uint32_t elog);
-// The masked inverse NTT with npw polynomials per workgroup (1, or 2 for elog <= 4).
-bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw);
+// Inverse stages (index bits 0 .. kMacPre-1) the LDS-staged MAC can apply to
+// its outputs before storing them, for the masked inverse NTT to skip.
+constexpr uint32_t kMacPre = 5;
+// The masked inverse NTT with npw polynomials per workgroup (1, or 2 for
+// elog <= 4) that starts at index bit pre (0, or kMacPre for logn >= 12).
+bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre);
 bool mac_variant_ok(const MacShape &m);
 // The MAC addresses its image and channel tiles with 32-bit byte offsets.
 bool mac_offsets_fit(const ConvGeom &g, const MacShape &m);
@@ -80,12 +86,14 @@ hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, ui
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st);
 // Masked mode: in = Yhat [B][O][2][L][N]; c1 polys go to c1_out [B][O][L][N],
 // c0 polys are extracted with the mask into c0_ext [B][c_out][L][ho][wo].
-// tab: optional per-image output tables (tab->n == B). npw: polynomials per workgroup.
-hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, uint32_t npw, const uint32_t *yhat,
+// tab: optional per-image output tables (tab->n == B). npw: polynomials per
+// workgroup; pre: stages already applied by the MAC (0 or kMacPre).
+hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre,
+                              const uint32_t *yhat,
                               const uint32_t *mask, uint32_t *c0_ext, uint32_t *c1_out, uint32_t B,
                               const LimbConsts &c, const Twiddles &tw, hipStream_t st, const OutPtrs *tab = nullptr);
 hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *xhat, const uint32_t *what,
-                      uint32_t *yhat, uint32_t B, const LimbConsts &c, hipStream_t st);
+                      uint32_t *yhat, uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st);
 hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *filters, uint32_t *w, const LimbConsts &c,
                                  hipStream_t st);
 hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st);

@@ -228,14 +228,22 @@ struct FwdPasses<LOGN, ELOG, 0> {
 // Polynomial m exchanges through lds + m * lds_words(LOGN).
 __host__ __device__ constexpr uint32_t lds_words(int logn) { return (1u << logn) + (1u << logn) / 32; }
 
-template <int LOGN, int ELOG, int K, int PS, int M>
+// Inverse passes cover index bits [PRE, LOGN): the stages on bits below PRE
+// were done by the multiply-accumulate's epilogue (PRE = 0: all stages here).
+__host__ __device__ constexpr int inv_np(int logn, int elog, int pre) { return n_pass(logn - pre, elog); }
+__host__ __device__ constexpr int inv_lo(int logn, int elog, int pre, int k) {
+  return pre + pass_lo_inv(logn - pre, elog, k);
+}
+__host__ __device__ constexpr int inv_ep(int logn, int elog, int pre, int k) { return pass_bits(logn - pre, elog, k); }
+
+template <int LOGN, int ELOG, int K, int PS, int M, int PRE>
 struct InvPasses {
   static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *lds, uint32_t tid,
                                              const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
                                              uint32_t bp) {
-    constexpr int LO = pass_lo_inv(LOGN, ELOG, K), EP = pass_bits(LOGN, ELOG, K);
-    constexpr int PLO = pass_lo_inv(LOGN, ELOG, K - 1), PEP = pass_bits(LOGN, ELOG, K - 1);
-    InvPasses<LOGN, ELOG, K - 1, PS, M>::run(v, lds, tid, tw, q, a, ap, b, bp);
+    constexpr int LO = inv_lo(LOGN, ELOG, PRE, K), EP = inv_ep(LOGN, ELOG, PRE, K);
+    constexpr int PLO = inv_lo(LOGN, ELOG, PRE, K - 1), PEP = inv_ep(LOGN, ELOG, PRE, K - 1);
+    InvPasses<LOGN, ELOG, K - 1, PS, M, PRE>::run(v, lds, tid, tw, q, a, ap, b, bp);
 #pragma unroll
     for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, PLO, PEP>(v[m], lds + m * lds_words(LOGN), tid);
     __syncthreads();
@@ -244,13 +252,13 @@ struct InvPasses {
     inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tid, tw, q, a, ap, b, bp);
   }
 };
-template <int LOGN, int ELOG, int PS, int M>
-struct InvPasses<LOGN, ELOG, 0, PS, M> {
-  // pass 0 (bits [0, EP)) expects its inputs already in registers
+template <int LOGN, int ELOG, int PS, int M, int PRE>
+struct InvPasses<LOGN, ELOG, 0, PS, M, PRE> {
+  // pass 0 (bits [PRE, PRE + EP)) expects its inputs already in registers
   static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *, uint32_t tid,
                                              const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
                                              uint32_t bp) {
-    constexpr int LO = pass_lo_inv(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
+    constexpr int LO = inv_lo(LOGN, ELOG, PRE, 0), EP = inv_ep(LOGN, ELOG, PRE, 0);
     inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tid, tw, q, a, ap, b, bp);
   }
 };
@@ -315,16 +323,28 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
 
 // ---------------------------------------------------------------- inverse NTT kernels
 // PS: top stages pruned (see inv_pass); 0 for the whole transform. M
-// polynomials src[m] of one limb, LDS of M * lds_words(LOGN) words.
-template <int LOGN, int ELOG, int PS, int M>
+// polynomials src[m] of one limb, LDS of M * lds_words(LOGN) words. PRE:
+// stages on bits below PRE already done (the first pass then reads its
+// coefficients with coalesced 4-byte loads: lanes map to the low bits).
+template <int LOGN, int ELOG, int PS, int M, int PRE>
 __device__ __forceinline__ void intt_core(const uint32_t *const (&src)[M], uint32_t (&v)[M][1 << ELOG],
                                           uint32_t *lds, uint32_t tid, const LimbConsts &c, const uint2 *tw,
                                           uint32_t l) {
-  constexpr int NP = n_pass(LOGN, ELOG);
+  constexpr int NP = inv_np(LOGN, ELOG, PRE);
+  if constexpr (PRE == 0) {
 #pragma unroll
-  for (int m = 0; m < M; ++m) load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v[m], src[m], tid);
-  InvPasses<LOGN, ELOG, NP - 1, PS, M>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l],
-                                            c.ninvw_p[l]);
+    for (int m = 0; m < M; ++m) load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v[m], src[m], tid);
+  } else {
+    constexpr int LO = inv_lo(LOGN, ELOG, PRE, 0), EP = inv_ep(LOGN, ELOG, PRE, 0);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const uint32_t *sb = src[m] + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+#pragma unroll
+      for (int u = 0; u < (1 << ELOG); ++u) v[m][u] = sb[gidx<LOGN, ELOG, LO, EP>(0, u)];
+    }
+  }
+  InvPasses<LOGN, ELOG, NP - 1, PS, M, PRE>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l],
+                                                 c.ninvw_p[l]);
 }
 
 // Full mode: [P][N] -> [P][N] canonical (in place allowed).
@@ -338,7 +358,7 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
   const uint32_t l = (uint32_t)(poly % c.L);
   uint32_t v[1][E];
   const uint32_t *const src[1] = {in + poly * N};
-  intt_core<LOGN, ELOG, 0, 1>(src, v, lds, tid, c, tws.inv + (size_t)l * N, l);
+  intt_core<LOGN, ELOG, 0, 1, 0>(src, v, lds, tid, c, tws.inv + (size_t)l * N, l);
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
   uint32_t *dst = out + poly * N;
   const uint32_t q = c.q[l];
@@ -357,13 +377,14 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
 // M: polynomials per workgroup, those of M consecutive (image, output
 // ciphertext) indices bo with the same half p and limb l; workgroup w is
 // ((pair 2 + p) L + l), bo = pair M + m. Slots past B O compute a copy of
-// slot 0 and store nothing.
-template <int LOGN, int ELOG, int PS, int M>
+// slot 0 and store nothing. PRE: the stages on index bits below PRE were done
+// by the multiply-accumulate (Yhat holds their output).
+template <int LOGN, int ELOG, int PS, int M, int PRE>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32_t *yhat, const uint32_t *mask,
                                                                      uint32_t *c0_ext, uint32_t *c1_out, ConvGeom g,
                                                                      uint32_t B, LimbConsts c, Twiddles tws,
                                                                      OutPtrs out) {
-  constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
+  constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = inv_np(LOGN, ELOG, PRE);
   __shared__ uint32_t lds[M * lds_words(LOGN)];
   const uint32_t tid = threadIdx.x;
   const uint32_t wg = blockIdx.x;
@@ -382,10 +403,10 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
   }
   const uint32_t q = c.q[l];
   uint32_t v[M][E];
-  constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
+  constexpr int LO = inv_lo(LOGN, ELOG, PRE, NP - 1), EP = inv_ep(LOGN, ELOG, PRE, NP - 1);
   const uint2 *tw = tws.inv + (size_t)l * N;
   if (p == 1) {
-    intt_core<LOGN, ELOG, 0, M>(src, v, lds, tid, c, tw, l);
+    intt_core<LOGN, ELOG, 0, M, PRE>(src, v, lds, tid, c, tw, l);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       if (!valid[m]) continue;
@@ -399,7 +420,7 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
     return;
   }
   // c0 needs only its extracted coefficients
-  intt_core<LOGN, ELOG, PS, M>(src, v, lds, tid, c, tw, l);
+  intt_core<LOGN, ELOG, PS, M, PRE>(src, v, lds, tid, c, tw, l);
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
@@ -624,11 +645,21 @@ struct Chunk<16> {
   __device__ void store(char *lds) const { *(uint4 *)lds = v; }
 };
 
-template <int BT, int CT, int RG, int CG, int R>
+// PRE > 0 (tiles with one output polynomial per lane, 2 BT CT = 64): before
+// storing, the epilogue applies the inverse NTT's first PRE Gentleman-Sande
+// stages (index bits 0 .. PRE-1), which act within the workgroup's block of 64
+// coefficients. In two rounds, one per half of the block, each wave moves its
+// 64 polynomials x 32 coefficients through LDS so that a lane holds 32
+// consecutive coefficients of one polynomial, runs the stages in registers
+// with twiddles that are the same for every lane (scalar loads, shared by the
+// whole workgroup), and goes back through LDS so that the stores are
+// coalesced. The masked inverse NTT then starts at bit PRE.
+template <int BT, int CT, int RG, int CG, int R, int PRE>
 __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__restrict__ X,
                                                           const uint32_t *__restrict__ Wt,
                                                           uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
-                                                          uint32_t nib, uint32_t nkb, LimbConsts c) {
+                                                          uint32_t nib, uint32_t nkb, LimbConsts c,
+                                                          const uint2 *__restrict__ twinv) {
   constexpr int NT = 64 * RG * CG;
   constexpr int NX = RG * BT * 2, NW = CG * CT;               // segments per step
   constexpr int XB = NX * 256 / NT, WB = NW * 256 / NT;       // bytes per thread per step
@@ -638,7 +669,10 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__rest
   static_assert((XW == 4 || XW == 8 || XW == 16) && (WWD == 4 || WWD == 8 || WWD == 16), "access width");
   static_assert(R >= 2 && R * (KX + KW) <= 63, "loads in flight beyond the vector memory counter");
   constexpr uint32_t BUFB = (NX + NW) * 256;  // bytes per LDS buffer
-  __shared__ uint4 stage4[2 * BUFB / 16];
+  static_assert(PRE == 0 || (PRE == 5 && 2 * BT * CT == 64), "epilogue stages need one polynomial per lane");
+  constexpr uint32_t RWW = 64 * 36;             // epilogue: words per wave (64 x (32 + 4 pad))
+  constexpr uint32_t LDSB = PRE ? (2 * BUFB > RG * CG * RWW * 4 ? 2 * BUFB : RG * CG * RWW * 4) : 2 * BUFB;
+  __shared__ uint4 stage4[LDSB / 16];
   char *stage = (char *)stage4;
   const uint32_t nwg = gridDim.x;
   uint32_t wg = blockIdx.x;
@@ -771,22 +805,94 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__rest
       __syncthreads();
     }
   }
-  // wave tile and its stores, as in k_mac_tiled
+  // wave tile and its stores
   const uint32_t i0 = iw + cg * CT, b0 = bw + rg * BT;
-  if (i0 >= g.c_out || b0 >= B) return;
-  const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
   const uint32_t r2p = c.r2_p[l], onep = c.one_p[l];
-  const uint32_t k = kb * 64 + lane;
+  if constexpr (PRE == 0) {
+    if (i0 >= g.c_out || b0 >= B) return;
+    const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
+    const uint32_t k = kb * 64 + lane;
 #pragma unroll
-  for (int cc = 0; cc < CT; ++cc) {
-    if ((uint32_t)cc >= nc) continue;
-    const uint32_t o = (i0 + cc) * g.T + tau;
+    for (int cc = 0; cc < CT; ++cc) {
+      if ((uint32_t)cc >= nc) continue;
+      const uint32_t o = (i0 + cc) * g.T + tau;
 #pragma unroll
-    for (int bb = 0; bb < BT; ++bb) {
-      if ((uint32_t)bb >= nb) continue;
-      uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + k;
-      y[0] = reduce64(acc[cc][bb][0], q, r2, r2p, onep);
-      y[LN] = reduce64(acc[cc][bb][1], q, r2, r2p, onep);
+      for (int bb = 0; bb < BT; ++bb) {
+        if ((uint32_t)bb >= nb) continue;
+        uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + k;
+        y[0] = reduce64(acc[cc][bb][0], q, r2, r2p, onep);
+        y[LN] = reduce64(acc[cc][bb][1], q, r2, r2p, onep);
+      }
+    }
+  } else {
+    // every wave takes part in the epilogue's barriers, also one whose tile
+    // is absent (it stores nothing)
+    uint32_t val[CT][BT][2];
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+        for (int pp = 0; pp < 2; ++pp) val[cc][bb][pp] = reduce64(acc[cc][bb][pp], q, r2, r2p, onep);
+    // polynomial P = (cc BT + bb) 2 + pp of the wave's tile is row P of the
+    // wave's LDS region
+    uint32_t *region = (uint32_t *)stage + wave * RWW;
+    const uint32_t q2 = 2 * q;
+    const uint32_t LOGN = 31 - __builtin_clz(g.N);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();  // the staging buffers, or the previous round's region, are free
+      if ((lane >> 5) == (uint32_t)h) {
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+          for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+            for (int pp = 0; pp < 2; ++pp) region[((cc * BT + bb) * 2 + pp) * 36 + (lane & 31u)] = val[cc][bb][pp];
+      }
+      __syncthreads();
+      uint32_t v[32];
+      const uint4 *r4 = (const uint4 *)(region + lane * 36);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint4 t4 = r4[k];
+        v[4 * k] = t4.x, v[4 * k + 1] = t4.y, v[4 * k + 2] = t4.z, v[4 * k + 3] = t4.w;
+      }
+      // stages on bits 0 .. PRE-1 of j = kb 64 + h 32 + u; twiddle index
+      // 2^(LOGN-1-b) + (j >> (b+1)), the same for every lane of the wave
+      const uint32_t j0 = kb * 64 + h * 32;
+#pragma unroll
+      for (int b = 0; b < PRE; ++b) {
+        const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1 - b)) + (j0 >> (b + 1)));
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          if (u & (1 << b)) continue;
+          const int u2 = u | (1 << b);
+          const uint64_t wt = tw[u >> (b + 1)];
+          const uint32_t X = v[u], Yv = v[u2];
+          v[u] = csub(X + Yv, q2);
+          v[u2] = shoup_lazy(X - Yv + q2, (uint32_t)wt, (uint32_t)(wt >> 32), q);
+        }
+      }
+      // back through the wave's region so that every store instruction
+      // writes two whole 128-byte runs: lanes 0-31 coefficient (lane) of
+      // polynomial 2 jp, lanes 32-63 the same of polynomial 2 jp + 1
+      uint4 *w4 = (uint4 *)(region + lane * 36);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w4[k] = make_uint4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint32_t half = lane >> 5, kk = lane & 31u;
+#pragma unroll
+      for (int jp = 0; jp < 32; ++jp) {
+        const uint32_t P = 2 * jp + half;  // this lane's polynomial for the jp-th store
+        const uint32_t scc = P / (2 * BT), sbb = (P >> 1) % BT, spp = P & 1u;
+        const uint32_t x = region[P * 36 + kk];
+        if (i0 + scc < g.c_out && b0 + sbb < B)
+          Y[(((size_t)(b0 + sbb) * g.O + (i0 + scc) * g.T + tau) * 2 + spp) * LN + (size_t)l * g.N + kb * 64 +
+            h * 32 + kk] = x;
+      }
     }
   }
 }
@@ -888,37 +994,48 @@ static hipError_t inv_t(const uint32_t *in, uint32_t *out, size_t np, const Limb
                      tw);
   return hipGetLastError();
 }
-template <int LOGN, int ELOG, int PS, int M>
+template <int LOGN, int ELOG, int PS, int M, int PRE>
 static hipError_t invm_ps(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
                           uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
   const size_t nbo = (size_t)B * g.O;
   const size_t nwg = (nbo + M - 1) / M * 2 * g.L;
   if (nwg == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG, PS, M>), dim3((uint32_t)nwg), dim3(1 << (LOGN - ELOG)), 0, st, y, m,
-                     c0, c1, g, B, c, tw, out);
+  hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG, PS, M, PRE>), dim3((uint32_t)nwg), dim3(1 << (LOGN - ELOG)), 0, st,
+                     y, m, c0, c1, g, B, c, tw, out);
   return hipGetLastError();
 }
-template <int LOGN, int ELOG, int M>
+template <int LOGN, int ELOG, int M, int PRE>
 static hipError_t invm_pm(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
                           uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
   const int ps = LOGN - (int)g.prune_bits;
-  if (ps >= 7) return invm_ps<LOGN, ELOG, 7, M>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 5) return invm_ps<LOGN, ELOG, 5, M>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 3) return invm_ps<LOGN, ELOG, 3, M>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 2) return invm_ps<LOGN, ELOG, 2, M>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 1) return invm_ps<LOGN, ELOG, 1, M>(g, y, m, c0, c1, B, c, tw, out, st);
-  return invm_ps<LOGN, ELOG, 0, M>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 7) return invm_ps<LOGN, ELOG, 7, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 5) return invm_ps<LOGN, ELOG, 5, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 3) return invm_ps<LOGN, ELOG, 3, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 2) return invm_ps<LOGN, ELOG, 2, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 1) return invm_ps<LOGN, ELOG, 1, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
+  return invm_ps<LOGN, ELOG, 0, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
 }
 // Pruning fewer stages than allowed is always exact: take the largest
 // instantiated count not above LOGN - prune_bits. Two polynomials per
-// workgroup exist for ELOG <= 4 (the register and LDS budgets of ELOG 5).
+// workgroup exist for ELOG <= 4 (the register and LDS budgets of ELOG 5);
+// the forms that start at bit kMacPre exist for LOGN >= 12.
 template <int LOGN, int ELOG>
-static hipError_t invm_t(const ConvGeom &g, uint32_t npw, const uint32_t *y, const uint32_t *m, uint32_t *c0,
-                         uint32_t *c1, uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out,
-                         hipStream_t st) {
-  if (npw == 1) return invm_pm<LOGN, ELOG, 1>(g, y, m, c0, c1, B, c, tw, out, st);
-  if constexpr (ELOG <= 4) {
-    if (npw == 2) return invm_pm<LOGN, ELOG, 2>(g, y, m, c0, c1, B, c, tw, out, st);
+static hipError_t invm_t(const ConvGeom &g, uint32_t npw, uint32_t pre, const uint32_t *y, const uint32_t *m,
+                         uint32_t *c0, uint32_t *c1, uint32_t B, const LimbConsts &c, const Twiddles &tw,
+                         const OutPtrs &out, hipStream_t st) {
+  if (pre == 0) {
+    if (npw == 1) return invm_pm<LOGN, ELOG, 1, 0>(g, y, m, c0, c1, B, c, tw, out, st);
+    if constexpr (ELOG <= 4) {
+      if (npw == 2) return invm_pm<LOGN, ELOG, 2, 0>(g, y, m, c0, c1, B, c, tw, out, st);
+    }
+  }
+  if constexpr (LOGN >= 12) {
+    if (pre == kMacPre) {
+      if (npw == 1) return invm_pm<LOGN, ELOG, 1, kMacPre>(g, y, m, c0, c1, B, c, tw, out, st);
+      if constexpr (ELOG <= 4) {
+        if (npw == 2) return invm_pm<LOGN, ELOG, 2, kMacPre>(g, y, m, c0, c1, B, c, tw, out, st);
+      }
+    }
   }
   return hipErrorInvalidValue;
 }
@@ -956,31 +1073,32 @@ hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, ui
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
   HC_NTT_DISPATCH(inv_t, in, out, np, c, tw, st)
 }
-bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw) {
-  return ntt_variant_ok(logn, elog) && (npw == 1 || (npw == 2 && elog <= 4));
+bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre) {
+  return ntt_variant_ok(logn, elog) && (npw == 1 || (npw == 2 && elog <= 4)) &&
+         (pre == 0 || (pre == kMacPre && logn >= 12));
 }
 
-hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, uint32_t npw, const uint32_t *y,
-                              const uint32_t *m, uint32_t *c0, uint32_t *c1, uint32_t B, const LimbConsts &c,
-                              const Twiddles &tw, hipStream_t st, const OutPtrs *tab) {
+hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre,
+                              const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1, uint32_t B,
+                              const LimbConsts &c, const Twiddles &tw, hipStream_t st, const OutPtrs *tab) {
   OutPtrs none{};
   if (tab && (tab->n != B || B > kMaxTab)) return hipErrorInvalidValue;
   const OutPtrs &t = tab ? *tab : none;
-  HC_NTT_DISPATCH(invm_t, g, npw, y, m, c0, c1, B, c, tw, t, st)
+  HC_NTT_DISPATCH(invm_t, g, npw, pre, y, m, c0, c1, B, c, tw, t, st)
 }
 
-template <int BT, int CT, int RG, int CG, int NS, int LDS>
+template <int BT, int CT, int RG, int CG, int NS, int LDS, int PRE>
 static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
-                        const LimbConsts &c, hipStream_t st) {
-  if (!mac_offsets_fit(g, MacShape{BT, CT, RG, CG, NS, LDS})) return hipErrorInvalidValue;
+                        const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  if (!mac_offsets_fit(g, MacShape{BT, CT, RG, CG, NS, LDS, PRE})) return hipErrorInvalidValue;
   const uint32_t nkb = g.N / 64;
   const uint32_t nib = (g.c_out + CG * CT - 1) / (CG * CT);
   const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
   const size_t nwg = (size_t)nib * g.T * nkb * g.L * nbt;
   if (nwg == 0) return hipSuccess;
   if constexpr (LDS != 0)
-    hipLaunchKernelGGL((k_mac_lds<BT, CT, RG, CG, NS>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y, g,
-                       B, nib, nkb, c);
+    hipLaunchKernelGGL((k_mac_lds<BT, CT, RG, CG, NS, PRE>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w,
+                       y, g, B, nib, nkb, c, tw.inv);
   else
     hipLaunchKernelGGL((k_mac_tiled<BT, CT, RG, CG, NS>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y,
                        g, B, nib, nkb, c);
@@ -996,28 +1114,32 @@ bool mac_offsets_fit(const ConvGeom &g, const MacShape &m) {
 }
 
 // (images per thread, channels per thread, image groups, channel groups,
-//  loads in flight (register sets), LDS-staged)
+//  loads in flight (register sets), LDS-staged, inverse stages in the epilogue)
 #define HC_MAC_VARIANTS(X)                                                                                      \
-  X(1, 8, 1, 4, 2, 0) X(1, 4, 1, 4, 2, 0) X(2, 4, 1, 4, 2, 0) X(4, 4, 1, 4, 2, 0) X(4, 2, 1, 4, 2, 0)           \
-  X(8, 2, 1, 4, 2, 0) X(4, 4, 4, 2, 2, 0) X(4, 8, 4, 2, 2, 0) X(2, 8, 4, 2, 2, 0) X(4, 4, 2, 4, 2, 0)           \
-  X(2, 4, 4, 4, 2, 0) X(1, 8, 2, 4, 2, 0) X(4, 8, 4, 2, 3, 0) X(2, 8, 4, 2, 4, 0) X(4, 4, 4, 2, 4, 0)           \
-  X(4, 4, 2, 4, 4, 0) X(1, 8, 2, 4, 4, 0) X(2, 4, 4, 4, 4, 0) X(1, 8, 1, 4, 4, 0) X(4, 8, 4, 2, 2, 1)           \
-  X(4, 8, 4, 2, 3, 1) X(4, 8, 2, 2, 2, 1) X(4, 8, 2, 2, 3, 1) X(2, 8, 4, 2, 3, 1) X(4, 4, 4, 2, 3, 1)           \
-  X(2, 8, 2, 2, 3, 1)
+  X(1, 8, 1, 4, 2, 0, 0) X(1, 4, 1, 4, 2, 0, 0) X(2, 4, 1, 4, 2, 0, 0) X(4, 4, 1, 4, 2, 0, 0)                   \
+  X(4, 2, 1, 4, 2, 0, 0) X(8, 2, 1, 4, 2, 0, 0) X(4, 4, 4, 2, 2, 0, 0) X(4, 8, 4, 2, 2, 0, 0)                   \
+  X(2, 8, 4, 2, 2, 0, 0) X(4, 4, 2, 4, 2, 0, 0) X(2, 4, 4, 4, 2, 0, 0) X(1, 8, 2, 4, 2, 0, 0)                   \
+  X(4, 8, 4, 2, 3, 0, 0) X(2, 8, 4, 2, 4, 0, 0) X(4, 4, 4, 2, 4, 0, 0) X(4, 4, 2, 4, 4, 0, 0)                   \
+  X(1, 8, 2, 4, 4, 0, 0) X(2, 4, 4, 4, 4, 0, 0) X(1, 8, 1, 4, 4, 0, 0) X(4, 8, 4, 2, 2, 1, 0)                   \
+  X(4, 8, 4, 2, 3, 1, 0) X(4, 8, 2, 2, 2, 1, 0) X(4, 8, 2, 2, 3, 1, 0) X(2, 8, 4, 2, 3, 1, 0)                   \
+  X(4, 4, 4, 2, 3, 1, 0) X(2, 8, 2, 2, 3, 1, 0) X(4, 8, 4, 2, 2, 1, 5) X(4, 8, 2, 2, 2, 1, 5)                   \
+  X(4, 8, 2, 2, 3, 1, 5)
 
 bool mac_variant_ok(const MacShape &m) {
-#define HC_MAC_OK(B_, C_, R_, G_, S_, D_) \
-  if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_) return true;
+#define HC_MAC_OK(B_, C_, R_, G_, S_, D_, P_)                                                                 \
+  if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_ && m.pre == P_) \
+    return true;
   HC_MAC_VARIANTS(HC_MAC_OK)
 #undef HC_MAC_OK
   return false;
 }
 
 hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *x, const uint32_t *w, uint32_t *y,
-                      uint32_t B, const LimbConsts &c, hipStream_t st) {
-#define HC_MAC_CASE(B_, C_, R_, G_, S_, D_)                                                          \
-  if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_)          \
-    return mac_t<B_, C_, R_, G_, S_, D_>(g, x, w, y, B, c, st);
+                      uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  if (m.pre && g.N < 4096) return hipErrorInvalidValue;  // the epilogue's twiddle layout needs N >= 4096
+#define HC_MAC_CASE(B_, C_, R_, G_, S_, D_, P_)                                                               \
+  if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_ && m.pre == P_) \
+    return mac_t<B_, C_, R_, G_, S_, D_, P_>(g, x, w, y, B, c, tw, st);
   HC_MAC_VARIANTS(HC_MAC_CASE)
 #undef HC_MAC_CASE
   return hipErrorInvalidValue;

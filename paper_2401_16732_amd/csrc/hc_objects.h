@@ -46,7 +46,7 @@ Shapes shapes_for(const hc_ctx &c, uint32_t B);
 // The MAC shape a tuning names (all four tile fields set); depth 0 means 2.
 inline MacShape mac_of(const hc_tuning &t) {
   return MacShape{t.mac_rows, t.mac_cols, t.mac_row_groups, t.mac_col_groups, t.mac_depth ? t.mac_depth : 2u,
-                  t.mac_lds};
+                  t.mac_lds, t.mac_pre};
 }
 // The layer's autotuned shapes when tuned for B images, else the context's.
 Shapes layer_shapes(const hc_layer *ly, uint32_t B);

@@ -44,7 +44,7 @@ class ConvShape(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("fwd_elog", "inv_elog", "mac_rows", "mac_cols", "mac_row_groups",
-                                               "mac_col_groups", "mac_depth", "mac_lds", "inv_polys")]
+                                               "mac_col_groups", "mac_depth", "mac_lds", "inv_polys", "mac_pre")]
 
     def as_tuple(self):
         return tuple(getattr(self, k) for k, _ in self._fields_)
@@ -202,9 +202,9 @@ class Context:
         _check(_lib.hc_sync(self.h), "hc_sync")
 
     def set_tuning(self, fwd_elog=0, inv_elog=0, mac_rows=0, mac_cols=0, mac_row_groups=0, mac_col_groups=0,
-                   mac_depth=0, mac_lds=0, inv_polys=0):
+                   mac_depth=0, mac_lds=0, inv_polys=0, mac_pre=0):
         t = Tuning(fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups, mac_depth, mac_lds,
-                   inv_polys)
+                   inv_polys, mac_pre)
         _check(_lib.hc_ctx_set_tuning(self.h, ctypes.byref(t)), "hc_ctx_set_tuning")
 
     def get_tuning(self):
@@ -286,7 +286,7 @@ class Layer:
 
     def tuning(self):
         """(batch size, (fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups, mac_depth,
-        mac_lds, inv_polys)) or (0, ...)."""
+        mac_lds, inv_polys, mac_pre)) or (0, ...)."""
         B = ctypes.c_uint32()
         t = Tuning()
         _check(_lib.hc_layer_get_tuning(self.h, ctypes.byref(B), ctypes.byref(t)), "hc_layer_get_tuning")

@@ -179,13 +179,21 @@ def test_error_paths(hc):
     ly.conv(zeros((1,)), zeros((1,)), 0, zeros((1,)))
 
 
-# (images, channels per thread, image groups, channel groups, loads in flight, LDS-staged)
-MAC_VARIANTS = [(1, 8, 1, 4, 2, 0), (1, 4, 1, 4, 2, 0), (2, 4, 1, 4, 2, 0), (4, 4, 1, 4, 2, 0), (4, 2, 1, 4, 2, 0),
-                (8, 2, 1, 4, 2, 0), (4, 4, 4, 2, 2, 0), (4, 8, 4, 2, 2, 0), (2, 8, 4, 2, 2, 0), (4, 4, 2, 4, 2, 0),
-                (2, 4, 4, 4, 2, 0), (1, 8, 2, 4, 2, 0), (4, 8, 4, 2, 3, 0), (2, 8, 4, 2, 4, 0), (4, 4, 4, 2, 4, 0),
-                (4, 4, 2, 4, 4, 0), (1, 8, 2, 4, 4, 0), (2, 4, 4, 4, 4, 0), (1, 8, 1, 4, 4, 0), (4, 8, 4, 2, 2, 1),
-                (4, 8, 4, 2, 3, 1), (4, 8, 2, 2, 2, 1), (4, 8, 2, 2, 3, 1), (2, 8, 4, 2, 3, 1), (4, 4, 4, 2, 3, 1),
-                (2, 8, 2, 2, 3, 1)]
+# (images, channels per thread, image groups, channel groups, loads in flight, LDS-staged,
+#  inverse NTT stages in the MAC epilogue)
+MAC_VARIANTS = [(1, 8, 1, 4, 2, 0, 0), (1, 4, 1, 4, 2, 0, 0), (2, 4, 1, 4, 2, 0, 0), (4, 4, 1, 4, 2, 0, 0),
+                (4, 2, 1, 4, 2, 0, 0), (8, 2, 1, 4, 2, 0, 0), (4, 4, 4, 2, 2, 0, 0), (4, 8, 4, 2, 2, 0, 0),
+                (2, 8, 4, 2, 2, 0, 0), (4, 4, 2, 4, 2, 0, 0), (2, 4, 4, 4, 2, 0, 0), (1, 8, 2, 4, 2, 0, 0),
+                (4, 8, 4, 2, 3, 0, 0), (2, 8, 4, 2, 4, 0, 0), (4, 4, 4, 2, 4, 0, 0), (4, 4, 2, 4, 4, 0, 0),
+                (1, 8, 2, 4, 4, 0, 0), (2, 4, 4, 4, 4, 0, 0), (1, 8, 1, 4, 4, 0, 0), (4, 8, 4, 2, 2, 1, 0),
+                (4, 8, 4, 2, 3, 1, 0), (4, 8, 2, 2, 2, 1, 0), (4, 8, 2, 2, 3, 1, 0), (2, 8, 4, 2, 3, 1, 0),
+                (4, 4, 4, 2, 3, 1, 0), (2, 8, 2, 2, 3, 1, 0), (4, 8, 4, 2, 2, 1, 5), (4, 8, 2, 2, 2, 1, 5),
+                (4, 8, 2, 2, 3, 1, 5)]
+
+
+def mac_tuning(v, inv_elog=0, inv_polys=0):
+    """set_tuning arguments for MAC variant v (and optional inverse-NTT shape)."""
+    return (0, inv_elog, *v[:6], inv_polys, v[6])
 
 
 @pytest.mark.parametrize("N,elogs", [(8192, (3, 4, 5)), (16384, (4, 5)), (4096, (3, 4, 5)), (1024, (3, 4))])
@@ -203,7 +211,8 @@ def test_every_launch_shape_gives_the_same_bits(hc, N, elogs):
     exp = [conv.mask_extract(calg1.alg1_layer(x[b], f, P, c.primes), r[b], P, c.primes, t) for b in range(B)]
     dx, dr = dev(x), dev(r)
     ws = zeros((ly.workspace_words(B, True),))
-    cases = [(fe, ie, 0, 0, 0, 0) for fe in elogs for ie in elogs] + [(0, 0) + v for v in MAC_VARIANTS]
+    cases = [(fe, ie, 0, 0, 0, 0) for fe in elogs for ie in elogs]
+    cases += [mac_tuning(v) for v in MAC_VARIANTS if N >= 4096 or v[6] == 0]
     # two inverse-NTT polynomials per workgroup; B * out_cts = 39 leaves the last pair half empty
     cases += [(0, ie, 0, 0, 0, 0, 0, 0, 2) for ie in elogs if ie <= 4]
     for tune in cases:
@@ -222,6 +231,8 @@ def test_every_launch_shape_gives_the_same_bits(hc, N, elogs):
         c.set_tuning(0, 0, 4, 4, 0, 0)
     with pytest.raises(hc.HcError):  # 4 x 16 loads in flight exceed the memory counter
         c.set_tuning(0, 0, 4, 8, 4, 2, 4)
+    with pytest.raises(hc.HcError):  # epilogue stages only on LDS-staged 4x8 tiles
+        c.set_tuning(0, 0, 4, 8, 4, 2, 2, 0, 0, 5)
     with pytest.raises(hc.HcError):  # a depth alone is not a tile
         c.set_tuning(0, 0, 0, 0, 0, 0, 4)
     with pytest.raises(hc.HcError):  # nor is the LDS flag
@@ -249,10 +260,41 @@ def test_mac_ring_over_many_input_ciphertexts(hc):
     dx, dr = dev(x), dev(r)
     ws = zeros((ly.workspace_words(B, True),))
     for v in MAC_VARIANTS:
+        if v[6]:
+            continue  # epilogue stages need N >= 4096 (own test below)
         print(f"mac {v}", flush=True)
-        c.set_tuning(0, 0, *v)
+        c.set_tuning(*mac_tuning(v))
         c0, c1 = zeros(ly.c0_shape(B)), zeros(ly.c1_shape(B))
         ly.conv_masked(dx, dr, c0, c1, B, ws)
         c0, c1 = host(c0), host(c1)
         for b in range(B):
             assert (c0[b] == exp[b][0]).all() and (c1[b] == exp[b][1]).all(), (v, b)
+
+
+@pytest.mark.parametrize("spec", [W.ConvSpec(148, 13, 28, 28, 3, 1, "g37"), W.ConvSpec(3, 13, 70, 70, 3, 1, "tiled")])
+def test_mac_epilogue_stages_match_oracle(hc, spec):
+    """MAC variants that apply the inverse NTT's first stages before storing,
+    with every inverse shape that starts after them: 37 input ciphertexts per
+    output (several folds), a row-tiled layer, c_out = 13 and B = 5 (channels
+    and images absent from a workgroup tile), against the oracle."""
+    N, L, t, B = 4096, 2, 2 ** 17, 5
+    c = _ctx(hc, N, L, t)
+    P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+    assert (P.G == 37) if spec.name == "g37" else P.tiled
+    g = W.rng(41)
+    f = W.gen_filters(g, spec)
+    x = W.gen_ct_limbs(g, (B, P.G, 2), c.primes, N)
+    r = W.gen_mask(g, (B, spec.c_o, P.ho, P.wo), t)
+    ly = hc.Layer(c, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride, f)
+    exp = [conv.mask_extract(calg1.alg1_layer(x[b], f, P, c.primes), r[b], P, c.primes, t) for b in range(B)]
+    dx, dr = dev(x), dev(r)
+    ws = zeros((ly.workspace_words(B, True),))
+    for v in [v for v in MAC_VARIANTS if v[6]]:
+        for ie, npw in ((3, 1), (4, 1), (5, 1), (3, 2), (4, 2)):
+            print(f"{spec.name} mac {v} inverse e={ie} x{npw}", flush=True)
+            c.set_tuning(*mac_tuning(v, ie, npw))
+            c0, c1 = zeros(ly.c0_shape(B)), zeros(ly.c1_shape(B))
+            ly.conv_masked(dx, dr, c0, c1, B, ws)
+            c0, c1 = host(c0), host(c1)
+            for b in range(B):
+                assert (c0[b] == exp[b][0]).all() and (c1[b] == exp[b][1]).all(), (v, ie, npw, b)
