@@ -89,13 +89,12 @@ def measured_traffic(kernel: str, tag: str):
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE,
     copy-calibrated), or None when the summary is missing or was taken on a
     different kernel source."""
-    import hashlib
+    from paper_2401_16732_amd.build import kernel_fingerprint
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", f"hbm_traffic_{tag}.md")
-    src = os.path.join(here, "paper_2401_16732_amd", "csrc", "hc_kernels.hip")
     if not os.path.exists(path):
         return None
-    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    cur = kernel_fingerprint()
     got, val = None, None
     for line in open(path):
         if line.startswith("source_sha256_16:"):

@@ -1,0 +1,309 @@
+// Device code shared by the gfx950 kernels of the homomorphic convolution (Flash, arXiv 2401.16732,
+// Algorithm 1 evaluated as y_i = sum_g c_g * W_{i,g} in R_q through the NTT).
+//
+// All arithmetic is exact 32-bit modular arithmetic on the vector ALUs:
+//  * Shoup multiplication by precomputed constants (twiddles, N^-1, Delta),
+//  * Harvey's lazy butterflies (forward values kept in [0, 4q), inverse in
+//    [0, 2q); q < 2^30 so 4q < 2^32),
+//  * the multiply-accumulate over input ciphertexts in 64-bit accumulators
+//    (v_mad_u64_u32), folded every few terms and reduced once per output: the
+//    GPU form of the paper's lazy reduction (Employing Lazy Reduction in
+//    Convolution).
+// No MFMA: nothing here is a floating-point contraction.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "hc_internal.h"
+
+namespace hc {
+
+// Third word of a gfx9-family raw buffer descriptor (32-bit data, no swizzle,
+// no stride), as used for gfx908/90a/94x/950.
+constexpr uint32_t kBufferWord3 = 0x00020000u;
+
+// ---------------------------------------------------------------- arithmetic
+__device__ __forceinline__ uint32_t shoup_lazy(uint32_t a, uint32_t w, uint32_t wp, uint32_t q) {
+  uint32_t Q = __umulhi(a, wp);
+  return a * w - Q * q;  // in [0, 2q) for any a < 2^32
+}
+__device__ __forceinline__ uint32_t csub(uint32_t a, uint32_t m) { return a >= m ? a - m : a; }
+
+// acc < 2^64 -> acc mod q, q < 2^30.
+__device__ __forceinline__ uint32_t reduce64(uint64_t acc, uint32_t q, uint32_t r2, uint32_t r2p, uint32_t onep) {
+  uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
+  uint32_t r = shoup_lazy(hi, r2, r2p, q) + shoup_lazy(lo, 1u, onep, q);  // [0, 4q)
+  r = csub(r, 2 * q);
+  return csub(r, q);
+}
+
+// ---------------------------------------------------------------- NTT shape
+// A polynomial of N = 2^LOGN coefficients is transformed by one workgroup of
+// 2^(LOGN - ELOG) threads; each thread holds E = 2^ELOG coefficients in
+// registers. The LOGN butterfly stages are split into passes of at most ELOG
+// consecutive index bits; within a pass every butterfly's pair lies in one
+// thread, and passes exchange data through LDS.
+__host__ __device__ constexpr int n_pass(int logn, int elog) { return (logn + elog - 1) / elog; }
+__host__ __device__ constexpr int pass_bits(int logn, int elog, int k) {
+  return logn / n_pass(logn, elog) + (k < logn % n_pass(logn, elog) ? 1 : 0);
+}
+// Forward passes walk the index bits from the top down (stage s touches bit
+// LOGN-1-s); inverse passes walk them from the bottom up.
+__host__ __device__ constexpr int pass_lo_fwd(int logn, int elog, int k) {
+  int lo = logn;
+  for (int i = 0; i <= k; ++i) lo -= pass_bits(logn, elog, i);
+  return lo;
+}
+__host__ __device__ constexpr int pass_lo_inv(int logn, int elog, int k) {
+  int lo = 0;
+  for (int i = 0; i < k; ++i) lo += pass_bits(logn, elog, i);
+  return lo;
+}
+
+// Coefficient index held in register u during a pass over bits [LO, LO+EP).
+// u = (grp << EP) | w: w walks the pass bits; the thread id and grp fill the
+// remaining bit positions, thread id lowest (so a pass with LO >= thread bits
+// reads consecutive words across the wave).
+template <int LOGN, int ELOG, int LO, int EP>
+__device__ __forceinline__ uint32_t gidx(uint32_t tid, int u) {
+  constexpr int TB = LOGN - ELOG;
+  const uint32_t w = (uint32_t)u & ((1u << EP) - 1u);
+  const uint32_t grp = (uint32_t)u >> EP;
+  const uint32_t v = tid | (grp << TB);
+  return (v & ((1u << LO) - 1u)) | (w << LO) | ((v >> LO) << (LO + EP));
+}
+// LDS word address: one pad word per 32 keeps strided passes off a single bank.
+// gidx(tid, u) is the OR of a thread part gidx(tid, 0) and a register part
+// gidx(0, u) over disjoint bits, so lpad(gidx(tid, u)) = lpad(gidx(tid, 0)) +
+// lpad(gidx(0, u)): one base per thread and compile-time offsets per register.
+__host__ __device__ constexpr uint32_t lpad(uint32_t j) { return j + (j >> 5); }
+
+// Twiddles of stage bit b (s = LOGN - 1 - b) read at index 2^s + (j >> (b+1)).
+// In a pass over bits [LO, LO + EP) with LO >= 6 the thread's share of j above
+// bit b comes from tid >> LO, which is the same for all 64 lanes of a wave:
+// the base is then wave-uniform and read through the constant address space,
+// so the compiler can fetch those twiddles with scalar loads instead of one
+// vector load per lane.
+using const_u64 = __attribute__((address_space(4))) const uint64_t;
+template <int LOGN, int ELOG, int LO, int EP>
+struct StageTw {
+  static constexpr bool kUniform = LO >= 6;
+  const uint2 *vec;
+  const_u64 *uni;  // the same {w, w'} pairs as 64-bit words
+  __device__ __forceinline__ StageTw(const uint2 *tw, uint32_t tid, int b) {
+    const int s = LOGN - 1 - b;
+    if constexpr (kUniform) {
+      const uint32_t hi = __builtin_amdgcn_readfirstlane(tid >> LO);
+      uni = (const_u64 *)(tw + (1u << s) + (((size_t)hi << (LO + EP)) >> (b + 1)));
+      vec = nullptr;
+    } else {
+      vec = tw + (1u << s) + (gidx<LOGN, ELOG, LO, EP>(tid, 0) >> (b + 1));
+      uni = nullptr;
+    }
+  }
+  // twiddle of register slot u (the register part of j is gidx(0, u))
+  __device__ __forceinline__ uint2 operator()(int u, int b) const {
+    const uint32_t k = gidx<LOGN, ELOG, LO, EP>(0, u) >> (b + 1);
+    if constexpr (kUniform) {
+      const uint64_t t = uni[k];
+      return make_uint2((uint32_t)t, (uint32_t)(t >> 32));
+    } else {
+      return vec[k];
+    }
+  }
+};
+
+// Forward (Cooley-Tukey, natural -> bit-reversed) stages of one pass.
+// Stage s works on pairs (j, j + 2^(LOGN-1-s)) with twiddle psi^brv(2^s + j >> (LOGN - s)).
+template <int LOGN, int ELOG, int LO, int EP>
+__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
+                                         uint32_t q) {
+  constexpr int E = 1 << ELOG;
+  const uint32_t q2 = 2 * q;
+#pragma unroll
+  for (int bb = EP - 1; bb >= 0; --bb) {
+    const int b = LO + bb;
+    const int s = LOGN - 1 - b;
+    // twiddle index 2^s + (j >> (b + 1)), split into thread and register parts
+    const StageTw<LOGN, ELOG, LO, EP> tws(tw, tid, b);
+    (void)s;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      if (u & (1 << bb)) continue;
+      const int u2 = u | (1 << bb);
+      const uint2 w = tws(u, b);
+      uint32_t X = v[u], Y = v[u2];
+      X = csub(X, q2);
+      const uint32_t T = shoup_lazy(Y, w.x, w.y, q);
+      v[u] = X + T;
+      v[u2] = X - T + q2;
+    }
+  }
+}
+
+// Inverse (Gentleman-Sande, bit-reversed -> natural) stages of one pass; the
+// last stage (s = 0) also multiplies by N^-1.
+// Pruning: when only outputs below 2^(LOGN - PS) are wanted, every stage on a
+// bit b >= LOGN - PS feeds wanted outputs from its lower (sum) half only - all
+// wanted indices have those bits clear - so the difference half, with its
+// twiddle multiply, is skipped there. PS = 0 computes the full transform. PS
+// is a compile-time constant, so no stage carries a run-time branch.
+// M polynomials of one limb go through the stages together (v[m]): each
+// twiddle is loaded once for all of them.
+template <int LOGN, int ELOG, int LO, int EP, int PS, int M>
+__device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
+                                         uint32_t q, uint32_t ninv, uint32_t ninvp, uint32_t ninvw,
+                                         uint32_t ninvwp) {
+  constexpr int E = 1 << ELOG;
+  const uint32_t q2 = 2 * q;
+#pragma unroll
+  for (int bb = 0; bb < EP; ++bb) {
+    const int b = LO + bb;
+    const int s = LOGN - 1 - b;
+    const bool sum_only = b >= LOGN - PS;
+    const StageTw<LOGN, ELOG, LO, EP> tws(tw, tid, b);
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      if (u & (1 << bb)) continue;
+      const int u2 = u | (1 << bb);
+      if (sum_only) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+          v[m][u] = s == 0 ? shoup_lazy(v[m][u] + v[m][u2], ninv, ninvp, q) : csub(v[m][u] + v[m][u2], q2);
+      } else if (s == 0) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const uint32_t X = v[m][u], Y = v[m][u2];
+          v[m][u] = shoup_lazy(X + Y, ninv, ninvp, q);
+          v[m][u2] = shoup_lazy(X - Y + q2, ninvw, ninvwp, q);
+        }
+      } else {
+        const uint2 w = tws(u, b);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const uint32_t X = v[m][u], Y = v[m][u2];
+          v[m][u] = csub(X + Y, q2);
+          v[m][u2] = shoup_lazy(X - Y + q2, w.x, w.y, q);
+        }
+      }
+    }
+  }
+}
+
+template <int LOGN, int ELOG, int LO, int EP>
+__device__ __forceinline__ void regs_to_lds(const uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid) {
+  uint32_t *p = lds + lpad(gidx<LOGN, ELOG, LO, EP>(tid, 0));
+#pragma unroll
+  for (int u = 0; u < (1 << ELOG); ++u) p[lpad(gidx<LOGN, ELOG, LO, EP>(0, u))] = v[u];
+}
+template <int LOGN, int ELOG, int LO, int EP>
+__device__ __forceinline__ void lds_to_regs(uint32_t (&v)[1 << ELOG], const uint32_t *lds, uint32_t tid) {
+  const uint32_t *p = lds + lpad(gidx<LOGN, ELOG, LO, EP>(tid, 0));
+#pragma unroll
+  for (int u = 0; u < (1 << ELOG); ++u) v[u] = p[lpad(gidx<LOGN, ELOG, LO, EP>(0, u))];
+}
+
+template <int LOGN, int ELOG, int K>
+struct FwdPasses {
+  // pass K reads from LDS (K > 0) and leaves its result in registers
+  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *lds, uint32_t tid,
+                                             const uint2 *tw, uint32_t q) {
+    constexpr int LO = pass_lo_fwd(LOGN, ELOG, K), EP = pass_bits(LOGN, ELOG, K);
+    constexpr int PLO = pass_lo_fwd(LOGN, ELOG, K - 1), PEP = pass_bits(LOGN, ELOG, K - 1);
+    FwdPasses<LOGN, ELOG, K - 1>::run(v, lds, tid, tw, q);
+    regs_to_lds<LOGN, ELOG, PLO, PEP>(v, lds, tid);
+    __syncthreads();
+    lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
+    fwd_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q);
+  }
+};
+template <int LOGN, int ELOG>
+struct FwdPasses<LOGN, ELOG, 0> {
+  // pass 0 expects its inputs already in registers (loaded from global)
+  static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *, uint32_t tid, const uint2 *tw,
+                                             uint32_t q) {
+    constexpr int LO = pass_lo_fwd(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
+    fwd_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q);
+  }
+};
+
+// Polynomial m exchanges through lds + m * lds_words(LOGN).
+__host__ __device__ constexpr uint32_t lds_words(int logn) { return (1u << logn) + (1u << logn) / 32; }
+
+// Inverse passes cover index bits [PRE, LOGN): the stages on bits below PRE
+// were done by the multiply-accumulate's epilogue (PRE = 0: all stages here).
+__host__ __device__ constexpr int inv_np(int logn, int elog, int pre) { return n_pass(logn - pre, elog); }
+__host__ __device__ constexpr int inv_lo(int logn, int elog, int pre, int k) {
+  return pre + pass_lo_inv(logn - pre, elog, k);
+}
+__host__ __device__ constexpr int inv_ep(int logn, int elog, int pre, int k) { return pass_bits(logn - pre, elog, k); }
+
+template <int LOGN, int ELOG, int K, int PS, int M, int PRE>
+struct InvPasses {
+  static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *lds, uint32_t tid,
+                                             const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
+                                             uint32_t bp) {
+    constexpr int LO = inv_lo(LOGN, ELOG, PRE, K), EP = inv_ep(LOGN, ELOG, PRE, K);
+    constexpr int PLO = inv_lo(LOGN, ELOG, PRE, K - 1), PEP = inv_ep(LOGN, ELOG, PRE, K - 1);
+    InvPasses<LOGN, ELOG, K - 1, PS, M, PRE>::run(v, lds, tid, tw, q, a, ap, b, bp);
+#pragma unroll
+    for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, PLO, PEP>(v[m], lds + m * lds_words(LOGN), tid);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
+    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tid, tw, q, a, ap, b, bp);
+  }
+};
+template <int LOGN, int ELOG, int PS, int M, int PRE>
+struct InvPasses<LOGN, ELOG, 0, PS, M, PRE> {
+  // pass 0 (bits [PRE, PRE + EP)) expects its inputs already in registers
+  static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *, uint32_t tid,
+                                             const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
+                                             uint32_t bp) {
+    constexpr int LO = inv_lo(LOGN, ELOG, PRE, 0), EP = inv_ep(LOGN, ELOG, PRE, 0);
+    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tid, tw, q, a, ap, b, bp);
+  }
+};
+
+// A pass over bits [0, EP) holds 2^EP consecutive coefficients per group in
+// registers: move them with 16-byte accesses.
+template <int LOGN, int ELOG, int EP>
+__device__ __forceinline__ void load_low_pass(uint32_t (&v)[1 << ELOG], const uint32_t *src, uint32_t tid) {
+  static_assert(EP >= 2, "vector access needs 4 consecutive words");
+  const uint32_t *sb = src + gidx<LOGN, ELOG, 0, EP>(tid, 0);
+#pragma unroll
+  for (int u = 0; u < (1 << ELOG); u += 4) {
+    const uint4 t4 = *reinterpret_cast<const uint4 *>(sb + gidx<LOGN, ELOG, 0, EP>(0, u));
+    v[u] = t4.x;
+    v[u + 1] = t4.y;
+    v[u + 2] = t4.z;
+    v[u + 3] = t4.w;
+  }
+}
+
+// ---------------------------------------------------------------- inverse NTT kernels
+// PS: top stages pruned (see inv_pass); 0 for the whole transform. M
+// polynomials src[m] of one limb, LDS of M * lds_words(LOGN) words. PRE:
+// stages on bits below PRE already done (the first pass then reads its
+// coefficients with coalesced 4-byte loads: lanes map to the low bits).
+template <int LOGN, int ELOG, int PS, int M, int PRE>
+__device__ __forceinline__ void intt_core(const uint32_t *const (&src)[M], uint32_t (&v)[M][1 << ELOG],
+                                          uint32_t *lds, uint32_t tid, const LimbConsts &c, const uint2 *tw,
+                                          uint32_t l) {
+  constexpr int NP = inv_np(LOGN, ELOG, PRE);
+  if constexpr (PRE == 0) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v[m], src[m], tid);
+  } else {
+    constexpr int LO = inv_lo(LOGN, ELOG, PRE, 0), EP = inv_ep(LOGN, ELOG, PRE, 0);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const uint32_t *sb = src[m] + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+#pragma unroll
+      for (int u = 0; u < (1 << ELOG); ++u) v[m][u] = sb[gidx<LOGN, ELOG, LO, EP>(0, u)];
+    }
+  }
+  InvPasses<LOGN, ELOG, NP - 1, PS, M, PRE>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l],
+                                                 c.ninvw_p[l]);
+}
+
+}  // namespace hc

@@ -2,8 +2,8 @@
 //
 // Parameters (RNS primes, roots of unity, twiddle and Shoup tables, Delta),
 // the direct-encoding layout planner, resident weight encoding, the per-layer
-// launch sequences and the graph-recorded batch. Kernels live in
-// hc_kernels.hip.
+// launch sequences and the graph-recorded batch. Kernels live in hc_ntt.hip,
+// hc_mac.hip and hc_intt_masked_*.hip.
 #include "../../include/hc.h"
 
 #include <hip/hip_runtime.h>

@@ -1,5 +1,5 @@
 // Internal declarations shared by the host library (hc_host.cpp) and the
-// gfx950 kernels (hc_kernels.hip). Not part of the ABI.
+// gfx950 kernels (hc_ntt.hip, hc_mac.hip, hc_intt_masked_*.hip). Not part of the ABI.
 #pragma once
 #include <cstddef>
 #include <cstdint>
@@ -55,7 +55,7 @@ struct OutPtrs {
   uint32_t n;  // 0: not used
 };
 
-// Launchers (hc_kernels.hip). Each enqueues on `st` and returns the launch status.
+// Launchers (the kernel sources). Each enqueues on `st` and returns the launch status.
 // Launch-shape variants: an NTT uses 2^(logn - elog) threads per polynomial;
 // the MAC gives each thread bt images x ct output channels, and a workgroup
 // rg x cg such threads per coefficient (image groups x channel groups); depth

@@ -1,0 +1,9 @@
+// Masked inverse NTT instances for N = 8192.
+#define HC_INTT_MASKED_IMPL
+#include "hc_intt_masked.h"
+
+namespace hc {
+template hipError_t intt_masked_logn<13>(const ConvGeom &, uint32_t, uint32_t, uint32_t, const uint32_t *,
+                                            const uint32_t *, uint32_t *, uint32_t *, uint32_t,
+                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t);
+}  // namespace hc

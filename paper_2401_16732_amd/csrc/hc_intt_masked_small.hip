@@ -1,0 +1,15 @@
+// Masked inverse NTT instances for N = 1024, 2048, 4096.
+#define HC_INTT_MASKED_IMPL
+#include "hc_intt_masked.h"
+
+namespace hc {
+template hipError_t intt_masked_logn<10>(const ConvGeom &, uint32_t, uint32_t, uint32_t, const uint32_t *,
+                                            const uint32_t *, uint32_t *, uint32_t *, uint32_t,
+                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t);
+template hipError_t intt_masked_logn<11>(const ConvGeom &, uint32_t, uint32_t, uint32_t, const uint32_t *,
+                                            const uint32_t *, uint32_t *, uint32_t *, uint32_t,
+                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t);
+template hipError_t intt_masked_logn<12>(const ConvGeom &, uint32_t, uint32_t, uint32_t, const uint32_t *,
+                                            const uint32_t *, uint32_t *, uint32_t *, uint32_t,
+                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t);
+}  // namespace hc

@@ -1,0 +1,509 @@
+// gfx950 multiply-accumulate kernels of the homomorphic convolution (A3): the
+// register-tiled and the LDS-staged form, with their launcher.
+#include "hc_device.h"
+
+namespace hc {
+
+// ---------------------------------------------------------------- multiply-accumulate
+// Yhat[b][o][p][l][k] = sum_{gw < G_w} What[i][gw][l][k] * Xhat[b][gw T + tau][p][l][k]  mod q_l,
+// o = i T + tau.
+// Register-tiled form: one thread owns coefficient k and CT output channels
+// (same row tile tau) for BT images x 2 polynomials, so each input value it
+// loads is used CT times and each weight 2 BT times. A workgroup is RG x CG
+// waves over the same 64 coefficients: RG groups of images times CG groups of
+// output channels. Waves of one channel group read the same weights and
+// waves of one image group the same inputs, which L1 then serves once.
+// NS register sets form a ring: the loads of input ciphertext gw + NS are
+// issued right after gw's multiply-accumulates, so NS - 1 ciphertexts are in
+// flight while one is being multiplied.
+template <int BT, int CT, int RG, int CG, int NS>
+__global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__restrict__ X,
+                                                            const uint32_t *__restrict__ Wt,
+                                                            uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
+                                                            uint32_t nib, uint32_t nkb, LimbConsts c) {
+  static_assert(NS >= 2 && NS * (CT + 2 * BT) <= 63, "loads in flight beyond the vector memory counter");
+  const uint32_t nwg = gridDim.x;
+  uint32_t wg = blockIdx.x;
+  if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
+  // image tiles vary fastest: the workgroups that share one weight tile run
+  // next to each other (on one XCD, by the remap above), then channel tiles,
+  // which share input tiles
+  const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
+  const uint32_t bt = wg % nbt;
+  uint32_t r = wg / nbt;
+  const uint32_t ib = r % nib;
+  r /= nib;
+  const uint32_t tau = r % g.T;
+  r /= g.T;
+  const uint32_t kb = r % nkb;
+  const uint32_t l = r / nkb;
+  // wave-uniform indices (readfirstlane keeps the bases in scalar registers)
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t rg = wave % RG, cg = wave / RG;
+  const uint32_t i0 = (ib * CG + cg) * CT;
+  const uint32_t b0 = (bt * RG + rg) * BT;
+  if (i0 >= g.c_out || b0 >= B) return;
+  const uint32_t nc = min((uint32_t)CT, g.c_out - i0);
+  const uint32_t nb = min((uint32_t)BT, B - b0);
+  const uint32_t LN = g.L * g.N;
+  // Scalar bases advance by one input ciphertext per step; each (image,
+  // polynomial) and each channel adds a wave-uniform byte offset (32-bit;
+  // the host guarantees BT*G*2*L*N*4 and CT*G_w*L*N*4 < 2^32), and every
+  // lane the same 4 * lane.
+  const char *xbase = (const char *)(X + ((size_t)b0 * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const char *wbase = (const char *)(Wt + (size_t)i0 * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
+  const uint32_t lane4 = lane * 4u;
+  uint32_t xo[BT][2], wo[CT];
+#pragma unroll
+  for (int bb = 0; bb < BT; ++bb) {
+    const uint32_t b = (uint32_t)bb < nb ? (uint32_t)bb : 0u;  // clamp: loads of absent images are discarded
+    xo[bb][0] = __builtin_amdgcn_readfirstlane(b * g.G * 2 * LN * 4u);
+    xo[bb][1] = __builtin_amdgcn_readfirstlane(xo[bb][0] + LN * 4u);
+  }
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc)
+    wo[cc] = __builtin_amdgcn_readfirstlane(((uint32_t)cc < nc ? (uint32_t)cc : 0u) * g.G_w * LN * 4u);
+  const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
+  uint64_t acc[CT][BT][2];
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+  const uint32_t G_w = g.G_w;
+  // Raw buffer loads: the step's base in the descriptor, the uniform offset
+  // in soffset, the lane's in voffset - no vector address arithmetic. Every
+  // access is in bounds by construction; num_records is the maximum.
+  auto load = [&](uint32_t gw, uint32_t (&w)[CT], uint32_t (&x)[BT][2]) {
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(xbase + gw * xstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+    const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(wbase + gw * wstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc) w[cc] = __builtin_amdgcn_raw_buffer_load_b32(wr, lane4, wo[cc], 0);
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) {
+      x[bb][0] = __builtin_amdgcn_raw_buffer_load_b32(xr, lane4, xo[bb][0], 0);
+      x[bb][1] = __builtin_amdgcn_raw_buffer_load_b32(xr, lane4, xo[bb][1], 0);
+    }
+  };
+  auto mac = [&](const uint32_t (&w)[CT], const uint32_t (&x)[BT][2]) {
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) {
+        acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
+        acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
+      }
+  };
+  // One loop over ring turns. Its body has no data-dependent branches, so the
+  // compiler keeps the ring's order: loads past the end re-read the last
+  // ciphertext, and sets past the end get zero weights. Every fold / NS turns
+  // (at most fold terms) the accumulators are folded, exactly mod q; that
+  // branch is uniform and does no loads, so both of its paths leave the same
+  // loads in flight. The last partial chunk needs no fold: reduce64 takes any
+  // 64-bit value. NS * (CT + 2 BT) loads in flight must stay within the
+  // 63 that the vector memory counter can track.
+  uint32_t ws[NS][CT], xs[NS][BT][2];
+  const uint32_t last = G_w - 1;
+  const uint32_t turns_per_fold = fold / NS;
+  // the prologue issues the sets in ring order too: the loop's first wait
+  // is computed from the order on entry as well as around the loop
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    asm volatile("" ::: "memory");
+    load(min((uint32_t)j, last), ws[j], xs[j]);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  uint32_t turn = 0;
+  for (uint32_t gw = 0; gw < G_w; gw += NS) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      // sched_barrier keeps each group in place: a set's loads are all
+      // issued before the next set's, so waiting for one never waits for
+      // a later one
+      if (j > 0) {
+        const bool tail = gw + j >= G_w;
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc) ws[j][cc] = tail ? 0u : ws[j][cc];
+      }
+      mac(ws[j], xs[j]);
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("" ::: "memory");  // compiler-only barrier: loads stay in this slot
+      load(min(gw + NS + j, last), ws[j], xs[j]);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (++turn == turns_per_fold) {
+      turn = 0;
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+        for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+          for (int pp = 0; pp < 2; ++pp)
+            acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+    }
+  }
+  const uint32_t r2p = c.r2_p[l], onep = c.one_p[l];
+  const uint32_t k = kb * 64 + lane;
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc) {
+    if ((uint32_t)cc >= nc) continue;
+    const uint32_t o = (i0 + cc) * g.T + tau;
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) {
+      if ((uint32_t)bb >= nb) continue;
+      uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + k;
+      y[0] = reduce64(acc[cc][bb][0], q, r2, r2p, onep);
+      y[LN] = reduce64(acc[cc][bb][1], q, r2, r2p, onep);
+    }
+  }
+}
+
+// LDS-staged form of the same register tile. Per input ciphertext ("step")
+// the workgroup needs NX = RG BT 2 input segments and NW = CG CT weight
+// segments of 64 coefficients (256 bytes). They are loaded once per
+// workgroup - every thread the same number of bytes of each, 16 at a time
+// where the share allows - into a ring of R register sets (R steps in
+// flight), written to one of two LDS buffers, and each wave reads its
+// operands from there. One barrier per step orders the LDS buffers: step g
+// is read from buffer g & 1 while step g + 1 is written to the other.
+template <int BYTES>
+struct Chunk;  // one thread's share of one operand per step
+template <>
+struct Chunk<4> {
+  uint32_t v;
+  __device__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off) { v = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0); }
+  __device__ void store(char *lds) const { *(uint32_t *)lds = v; }
+};
+template <>
+struct Chunk<8> {
+  uint2 v;
+  __device__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    v = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  __device__ void store(char *lds) const { *(uint2 *)lds = v; }
+};
+template <>
+struct Chunk<16> {
+  uint4 v;
+  __device__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  }
+  __device__ void store(char *lds) const { *(uint4 *)lds = v; }
+};
+
+// PRE > 0 (tiles with one output polynomial per lane, 2 BT CT = 64): before
+// storing, the epilogue applies the inverse NTT's first PRE Gentleman-Sande
+// stages (index bits 0 .. PRE-1), which act within the workgroup's block of 64
+// coefficients. In two rounds, one per half of the block, each wave moves its
+// 64 polynomials x 32 coefficients through LDS so that a lane holds 32
+// consecutive coefficients of one polynomial, runs the stages in registers
+// with twiddles that are the same for every lane (scalar loads, shared by the
+// whole workgroup), and goes back through LDS so that the stores are
+// coalesced. The masked inverse NTT then starts at bit PRE.
+template <int BT, int CT, int RG, int CG, int R, int PRE>
+__global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__restrict__ X,
+                                                          const uint32_t *__restrict__ Wt,
+                                                          uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
+                                                          uint32_t nib, uint32_t nkb, LimbConsts c,
+                                                          const uint2 *__restrict__ twinv) {
+  constexpr int NT = 64 * RG * CG;
+  constexpr int NX = RG * BT * 2, NW = CG * CT;               // segments per step
+  constexpr int XB = NX * 256 / NT, WB = NW * 256 / NT;       // bytes per thread per step
+  static_assert(NX * 256 % NT == 0 && NW * 256 % NT == 0, "shares must be whole");
+  constexpr int XW = XB < 16 ? XB : 16, WWD = WB < 16 ? WB : 16;  // access widths
+  constexpr int KX = XB / XW, KW = WB / WWD;                      // accesses per thread per step
+  static_assert((XW == 4 || XW == 8 || XW == 16) && (WWD == 4 || WWD == 8 || WWD == 16), "access width");
+  static_assert(R >= 2 && R * (KX + KW) <= 63, "loads in flight beyond the vector memory counter");
+  constexpr uint32_t BUFB = (NX + NW) * 256;  // bytes per LDS buffer
+  static_assert(PRE == 0 || (PRE == 5 && 2 * BT * CT == 64), "epilogue stages need one polynomial per lane");
+  constexpr uint32_t RWW = 64 * 36;             // epilogue: words per wave (64 x (32 + 4 pad))
+  constexpr uint32_t LDSB = PRE ? (2 * BUFB > RG * CG * RWW * 4 ? 2 * BUFB : RG * CG * RWW * 4) : 2 * BUFB;
+  __shared__ uint4 stage4[LDSB / 16];
+  char *stage = (char *)stage4;
+  const uint32_t nwg = gridDim.x;
+  uint32_t wg = blockIdx.x;
+  if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
+  // image tiles vary fastest: the workgroups that share one weight tile run
+  // next to each other (on one XCD, by the remap above), then channel tiles,
+  // which share input tiles
+  const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
+  const uint32_t bt = wg % nbt;
+  uint32_t r = wg / nbt;
+  const uint32_t ib = r % nib;
+  r /= nib;
+  const uint32_t tau = r % g.T;
+  r /= g.T;
+  const uint32_t kb = r % nkb;
+  const uint32_t l = r / nkb;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t lane = tid & 63u;
+  const uint32_t rg = wave % RG, cg = wave / RG;
+  // workgroup tile: images [bw, bw + nbw), channels [iw, iw + ncw)
+  const uint32_t bw = bt * RG * BT, iw = ib * CG * CT;
+  if (bw >= B || iw >= g.c_out) return;  // uniform over the workgroup
+  const uint32_t nbw = min((uint32_t)(RG * BT), B - bw), ncw = min((uint32_t)(CG * CT), g.c_out - iw);
+  const uint32_t LN = g.L * g.N;
+  // Per-thread global byte offsets and LDS byte positions of its accesses
+  // (fixed for the whole loop). Byte e of the step's input share sits in
+  // segment e / 256 = 2 i + p; absent images and channels read image /
+  // channel 0 of the tile, whose results are never stored.
+  uint32_t xoff[KX], woff[KW];
+#pragma unroll
+  for (int k = 0; k < KX; ++k) {
+    const uint32_t e = (tid + k * NT) * XW, seg = e >> 8, i = seg >> 1;
+    xoff[k] = (((i < nbw ? i : 0u) * g.G * 2 + (seg & 1u)) * LN) * 4u + (e & 255u);
+  }
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const uint32_t e = (tid + k * NT) * WWD, cc = e >> 8;
+    woff[k] = ((cc < ncw ? cc : 0u) * g.G_w * LN) * 4u + (e & 255u);
+  }
+  const char *xbase = (const char *)(X + ((size_t)bw * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const char *wbase = (const char *)(Wt + (size_t)iw * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
+  const uint32_t G_w = g.G_w, last = G_w - 1;
+  using CX = Chunk<XW>;
+  using CW = Chunk<WWD>;
+  auto gload = [&](uint32_t gw, CX (&rx)[KX], CW (&rw)[KW]) {
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(xbase + gw * xstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+    const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(wbase + gw * wstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+#pragma unroll
+    for (int k = 0; k < KX; ++k) rx[k].load(xr, xoff[k]);
+#pragma unroll
+    for (int k = 0; k < KW; ++k) rw[k].load(wr, woff[k]);
+  };
+  auto lstore = [&](uint32_t buf, const CX (&rx)[KX], const CW (&rw)[KW]) {
+    char *sb = stage + buf * BUFB;
+#pragma unroll
+    for (int k = 0; k < KX; ++k) rx[k].store(sb + (tid + k * NT) * XW);
+#pragma unroll
+    for (int k = 0; k < KW; ++k) rw[k].store(sb + NX * 256 + (tid + k * NT) * WWD);
+  };
+  const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
+  uint64_t acc[CT][BT][2];
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+  // this wave's operands inside a stage buffer (words)
+  const uint32_t *xs0 = (const uint32_t *)stage + (rg * BT * 2) * 64 + lane;
+  const uint32_t *ws0 = (const uint32_t *)stage + (NX + cg * CT) * 64 + lane;
+  constexpr uint32_t BUFW = BUFB / 4;  // words per buffer
+  CX rx[R][KX];
+  CW rw[R][KW];
+  // prologue: steps 0 .. R-1 in flight, step 0 into buffer 0, step R into set 0
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    asm volatile("" ::: "memory");
+    gload(min((uint32_t)j, last), rx[j], rw[j]);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  lstore(0, rx[0], rw[0]);
+  asm volatile("" ::: "memory");
+  gload(min((uint32_t)R, last), rx[0], rw[0]);
+  asm volatile("" ::: "memory");
+  __syncthreads();
+  uint32_t since_fold = 0;
+  // step g: operands from buffer g & 1; set (g + 1) % R holds step g + 1 and
+  // goes to the other buffer, then reloads with step g + 1 + R
+  for (uint32_t g0 = 0; g0 < G_w; g0 += R) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint32_t gw = g0 + j;
+      if (gw >= G_w) break;  // uniform
+      const uint32_t *xs = xs0 + (gw & 1u) * BUFW, *wsp = ws0 + (gw & 1u) * BUFW;
+      uint32_t w[CT], x[BT][2];
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc) w[cc] = wsp[cc * 64];
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) {
+        x[bb][0] = xs[(bb * 2) * 64];
+        x[bb][1] = xs[(bb * 2 + 1) * 64];
+      }
+      const int jn = (j + 1) % R;
+      asm volatile("" ::: "memory");
+      lstore((gw + 1) & 1u, rx[jn], rw[jn]);
+      asm volatile("" ::: "memory");
+      gload(min(gw + 1 + R, last), rx[jn], rw[jn]);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+        for (int bb = 0; bb < BT; ++bb) {
+          acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
+          acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
+        }
+      if (++since_fold == fold) {
+        since_fold = 0;
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+          for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+            for (int pp = 0; pp < 2; ++pp)
+              acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+      }
+      __syncthreads();
+    }
+  }
+  // wave tile and its stores
+  const uint32_t i0 = iw + cg * CT, b0 = bw + rg * BT;
+  const uint32_t r2p = c.r2_p[l], onep = c.one_p[l];
+  if constexpr (PRE == 0) {
+    if (i0 >= g.c_out || b0 >= B) return;
+    const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
+    const uint32_t k = kb * 64 + lane;
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc) {
+      if ((uint32_t)cc >= nc) continue;
+      const uint32_t o = (i0 + cc) * g.T + tau;
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) {
+        if ((uint32_t)bb >= nb) continue;
+        uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + k;
+        y[0] = reduce64(acc[cc][bb][0], q, r2, r2p, onep);
+        y[LN] = reduce64(acc[cc][bb][1], q, r2, r2p, onep);
+      }
+    }
+  } else {
+    // every wave takes part in the epilogue's barriers, also one whose tile
+    // is absent (it stores nothing)
+    uint32_t val[CT][BT][2];
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+        for (int pp = 0; pp < 2; ++pp) val[cc][bb][pp] = reduce64(acc[cc][bb][pp], q, r2, r2p, onep);
+    // polynomial P = (cc BT + bb) 2 + pp of the wave's tile is row P of the
+    // wave's LDS region
+    uint32_t *region = (uint32_t *)stage + wave * RWW;
+    const uint32_t q2 = 2 * q;
+    const uint32_t LOGN = 31 - __builtin_clz(g.N);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();  // the staging buffers, or the previous round's region, are free
+      if ((lane >> 5) == (uint32_t)h) {
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+          for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+            for (int pp = 0; pp < 2; ++pp) region[((cc * BT + bb) * 2 + pp) * 36 + (lane & 31u)] = val[cc][bb][pp];
+      }
+      __syncthreads();
+      uint32_t v[32];
+      const uint4 *r4 = (const uint4 *)(region + lane * 36);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint4 t4 = r4[k];
+        v[4 * k] = t4.x, v[4 * k + 1] = t4.y, v[4 * k + 2] = t4.z, v[4 * k + 3] = t4.w;
+      }
+      // stages on bits 0 .. PRE-1 of j = kb 64 + h 32 + u; twiddle index
+      // 2^(LOGN-1-b) + (j >> (b+1)), the same for every lane of the wave
+      const uint32_t j0 = kb * 64 + h * 32;
+#pragma unroll
+      for (int b = 0; b < PRE; ++b) {
+        const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1 - b)) + (j0 >> (b + 1)));
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          if (u & (1 << b)) continue;
+          const int u2 = u | (1 << b);
+          const uint64_t wt = tw[u >> (b + 1)];
+          const uint32_t X = v[u], Yv = v[u2];
+          v[u] = csub(X + Yv, q2);
+          v[u2] = shoup_lazy(X - Yv + q2, (uint32_t)wt, (uint32_t)(wt >> 32), q);
+        }
+      }
+      // back through the wave's region so that every store instruction
+      // writes two whole 128-byte runs: lanes 0-31 coefficient (lane) of
+      // polynomial 2 jp, lanes 32-63 the same of polynomial 2 jp + 1
+      uint4 *w4 = (uint4 *)(region + lane * 36);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w4[k] = make_uint4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint32_t half = lane >> 5, kk = lane & 31u;
+#pragma unroll
+      for (int jp = 0; jp < 32; ++jp) {
+        const uint32_t P = 2 * jp + half;  // this lane's polynomial for the jp-th store
+        const uint32_t scc = P / (2 * BT), sbb = (P >> 1) % BT, spp = P & 1u;
+        const uint32_t x = region[P * 36 + kk];
+        if (i0 + scc < g.c_out && b0 + sbb < B)
+          Y[(((size_t)(b0 + sbb) * g.O + (i0 + scc) * g.T + tau) * 2 + spp) * LN + (size_t)l * g.N + kb * 64 +
+            h * 32 + kk] = x;
+      }
+    }
+  }
+}
+
+template <int BT, int CT, int RG, int CG, int NS, int LDS, int PRE>
+static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
+                        const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  if (!mac_offsets_fit(g, MacShape{BT, CT, RG, CG, NS, LDS, PRE})) return hipErrorInvalidValue;
+  const uint32_t nkb = g.N / 64;
+  const uint32_t nib = (g.c_out + CG * CT - 1) / (CG * CT);
+  const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
+  const size_t nwg = (size_t)nib * g.T * nkb * g.L * nbt;
+  if (nwg == 0) return hipSuccess;
+  if constexpr (LDS != 0)
+    hipLaunchKernelGGL((k_mac_lds<BT, CT, RG, CG, NS, PRE>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w,
+                       y, g, B, nib, nkb, c, tw.inv);
+  else
+    hipLaunchKernelGGL((k_mac_tiled<BT, CT, RG, CG, NS>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y,
+                       g, B, nib, nkb, c);
+  return hipGetLastError();
+}
+
+// The register tile's 32-bit offsets span BT images and CT channels; the
+// LDS-staged form's span the workgroup's RG BT images and CG CT channels.
+bool mac_offsets_fit(const ConvGeom &g, const MacShape &m) {
+  const uint64_t ln = (uint64_t)g.L * g.N * 4;
+  const uint64_t bi = m.lds ? (uint64_t)m.rg * m.bt : m.bt, ch = m.lds ? (uint64_t)m.cg * m.ct : m.ct;
+  return bi * g.G * 2 * ln < (1ull << 32) && ch * g.G_w * ln < (1ull << 32);
+}
+
+// (images per thread, channels per thread, image groups, channel groups,
+//  loads in flight (register sets), LDS-staged, inverse stages in the epilogue)
+#define HC_MAC_VARIANTS(X)                                                                                      \
+  X(1, 8, 1, 4, 2, 0, 0) X(1, 4, 1, 4, 2, 0, 0) X(2, 4, 1, 4, 2, 0, 0) X(4, 4, 1, 4, 2, 0, 0)                   \
+  X(4, 2, 1, 4, 2, 0, 0) X(8, 2, 1, 4, 2, 0, 0) X(4, 4, 4, 2, 2, 0, 0) X(4, 8, 4, 2, 2, 0, 0)                   \
+  X(2, 8, 4, 2, 2, 0, 0) X(4, 4, 2, 4, 2, 0, 0) X(2, 4, 4, 4, 2, 0, 0) X(1, 8, 2, 4, 2, 0, 0)                   \
+  X(4, 8, 4, 2, 3, 0, 0) X(2, 8, 4, 2, 4, 0, 0) X(4, 4, 4, 2, 4, 0, 0) X(4, 4, 2, 4, 4, 0, 0)                   \
+  X(1, 8, 2, 4, 4, 0, 0) X(2, 4, 4, 4, 4, 0, 0) X(1, 8, 1, 4, 4, 0, 0) X(4, 8, 4, 2, 2, 1, 0)                   \
+  X(4, 8, 4, 2, 3, 1, 0) X(4, 8, 2, 2, 2, 1, 0) X(4, 8, 2, 2, 3, 1, 0) X(2, 8, 4, 2, 3, 1, 0)                   \
+  X(4, 4, 4, 2, 3, 1, 0) X(2, 8, 2, 2, 3, 1, 0) X(4, 8, 4, 2, 2, 1, 5) X(4, 8, 2, 2, 2, 1, 5)                   \
+  X(4, 8, 2, 2, 3, 1, 5)
+
+bool mac_variant_ok(const MacShape &m) {
+#define HC_MAC_OK(B_, C_, R_, G_, S_, D_, P_)                                                                 \
+  if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_ && m.pre == P_) \
+    return true;
+  HC_MAC_VARIANTS(HC_MAC_OK)
+#undef HC_MAC_OK
+  return false;
+}
+
+hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *x, const uint32_t *w, uint32_t *y,
+                      uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  if (m.pre && g.N < 4096) return hipErrorInvalidValue;  // the epilogue's twiddle layout needs N >= 4096
+#define HC_MAC_CASE(B_, C_, R_, G_, S_, D_, P_)                                                               \
+  if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_ && m.pre == P_) \
+    return mac_t<B_, C_, R_, G_, S_, D_, P_>(g, x, w, y, B, c, tw, st);
+  HC_MAC_VARIANTS(HC_MAC_CASE)
+#undef HC_MAC_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace hc

@@ -1,0 +1,265 @@
+// gfx950 kernels of the homomorphic convolution: forward NTT, full inverse NTT,
+// weight encoding and the small helper kernels, with their launchers. The
+// masked inverse NTT lives in hc_intt_masked.h, the multiply-accumulate in
+// hc_mac.hip.
+#include "hc_device.h"
+#include "hc_intt_masked.h"
+
+namespace hc {
+
+// ---------------------------------------------------------------- forward NTT kernel
+// One workgroup per polynomial of in/out [P][N] (limb = poly mod L). Input
+// canonical; output canonical, in bit-reversed evaluation order.
+// With a pointer table (tab.n > 0) polynomial `poly` is read from image
+// poly / ppi at polynomial poly % ppi of that image's buffer instead.
+template <int LOGN, int ELOG>
+__global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *in, uint32_t *out, LimbConsts c,
+                                                                 Twiddles tws, ImgPtrs tab, uint32_t ppi) {
+  constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
+  __shared__ uint32_t lds[N + N / 32];
+  const uint32_t tid = threadIdx.x;
+  const size_t poly = blockIdx.x;
+  const uint32_t l = (uint32_t)(poly % c.L);
+  const uint32_t q = c.q[l];
+  const uint2 *tw = tws.fwd + (size_t)l * N;
+  const uint32_t *src = tab.n ? (const uint32_t *)tab.p[poly / ppi] + (poly % ppi) * N : in + poly * N;
+  uint32_t v[E];
+  {
+    constexpr int LO = pass_lo_fwd(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
+    const uint32_t *sb = src + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+#pragma unroll
+    for (int u = 0; u < E; ++u) v[u] = __builtin_nontemporal_load(sb + gidx<LOGN, ELOG, LO, EP>(0, u));
+  }
+  FwdPasses<LOGN, ELOG, NP - 1>::run(v, lds, tid, tw, q);
+  // the last pass (bits [0, EP)) leaves runs of 2^EP consecutive coefficients
+  // in each thread: canonicalise and store them 16 bytes at a time
+  constexpr int EPL = pass_bits(LOGN, ELOG, NP - 1);
+  static_assert(pass_lo_fwd(LOGN, ELOG, NP - 1) == 0 && EPL >= 2, "last forward pass covers the low bits");
+  uint32_t *dst = out + poly * N;
+  const uint32_t q2 = 2 * q;
+#pragma unroll
+  for (int u = 0; u < E; u += 4) {
+    uint4 t4;
+    t4.x = csub(csub(v[u], q2), q);
+    t4.y = csub(csub(v[u + 1], q2), q);
+    t4.z = csub(csub(v[u + 2], q2), q);
+    t4.w = csub(csub(v[u + 3], q2), q);
+    *reinterpret_cast<uint4 *>(dst + gidx<LOGN, ELOG, 0, EPL>(tid, 0) + gidx<LOGN, ELOG, 0, EPL>(0, u)) = t4;
+  }
+  (void)NT;
+}
+
+// Full mode: [P][N] -> [P][N] canonical (in place allowed).
+template <int LOGN, int ELOG>
+__global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t *in, uint32_t *out, LimbConsts c,
+                                                                   Twiddles tws) {
+  constexpr int N = 1 << LOGN, E = 1 << ELOG, NP = n_pass(LOGN, ELOG);
+  __shared__ uint32_t lds[N + N / 32];
+  const uint32_t tid = threadIdx.x;
+  const size_t poly = blockIdx.x;
+  const uint32_t l = (uint32_t)(poly % c.L);
+  uint32_t v[1][E];
+  const uint32_t *const src[1] = {in + poly * N};
+  intt_core<LOGN, ELOG, 0, 1, 0>(src, v, lds, tid, c, tws.inv + (size_t)l * N, l);
+  constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
+  uint32_t *dst = out + poly * N;
+  const uint32_t q = c.q[l];
+  uint32_t *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+#pragma unroll
+  for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[0][u], q);
+}
+
+// ---------------------------------------------------------------- weight encoding
+// What[i][gw][l][idx] = sign * f[i][j][ky][kx] mod q_l with x^(-e) = sign x^idx,
+// e = o_j + ky w' + kx (x^0 = 1; x^(-e) = -x^(N-e) for e > 0). The e values of
+// one (i, gw) are pairwise distinct, so every slot is written at most once.
+__global__ void k_weight_scatter(const int8_t *__restrict__ f, uint32_t *__restrict__ Wt, ConvGeom g,
+                                 LimbConsts c) {
+  const size_t ff = (size_t)g.f * g.f;
+  const size_t total = (size_t)g.c_out * g.c_in * ff;
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const uint32_t tap = (uint32_t)(id % ff);
+  const uint32_t j = (uint32_t)((id / ff) % g.c_in);
+  const uint32_t i = (uint32_t)(id / (ff * g.c_in));
+  const uint32_t ky = tap / g.f, kx = tap % g.f;
+  const uint32_t gw = g.tiled ? j : j / g.cn;
+  const uint32_t oj = g.tiled ? 0u : (j % g.cn) * g.F;
+  const uint32_t e = oj + ky * g.w_pad + kx;
+  const uint32_t idx = e == 0 ? 0u : g.N - e;
+  const bool neg = e != 0;
+  const int32_t val = f[id];
+  for (uint32_t l = 0; l < g.L; ++l) {
+    const uint32_t q = c.q[l];
+    int32_t sv = neg ? -val : val;
+    const uint32_t res = sv >= 0 ? (uint32_t)sv : q - (uint32_t)(-sv);
+    Wt[(((size_t)i * g.G_w + gw) * g.L + l) * g.N + idx] = res;
+  }
+}
+
+__global__ void k_fill_zero(uint32_t *p, size_t n) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = id; k < n; k += stride) p[k] = 0u;
+}
+
+// ---------------------------------------------------------------- unfused mask + extract
+// c0_ext[b][i][l][oy][ox] = ct_out[b][(i,tau)][0][l][e] + Delta_l (r_c mod q_l) mod q_l
+__global__ void k_mask_extract(const uint32_t *__restrict__ ct, const uint32_t *__restrict__ mask,
+                               uint32_t *__restrict__ c0_ext, ConvGeom g, uint32_t B, LimbConsts c) {
+  const size_t total = (size_t)B * g.c_out * g.ho * g.wo;
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const uint32_t ox = (uint32_t)(id % g.wo);
+  const uint32_t oy = (uint32_t)((id / g.wo) % g.ho);
+  const uint32_t i = (uint32_t)((id / ((size_t)g.wo * g.ho)) % g.c_out);
+  const size_t b = id / ((size_t)g.wo * g.ho * g.c_out);
+  const uint32_t Y = g.s * oy;
+  const uint32_t tau = Y / g.r_o;
+  const uint32_t e = (Y - tau * g.r_o) * g.w_pad + g.s * ox;
+  const uint32_t o = i * g.T + tau;
+  const uint32_t r = mask[id];
+  const uint32_t t = c.t, half = c.t / 2;
+  for (uint32_t l = 0; l < g.L; ++l) {
+    const uint32_t q = c.q[l];
+    const uint32_t rc = r > half ? r - t + q : r;
+    const uint32_t add = csub(shoup_lazy(rc, c.delta[l], c.delta_p[l], q), q);
+    const uint32_t y = ct[(((b * g.O + o) * 2 + 0) * g.L + l) * (size_t)g.N + e];
+    c0_ext[((b * g.c_out + i) * g.L + l) * (size_t)g.ho * g.wo + (size_t)oy * g.wo + ox] = csub(y + add, q);
+  }
+}
+
+// c1_out[b][o][l][:] = ct[b][o][1][l][:], 16-byte copies.
+__global__ void k_copy_c1(const uint4 *__restrict__ ct, uint4 *__restrict__ c1, size_t n_ct, size_t ln4) {
+  const size_t total = n_ct * ln4;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+    const size_t ctn = id / ln4, k = id % ln4;
+    c1[id] = ct[(2 * ctn + 1) * ln4 + k];
+  }
+}
+
+// c[j] = a[j] * b[j] mod q over [P][N] (both operands variable).
+__global__ void k_pointwise_mul(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                                uint32_t *__restrict__ cc, size_t total, uint32_t N, LimbConsts c) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+    const uint32_t l = (uint32_t)((id / N) % c.L);
+    cc[id] = reduce64((uint64_t)a[id] * b[id], c.q[l], c.r2[l], c.r2_p[l], c.one_p[l]);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int LOGN, int ELOG>
+static hipError_t fwd_t(const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c, const Twiddles &tw,
+                        const ImgPtrs &tab, uint32_t ppi, hipStream_t st) {
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_ntt_fwd<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c, tw,
+                     tab, ppi);
+  return hipGetLastError();
+}
+template <int LOGN, int ELOG>
+static hipError_t inv_t(const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c, const Twiddles &tw,
+                        hipStream_t st) {
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_intt_full<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c,
+                     tw);
+  return hipGetLastError();
+}
+// (LOGN, ELOG) instances: 2^(LOGN - ELOG) threads per polynomial.
+#define HC_NTT_CASE(L, E, FN, ...) \
+  if (logn == L && elog == E) return FN<L, E>(__VA_ARGS__);
+#define HC_NTT_DISPATCH(FN, ...)                                                             \
+  HC_NTT_CASE(10, 3, FN, __VA_ARGS__) HC_NTT_CASE(10, 4, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(11, 3, FN, __VA_ARGS__) HC_NTT_CASE(11, 4, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(12, 3, FN, __VA_ARGS__) HC_NTT_CASE(12, 4, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(12, 5, FN, __VA_ARGS__) HC_NTT_CASE(13, 3, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(13, 4, FN, __VA_ARGS__) HC_NTT_CASE(13, 5, FN, __VA_ARGS__)                    \
+  HC_NTT_CASE(14, 4, FN, __VA_ARGS__) HC_NTT_CASE(14, 5, FN, __VA_ARGS__)                    \
+  return hipErrorInvalidValue;
+
+bool ntt_variant_ok(uint32_t logn, uint32_t elog) {
+  switch (logn) {
+    case 10: case 11: return elog == 3 || elog == 4;
+    case 12: case 13: return elog >= 3 && elog <= 5;
+    case 14: return elog == 4 || elog == 5;
+  }
+  return false;
+}
+
+hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
+                          const LimbConsts &c, const Twiddles &tw, hipStream_t st, const ImgPtrs *tab,
+                          uint32_t ppi) {
+  ImgPtrs none{};
+  if (tab && (tab->n == 0 || tab->n > kMaxTab || ppi == 0 || np != (size_t)tab->n * ppi)) return hipErrorInvalidValue;
+  const ImgPtrs &t = tab ? *tab : none;
+  HC_NTT_DISPATCH(fwd_t, in, out, np, c, tw, t, ppi, st)
+}
+hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
+                            const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  HC_NTT_DISPATCH(inv_t, in, out, np, c, tw, st)
+}
+
+bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre) {
+  return ntt_variant_ok(logn, elog) && (npw == 1 || (npw == 2 && elog <= 4)) &&
+         (pre == 0 || (pre == kMacPre && logn >= 12));
+}
+
+hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre,
+                              const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1, uint32_t B,
+                              const LimbConsts &c, const Twiddles &tw, hipStream_t st, const OutPtrs *tab) {
+  OutPtrs none{};
+  if (tab && (tab->n != B || B > kMaxTab)) return hipErrorInvalidValue;
+  if (!intt_masked_ok(logn, elog, npw, pre)) return hipErrorInvalidValue;
+  const OutPtrs &t = tab ? *tab : none;
+  switch (logn) {
+    case 10: return intt_masked_logn<10>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
+    case 11: return intt_masked_logn<11>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
+    case 12: return intt_masked_logn<12>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
+    case 13: return intt_masked_logn<13>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
+    case 14: return intt_masked_logn<14>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *f, uint32_t *w, const LimbConsts &c,
+                                 hipStream_t st) {
+  const size_t total = (size_t)g.c_out * g.c_in * g.f * g.f;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_weight_scatter, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, f, w, g, c);
+  return hipGetLastError();
+}
+hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_mask_extract(const ConvGeom &g, const uint32_t *ct, const uint32_t *mask, uint32_t *c0,
+                               uint32_t *c1, uint32_t B, const LimbConsts &c, hipStream_t st) {
+  const size_t total = (size_t)B * g.c_out * g.ho * g.wo;
+  if (total) {
+    hipLaunchKernelGGL(k_mask_extract, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, ct, mask, c0, g, B,
+                       c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const size_t n_ct = (size_t)B * g.O, ln4 = (size_t)g.L * g.N / 4;
+  if (n_ct == 0) return hipSuccess;
+  size_t blocks = (n_ct * ln4 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_copy_c1, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint4 *)ct, (uint4 *)c1, n_ct, ln4);
+  return hipGetLastError();
+}
+hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *cc, size_t np, uint32_t N,
+                                const LimbConsts &k, hipStream_t st) {
+  const size_t total = np * N;
+  if (total == 0) return hipSuccess;
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_pointwise_mul, dim3((uint32_t)blocks), dim3(256), 0, st, a, b, cc, total, N, k);
+  return hipGetLastError();
+}
+
+}  // namespace hc
