@@ -14,6 +14,11 @@ hipError_t intt_masked_logn(const ConvGeom &g, uint32_t elog, uint32_t npw, uint
                             const Twiddles &tw, const OutPtrs &out, hipStream_t st);
 
 #ifdef HC_INTT_MASKED_IMPL
+// Output and mask buffers are global memory; table entries are plain
+// integers, so their pointers are cast to the global address space (vector
+// global accesses rather than flat ones, which also count as LDS accesses).
+using gu32 = __attribute__((address_space(1))) uint32_t;
+
 // Masked mode over Yhat [B][O][2][L][N]: c1 polynomials are written whole to
 // c1_out [B][O][L][N]; c0 polynomials get the server mask added at the valid
 // output coefficients, which are gathered into c0_ext [B][c_out][L][ho][wo].
@@ -59,8 +64,8 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
       if (!valid[m]) continue;
       const uint32_t o = (uint32_t)(bo[m] % g.O);
       const size_t b = bo[m] / g.O;
-      uint32_t *dst = out.n ? (uint32_t *)out.c1[b] + ((size_t)o * g.L + l) * N : c1_out + (bo[m] * g.L + l) * (size_t)N;
-      uint32_t *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+      gu32 *dst = out.n ? (gu32 *)out.c1[b] + ((size_t)o * g.L + l) * N : (gu32 *)c1_out + (bo[m] * g.L + l) * (size_t)N;
+      gu32 *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
 #pragma unroll
       for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[m][u], q);
     }
@@ -86,9 +91,9 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32
     const uint32_t oy0 = tau * g.r_o / g.s;
     const uint32_t oy1 = min(g.ho, (tau + 1) * g.r_o / g.s);
     const uint32_t count = (oy1 > oy0 ? oy1 - oy0 : 0) * g.wo;
-    const uint32_t *mrow = out.n ? (const uint32_t *)out.mask[b] + i * hw : mask + (b * g.c_out + i) * hw;
-    uint32_t *orow = out.n ? (uint32_t *)out.c0[b] + ((size_t)i * g.L + l) * hw
-                           : c0_ext + ((b * g.c_out + i) * g.L + l) * hw;
+    const gu32 *mrow = out.n ? (const gu32 *)out.mask[b] + i * hw : (const gu32 *)mask + (b * g.c_out + i) * hw;
+    gu32 *orow = out.n ? (gu32 *)out.c0[b] + ((size_t)i * g.L + l) * hw
+                       : (gu32 *)c0_ext + ((b * g.c_out + i) * g.L + l) * hw;
     for (uint32_t idx = tid; idx < count; idx += NT) {
       const uint32_t oy = oy0 + idx / g.wo, ox = idx % g.wo;
       const uint32_t e = (g.s * oy - tau * g.r_o) * g.w_pad + g.s * ox;

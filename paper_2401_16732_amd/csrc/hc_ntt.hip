@@ -22,11 +22,14 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
   const uint32_t l = (uint32_t)(poly % c.L);
   const uint32_t q = c.q[l];
   const uint2 *tw = tws.fwd + (size_t)l * N;
-  const uint32_t *src = tab.n ? (const uint32_t *)tab.p[poly / ppi] + (poly % ppi) * N : in + poly * N;
+  // table entries are integers: cast to the global address space so the
+  // loads are global rather than flat ones (which also count as LDS accesses)
+  using gu32 = __attribute__((address_space(1))) const uint32_t;
+  gu32 *src = tab.n ? (gu32 *)tab.p[poly / ppi] + (poly % ppi) * N : (gu32 *)in + poly * N;
   uint32_t v[E];
   {
     constexpr int LO = pass_lo_fwd(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
-    const uint32_t *sb = src + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+    gu32 *sb = src + gidx<LOGN, ELOG, LO, EP>(tid, 0);
 #pragma unroll
     for (int u = 0; u < E; ++u) v[u] = __builtin_nontemporal_load(sb + gidx<LOGN, ELOG, LO, EP>(0, u));
   }
