@@ -140,6 +140,39 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
   }
 }
 
+// Twiddle sources of an inverse pass over bits [LO, LO + EP): MemTw reads
+// each twiddle from the table where it is used; RegTw holds the whole pass's
+// twiddles in registers, loaded once (for kernels that transform several
+// polynomials of one limb in turn).
+template <int LOGN, int ELOG, int LO, int EP>
+struct MemTw {
+  const uint2 *tw;
+  uint32_t tid;
+  __device__ __forceinline__ uint2 operator()(int bb, int u) const {
+    const StageTw<LOGN, ELOG, LO, EP> st(tw, tid, LO + bb);
+    return st(u, LO + bb);
+  }
+};
+template <int LOGN, int ELOG, int LO, int EP>
+struct RegTw {
+  // slot [bb][u] for u with bit bb clear; entries a pass never reads are
+  // dropped. The two words are kept apart so that no register pair is tied up.
+  uint32_t w[EP][1 << ELOG], wp[EP][1 << ELOG];
+  __device__ __forceinline__ void load(const uint2 *tw, uint32_t tid) {
+    const MemTw<LOGN, ELOG, LO, EP> m{tw, tid};
+#pragma unroll
+    for (int bb = 0; bb < EP; ++bb)
+#pragma unroll
+      for (int u = 0; u < (1 << ELOG); ++u)
+        if (!(u & (1 << bb))) {
+          const uint2 t = m(bb, u);
+          w[bb][u] = t.x;
+          wp[bb][u] = t.y;
+        }
+  }
+  __device__ __forceinline__ uint2 operator()(int bb, int u) const { return make_uint2(w[bb][u], wp[bb][u]); }
+};
+
 // Inverse (Gentleman-Sande, bit-reversed -> natural) stages of one pass; the
 // last stage (s = 0) also multiplies by N^-1.
 // Pruning: when only outputs below 2^(LOGN - PS) are wanted, every stage on a
@@ -149,10 +182,10 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
 // is a compile-time constant, so no stage carries a run-time branch.
 // M polynomials of one limb go through the stages together (v[m]): each
 // twiddle is loaded once for all of them.
-template <int LOGN, int ELOG, int LO, int EP, int PS, int M>
-__device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
-                                         uint32_t q, uint32_t ninv, uint32_t ninvp, uint32_t ninvw,
-                                         uint32_t ninvwp) {
+// tws(bb, u): twiddle of stage bit LO + bb for register slot u (MemTw, RegTw).
+template <int LOGN, int ELOG, int LO, int EP, int PS, int M, class TW>
+__device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &tws, uint32_t q, uint32_t ninv,
+                                         uint32_t ninvp, uint32_t ninvw, uint32_t ninvwp) {
   constexpr int E = 1 << ELOG;
   const uint32_t q2 = 2 * q;
 #pragma unroll
@@ -160,7 +193,6 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], uint32_t t
     const int b = LO + bb;
     const int s = LOGN - 1 - b;
     const bool sum_only = b >= LOGN - PS;
-    const StageTw<LOGN, ELOG, LO, EP> tws(tw, tid, b);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       if (u & (1 << bb)) continue;
@@ -177,7 +209,7 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], uint32_t t
           v[m][u2] = shoup_lazy(X - Y + q2, ninvw, ninvwp, q);
         }
       } else {
-        const uint2 w = tws(u, b);
+        const uint2 w = tws(bb, u);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           const uint32_t X = v[m][u], Y = v[m][u2];
@@ -237,30 +269,83 @@ __host__ __device__ constexpr int inv_lo(int logn, int elog, int pre, int k) {
 }
 __host__ __device__ constexpr int inv_ep(int logn, int elog, int pre, int k) { return pass_bits(logn - pre, elog, k); }
 
+// Twiddle sets for InvPasses: pass<K>() is the source for inverse pass K.
+template <int LOGN, int ELOG, int PRE>
+struct MemTws {
+  const uint2 *tw;
+  uint32_t tid;
+  template <int K>
+  __device__ __forceinline__ MemTw<LOGN, ELOG, inv_lo(LOGN, ELOG, PRE, K), inv_ep(LOGN, ELOG, PRE, K)> pass() const {
+    return {tw, tid};
+  }
+};
+
+// after_first() runs once the first pass's butterflies are done, before any
+// LDS exchange (the looped kernel issues its stores and loads there).
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
+
+// Twiddle set whose passes that start below bit 6 (twiddles vary across a
+// wave: the first pass, and the second when it starts below bit 6) hold
+// their twiddles in registers, loaded when the set is built: before the
+// first LDS exchange, so that the second pass's loads are not issued behind
+// a barrier and waited for right after it. Later passes read theirs where
+// they are used (wave-uniform, scalar loads).
+template <int LOGN, int ELOG, int PRE>
+struct EarlyTws {
+  static constexpr int NP = inv_np(LOGN, ELOG, PRE);
+  static constexpr int LO0 = inv_lo(LOGN, ELOG, PRE, 0), EP0 = inv_ep(LOGN, ELOG, PRE, 0);
+  static constexpr int LO1 = NP > 1 ? inv_lo(LOGN, ELOG, PRE, 1) : 0;
+  static constexpr int EP1 = NP > 1 ? inv_ep(LOGN, ELOG, PRE, 1) : 1;
+  static constexpr bool kReg0 = LO0 < 6, kReg1 = NP > 1 && LO1 < 6;
+  const uint2 *tw;
+  uint32_t tid;
+  RegTw<LOGN, ELOG, LO0, EP0> t0;
+  RegTw<LOGN, ELOG, LO1, EP1> t1;
+  __device__ __forceinline__ EarlyTws(const uint2 *tw_, uint32_t tid_) : tw(tw_), tid(tid_) {
+    if constexpr (kReg0) t0.load(tw, tid);
+    if constexpr (kReg1) t1.load(tw, tid);
+  }
+  template <int K>
+  __device__ __forceinline__ auto pass() const {
+    if constexpr (K == 0 && kReg0) {
+      return t0;
+    } else if constexpr (K == 1 && kReg1) {
+      return t1;
+    } else {
+      return MemTw<LOGN, ELOG, inv_lo(LOGN, ELOG, PRE, K), inv_ep(LOGN, ELOG, PRE, K)>{tw, tid};
+    }
+  }
+};
+
 template <int LOGN, int ELOG, int K, int PS, int M, int PRE>
 struct InvPasses {
+  template <class TWS, class H>
   static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *lds, uint32_t tid,
-                                             const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
-                                             uint32_t bp) {
+                                             const TWS &tws, const H &after_first, uint32_t q, uint32_t a,
+                                             uint32_t ap, uint32_t b, uint32_t bp) {
     constexpr int LO = inv_lo(LOGN, ELOG, PRE, K), EP = inv_ep(LOGN, ELOG, PRE, K);
     constexpr int PLO = inv_lo(LOGN, ELOG, PRE, K - 1), PEP = inv_ep(LOGN, ELOG, PRE, K - 1);
-    InvPasses<LOGN, ELOG, K - 1, PS, M, PRE>::run(v, lds, tid, tw, q, a, ap, b, bp);
+    InvPasses<LOGN, ELOG, K - 1, PS, M, PRE>::run(v, lds, tid, tws, after_first, q, a, ap, b, bp);
 #pragma unroll
     for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, PLO, PEP>(v[m], lds + m * lds_words(LOGN), tid);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
-    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tid, tw, q, a, ap, b, bp);
+    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tws.template pass<K>(), q, a, ap, b, bp);
   }
 };
 template <int LOGN, int ELOG, int PS, int M, int PRE>
 struct InvPasses<LOGN, ELOG, 0, PS, M, PRE> {
   // pass 0 (bits [PRE, PRE + EP)) expects its inputs already in registers
-  static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *, uint32_t tid,
-                                             const uint2 *tw, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
+  template <class TWS, class H>
+  static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *, uint32_t, const TWS &tws,
+                                             const H &after_first, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
                                              uint32_t bp) {
     constexpr int LO = inv_lo(LOGN, ELOG, PRE, 0), EP = inv_ep(LOGN, ELOG, PRE, 0);
-    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tid, tw, q, a, ap, b, bp);
+    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tws.template pass<0>(), q, a, ap, b, bp);
+    after_first();
   }
 };
 
@@ -285,25 +370,49 @@ __device__ __forceinline__ void load_low_pass(uint32_t (&v)[1 << ELOG], const ui
 // polynomials src[m] of one limb, LDS of M * lds_words(LOGN) words. PRE:
 // stages on bits below PRE already done (the first pass then reads its
 // coefficients with coalesced 4-byte loads: lanes map to the low bits).
+// The first inverse pass's registers from global memory: with PRE = 0 the
+// pass covers bits [0, EP), 2^EP consecutive words per group (16-byte
+// loads); otherwise lanes map to the low bits (coalesced 4-byte loads).
+template <int LOGN, int ELOG, int PRE>
+__device__ __forceinline__ void load_first(uint32_t (&v)[1 << ELOG], const uint32_t *src, uint32_t tid) {
+  if constexpr (PRE == 0) {
+    load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v, src, tid);
+  } else {
+    constexpr int LO = inv_lo(LOGN, ELOG, PRE, 0), EP = inv_ep(LOGN, ELOG, PRE, 0);
+    const uint32_t *sb = src + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+#pragma unroll
+    for (int u = 0; u < (1 << ELOG); ++u) v[u] = sb[gidx<LOGN, ELOG, LO, EP>(0, u)];
+  }
+}
+
+// The inverse passes over registers already loaded (load_first), with
+// twiddles from tws: the result is in registers, laid out for the last pass.
+template <int LOGN, int ELOG, int PS, int M, int PRE, class TWS, class H = NoHook>
+__device__ __forceinline__ void intt_passes(uint32_t (&v)[M][1 << ELOG], uint32_t *lds, uint32_t tid,
+                                            const LimbConsts &c, const TWS &tws, uint32_t l,
+                                            const H &after_first = H{}) {
+  InvPasses<LOGN, ELOG, inv_np(LOGN, ELOG, PRE) - 1, PS, M, PRE>::run(v, lds, tid, tws, after_first, c.q[l],
+                                                                      c.ninv[l], c.ninv_p[l], c.ninvw[l],
+                                                                      c.ninvw_p[l]);
+}
+
+// PS: top stages pruned (see inv_pass); 0 for the whole transform. M
+// polynomials src[m] of one limb, LDS of M * lds_words(LOGN) words. PRE:
+// stages on bits below PRE already done.
 template <int LOGN, int ELOG, int PS, int M, int PRE>
 __device__ __forceinline__ void intt_core(const uint32_t *const (&src)[M], uint32_t (&v)[M][1 << ELOG],
                                           uint32_t *lds, uint32_t tid, const LimbConsts &c, const uint2 *tw,
                                           uint32_t l) {
-  constexpr int NP = inv_np(LOGN, ELOG, PRE);
-  if constexpr (PRE == 0) {
 #pragma unroll
-    for (int m = 0; m < M; ++m) load_low_pass<LOGN, ELOG, pass_bits(LOGN, ELOG, 0)>(v[m], src[m], tid);
+  for (int m = 0; m < M; ++m) load_first<LOGN, ELOG, PRE>(v[m], src[m], tid);
+  // ELOG 5 keeps the per-use loads: its first two passes' twiddles would
+  // cost it occupancy
+  if constexpr (ELOG <= 4) {
+    const EarlyTws<LOGN, ELOG, PRE> tws(tw, tid);
+    intt_passes<LOGN, ELOG, PS, M, PRE>(v, lds, tid, c, tws, l);
   } else {
-    constexpr int LO = inv_lo(LOGN, ELOG, PRE, 0), EP = inv_ep(LOGN, ELOG, PRE, 0);
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const uint32_t *sb = src[m] + gidx<LOGN, ELOG, LO, EP>(tid, 0);
-#pragma unroll
-      for (int u = 0; u < (1 << ELOG); ++u) v[m][u] = sb[gidx<LOGN, ELOG, LO, EP>(0, u)];
-    }
+    intt_passes<LOGN, ELOG, PS, M, PRE>(v, lds, tid, c, MemTws<LOGN, ELOG, PRE>{tw, tid}, l);
   }
-  InvPasses<LOGN, ELOG, NP - 1, PS, M, PRE>::run(v, lds, tid, tw, c.q[l], c.ninv[l], c.ninv_p[l], c.ninvw[l],
-                                                 c.ninvw_p[l]);
 }
 
 }  // namespace hc
