@@ -8,6 +8,7 @@ output coefficients extracted, replayed as one HIP graph. Inputs (ciphertexts,
 masks) are resident in HBM before the timed region. Reported:
 
   value                ms of HE convolution per ResNet-50 image (batched graph)
+  ms_per_step_spread   median, p10 and p90 of the single-step times
   plain_ms_per_image   the same work per image with one launch sequence per
                        layer at B = 1 (stream order, no graph)
   speedup_vs_plain     plain / batched
@@ -39,7 +40,7 @@ MAC_PEAK = CUS * CLK * MUL_LANES
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--net", default="resnet50_224", choices=["resnet50_224", "resnet18_cifar", "resnet18_224"])
     ap.add_argument("--batch", type=int, default=16)
@@ -203,16 +204,22 @@ def main():
         bt.run(ct_in, mask, c0, c1)
     torch.cuda.synchronize()
     ms_step = float("nan")
+    spread = None
     if a.steps > 0:
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # one event between consecutive steps on the launch stream: the whole
+        # region (first to last) gives ms_per_step, the gaps the per-step spread
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
         w0 = time.perf_counter()
-        e0.record()
-        for _ in range(a.steps):
+        ev[0].record()
+        for k in range(a.steps):
             bt.run(ct_in, mask, c0, c1)
-        e1.record()
+            ev[k + 1].record()
         torch.cuda.synchronize()
         wall_ms = (time.perf_counter() - w0) * 1e3 / a.steps
-        ms_step = e0.elapsed_time(e1) / a.steps
+        ms_step = ev[0].elapsed_time(ev[-1]) / a.steps
+        per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps))
+        q = lambda f: per[min(len(per) - 1, int(round(f * (len(per) - 1))))]
+        spread = {"median": round(q(0.5), 3), "p10": round(q(0.1), 3), "p90": round(q(0.9), 3)}
         print(f"[bench] batched: {ms_step:.2f} ms/step ({ms_step / B:.3f} ms/image), wall {wall_ms:.2f}",
               file=sys.stderr, flush=True)
 
@@ -299,6 +306,7 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": round(ms_step, 3),
+        "ms_per_step_spread": spread,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,

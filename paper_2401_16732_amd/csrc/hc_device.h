@@ -126,14 +126,19 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
     // twiddle index 2^s + (j >> (b + 1)), split into thread and register parts
     const StageTw<LOGN, ELOG, LO, EP> tws(tw, tid, b);
     (void)s;
+    // butterflies side by side, one operation at a time (as in inv_pass);
+    // pair k is (u, u + 2^bb), u = k with a zero inserted at bit bb
+    uint32_t hi[E / 2];
 #pragma unroll
-    for (int u = 0; u < E; ++u) {
-      if (u & (1 << bb)) continue;
-      const int u2 = u | (1 << bb);
-      const uint2 w = tws(u, b);
-      uint32_t X = v[u], Y = v[u2];
-      X = csub(X, q2);
-      const uint32_t T = shoup_lazy(Y, w.x, w.y, q);
+    for (int k = 0; k < E / 2; ++k) {
+      const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+      hi[k] = __umulhi(v[u2], tws(u, b).y);
+    }
+#pragma unroll
+    for (int k = 0; k < E / 2; ++k) {
+      const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+      const uint32_t X = csub(v[u], q2);
+      const uint32_t T = v[u2] * tws(u, b).x - hi[k] * q;  // Shoup: in [0, 2q)
       v[u] = X + T;
       v[u2] = X - T + q2;
     }
@@ -182,7 +187,8 @@ struct RegTw {
 // is a compile-time constant, so no stage carries a run-time branch.
 // M polynomials of one limb go through the stages together (v[m]): each
 // twiddle is loaded once for all of them.
-// tws(bb, u): twiddle of stage bit LO + bb for register slot u (MemTw, RegTw).
+// tws(bb, u): twiddle {w, w'} of stage bit LO + bb for register slot u
+// (MemTw, RegTw).
 template <int LOGN, int ELOG, int LO, int EP, int PS, int M, class TW>
 __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &tws, uint32_t q, uint32_t ninv,
                                          uint32_t ninvp, uint32_t ninvw, uint32_t ninvwp) {
@@ -193,30 +199,69 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &
     const int b = LO + bb;
     const int s = LOGN - 1 - b;
     const bool sum_only = b >= LOGN - PS;
+    // The stage's butterflies go side by side, one operation at a time, so
+    // that independent instructions follow each other rather than each
+    // butterfly's dependent chain (Shoup: a w - umulhi(a, w') q). Pair k
+    // is (u, u + 2^bb) with u = k with a zero inserted at bit bb.
+    if (s == 0) {
+      // N^-1 on the sum; N^-1 psi^-brv(1) on the difference (or nothing: pruned)
+      uint32_t a[M][E / 2], d[M][E / 2], ha[M][E / 2], hd[M][E / 2];
 #pragma unroll
-    for (int u = 0; u < E; ++u) {
-      if (u & (1 << bb)) continue;
-      const int u2 = u | (1 << bb);
-      if (sum_only) {
+      for (int m = 0; m < M; ++m)
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-          v[m][u] = s == 0 ? shoup_lazy(v[m][u] + v[m][u2], ninv, ninvp, q) : csub(v[m][u] + v[m][u2], q2);
-      } else if (s == 0) {
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          const uint32_t X = v[m][u], Y = v[m][u2];
-          v[m][u] = shoup_lazy(X + Y, ninv, ninvp, q);
-          v[m][u2] = shoup_lazy(X - Y + q2, ninvw, ninvwp, q);
+        for (int k = 0; k < E / 2; ++k) {
+          const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+          a[m][k] = v[m][u] + v[m][u2];
+          d[m][k] = v[m][u] - v[m][u2] + q2;
         }
-      } else {
-        const uint2 w = tws(bb, u);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int k = 0; k < E / 2; ++k) {
+          ha[m][k] = __umulhi(a[m][k], ninvp);
+          if (!sum_only) hd[m][k] = __umulhi(d[m][k], ninvwp);
+        }
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int k = 0; k < E / 2; ++k) {
+          const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+          v[m][u] = a[m][k] * ninv - ha[m][k] * q;
+          if (!sum_only) v[m][u2] = d[m][k] * ninvw - hd[m][k] * q;
+        }
+    } else if (sum_only) {
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int k = 0; k < E / 2; ++k) {
+          const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+          v[m][u] = csub(v[m][u] + v[m][u2], q2);
+        }
+    } else {
+      uint32_t d[M][E / 2], hi[M][E / 2];
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int k = 0; k < E / 2; ++k) {
+          const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
           const uint32_t X = v[m][u], Y = v[m][u2];
+          d[m][k] = X - Y + q2;
           v[m][u] = csub(X + Y, q2);
-          v[m][u2] = shoup_lazy(X - Y + q2, w.x, w.y, q);
         }
-      }
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int k = 0; k < E / 2; ++k) {
+          const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1));
+          hi[m][k] = __umulhi(d[m][k], tws(bb, u).y);
+        }
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int k = 0; k < E / 2; ++k) {
+          const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+          v[m][u2] = d[m][k] * tws(bb, u).x - hi[m][k] * q;  // in [0, 2q)
+        }
     }
   }
 }
