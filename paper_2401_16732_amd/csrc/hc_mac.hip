@@ -415,14 +415,22 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__rest
 #pragma unroll
       for (int b = 0; b < PRE; ++b) {
         const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1 - b)) + (j0 >> (b + 1)));
+        // the stage's 16 butterflies side by side, one operation at a time
+        // (pair k is (u, u + 2^b), u = k with a zero inserted at bit b)
+        uint32_t d[16], hi[16];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-          if (u & (1 << b)) continue;
-          const int u2 = u | (1 << b);
-          const uint64_t wt = tw[u >> (b + 1)];
+        for (int k = 0; k < 16; ++k) {
+          const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
           const uint32_t X = v[u], Yv = v[u2];
+          d[k] = X - Yv + q2;
           v[u] = csub(X + Yv, q2);
-          v[u2] = shoup_lazy(X - Yv + q2, (uint32_t)wt, (uint32_t)(wt >> 32), q);
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) hi[k] = __umulhi(d[k], (uint32_t)(tw[k >> b] >> 32));
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
+          v[u2] = d[k] * (uint32_t)tw[k >> b] - hi[k] * q;  // Shoup: in [0, 2q)
         }
       }
       // back through the wave's region so that every store instruction
