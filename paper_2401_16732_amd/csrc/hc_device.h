@@ -147,8 +147,7 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid,
 
 // Twiddle sources of an inverse pass over bits [LO, LO + EP): MemTw reads
 // each twiddle from the table where it is used; RegTw holds the whole pass's
-// twiddles in registers, loaded once (for kernels that transform several
-// polynomials of one limb in turn).
+// twiddles in registers, loaded ahead of time (EarlyTws below).
 template <int LOGN, int ELOG, int LO, int EP>
 struct MemTw {
   const uint2 *tw;
@@ -325,11 +324,6 @@ struct MemTws {
   }
 };
 
-// after_first() runs once the first pass's butterflies are done, before any
-// LDS exchange (the looped kernel issues its stores and loads there).
-struct NoHook {
-  __device__ __forceinline__ void operator()() const {}
-};
 
 // Twiddle set whose passes that start below bit 6 (twiddles vary across a
 // wave: the first pass, and the second when it starts below bit 6) hold
@@ -366,13 +360,13 @@ struct EarlyTws {
 
 template <int LOGN, int ELOG, int K, int PS, int M, int PRE>
 struct InvPasses {
-  template <class TWS, class H>
+  template <class TWS>
   static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *lds, uint32_t tid,
-                                             const TWS &tws, const H &after_first, uint32_t q, uint32_t a,
-                                             uint32_t ap, uint32_t b, uint32_t bp) {
+                                             const TWS &tws, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
+                                             uint32_t bp) {
     constexpr int LO = inv_lo(LOGN, ELOG, PRE, K), EP = inv_ep(LOGN, ELOG, PRE, K);
     constexpr int PLO = inv_lo(LOGN, ELOG, PRE, K - 1), PEP = inv_ep(LOGN, ELOG, PRE, K - 1);
-    InvPasses<LOGN, ELOG, K - 1, PS, M, PRE>::run(v, lds, tid, tws, after_first, q, a, ap, b, bp);
+    InvPasses<LOGN, ELOG, K - 1, PS, M, PRE>::run(v, lds, tid, tws, q, a, ap, b, bp);
 #pragma unroll
     for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, PLO, PEP>(v[m], lds + m * lds_words(LOGN), tid);
     __syncthreads();
@@ -384,13 +378,11 @@ struct InvPasses {
 template <int LOGN, int ELOG, int PS, int M, int PRE>
 struct InvPasses<LOGN, ELOG, 0, PS, M, PRE> {
   // pass 0 (bits [PRE, PRE + EP)) expects its inputs already in registers
-  template <class TWS, class H>
+  template <class TWS>
   static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *, uint32_t, const TWS &tws,
-                                             const H &after_first, uint32_t q, uint32_t a, uint32_t ap, uint32_t b,
-                                             uint32_t bp) {
+                                             uint32_t q, uint32_t a, uint32_t ap, uint32_t b, uint32_t bp) {
     constexpr int LO = inv_lo(LOGN, ELOG, PRE, 0), EP = inv_ep(LOGN, ELOG, PRE, 0);
     inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tws.template pass<0>(), q, a, ap, b, bp);
-    after_first();
   }
 };
 
@@ -432,13 +424,11 @@ __device__ __forceinline__ void load_first(uint32_t (&v)[1 << ELOG], const uint3
 
 // The inverse passes over registers already loaded (load_first), with
 // twiddles from tws: the result is in registers, laid out for the last pass.
-template <int LOGN, int ELOG, int PS, int M, int PRE, class TWS, class H = NoHook>
+template <int LOGN, int ELOG, int PS, int M, int PRE, class TWS>
 __device__ __forceinline__ void intt_passes(uint32_t (&v)[M][1 << ELOG], uint32_t *lds, uint32_t tid,
-                                            const LimbConsts &c, const TWS &tws, uint32_t l,
-                                            const H &after_first = H{}) {
-  InvPasses<LOGN, ELOG, inv_np(LOGN, ELOG, PRE) - 1, PS, M, PRE>::run(v, lds, tid, tws, after_first, c.q[l],
-                                                                      c.ninv[l], c.ninv_p[l], c.ninvw[l],
-                                                                      c.ninvw_p[l]);
+                                            const LimbConsts &c, const TWS &tws, uint32_t l) {
+  InvPasses<LOGN, ELOG, inv_np(LOGN, ELOG, PRE) - 1, PS, M, PRE>::run(v, lds, tid, tws, c.q[l], c.ninv[l],
+                                                                      c.ninv_p[l], c.ninvw[l], c.ninvw_p[l]);
 }
 
 // PS: top stages pruned (see inv_pass); 0 for the whole transform. M
