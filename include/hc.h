@@ -41,7 +41,12 @@
  *   mask r           [B][c_out][ho][wo]  values in [0, t)
  *   c0_ext           [B][c_out][L][ho][wo]
  *   c1_out           [B][out_cts][L][n]
- * Inputs must be canonical residues (in [0, q_l)); outputs always are.
+ * Inputs must be canonical residues (in [0, q_l)); outputs always are. The
+ * library trusts them, unless the environment variable HC_CHECK_INPUTS=1 is
+ * set when a context is created: hc_conv and hc_conv_masked on its layers
+ * then count the input ciphertexts' non-canonical words first (a device pass
+ * and a wait for the stream) and return HC_EINVAL if there are any.
+ * hc_check_residues does the same count on demand.
  *
  * Errors: every call returns hc_status. Argument and shape errors are
  * synchronous (HC_EINVAL / HC_EUNSUPPORTED); kernel faults are asynchronous and
@@ -281,6 +286,15 @@ void hc_server_destroy(hc_server *s);
  * ws: at least 2 * count * L * N * 4 bytes. Exposes the NTT for testing. */
 hc_status hc_poly_mul(const hc_ctx *ctx, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t count,
                       void *ws, size_t ws_bytes, void *stream);
+
+/* Count the words of npolys polynomials laid out [..][L][N] (device memory,
+ * e.g. ciphertexts [B][cts][2][L][N] with npolys = B * cts * 2 * L) that are
+ * not canonical, i.e. not below the prime of their limb, into *n_bad (host).
+ * Enqueued on `stream`; the call waits for the stream. The input-validation
+ * step of the interface (the same count HC_CHECK_INPUTS=1 runs in the conv
+ * calls). */
+hc_status hc_check_residues(const hc_ctx *ctx, const uint32_t *polys, size_t npolys, void *stream,
+                            uint64_t *n_bad);
 
 /* Wait for all work on the context's device; reports earlier asynchronous faults. */
 hc_status hc_sync(hc_ctx *ctx);

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <map>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -360,6 +361,10 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
   c->L = L;
   c->t = t;
   c->device = hip_device;
+  {
+    const char *chk = std::getenv("HC_CHECK_INPUTS");
+    c->check_inputs = chk && chk[0] == '1';
+  }
   while ((1u << c->logn) < N) ++c->logn;
   const uint64_t two_n = 2ull * N;
   if (primes) {
@@ -588,12 +593,48 @@ hc_status hc_workspace_size(const hc_layer *ly, uint32_t B, int masked, size_t *
   return HC_OK;
 }
 
+namespace {
+// Number of non-canonical words in npolys polynomials [..][L][N], counted on
+// the device; the call waits for the stream.
+hc_status count_noncanonical(const hc_ctx &c, const uint32_t *p, size_t npolys, hipStream_t st, uint64_t *n_bad) {
+  unsigned long long *d = nullptr;
+  HC_HIP(hipMalloc((void **)&d, sizeof(*d)));
+  unsigned long long h = 0;
+  hipError_t e = hipMemsetAsync(d, 0, sizeof(*d), st);
+  if (e == hipSuccess) e = hc::launch_count_noncanonical(p, npolys, c.N, c.consts, d, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "residue check");
+  *n_bad = h;
+  return HC_OK;
+}
+// With HC_CHECK_INPUTS=1: HC_EINVAL when an input ciphertext word is not canonical.
+hc_status check_input(const hc_layer *ly, const uint32_t *ct_in, uint32_t B, hipStream_t st) {
+  if (!ly->ctx->check_inputs) return HC_OK;
+  uint64_t bad = 0;
+  hc_status s = count_noncanonical(*ly->ctx, ct_in, (size_t)B * ly->lay.in_cts * 2 * ly->ctx->L, st, &bad);
+  if (s != HC_OK) return s;
+  return bad ? fail(HC_EINVAL, "input ciphertext word not below its prime") : HC_OK;
+}
+}  // namespace
+
+hc_status hc_check_residues(const hc_ctx *c, const uint32_t *polys, size_t npolys, void *stream, uint64_t *n_bad) {
+  if (!c || !n_bad || (npolys && !polys)) return fail(HC_EINVAL, "null argument");
+  *n_bad = 0;
+  if (npolys == 0) return HC_OK;
+  DeviceGuard dg(c->device);
+  return count_noncanonical(*c, polys, npolys, (hipStream_t)stream, n_bad);
+}
+
 hc_status hc_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_out, uint32_t B, void *ws, size_t ws_bytes,
                   void *stream) {
   if (!ly || (B && (!ct_in || !ct_out || !ws))) return fail(HC_EINVAL, "null argument");
   if (B == 0) return HC_OK;
   if (ws_bytes < ws_bytes_for(ly, B, false)) return fail(HC_EINVAL, "workspace too small");
   DeviceGuard dg(ly->ctx->device);
+  hc_status s = check_input(ly, ct_in, B, (hipStream_t)stream);
+  if (s != HC_OK) return s;
   return enqueue_conv(ly, ct_in, ct_out, nullptr, nullptr, nullptr, B, ws, false, (hipStream_t)stream);
 }
 
@@ -613,6 +654,8 @@ hc_status hc_conv_masked(const hc_layer *ly, const uint32_t *ct_in, const uint32
   if (B == 0) return HC_OK;
   if (ws_bytes < ws_bytes_for(ly, B, true)) return fail(HC_EINVAL, "workspace too small");
   DeviceGuard dg(ly->ctx->device);
+  hc_status s = check_input(ly, ct_in, B, (hipStream_t)stream);
+  if (s != HC_OK) return s;
   return enqueue_conv(ly, ct_in, nullptr, mask, c0_ext, c1_out, B, ws, true, (hipStream_t)stream);
 }
 

@@ -99,6 +99,10 @@ hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *filters, uint3
 hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st);
 hipError_t launch_mask_extract(const ConvGeom &g, const uint32_t *ct_out, const uint32_t *mask, uint32_t *c0_ext,
                                uint32_t *c1_out, uint32_t B, const LimbConsts &c, hipStream_t st);
+// Adds to *count (device) the number of words of np polynomials [..][L][N]
+// that are >= the prime of their limb.
+hipError_t launch_count_noncanonical(const uint32_t *p, size_t np, uint32_t N, const LimbConsts &k,
+                                     unsigned long long *count, hipStream_t st);
 hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *c, size_t npolys, uint32_t N,
                                 const LimbConsts &k, hipStream_t st);
 

@@ -152,6 +152,21 @@ __global__ void k_pointwise_mul(const uint32_t *__restrict__ a, const uint32_t *
   }
 }
 
+// Count of words that are not canonical residues (word >= q_l of its limb) in
+// polynomials laid out [..][L][N]: one atomic add per wave.
+__global__ void k_count_noncanonical(const uint32_t *__restrict__ p, size_t total, uint32_t N, LimbConsts c,
+                                     unsigned long long *count) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  uint32_t bad = 0;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+    const uint32_t l = (uint32_t)((id / N) % c.L);
+    bad += p[id] >= c.q[l] ? 1u : 0u;
+  }
+  // wave sum, then one vector atomic from lane 0
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off);
+  if ((threadIdx.x & 63u) == 0 && bad) atomicAdd(count, (unsigned long long)bad);
+}
+
 // ---------------------------------------------------------------- launchers
 template <int LOGN, int ELOG>
 static hipError_t fwd_t(const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c, const Twiddles &tw,
@@ -253,6 +268,15 @@ hipError_t launch_mask_extract(const ConvGeom &g, const uint32_t *ct, const uint
   size_t blocks = (n_ct * ln4 + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_copy_c1, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint4 *)ct, (uint4 *)c1, n_ct, ln4);
+  return hipGetLastError();
+}
+hipError_t launch_count_noncanonical(const uint32_t *p, size_t np, uint32_t N, const LimbConsts &k,
+                                     unsigned long long *count, hipStream_t st) {
+  const size_t total = np * N;
+  if (total == 0) return hipSuccess;
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_count_noncanonical, dim3((uint32_t)blocks), dim3(256), 0, st, p, total, N, k, count);
   return hipGetLastError();
 }
 hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *cc, size_t np, uint32_t N,

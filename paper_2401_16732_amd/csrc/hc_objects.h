@@ -18,6 +18,7 @@ struct hc_ctx {
   uint2 *d_tw = nullptr;  // [2][L][N]: forward then inverse
   hc::Twiddles tw{};
   hc_tuning tune{};        // 0 fields = defaults
+  bool check_inputs = false;  // HC_CHECK_INPUTS=1 at creation: conv entry points validate their inputs
 };
 
 struct hc_layer {

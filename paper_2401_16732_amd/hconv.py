@@ -29,6 +29,7 @@ SYMBOLS = [
     "hc_server_create", "hc_server_add_net", "hc_server_request_bytes", "hc_server_submit", "hc_server_step",
     "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
     "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
+    "hc_check_residues",
 ]
 
 
@@ -90,6 +91,7 @@ def load(path: str = LIB_PATH):
         "hc_batch_run_eager": (I, [P, P, P, P, P, P]),
         "hc_batch_destroy": (None, [P]),
         "hc_poly_mul": (I, [P, P, P, P, u32, P, sz, P]),
+        "hc_check_residues": (I, [P, P, sz, P, P]),
         "hc_sync": (I, [P]),
         "hc_status_string": (ctypes.c_char_p, [I]),
         "hc_last_error": (ctypes.c_char_p, []),
@@ -197,6 +199,17 @@ class Context:
         _check(_lib.hc_poly_mul(self.h, _dptr(a, "a", self.device), _dptr(b, "b", self.device),
                                 _dptr(out, "out", self.device), count, _dptr(ws, "ws", self.device),
                                 ws.numel() * 4, _stream(stream)), "hc_poly_mul")
+
+    def check_residues(self, polys, stream=None) -> int:
+        """Number of words of `polys` (device int32 tensor, [..][L][N]) that are
+        not below the prime of their limb."""
+        npolys = polys.numel() // self.N
+        if npolys * self.N != polys.numel() or npolys % self.L:
+            raise ValueError("polys must hold a whole number of [L][N] blocks")
+        n = ctypes.c_uint64()
+        _check(_lib.hc_check_residues(self.h, _dptr(polys, "polys", self.device), npolys, _stream(stream),
+                                      ctypes.byref(n)), "hc_check_residues")
+        return n.value
 
     def sync(self):
         _check(_lib.hc_sync(self.h), "hc_sync")
