@@ -318,6 +318,7 @@ template <int LOGN, int ELOG, int PRE>
 struct MemTws {
   const uint2 *tw;
   uint32_t tid;
+  __device__ __forceinline__ const uint2 *table() const { return tw; }
   template <int K>
   __device__ __forceinline__ MemTw<LOGN, ELOG, inv_lo(LOGN, ELOG, PRE, K), inv_ep(LOGN, ELOG, PRE, K)> pass() const {
     return {tw, tid};
@@ -346,6 +347,7 @@ struct EarlyTws {
     if constexpr (kReg0) t0.load(tw, tid);
     if constexpr (kReg1) t1.load(tw, tid);
   }
+  __device__ __forceinline__ const uint2 *table() const { return tw; }
   template <int K>
   __device__ __forceinline__ auto pass() const {
     if constexpr (K == 0 && kReg0) {
@@ -370,9 +372,20 @@ struct InvPasses {
 #pragma unroll
     for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, PLO, PEP>(v[m], lds + m * lds_words(LOGN), tid);
     __syncthreads();
+    if constexpr (LO >= 6) {
+      // wave-uniform twiddles: their scalar loads go out ahead of the pass's
+      // LDS reads, so that the two latencies overlap rather than add up
+      RegTw<LOGN, ELOG, LO, EP> t;
+      t.load(tws.table(), tid);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
-    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tws.template pass<K>(), q, a, ap, b, bp);
+      for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
+      inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, t, q, a, ap, b, bp);
+    } else {
+#pragma unroll
+      for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
+      inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tws.template pass<K>(), q, a, ap, b, bp);
+    }
   }
 };
 template <int LOGN, int ELOG, int PS, int M, int PRE>
