@@ -112,40 +112,7 @@ struct StageTw {
   }
 };
 
-// Forward (Cooley-Tukey, natural -> bit-reversed) stages of one pass.
-// Stage s works on pairs (j, j + 2^(LOGN-1-s)) with twiddle psi^brv(2^s + j >> (LOGN - s)).
-template <int LOGN, int ELOG, int LO, int EP>
-__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], uint32_t tid, const uint2 *__restrict__ tw,
-                                         uint32_t q) {
-  constexpr int E = 1 << ELOG;
-  const uint32_t q2 = 2 * q;
-#pragma unroll
-  for (int bb = EP - 1; bb >= 0; --bb) {
-    const int b = LO + bb;
-    const int s = LOGN - 1 - b;
-    // twiddle index 2^s + (j >> (b + 1)), split into thread and register parts
-    const StageTw<LOGN, ELOG, LO, EP> tws(tw, tid, b);
-    (void)s;
-    // butterflies side by side, one operation at a time (as in inv_pass);
-    // pair k is (u, u + 2^bb), u = k with a zero inserted at bit bb
-    uint32_t hi[E / 2];
-#pragma unroll
-    for (int k = 0; k < E / 2; ++k) {
-      const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
-      hi[k] = __umulhi(v[u2], tws(u, b).y);
-    }
-#pragma unroll
-    for (int k = 0; k < E / 2; ++k) {
-      const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
-      const uint32_t X = csub(v[u], q2);
-      const uint32_t T = v[u2] * tws(u, b).x - hi[k] * q;  // Shoup: in [0, 2q)
-      v[u] = X + T;
-      v[u2] = X - T + q2;
-    }
-  }
-}
-
-// Twiddle sources of an inverse pass over bits [LO, LO + EP): MemTw reads
+// Twiddle sources of a pass over bits [LO, LO + EP): MemTw reads
 // each twiddle from the table where it is used; RegTw holds the whole pass's
 // twiddles in registers, loaded ahead of time (EarlyTws below).
 template <int LOGN, int ELOG, int LO, int EP>
@@ -176,6 +143,35 @@ struct RegTw {
   }
   __device__ __forceinline__ uint2 operator()(int bb, int u) const { return make_uint2(w[bb][u], wp[bb][u]); }
 };
+
+// Forward (Cooley-Tukey, natural -> bit-reversed) stages of one pass.
+// Stage s works on pairs (j, j + 2^(LOGN-1-s)) with twiddle psi^brv(2^s + j >> (LOGN - s)).
+// tws(bb, u): twiddle {w, w'} of stage bit LO + bb for register slot u
+// (index 2^s + (j >> (b + 1)), s = LOGN - 1 - b).
+template <int LOGN, int ELOG, int LO, int EP, class TW>
+__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], const TW &tws, uint32_t q) {
+  constexpr int E = 1 << ELOG;
+  const uint32_t q2 = 2 * q;
+#pragma unroll
+  for (int bb = EP - 1; bb >= 0; --bb) {
+    // butterflies side by side, one operation at a time (as in inv_pass);
+    // pair k is (u, u + 2^bb), u = k with a zero inserted at bit bb
+    uint32_t hi[E / 2];
+#pragma unroll
+    for (int k = 0; k < E / 2; ++k) {
+      const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+      hi[k] = __umulhi(v[u2], tws(bb, u).y);
+    }
+#pragma unroll
+    for (int k = 0; k < E / 2; ++k) {
+      const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+      const uint32_t X = csub(v[u], q2);
+      const uint32_t T = v[u2] * tws(bb, u).x - hi[k] * q;  // Shoup: in [0, 2q)
+      v[u] = X + T;
+      v[u2] = X - T + q2;
+    }
+  }
+}
 
 // Inverse (Gentleman-Sande, bit-reversed -> natural) stages of one pass; the
 // last stage (s = 0) also multiplies by N^-1.
@@ -288,8 +284,17 @@ struct FwdPasses {
     FwdPasses<LOGN, ELOG, K - 1>::run(v, lds, tid, tw, q);
     regs_to_lds<LOGN, ELOG, PLO, PEP>(v, lds, tid);
     __syncthreads();
-    lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
-    fwd_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q);
+    if constexpr (LO >= 6) {
+      // wave-uniform twiddles: scalar loads ahead of the LDS reads (as in InvPasses)
+      RegTw<LOGN, ELOG, LO, EP> t;
+      t.load(tw, tid);
+      __builtin_amdgcn_sched_barrier(0);
+      lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
+      fwd_pass<LOGN, ELOG, LO, EP>(v, t, q);
+    } else {
+      lds_to_regs<LOGN, ELOG, LO, EP>(v, lds, tid);
+      fwd_pass<LOGN, ELOG, LO, EP>(v, MemTw<LOGN, ELOG, LO, EP>{tw, tid}, q);
+    }
   }
 };
 template <int LOGN, int ELOG>
@@ -298,7 +303,7 @@ struct FwdPasses<LOGN, ELOG, 0> {
   static __device__ __forceinline__ void run(uint32_t (&v)[1 << ELOG], uint32_t *, uint32_t tid, const uint2 *tw,
                                              uint32_t q) {
     constexpr int LO = pass_lo_fwd(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
-    fwd_pass<LOGN, ELOG, LO, EP>(v, tid, tw, q);
+    fwd_pass<LOGN, ELOG, LO, EP>(v, MemTw<LOGN, ELOG, LO, EP>{tw, tid}, q);
   }
 };
 
