@@ -123,7 +123,8 @@ typedef struct {
 } hc_tuning;
 
 /* Create a context on HIP device `hip_device`: ring degree N (power of two,
- * 1024..16384), L RNS primes (1..4), plaintext modulus t (2..2^30).
+ * 1024..16384), L RNS primes (1..4), plaintext modulus t (2..2^30, below
+ * 2 q_l for every prime, so centred plaintext values are residues).
  * primes: L distinct primes < 2^30 with q = 1 mod 2N, or NULL to choose the
  * L largest such primes, in descending order. Builds the NTT twiddle tables
  * on the device. The caller destroys it with hc_ctx_destroy. */
@@ -295,6 +296,48 @@ hc_status hc_poly_mul(const hc_ctx *ctx, const uint32_t *a, const uint32_t *b, u
  * calls). */
 hc_status hc_check_residues(const hc_ctx *ctx, const uint32_t *polys, size_t npolys, void *stream,
                             uint64_t *n_bad);
+
+/* ------------------------------------------------------------ client side
+ * The steps on either side of the convolution, for a client that runs on the
+ * GPU (or for checking the server's outputs at full size). Plaintext values
+ * are in [0, t) and are lifted to (-t/2, t/2] before Delta scales them
+ * (plaintext coefficients of R_p, Background: Homomorphic Encryption).
+ *
+ * Direct encoding (eq. de) plus online encryption (Algorithm 2, section
+ * "Moving Data-independent Operations to Offline Phase"): for each image b and
+ * input ciphertext g of the layer, ct_in[b][g] = [[0]]_(b,g) + Delta * m_(b,g),
+ * where m_(b,g) is the plaintext polynomial that the layout (header comment)
+ * gives ciphertext g from act[b] (zero padding, channel packing, row tiles,
+ * client-side subsampling); only c0 changes.
+ *   act      [B][c_in][h][w] values in [0, t) (device; other values give a
+ *            well-formed but meaningless ciphertext)
+ *   ct_zero  [B][G][2][L][N] canonical encryptions of zero, one per ciphertext,
+ *            made offline (c0 = -(a s + e), c1 = a; Table 2's private-key form)
+ *   ct_in    [B][G][2][L][N] output, the conv's input; may be ct_zero itself
+ *            (then only c0 is written), must not otherwise overlap it or act.
+ * Enqueued on `stream`; no allocation. */
+hc_status hc_encrypt_online(const hc_layer *layer, const uint32_t *act, const uint32_t *ct_zero, uint32_t *ct_in,
+                            uint32_t B, void *stream);
+
+/* BFV decryption (eq. bfv_dec): m = round(t [c1 s + c0]_q / q) mod t, rounded
+ * half up and exact for every phase (the RNS rounding carries 160 fraction bits;
+ * q < 2^120). The secret key sk is given as its residues [L][N] (s mod q_l,
+ * canonical, device); c1 s is the negacyclic product through the forward NTT,
+ * a pointwise product and the inverse NTT.
+ *
+ * hc_decrypt_extracted decrypts the masked conv's outputs (hc_conv_masked):
+ * output pixel (i, oy, ox) has phase c0_ext[b][i][:][oy][ox] + (c1_out[b][(i,tau)] s)[e]
+ * at its coefficient e (header comment); m [B][c_out][ho][wo] receives values in
+ * [0, t), i.e. conv(a) + r mod t for a fresh encryption of a under mask r.
+ * ws: hc_decrypt_workspace_size bytes, (B out_cts + 1) L N words. */
+hc_status hc_decrypt_workspace_size(const hc_layer *layer, uint32_t B, size_t *bytes);
+hc_status hc_decrypt_extracted(const hc_layer *layer, const uint32_t *c0_ext, const uint32_t *c1_out,
+                               const uint32_t *sk, uint32_t *m, uint32_t B, void *ws, size_t ws_bytes,
+                               void *stream);
+/* Decrypts `count` whole ciphertexts ct [count][2][L][N] into m [count][N]
+ * (every coefficient, values in [0, t)). ws: at least (count + 1) L N words. */
+hc_status hc_decrypt(const hc_ctx *ctx, const uint32_t *ct, const uint32_t *sk, uint32_t *m, uint32_t count,
+                     void *ws, size_t ws_bytes, void *stream);
 
 /* Wait for all work on the context's device; reports earlier asynchronous faults. */
 hc_status hc_sync(hc_ctx *ctx);

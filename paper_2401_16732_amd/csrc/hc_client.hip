@@ -1,0 +1,200 @@
+// gfx950 kernels of the client-side steps around the convolution: direct
+// encoding with online encryption (Algorithm 2) of a layer's input, and BFV
+// decryption (eq. bfv_dec) of its extracted outputs or of whole ciphertexts.
+// All of them are elementwise and bound by HBM traffic: one thread per output
+// word, dword accesses that are consecutive across a wave's lanes. The ring
+// product c1 * s of decryption runs through the forward NTT, a pointwise
+// product and the full inverse NTT of hc_ntt.hip.
+#include "hc_device.h"
+
+namespace hc {
+
+// ---------------------------------------------------------------- encryption
+// Plaintext value at coefficient k of input ciphertext gi of image b under
+// the direct-encoding layout: zero padding, c_n channels per ciphertext at
+// offsets (j mod c_n) F, or row tiles with f - 1 halo rows when F > N; with
+// client subsampling the encoded pixel (y, x) is act[j][sub y][sub x].
+__device__ __forceinline__ uint32_t encoded_value(const uint32_t *__restrict__ act, const ConvGeom &g,
+                                                  const EncGeom &e, size_t b, uint32_t gi, uint32_t k) {
+  uint32_t j, y, x;
+  if (!g.tiled) {
+    const uint32_t slot = k / g.F;
+    j = gi * g.cn + slot;
+    if (slot >= g.cn || j >= g.c_in) return 0;
+    const uint32_t pos = k - slot * g.F;
+    y = pos / g.w_pad;
+    x = pos - y * g.w_pad;
+  } else {
+    j = gi / g.T;
+    const uint32_t tau = gi - j * g.T;
+    const uint32_t yl = k / g.w_pad;
+    if (yl >= e.rows_per_ct) return 0;
+    x = k - yl * g.w_pad;
+    y = tau * g.r_o + yl;
+    if (y >= e.h_pad) return 0;
+  }
+  if (y < e.pad || x < e.pad) return 0;
+  const uint32_t ya = y - e.pad, xa = x - e.pad;
+  if (ya >= e.h_enc || xa >= e.w_enc) return 0;
+  return act[((b * g.c_in + j) * e.h + (size_t)ya * e.sub) * e.w + (size_t)xa * e.sub];
+}
+
+// One thread per coefficient k of input ciphertext (b, gi): c0_l += Delta_l
+// (m mod q_l) for the centred plaintext m in (-t/2, t/2], every limb.
+__global__ void k_encrypt_online(const uint32_t *__restrict__ act, const uint32_t *__restrict__ ct0,
+                                 uint32_t *__restrict__ ct, ConvGeom g, EncGeom e, uint32_t B, uint32_t copy_c1,
+                                 LimbConsts c) {
+  const size_t total = (size_t)B * g.G * g.N;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const uint32_t half = c.t / 2;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+    const uint32_t k = (uint32_t)(id % g.N);
+    const size_t ctn = id / g.N;  // b * G + gi
+    const uint32_t gi = (uint32_t)(ctn % g.G);
+    const uint32_t m = encoded_value(act, g, e, ctn / g.G, gi, k);
+    for (uint32_t l = 0; l < g.L; ++l) {
+      const uint32_t q = c.q[l];
+      // m <= t/2: m itself; else m - t + q (t < 2 q_l keeps both in [0, q_l))
+      const uint32_t mc = m > half ? m - c.t + q : m;
+      const uint32_t add = csub(shoup_lazy(mc, c.delta[l], c.delta_p[l], q), q);
+      const size_t w0 = ((ctn * 2 + 0) * g.L + l) * (size_t)g.N + k;
+      const size_t w1 = w0 + (size_t)g.L * g.N;
+      ct[w0] = csub(ct0[w0] + add, q);
+      if (copy_c1) ct[w1] = ct0[w1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- decryption
+// a[p][k] = a[p][k] * s[p mod L][k] mod q (both NTT-domain, canonical).
+__global__ void k_mul_bcast(uint32_t *__restrict__ a, const uint32_t *__restrict__ s, size_t total, uint32_t N,
+                            LimbConsts c) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t ln = (size_t)c.L * N;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+    const uint32_t l = (uint32_t)((id / N) % c.L);
+    a[id] = reduce64((uint64_t)a[id] * s[id % ln], c.q[l], c.r2[l], c.r2_p[l], c.one_p[l]);
+  }
+}
+
+__global__ void k_gather_c1(const uint32_t *__restrict__ ct, uint32_t *__restrict__ c1, size_t n_ct, size_t ln) {
+  const size_t total = n_ct * ln;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride)
+    c1[id] = ct[(2 * (id / ln) + 1) * ln + id % ln];
+}
+
+// round(t v / q) mod t for the phase with residues v[0..L) (canonical).
+__device__ __forceinline__ uint32_t decode_phase(const uint32_t (&v)[kMaxLimbs], const LimbConsts &c,
+                                                 const DecodeConsts &d) {
+  uint64_t whole = 0;                       // sum_l x_l a_l
+  uint32_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;  // sum_l x_l phi_l: 160 fraction bits in f0..f4,
+  uint32_t f4 = 0, top = 0;                 // the integer part (< 2^32) in top
+#pragma unroll
+  for (uint32_t l = 0; l < (uint32_t)kMaxLimbs; ++l) {
+    if (l < c.L) {
+      const uint32_t q = c.q[l];
+      const uint32_t x = csub(shoup_lazy(v[l], d.qt[l], d.qt_p[l], q), q);
+      whole += (uint64_t)x * d.a[l];
+      uint64_t p = (uint64_t)x * d.phi[l][0] + f0;
+      f0 = (uint32_t)p;
+      p = (uint64_t)x * d.phi[l][1] + f1 + (p >> 32);
+      f1 = (uint32_t)p;
+      p = (uint64_t)x * d.phi[l][2] + f2 + (p >> 32);
+      f2 = (uint32_t)p;
+      p = (uint64_t)x * d.phi[l][3] + f3 + (p >> 32);
+      f3 = (uint32_t)p;
+      p = (uint64_t)x * d.phi[l][4] + f4 + (p >> 32);
+      f4 = (uint32_t)p;
+      top += (uint32_t)(p >> 32);
+    }
+  }
+  top += (uint32_t)(((uint64_t)f4 + 0x80000000u) >> 32);  // + 1/2, then floor
+  return (uint32_t)((whole + top) % c.t);
+}
+
+__global__ void k_decrypt_extracted(const uint32_t *__restrict__ c0_ext, const uint32_t *__restrict__ c1s,
+                                    uint32_t *__restrict__ m, ConvGeom g, uint32_t B, LimbConsts c,
+                                    DecodeConsts d) {
+  const size_t hw = (size_t)g.ho * g.wo;
+  const size_t total = (size_t)B * g.c_out * hw;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+    const uint32_t ox = (uint32_t)(id % g.wo);
+    const uint32_t oy = (uint32_t)((id / g.wo) % g.ho);
+    const size_t bi = id / hw;  // b * c_out + i
+    const uint32_t i = (uint32_t)(bi % g.c_out);
+    const size_t b = bi / g.c_out;
+    const uint32_t Y = g.s * oy;
+    const uint32_t tau = Y / g.r_o;
+    const uint32_t e = (Y - tau * g.r_o) * g.w_pad + g.s * ox;
+    const size_t o = b * g.O + (size_t)i * g.T + tau;
+    uint32_t v[kMaxLimbs] = {};
+#pragma unroll
+    for (uint32_t l = 0; l < (uint32_t)kMaxLimbs; ++l)
+      if (l < c.L)
+        v[l] = csub(c0_ext[(bi * g.L + l) * hw + (size_t)oy * g.wo + ox] + c1s[(o * g.L + l) * g.N + e], c.q[l]);
+    m[id] = decode_phase(v, c, d);
+  }
+}
+
+__global__ void k_decrypt_full(const uint32_t *__restrict__ ct, const uint32_t *__restrict__ c1s,
+                               uint32_t *__restrict__ m, size_t n_ct, uint32_t N, LimbConsts c, DecodeConsts d) {
+  const size_t total = n_ct * N;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+    const size_t cn = id / N;
+    const uint32_t k = (uint32_t)(id % N);
+    uint32_t v[kMaxLimbs] = {};
+#pragma unroll
+    for (uint32_t l = 0; l < (uint32_t)kMaxLimbs; ++l)
+      if (l < c.L)
+        v[l] = csub(ct[((cn * 2) * c.L + l) * N + k] + c1s[(cn * c.L + l) * N + k], c.q[l]);
+    m[id] = decode_phase(v, c, d);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+namespace {
+uint32_t grid_for(size_t total) {
+  size_t blocks = (total + 255) / 256;
+  return (uint32_t)(blocks > 65536 ? 65536 : blocks);
+}
+}  // namespace
+
+hipError_t launch_encrypt_online(const ConvGeom &g, const EncGeom &e, const uint32_t *act, const uint32_t *ct0,
+                                 uint32_t *ct, uint32_t B, bool copy_c1, const LimbConsts &c, hipStream_t st) {
+  const size_t total = (size_t)B * g.G * g.N;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_encrypt_online, dim3(grid_for(total)), dim3(256), 0, st, act, ct0, ct, g, e, B,
+                     copy_c1 ? 1u : 0u, c);
+  return hipGetLastError();
+}
+hipError_t launch_mul_bcast(uint32_t *a, const uint32_t *s, size_t np, uint32_t N, const LimbConsts &k,
+                            hipStream_t st) {
+  const size_t total = np * N;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mul_bcast, dim3(grid_for(total)), dim3(256), 0, st, a, s, total, N, k);
+  return hipGetLastError();
+}
+hipError_t launch_gather_c1(const uint32_t *ct, uint32_t *c1, size_t n_ct, uint32_t L, uint32_t N, hipStream_t st) {
+  const size_t ln = (size_t)L * N;
+  if (n_ct * ln == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_c1, dim3(grid_for(n_ct * ln)), dim3(256), 0, st, ct, c1, n_ct, ln);
+  return hipGetLastError();
+}
+hipError_t launch_decrypt_extracted(const ConvGeom &g, const uint32_t *c0_ext, const uint32_t *c1s, uint32_t *m,
+                                    uint32_t B, const LimbConsts &c, const DecodeConsts &d, hipStream_t st) {
+  const size_t total = (size_t)B * g.c_out * g.ho * g.wo;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_decrypt_extracted, dim3(grid_for(total)), dim3(256), 0, st, c0_ext, c1s, m, g, B, c, d);
+  return hipGetLastError();
+}
+hipError_t launch_decrypt_full(const uint32_t *ct, const uint32_t *c1s, uint32_t *m, size_t n_ct, uint32_t N,
+                               const LimbConsts &c, const DecodeConsts &d, hipStream_t st) {
+  if (n_ct * N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_decrypt_full, dim3(grid_for(n_ct * N)), dim3(256), 0, st, ct, c1s, m, n_ct, N, c, d);
+  return hipGetLastError();
+}
+
+}  // namespace hc

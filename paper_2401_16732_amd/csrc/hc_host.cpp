@@ -3,7 +3,8 @@
 // Parameters (RNS primes, roots of unity, twiddle and Shoup tables, Delta),
 // the direct-encoding layout planner, resident weight encoding, the per-layer
 // launch sequences and the graph-recorded batch. Kernels live in hc_ntt.hip,
-// hc_mac.hip and hc_intt_masked_*.hip.
+// hc_mac.hip and hc_intt_masked_*.hip; the client-side entry points in
+// hc_client.cpp, the serving loop in hc_server.cpp.
 #include "../../include/hc.h"
 
 #include <hip/hip_runtime.h>
@@ -385,6 +386,13 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
     delete c;
     return fail(HC_EUNSUPPORTED, "not enough primes");
   }
+  // centred plaintext values |m| <= t/2 must be residues of every limb
+  for (uint32_t l = 0; l < L; ++l)
+    if (t >= 2ull * c->q[l]) {
+      delete c;
+      return fail(HC_EUNSUPPORTED, "t must be below 2 q_l for every prime");
+    }
+  c->dec = hc::make_decode_consts(c->q, L, t);
   // Delta = floor(q / t), q = prod q_l < 2^120 (Notation table)
   u128 Q = 1;
   for (uint32_t l = 0; l < L; ++l) Q *= c->q[l];

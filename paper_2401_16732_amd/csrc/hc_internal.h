@@ -1,5 +1,6 @@
-// Internal declarations shared by the host library (hc_host.cpp) and the
-// gfx950 kernels (hc_ntt.hip, hc_mac.hip, hc_intt_masked_*.hip). Not part of the ABI.
+// Internal declarations shared by the host library (hc_host.cpp, hc_server.cpp,
+// hc_client.cpp) and the gfx950 kernels (hc_ntt.hip, hc_mac.hip,
+// hc_intt_masked_*.hip, hc_client.hip). Not part of the ABI.
 #pragma once
 #include <cstddef>
 #include <cstdint>
@@ -105,5 +106,45 @@ hipError_t launch_count_noncanonical(const uint32_t *p, size_t np, uint32_t N, c
                                      unsigned long long *count, hipStream_t st);
 hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *c, size_t npolys, uint32_t N,
                                 const LimbConsts &k, hipStream_t st);
+
+// ---------------------------------------------------------------- client side (hc_client.hip)
+// Exact BFV decoding m = round(t v / q) mod t of a phase v in [0, q) given by
+// its residues v_l. With x_l = v_l (q / q_l)^-1 mod q_l, v = sum_l x_l q / q_l
+// minus a multiple of q, so t v / q equals sum_l x_l t / q_l up to a multiple
+// of t; t / q_l = a_l + tau_l / q_l with a_l an integer and tau_l = t mod q_l.
+// The fractions x_l tau_l / q_l are summed in 160-bit fixed point (phi_l =
+// floor(tau_l 2^160 / q_l)): the sum is low by less than 2^-128, while the
+// exact sum plus 1/2 is at least 1 / (2q) > 2^-121 away from an integer
+// (2q does not divide an odd numerator), so the rounding is exact.
+struct DecodeConsts {
+  uint32_t qt[kMaxLimbs], qt_p[kMaxLimbs];  // (q / q_l)^-1 mod q_l and its Shoup constant
+  uint32_t a[kMaxLimbs];                    // floor(t / q_l) mod t
+  uint32_t phi[kMaxLimbs][5];               // floor(tau_l 2^160 / q_l), least significant word first
+};
+// Input geometry of a layer's direct encoding beyond ConvGeom.
+struct EncGeom {
+  uint32_t h, w;          // activation size as given
+  uint32_t sub;           // client-side subsampling factor (1 if none)
+  uint32_t pad;           // (f - 1) / 2
+  uint32_t h_enc, w_enc;  // encoded (subsampled) size
+  uint32_t h_pad;         // h_enc + 2 pad
+  uint32_t rows_per_ct;   // padded rows one input ciphertext holds (h_pad, or R_o + f - 1 when tiled)
+};
+// ct[b][g] = ct_zero[b][g] + Delta * m_(b,g): c0 gains Delta times the
+// direct-encoded, centred activations act [B][c_in][h][w]; c1 is copied
+// unless copy_c1 is false (ct == ct_zero).
+hipError_t launch_encrypt_online(const ConvGeom &g, const EncGeom &e, const uint32_t *act, const uint32_t *ct_zero,
+                                 uint32_t *ct, uint32_t B, bool copy_c1, const LimbConsts &c, hipStream_t st);
+// a[p][:] *= s[p mod L][:] mod q_(p mod L) over a [P][N] (s: [L][N]).
+hipError_t launch_mul_bcast(uint32_t *a, const uint32_t *s, size_t npolys, uint32_t N, const LimbConsts &k,
+                            hipStream_t st);
+// c1[c][l][:] = ct[c][1][l][:] for n_ct ciphertexts [n_ct][2][L][N].
+hipError_t launch_gather_c1(const uint32_t *ct, uint32_t *c1, size_t n_ct, uint32_t L, uint32_t N, hipStream_t st);
+// m[b][i][oy][ox] = decode(c0_ext[b][i][:][oy][ox] + c1s[b][(i, tau)][:][e]).
+hipError_t launch_decrypt_extracted(const ConvGeom &g, const uint32_t *c0_ext, const uint32_t *c1s, uint32_t *m,
+                                    uint32_t B, const LimbConsts &c, const DecodeConsts &d, hipStream_t st);
+// m[c][k] = decode(ct[c][0][:][k] + c1s[c][:][k]).
+hipError_t launch_decrypt_full(const uint32_t *ct, const uint32_t *c1s, uint32_t *m, size_t n_ct, uint32_t N,
+                               const LimbConsts &c, const DecodeConsts &d, hipStream_t st);
 
 }  // namespace hc

@@ -1,4 +1,4 @@
-// Library-private definitions shared by hc_host.cpp and hc_server.cpp.
+// Library-private definitions shared by hc_host.cpp, hc_server.cpp and hc_client.cpp.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -19,6 +19,7 @@ struct hc_ctx {
   hc::Twiddles tw{};
   hc_tuning tune{};        // 0 fields = defaults
   bool check_inputs = false;  // HC_CHECK_INPUTS=1 at creation: conv entry points validate their inputs
+  hc::DecodeConsts dec{};     // exact decryption rounding (client side)
 };
 
 struct hc_layer {
@@ -51,6 +52,9 @@ inline MacShape mac_of(const hc_tuning &t) {
 }
 // The layer's autotuned shapes when tuned for B images, else the context's.
 Shapes layer_shapes(const hc_layer *ly, uint32_t B);
+
+// Constants of the exact decryption rounding for primes q[0..L) and t.
+DecodeConsts make_decode_consts(const uint32_t *q, uint32_t L, uint64_t t);
 
 // Device workspace of one layer's conv for B images (X-hat, plus Y-hat when masked).
 size_t ws_bytes_for(const hc_layer *ly, uint32_t B, bool masked);

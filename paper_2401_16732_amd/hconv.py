@@ -29,7 +29,7 @@ SYMBOLS = [
     "hc_server_create", "hc_server_add_net", "hc_server_request_bytes", "hc_server_submit", "hc_server_step",
     "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
     "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
-    "hc_check_residues",
+    "hc_check_residues", "hc_encrypt_online", "hc_decrypt_workspace_size", "hc_decrypt_extracted", "hc_decrypt",
 ]
 
 
@@ -92,6 +92,10 @@ def load(path: str = LIB_PATH):
         "hc_batch_destroy": (None, [P]),
         "hc_poly_mul": (I, [P, P, P, P, u32, P, sz, P]),
         "hc_check_residues": (I, [P, P, sz, P, P]),
+        "hc_encrypt_online": (I, [P, P, P, P, u32, P]),
+        "hc_decrypt_workspace_size": (I, [P, u32, P]),
+        "hc_decrypt_extracted": (I, [P, P, P, P, P, u32, P, sz, P]),
+        "hc_decrypt": (I, [P, P, P, P, u32, P, sz, P]),
         "hc_sync": (I, [P]),
         "hc_status_string": (ctypes.c_char_p, [I]),
         "hc_last_error": (ctypes.c_char_p, []),
@@ -211,6 +215,19 @@ class Context:
                                       ctypes.byref(n)), "hc_check_residues")
         return n.value
 
+    def decrypt(self, ct, sk, m, ws, stream=None):
+        """m [count][N] <- decryption of ct [count][2][L][N] under the key
+        residues sk [L][N] (all device int32 tensors); ws: (count + 1) L N words."""
+        ln = self.L * self.N
+        count = ct.numel() // (2 * ln)
+        if ct.numel() != count * 2 * ln or sk.numel() != ln or m.numel() < count * self.N:
+            raise ValueError("ct must hold count * 2 * L * N words, sk L * N, m count * N")
+        if ws.numel() < (count + 1) * ln:
+            raise ValueError("ws must hold (count + 1) * L * N words")
+        _check(_lib.hc_decrypt(self.h, _dptr(ct, "ct", self.device), _dptr(sk, "sk", self.device),
+                               _dptr(m, "m", self.device), count, _dptr(ws, "ws", self.device), ws.numel() * 4,
+                               _stream(stream)), "hc_decrypt")
+
     def sync(self):
         _check(_lib.hc_sync(self.h), "hc_sync")
 
@@ -297,6 +314,34 @@ class Layer:
                                    _dptr(c0_ext, "c0_ext", d), _dptr(c1_out, "c1_out", d), B, _dptr(ws, "ws", d),
                                    ws.numel() * 4, _stream(stream)), "hc_conv_masked")
 
+    def encrypt_online(self, act, ct_zero, ct_in, B: int, stream=None):
+        """ct_in <- [[0]] + Delta * (direct encoding of act [B][c_in][h][w]);
+        ct_in may be ct_zero itself (only c0 is then written)."""
+        d = self.ctx.device
+        self._need(act, self.act_shape(B), "act")
+        self._need(ct_zero, self.in_shape(B), "ct_zero")
+        self._need(ct_in, self.in_shape(B), "ct_in")
+        _check(_lib.hc_encrypt_online(self.h, _dptr(act, "act", d), _dptr(ct_zero, "ct_zero", d),
+                                      _dptr(ct_in, "ct_in", d), B, _stream(stream)), "hc_encrypt_online")
+
+    def decrypt_workspace_words(self, B: int) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.hc_decrypt_workspace_size(self.h, B, ctypes.byref(n)), "hc_decrypt_workspace_size")
+        return (n.value + 3) // 4
+
+    def decrypt_extracted(self, c0_ext, c1_out, sk, m, B: int, ws, stream=None):
+        """m [B][c_out][ho][wo] <- decryption of the masked conv's outputs under
+        the key residues sk [L][N]."""
+        d = self.ctx.device
+        self._need(c0_ext, self.c0_shape(B), "c0_ext")
+        self._need(c1_out, self.c1_shape(B), "c1_out")
+        self._need(sk, (self.ctx.L, self.ctx.N), "sk")
+        self._need(m, self.mask_shape(B), "m")
+        self._need(ws, (self.decrypt_workspace_words(B),), "ws")
+        _check(_lib.hc_decrypt_extracted(self.h, _dptr(c0_ext, "c0_ext", d), _dptr(c1_out, "c1_out", d),
+                                         _dptr(sk, "sk", d), _dptr(m, "m", d), B, _dptr(ws, "ws", d),
+                                         ws.numel() * 4, _stream(stream)), "hc_decrypt_extracted")
+
     def tuning(self):
         """(batch size, (fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups, mac_depth,
         mac_lds, inv_polys, mac_pre)) or (0, ...)."""
@@ -309,6 +354,9 @@ class Layer:
         _check(_lib.hc_layer_clear_tuning(self.h), "hc_layer_clear_tuning")
 
     # shapes of the device buffers for B images
+    def act_shape(self, B):
+        return (B, self.shape[0], self.shape[2], self.shape[3])
+
     def in_shape(self, B):
         return (B, self.layout.in_cts, 2, self.ctx.L, self.ctx.N)
 
