@@ -16,6 +16,10 @@ masks) are resident in HBM before the timed region. Reported:
                        per second, batched
   roofline             the dominant kernel against the VALU / HBM ceiling
   cpu_baseline         the CPU oracle (Algorithm 1 in C, OpenMP) on a sample
+  client               the client-side steps around the step, timed apart:
+                       online encryption (Algorithm 2) of every layer's input
+                       against HBM bandwidth, and decryption of every layer's
+                       extracted outputs (its NTTs against the butterfly peak)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -51,6 +55,7 @@ def parse():
     ap.add_argument("--cpu-fraction", type=float, default=1.0 / 16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-client", action="store_true", help="skip the client-side (encrypt/decrypt) timing")
     ap.add_argument("--seed", type=int, default=50)
     ap.add_argument("--stage-passes", type=int, default=3, help="eager passes timed per kernel for the roofline")
     ap.add_argument("--copy-gib", type=float, default=4.0, help="size of the HBM stream-copy calibration")
@@ -128,6 +133,60 @@ def layer_counts(ly, B, N, L):
         "bytes_path": (B * (lay.in_cts * 2 * L * N + lay.out_cts * L * N + c_out * L * lay.ho * lay.wo
                             + c_out * lay.ho * lay.wo)) * 4,
         "bytes_w": c_out * lay.w_cts * L * N * 4,
+    }
+
+
+def client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, passes=3):
+    """Times the client-side entry points over every layer for B images:
+    online encryption of the layer inputs (in place on ct_in, which stays a
+    set of canonical ciphertexts) and decryption of the extracted outputs."""
+    N, L = ctx.N, ctx.L
+    acts = [torch.randint(0, t, ly.act_shape(B), generator=tg, device=dev, dtype=torch.int32) for ly in layers]
+    s = torch.randint(-1, 2, (N,), generator=tg, device=dev, dtype=torch.int64)
+    sk = torch.stack([torch.remainder(s, q) for q in ctx.primes]).to(torch.int32).contiguous()
+    ws = torch.empty((max(ly.decrypt_workspace_words(B) for ly in layers),), dtype=torch.int32, device=dev)
+    m = torch.empty((max(math.prod(ly.mask_shape(B)) for ly in layers),), dtype=torch.int32, device=dev)
+
+    def enc():
+        for k, ly in enumerate(layers):
+            ly.encrypt_online(acts[k], ct_in[k], ct_in[k], B)
+
+    def dec():
+        for k, ly in enumerate(layers):
+            ly.decrypt_extracted(c0[k], c1[k], sk, m, B, ws)
+
+    # each pass is recorded once as a graph and replayed, so that the host's
+    # per-call cost (tens of microseconds, more than a small layer's kernel)
+    # does not enter the device time
+    res = {}
+    for name, fn in (("encrypt_online", enc), ("decrypt_extracted", dec)):
+        fn()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            fn()
+        graph.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(passes):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / passes
+        del graph
+    # encryption: read and write c0 of every input ciphertext, read the activations
+    enc_bytes = sum(B * ly.layout.in_cts * L * N * 8 + math.prod(ly.act_shape(B)) * 4 for ly in layers)
+    # decryption: forward and inverse NTT of every output ciphertext's c1
+    dec_bfly = sum(2 * B * ly.layout.out_cts * L * (N // 2) * int(math.log2(N)) for ly in layers)
+    enc_s, dec_s = res["encrypt_online"] * 1e-3, res["decrypt_extracted"] * 1e-3
+    return {
+        "encrypt_online": {"ms_per_image": round(res["encrypt_online"] / B, 4), "launches": len(layers),
+                           "algorithmic_bytes": enc_bytes, "achieved_GBps": round(enc_bytes / enc_s / 1e9, 1),
+                           "hbm_frac": round(enc_bytes / enc_s / HBM_PEAK, 4)},
+        "decrypt_extracted": {"ms_per_image": round(res["decrypt_extracted"] / B, 4), "launches": 4 * len(layers),
+                              "butterflies": dec_bfly, "tbutterfly_per_s": round(dec_bfly / dec_s / 1e12, 4),
+                              "alu_frac": round(dec_bfly / dec_s / BFLY_PEAK, 4)},
     }
 
 
@@ -262,6 +321,13 @@ def main():
         plain_ms = p0.elapsed_time(p1) / a.plain_images
         print(f"[bench] plain: {plain_ms:.3f} ms/image", file=sys.stderr, flush=True)
 
+    client = None
+    if not a.no_client:
+        client = client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg)
+        print(f"[bench] client: encrypt {client['encrypt_online']['ms_per_image']:.3f} ms/image "
+              f"({client['encrypt_online']['achieved_GBps']} GB/s), decrypt "
+              f"{client['decrypt_extracted']['ms_per_image']:.3f} ms/image", file=sys.stderr, flush=True)
+
     # roofline of the dominant kernel (largest stage time)
     names = [("ntt_fwd", stage[0], tot["bfly_fwd"], tot["bytes_fwd"]),
              ("mac", stage[1], tot["mac"], tot["bytes_mac"]),
@@ -327,6 +393,7 @@ def main():
         "hbm_copy": copy,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "client": client,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -329,13 +329,14 @@ hc_status hc_encrypt_online(const hc_layer *layer, const uint32_t *act, const ui
  * output pixel (i, oy, ox) has phase c0_ext[b][i][:][oy][ox] + (c1_out[b][(i,tau)] s)[e]
  * at its coefficient e (header comment); m [B][c_out][ho][wo] receives values in
  * [0, t), i.e. conv(a) + r mod t for a fresh encryption of a under mask r.
- * ws: hc_decrypt_workspace_size bytes, (B out_cts + 1) L N words. */
+ * ws: hc_decrypt_workspace_size bytes, (B out_cts + 1) L N words, 16-byte aligned. */
 hc_status hc_decrypt_workspace_size(const hc_layer *layer, uint32_t B, size_t *bytes);
 hc_status hc_decrypt_extracted(const hc_layer *layer, const uint32_t *c0_ext, const uint32_t *c1_out,
                                const uint32_t *sk, uint32_t *m, uint32_t B, void *ws, size_t ws_bytes,
                                void *stream);
 /* Decrypts `count` whole ciphertexts ct [count][2][L][N] into m [count][N]
- * (every coefficient, values in [0, t)). ws: at least (count + 1) L N words. */
+ * (every coefficient, values in [0, t)). ws: at least (count + 1) L N words, 16-byte
+ * aligned. */
 hc_status hc_decrypt(const hc_ctx *ctx, const uint32_t *ct, const uint32_t *sk, uint32_t *m, uint32_t count,
                      void *ws, size_t ws_bytes, void *stream);
 

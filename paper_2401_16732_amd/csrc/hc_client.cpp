@@ -58,13 +58,12 @@ hc::EncGeom enc_geom(const hc_layer &ly) {
 }
 
 // NTT(s) into s_hat [L][N], then c1s [P][N] <- INTT(NTT(c1) * s_hat) for c1 [P][N]
-// (c1 == c1s allowed).
+// (c1 == c1s allowed): the product is taken as the forward NTT stores.
 hc_status ring_times_secret(const hc_ctx &c, const uint32_t *sk, const uint32_t *c1, uint32_t *c1s, size_t np,
                             uint32_t *s_hat, hipStream_t st) {
   const hc::Shapes sh = hc::shapes_for(c, 1);
   CL_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, sk, s_hat, c.L, c.consts, c.tw, st));
-  CL_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, c1, c1s, np, c.consts, c.tw, st));
-  CL_HIP(hc::launch_mul_bcast(c1s, s_hat, np, c.N, c.consts, st));
+  CL_HIP(hc::launch_ntt_fwd_mul(c.logn, sh.fe, c1, c1s, np, s_hat, c.consts, c.tw, st));
   CL_HIP(hc::launch_intt_full(c.logn, sh.ie, c1s, c1s, np, c.consts, c.tw, st));
   return HC_OK;
 }
@@ -125,6 +124,7 @@ hc_status hc_decrypt_extracted(const hc_layer *ly, const uint32_t *c0_ext, const
   size_t need = 0;
   (void)hc_decrypt_workspace_size(ly, B, &need);
   if (ws_bytes < need) return fail(HC_EINVAL, "workspace too small");
+  if ((uintptr_t)ws & 15u) return fail(HC_EINVAL, "ws must be 16-byte aligned");
   const size_t np = (size_t)B * ly->lay.out_cts * c.L;
   uint32_t *c1s = (uint32_t *)ws, *s_hat = c1s + np * c.N;
   hipStream_t st = (hipStream_t)stream;
@@ -141,6 +141,7 @@ hc_status hc_decrypt(const hc_ctx *c, const uint32_t *ct, const uint32_t *sk, ui
   if (count == 0) return HC_OK;
   const size_t np = (size_t)count * c->L;
   if (ws_bytes < (np + c->L) * c->N * sizeof(uint32_t)) return fail(HC_EINVAL, "workspace too small");
+  if ((uintptr_t)ws & 15u) return fail(HC_EINVAL, "ws must be 16-byte aligned");
   uint32_t *c1s = (uint32_t *)ws, *s_hat = c1s + np * c->N;
   hipStream_t st = (hipStream_t)stream;
   hc::DeviceGuard dg(c->device);

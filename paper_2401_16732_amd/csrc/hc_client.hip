@@ -1,10 +1,11 @@
 // gfx950 kernels of the client-side steps around the convolution: direct
 // encoding with online encryption (Algorithm 2) of a layer's input, and BFV
 // decryption (eq. bfv_dec) of its extracted outputs or of whole ciphertexts.
-// All of them are elementwise and bound by HBM traffic: one thread per output
-// word, dword accesses that are consecutive across a wave's lanes. The ring
-// product c1 * s of decryption runs through the forward NTT, a pointwise
-// product and the full inverse NTT of hc_ntt.hip.
+// All of them are elementwise and bound by HBM traffic: dword accesses that
+// are consecutive across a wave's lanes, 2-D grids (ciphertext or channel x
+// chunk) so that no thread divides a 64-bit index. The ring product c1 * s of
+// decryption runs through the forward NTT with the pointwise product by NTT(s)
+// fused into its store, and the full inverse NTT, of hc_ntt.hip.
 #include "hc_device.h"
 
 namespace hc {
@@ -39,44 +40,37 @@ __device__ __forceinline__ uint32_t encoded_value(const uint32_t *__restrict__ a
   return act[((b * g.c_in + j) * e.h + (size_t)ya * e.sub) * e.w + (size_t)xa * e.sub];
 }
 
-// One thread per coefficient k of input ciphertext (b, gi): c0_l += Delta_l
-// (m mod q_l) for the centred plaintext m in (-t/2, t/2], every limb.
-__global__ void k_encrypt_online(const uint32_t *__restrict__ act, const uint32_t *__restrict__ ct0,
-                                 uint32_t *__restrict__ ct, ConvGeom g, EncGeom e, uint32_t B, uint32_t copy_c1,
-                                 LimbConsts c) {
-  const size_t total = (size_t)B * g.G * g.N;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
+// Grid: x = input ciphertext (b * G + gi), y = chunk of 1024 coefficients;
+// each thread takes 4 coefficients 256 apart, so every access instruction of a
+// wave covers 256 consecutive bytes. c0_l += Delta_l (m mod q_l) for the
+// centred plaintext m in (-t/2, t/2], every limb.
+__global__ __launch_bounds__(256) void k_encrypt_online(const uint32_t *__restrict__ act,
+                                                         const uint32_t *__restrict__ ct0,
+                                                         uint32_t *__restrict__ ct, ConvGeom g, EncGeom e,
+                                                         uint32_t copy_c1, LimbConsts c) {
+  const uint32_t ctn = blockIdx.x;
+  const uint32_t b = ctn / g.G, gi = ctn - b * g.G;
+  const uint32_t k0 = blockIdx.y * 1024 + threadIdx.x;
   const uint32_t half = c.t / 2;
-  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
-    const uint32_t k = (uint32_t)(id % g.N);
-    const size_t ctn = id / g.N;  // b * G + gi
-    const uint32_t gi = (uint32_t)(ctn % g.G);
-    const uint32_t m = encoded_value(act, g, e, ctn / g.G, gi, k);
-    for (uint32_t l = 0; l < g.L; ++l) {
-      const uint32_t q = c.q[l];
+  uint32_t m[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) m[j] = encoded_value(act, g, e, b, gi, k0 + 256 * j);
+  const size_t base = (size_t)ctn * 2 * g.L * g.N + k0;
+  for (uint32_t l = 0; l < g.L; ++l) {
+    const uint32_t q = c.q[l];
+    const size_t w0 = base + (size_t)l * g.N, w1 = w0 + (size_t)g.L * g.N;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
       // m <= t/2: m itself; else m - t + q (t < 2 q_l keeps both in [0, q_l))
-      const uint32_t mc = m > half ? m - c.t + q : m;
+      const uint32_t mc = m[j] > half ? m[j] - c.t + q : m[j];
       const uint32_t add = csub(shoup_lazy(mc, c.delta[l], c.delta_p[l], q), q);
-      const size_t w0 = ((ctn * 2 + 0) * g.L + l) * (size_t)g.N + k;
-      const size_t w1 = w0 + (size_t)g.L * g.N;
-      ct[w0] = csub(ct0[w0] + add, q);
-      if (copy_c1) ct[w1] = ct0[w1];
+      ct[w0 + 256 * j] = csub(ct0[w0 + 256 * j] + add, q);
+      if (copy_c1) ct[w1 + 256 * j] = ct0[w1 + 256 * j];
     }
   }
 }
 
 // ---------------------------------------------------------------- decryption
-// a[p][k] = a[p][k] * s[p mod L][k] mod q (both NTT-domain, canonical).
-__global__ void k_mul_bcast(uint32_t *__restrict__ a, const uint32_t *__restrict__ s, size_t total, uint32_t N,
-                            LimbConsts c) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  const size_t ln = (size_t)c.L * N;
-  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
-    const uint32_t l = (uint32_t)((id / N) % c.L);
-    a[id] = reduce64((uint64_t)a[id] * s[id % ln], c.q[l], c.r2[l], c.r2_p[l], c.one_p[l]);
-  }
-}
-
 __global__ void k_gather_c1(const uint32_t *__restrict__ ct, uint32_t *__restrict__ c1, size_t n_ct, size_t ln) {
   const size_t total = n_ct * ln;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -113,45 +107,41 @@ __device__ __forceinline__ uint32_t decode_phase(const uint32_t (&v)[kMaxLimbs],
   return (uint32_t)((whole + top) % c.t);
 }
 
-__global__ void k_decrypt_extracted(const uint32_t *__restrict__ c0_ext, const uint32_t *__restrict__ c1s,
-                                    uint32_t *__restrict__ m, ConvGeom g, uint32_t B, LimbConsts c,
-                                    DecodeConsts d) {
-  const size_t hw = (size_t)g.ho * g.wo;
-  const size_t total = (size_t)B * g.c_out * hw;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
-    const uint32_t ox = (uint32_t)(id % g.wo);
-    const uint32_t oy = (uint32_t)((id / g.wo) % g.ho);
-    const size_t bi = id / hw;  // b * c_out + i
-    const uint32_t i = (uint32_t)(bi % g.c_out);
-    const size_t b = bi / g.c_out;
-    const uint32_t Y = g.s * oy;
-    const uint32_t tau = Y / g.r_o;
-    const uint32_t e = (Y - tau * g.r_o) * g.w_pad + g.s * ox;
-    const size_t o = b * g.O + (size_t)i * g.T + tau;
-    uint32_t v[kMaxLimbs] = {};
+// Grid: x = (b, i) output channel of an image, y = chunk of 256 output pixels.
+__global__ __launch_bounds__(256) void k_decrypt_extracted(const uint32_t *__restrict__ c0_ext,
+                                                            const uint32_t *__restrict__ c1s,
+                                                            uint32_t *__restrict__ m, ConvGeom g, LimbConsts c,
+                                                            DecodeConsts d) {
+  const uint32_t hw = g.ho * g.wo;
+  const uint32_t p = blockIdx.y * 256 + threadIdx.x;
+  if (p >= hw) return;
+  const uint32_t bi = blockIdx.x;  // b * c_out + i
+  const uint32_t b = bi / g.c_out, i = bi - b * g.c_out;
+  const uint32_t oy = p / g.wo, ox = p - oy * g.wo;
+  const uint32_t Y = g.s * oy;
+  const uint32_t tau = Y / g.r_o;
+  const uint32_t e = (Y - tau * g.r_o) * g.w_pad + g.s * ox;
+  const size_t o = (size_t)b * g.O + (size_t)i * g.T + tau;
+  uint32_t v[kMaxLimbs] = {};
 #pragma unroll
-    for (uint32_t l = 0; l < (uint32_t)kMaxLimbs; ++l)
-      if (l < c.L)
-        v[l] = csub(c0_ext[(bi * g.L + l) * hw + (size_t)oy * g.wo + ox] + c1s[(o * g.L + l) * g.N + e], c.q[l]);
-    m[id] = decode_phase(v, c, d);
-  }
+  for (uint32_t l = 0; l < (uint32_t)kMaxLimbs; ++l)
+    if (l < c.L)
+      v[l] = csub(c0_ext[((size_t)bi * g.L + l) * hw + p] + c1s[(o * g.L + l) * g.N + e], c.q[l]);
+  m[(size_t)bi * hw + p] = decode_phase(v, c, d);
 }
 
-__global__ void k_decrypt_full(const uint32_t *__restrict__ ct, const uint32_t *__restrict__ c1s,
-                               uint32_t *__restrict__ m, size_t n_ct, uint32_t N, LimbConsts c, DecodeConsts d) {
-  const size_t total = n_ct * N;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
-    const size_t cn = id / N;
-    const uint32_t k = (uint32_t)(id % N);
-    uint32_t v[kMaxLimbs] = {};
+// Grid: x = ciphertext, y = chunk of 256 coefficients.
+__global__ __launch_bounds__(256) void k_decrypt_full(const uint32_t *__restrict__ ct,
+                                                       const uint32_t *__restrict__ c1s, uint32_t *__restrict__ m,
+                                                       uint32_t N, LimbConsts c, DecodeConsts d) {
+  const size_t cn = blockIdx.x;
+  const uint32_t k = blockIdx.y * 256 + threadIdx.x;
+  uint32_t v[kMaxLimbs] = {};
 #pragma unroll
-    for (uint32_t l = 0; l < (uint32_t)kMaxLimbs; ++l)
-      if (l < c.L)
-        v[l] = csub(ct[((cn * 2) * c.L + l) * N + k] + c1s[(cn * c.L + l) * N + k], c.q[l]);
-    m[id] = decode_phase(v, c, d);
-  }
+  for (uint32_t l = 0; l < (uint32_t)kMaxLimbs; ++l)
+    if (l < c.L)
+      v[l] = csub(ct[((cn * 2) * c.L + l) * N + k] + c1s[(cn * c.L + l) * N + k], c.q[l]);
+  m[cn * N + k] = decode_phase(v, c, d);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -162,19 +152,15 @@ uint32_t grid_for(size_t total) {
 }
 }  // namespace
 
+// Grid x dimensions are below 2^31 (checked by the callers' sizes: B * G, B * c_out and
+// ciphertext counts are 32-bit); y is at most N / 256 = 64.
 hipError_t launch_encrypt_online(const ConvGeom &g, const EncGeom &e, const uint32_t *act, const uint32_t *ct0,
                                  uint32_t *ct, uint32_t B, bool copy_c1, const LimbConsts &c, hipStream_t st) {
-  const size_t total = (size_t)B * g.G * g.N;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_encrypt_online, dim3(grid_for(total)), dim3(256), 0, st, act, ct0, ct, g, e, B,
+  const uint64_t n_ct = (uint64_t)B * g.G;
+  if (n_ct == 0) return hipSuccess;
+  if (n_ct >= (1ull << 31) || g.N % 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_encrypt_online, dim3((uint32_t)n_ct, g.N / 1024), dim3(256), 0, st, act, ct0, ct, g, e,
                      copy_c1 ? 1u : 0u, c);
-  return hipGetLastError();
-}
-hipError_t launch_mul_bcast(uint32_t *a, const uint32_t *s, size_t np, uint32_t N, const LimbConsts &k,
-                            hipStream_t st) {
-  const size_t total = np * N;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mul_bcast, dim3(grid_for(total)), dim3(256), 0, st, a, s, total, N, k);
   return hipGetLastError();
 }
 hipError_t launch_gather_c1(const uint32_t *ct, uint32_t *c1, size_t n_ct, uint32_t L, uint32_t N, hipStream_t st) {
@@ -185,15 +171,18 @@ hipError_t launch_gather_c1(const uint32_t *ct, uint32_t *c1, size_t n_ct, uint3
 }
 hipError_t launch_decrypt_extracted(const ConvGeom &g, const uint32_t *c0_ext, const uint32_t *c1s, uint32_t *m,
                                     uint32_t B, const LimbConsts &c, const DecodeConsts &d, hipStream_t st) {
-  const size_t total = (size_t)B * g.c_out * g.ho * g.wo;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_decrypt_extracted, dim3(grid_for(total)), dim3(256), 0, st, c0_ext, c1s, m, g, B, c, d);
+  const uint64_t rows = (uint64_t)B * g.c_out, hw = (uint64_t)g.ho * g.wo;
+  if (rows == 0 || hw == 0) return hipSuccess;
+  if (rows >= (1ull << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_decrypt_extracted, dim3((uint32_t)rows, (uint32_t)((hw + 255) / 256)), dim3(256), 0, st,
+                     c0_ext, c1s, m, g, c, d);
   return hipGetLastError();
 }
 hipError_t launch_decrypt_full(const uint32_t *ct, const uint32_t *c1s, uint32_t *m, size_t n_ct, uint32_t N,
                                const LimbConsts &c, const DecodeConsts &d, hipStream_t st) {
-  if (n_ct * N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_decrypt_full, dim3(grid_for(n_ct * N)), dim3(256), 0, st, ct, c1s, m, n_ct, N, c, d);
+  if (n_ct == 0) return hipSuccess;
+  if (n_ct >= (1ull << 31) || N % 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_decrypt_full, dim3((uint32_t)n_ct, N / 256), dim3(256), 0, st, ct, c1s, m, N, c, d);
   return hipGetLastError();
 }
 

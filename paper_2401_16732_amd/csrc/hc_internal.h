@@ -82,6 +82,10 @@ bool mac_offsets_fit(const ConvGeom &g, const MacShape &m);
 hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                           const LimbConsts &c, const Twiddles &tw, hipStream_t st, const ImgPtrs *tab = nullptr,
                           uint32_t ppi = 0);
+// Forward NTT whose outputs are multiplied pointwise by mul [L][N] (NTT domain,
+// canonical, 16-byte aligned) before they are stored (in place allowed).
+hipError_t launch_ntt_fwd_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
+                              const uint32_t *mul, const LimbConsts &c, const Twiddles &tw, hipStream_t st);
 // Full mode: in [P][N] -> out [P][N] (in place allowed).
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st);
@@ -135,9 +139,6 @@ struct EncGeom {
 // unless copy_c1 is false (ct == ct_zero).
 hipError_t launch_encrypt_online(const ConvGeom &g, const EncGeom &e, const uint32_t *act, const uint32_t *ct_zero,
                                  uint32_t *ct, uint32_t B, bool copy_c1, const LimbConsts &c, hipStream_t st);
-// a[p][:] *= s[p mod L][:] mod q_(p mod L) over a [P][N] (s: [L][N]).
-hipError_t launch_mul_bcast(uint32_t *a, const uint32_t *s, size_t npolys, uint32_t N, const LimbConsts &k,
-                            hipStream_t st);
 // c1[c][l][:] = ct[c][1][l][:] for n_ct ciphertexts [n_ct][2][L][N].
 hipError_t launch_gather_c1(const uint32_t *ct, uint32_t *c1, size_t n_ct, uint32_t L, uint32_t N, hipStream_t st);
 // m[b][i][oy][ox] = decode(c0_ext[b][i][:][oy][ox] + c1s[b][(i, tau)][:][e]).

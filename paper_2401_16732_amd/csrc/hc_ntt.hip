@@ -12,9 +12,12 @@ namespace hc {
 // canonical; output canonical, in bit-reversed evaluation order.
 // With a pointer table (tab.n > 0) polynomial `poly` is read from image
 // poly / ppi at polynomial poly % ppi of that image's buffer instead.
-template <int LOGN, int ELOG>
+// MUL: each output is multiplied by mul[l][same index] mod q before it is
+// stored (a pointwise product with an NTT-domain polynomial per limb).
+template <int LOGN, int ELOG, bool MUL = false>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *in, uint32_t *out, LimbConsts c,
-                                                                 Twiddles tws, ImgPtrs tab, uint32_t ppi) {
+                                                                 Twiddles tws, ImgPtrs tab, uint32_t ppi,
+                                                                 const uint32_t *mul) {
   constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
   __shared__ uint32_t lds[N + N / 32];
   const uint32_t tid = threadIdx.x;
@@ -47,7 +50,15 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
     t4.y = csub(csub(v[u + 1], q2), q);
     t4.z = csub(csub(v[u + 2], q2), q);
     t4.w = csub(csub(v[u + 3], q2), q);
-    *reinterpret_cast<uint4 *>(dst + gidx<LOGN, ELOG, 0, EPL>(tid, 0) + gidx<LOGN, ELOG, 0, EPL>(0, u)) = t4;
+    const uint32_t idx = gidx<LOGN, ELOG, 0, EPL>(tid, 0) + gidx<LOGN, ELOG, 0, EPL>(0, u);
+    if constexpr (MUL) {
+      const uint4 s4 = *reinterpret_cast<const uint4 *>(mul + (size_t)l * N + idx);
+      t4.x = reduce64((uint64_t)t4.x * s4.x, q, c.r2[l], c.r2_p[l], c.one_p[l]);
+      t4.y = reduce64((uint64_t)t4.y * s4.y, q, c.r2[l], c.r2_p[l], c.one_p[l]);
+      t4.z = reduce64((uint64_t)t4.z * s4.z, q, c.r2[l], c.r2_p[l], c.one_p[l]);
+      t4.w = reduce64((uint64_t)t4.w * s4.w, q, c.r2[l], c.r2_p[l], c.one_p[l]);
+    }
+    *reinterpret_cast<uint4 *>(dst + idx) = t4;
   }
   (void)NT;
 }
@@ -173,7 +184,15 @@ static hipError_t fwd_t(const uint32_t *in, uint32_t *out, size_t np, const Limb
                         const ImgPtrs &tab, uint32_t ppi, hipStream_t st) {
   if (np == 0) return hipSuccess;
   hipLaunchKernelGGL((k_ntt_fwd<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c, tw,
-                     tab, ppi);
+                     tab, ppi, (const uint32_t *)nullptr);
+  return hipGetLastError();
+}
+template <int LOGN, int ELOG>
+static hipError_t fwd_mul_t(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, const LimbConsts &c,
+                            const Twiddles &tw, hipStream_t st) {
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_ntt_fwd<LOGN, ELOG, true>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c,
+                     tw, ImgPtrs{}, 0u, mul);
   return hipGetLastError();
 }
 template <int LOGN, int ELOG>
@@ -212,6 +231,10 @@ hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint
   if (tab && (tab->n == 0 || tab->n > kMaxTab || ppi == 0 || np != (size_t)tab->n * ppi)) return hipErrorInvalidValue;
   const ImgPtrs &t = tab ? *tab : none;
   HC_NTT_DISPATCH(fwd_t, in, out, np, c, tw, t, ppi, st)
+}
+hipError_t launch_ntt_fwd_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
+                              const uint32_t *mul, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  HC_NTT_DISPATCH(fwd_mul_t, in, out, np, mul, c, tw, st)
 }
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
