@@ -136,10 +136,11 @@ def layer_counts(ly, B, N, L):
     }
 
 
-def client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, passes=3):
+def client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, passes=3, graphs=True):
     """Times the client-side entry points over every layer for B images:
     online encryption of the layer inputs (in place on ct_in, which stays a
-    set of canonical ciphertexts) and decryption of the extracted outputs."""
+    set of canonical ciphertexts) and decryption of the extracted outputs.
+    graphs=False (profiling passes): one eager pass each, nothing timed."""
     N, L = ctx.N, ctx.L
     acts = [torch.randint(0, t, ly.act_shape(B), generator=tg, device=dev, dtype=torch.int32) for ly in layers]
     s = torch.randint(-1, 2, (N,), generator=tg, device=dev, dtype=torch.int64)
@@ -162,6 +163,8 @@ def client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, passes=3):
     for name, fn in (("encrypt_online", enc), ("decrypt_extracted", dec)):
         fn()
         torch.cuda.synchronize()
+        if not graphs:
+            continue
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             fn()
@@ -179,6 +182,8 @@ def client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, passes=3):
     enc_bytes = sum(B * ly.layout.in_cts * L * N * 8 + math.prod(ly.act_shape(B)) * 4 for ly in layers)
     # decryption: forward and inverse NTT of every output ciphertext's c1
     dec_bfly = sum(2 * B * ly.layout.out_cts * L * (N // 2) * int(math.log2(N)) for ly in layers)
+    if not graphs:
+        return None
     enc_s, dec_s = res["encrypt_online"] * 1e-3, res["decrypt_extracted"] * 1e-3
     return {
         "encrypt_online": {"ms_per_image": round(res["encrypt_online"] / B, 4), "launches": len(layers),
@@ -323,7 +328,8 @@ def main():
 
     client = None
     if not a.no_client:
-        client = client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg)
+        client = client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, graphs=a.steps > 0)
+    if client is not None:
         print(f"[bench] client: encrypt {client['encrypt_online']['ms_per_image']:.3f} ms/image "
               f"({client['encrypt_online']['achieved_GBps']} GB/s), decrypt "
               f"{client['decrypt_extracted']['ms_per_image']:.3f} ms/image", file=sys.stderr, flush=True)
