@@ -2,8 +2,8 @@
 // online encryption of a layer's input (Algorithm 2, section "Moving
 // Data-independent Operations to Offline Phase") and BFV decryption
 // (eq. bfv_dec) of the masked convolution's outputs or of whole ciphertexts.
-// Kernels live in hc_client.hip; decryption's ring product c1 * s uses the
-// forward and full inverse NTT kernels of hc_ntt.hip.
+// Kernels live in hc_client.hip; decryption's ring product c1 * s is the
+// fused forward NTT / product / inverse NTT kernel of hc_ntt.hip.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -57,14 +57,13 @@ hc::EncGeom enc_geom(const hc_layer &ly) {
   return e;
 }
 
-// NTT(s) into s_hat [L][N], then c1s [P][N] <- INTT(NTT(c1) * s_hat) for c1 [P][N]
-// (c1 == c1s allowed): the product is taken as the forward NTT stores.
+// NTT(s) into s_hat [L][N], then c1s [P][N] <- c1 * s for c1 [P][N] (c1 == c1s
+// allowed): forward NTT, product and inverse NTT in one kernel per polynomial.
 hc_status ring_times_secret(const hc_ctx &c, const uint32_t *sk, const uint32_t *c1, uint32_t *c1s, size_t np,
                             uint32_t *s_hat, hipStream_t st) {
   const hc::Shapes sh = hc::shapes_for(c, 1);
   CL_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, sk, s_hat, c.L, c.consts, c.tw, st));
-  CL_HIP(hc::launch_ntt_fwd_mul(c.logn, sh.fe, c1, c1s, np, s_hat, c.consts, c.tw, st));
-  CL_HIP(hc::launch_intt_full(c.logn, sh.ie, c1s, c1s, np, c.consts, c.tw, st));
+  CL_HIP(hc::launch_ring_mul(c.logn, sh.ie, c1, c1s, np, s_hat, c.consts, c.tw, st));
   return HC_OK;
 }
 

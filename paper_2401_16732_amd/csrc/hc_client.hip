@@ -4,8 +4,8 @@
 // All of them are elementwise and bound by HBM traffic: dword accesses that
 // are consecutive across a wave's lanes, 2-D grids (ciphertext or channel x
 // chunk) so that no thread divides a 64-bit index. The ring product c1 * s of
-// decryption runs through the forward NTT with the pointwise product by NTT(s)
-// fused into its store, and the full inverse NTT, of hc_ntt.hip.
+// decryption is hc_ntt.hip's k_ring_mul: forward NTT, product by NTT(s) and
+// inverse NTT in one pass over HBM.
 #include "hc_device.h"
 
 namespace hc {

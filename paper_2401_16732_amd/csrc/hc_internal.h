@@ -82,10 +82,11 @@ bool mac_offsets_fit(const ConvGeom &g, const MacShape &m);
 hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                           const LimbConsts &c, const Twiddles &tw, hipStream_t st, const ImgPtrs *tab = nullptr,
                           uint32_t ppi = 0);
-// Forward NTT whose outputs are multiplied pointwise by mul [L][N] (NTT domain,
-// canonical, 16-byte aligned) before they are stored (in place allowed).
-hipError_t launch_ntt_fwd_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
-                              const uint32_t *mul, const LimbConsts &c, const Twiddles &tw, hipStream_t st);
+// out[p] = in[p] * s_(p mod L) mod (x^N + 1, q_(p mod L)) over [P][N], where
+// mul [L][N] holds NTT(s_l) as launch_ntt_fwd writes it (canonical, 16-byte
+// aligned): forward NTT, product and inverse NTT in one kernel (in place allowed).
+hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
+                           const uint32_t *mul, const LimbConsts &c, const Twiddles &tw, hipStream_t st);
 // Full mode: in [P][N] -> out [P][N] (in place allowed).
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st);

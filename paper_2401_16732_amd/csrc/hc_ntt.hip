@@ -12,12 +12,9 @@ namespace hc {
 // canonical; output canonical, in bit-reversed evaluation order.
 // With a pointer table (tab.n > 0) polynomial `poly` is read from image
 // poly / ppi at polynomial poly % ppi of that image's buffer instead.
-// MUL: each output is multiplied by mul[l][same index] mod q before it is
-// stored (a pointwise product with an NTT-domain polynomial per limb).
-template <int LOGN, int ELOG, bool MUL = false>
+template <int LOGN, int ELOG>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *in, uint32_t *out, LimbConsts c,
-                                                                 Twiddles tws, ImgPtrs tab, uint32_t ppi,
-                                                                 const uint32_t *mul) {
+                                                                 Twiddles tws, ImgPtrs tab, uint32_t ppi) {
   constexpr int N = 1 << LOGN, E = 1 << ELOG, NT = 1 << (LOGN - ELOG), NP = n_pass(LOGN, ELOG);
   __shared__ uint32_t lds[N + N / 32];
   const uint32_t tid = threadIdx.x;
@@ -50,15 +47,7 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
     t4.y = csub(csub(v[u + 1], q2), q);
     t4.z = csub(csub(v[u + 2], q2), q);
     t4.w = csub(csub(v[u + 3], q2), q);
-    const uint32_t idx = gidx<LOGN, ELOG, 0, EPL>(tid, 0) + gidx<LOGN, ELOG, 0, EPL>(0, u);
-    if constexpr (MUL) {
-      const uint4 s4 = *reinterpret_cast<const uint4 *>(mul + (size_t)l * N + idx);
-      t4.x = reduce64((uint64_t)t4.x * s4.x, q, c.r2[l], c.r2_p[l], c.one_p[l]);
-      t4.y = reduce64((uint64_t)t4.y * s4.y, q, c.r2[l], c.r2_p[l], c.one_p[l]);
-      t4.z = reduce64((uint64_t)t4.z * s4.z, q, c.r2[l], c.r2_p[l], c.one_p[l]);
-      t4.w = reduce64((uint64_t)t4.w * s4.w, q, c.r2[l], c.r2_p[l], c.one_p[l]);
-    }
-    *reinterpret_cast<uint4 *>(dst + idx) = t4;
+    *reinterpret_cast<uint4 *>(dst + gidx<LOGN, ELOG, 0, EPL>(tid, 0) + gidx<LOGN, ELOG, 0, EPL>(0, u)) = t4;
   }
   (void)NT;
 }
@@ -79,6 +68,61 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
   uint32_t *dst = out + poly * N;
   const uint32_t q = c.q[l];
   uint32_t *db = dst + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+#pragma unroll
+  for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[0][u], q);
+}
+
+// Negacyclic product of each polynomial of in [P][N] (limb = poly mod L) with
+// the limb's polynomial whose NTT is mul [L][N] (bit-reversed evaluation order,
+// canonical, 16-byte aligned), in one pass over HBM: the forward transform,
+// the pointwise product as the forward's last pass leaves its registers, one
+// LDS exchange into the inverse transform's first-pass layout, the inverse
+// transform, and a canonical store (in place allowed).
+template <int LOGN, int ELOG>
+__global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ring_mul(const uint32_t *in, uint32_t *out,
+                                                                  const uint32_t *mul, LimbConsts c, Twiddles tws) {
+  constexpr int N = 1 << LOGN, E = 1 << ELOG, NP = n_pass(LOGN, ELOG);
+  __shared__ uint32_t lds[N + N / 32];
+  const uint32_t tid = threadIdx.x;
+  const size_t poly = blockIdx.x;
+  const uint32_t l = (uint32_t)(poly % c.L);
+  const uint32_t q = c.q[l];
+  using gu32 = __attribute__((address_space(1))) const uint32_t;
+  uint32_t v[1][E];
+  {
+    constexpr int LO = pass_lo_fwd(LOGN, ELOG, 0), EP = pass_bits(LOGN, ELOG, 0);
+    gu32 *sb = (gu32 *)in + poly * N + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+#pragma unroll
+    for (int u = 0; u < E; ++u) v[0][u] = __builtin_nontemporal_load(sb + gidx<LOGN, ELOG, LO, EP>(0, u));
+  }
+  FwdPasses<LOGN, ELOG, NP - 1>::run(v[0], lds, tid, tws.fwd + (size_t)l * N, q);
+  // the forward's last pass covers bits [0, EPL): 2^EPL consecutive words per group
+  constexpr int EPL = pass_bits(LOGN, ELOG, NP - 1);
+  static_assert(pass_lo_fwd(LOGN, ELOG, NP - 1) == 0 && EPL >= 2, "last forward pass covers the low bits");
+  const uint32_t q2 = 2 * q;
+  const uint32_t *ml = mul + (size_t)l * N + gidx<LOGN, ELOG, 0, EPL>(tid, 0);
+#pragma unroll
+  for (int u = 0; u < E; u += 4) {
+    const uint4 s4 = *reinterpret_cast<const uint4 *>(ml + gidx<LOGN, ELOG, 0, EPL>(0, u));
+    const uint32_t sv[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      v[0][u + j] = reduce64((uint64_t)csub(csub(v[0][u + j], q2), q) * sv[j], q, c.r2[l], c.r2_p[l], c.one_p[l]);
+  }
+  // each thread writes back the LDS words its last forward pass read, so the
+  // exchange needs only the barrier before the reads
+  regs_to_lds<LOGN, ELOG, 0, EPL>(v[0], lds, tid);
+  __syncthreads();
+  lds_to_regs<LOGN, ELOG, 0, pass_bits(LOGN, ELOG, 0)>(v[0], lds, tid);
+  const uint2 *itw = tws.inv + (size_t)l * N;
+  if constexpr (ELOG <= 4) {
+    const EarlyTws<LOGN, ELOG, 0> t(itw, tid);
+    intt_passes<LOGN, ELOG, 0, 1, 0>(v, lds, tid, c, t, l);
+  } else {
+    intt_passes<LOGN, ELOG, 0, 1, 0>(v, lds, tid, c, MemTws<LOGN, ELOG, 0>{itw, tid}, l);
+  }
+  constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
+  uint32_t *db = out + poly * N + gidx<LOGN, ELOG, LO, EP>(tid, 0);
 #pragma unroll
   for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[0][u], q);
 }
@@ -184,15 +228,15 @@ static hipError_t fwd_t(const uint32_t *in, uint32_t *out, size_t np, const Limb
                         const ImgPtrs &tab, uint32_t ppi, hipStream_t st) {
   if (np == 0) return hipSuccess;
   hipLaunchKernelGGL((k_ntt_fwd<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c, tw,
-                     tab, ppi, (const uint32_t *)nullptr);
+                     tab, ppi);
   return hipGetLastError();
 }
 template <int LOGN, int ELOG>
-static hipError_t fwd_mul_t(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, const LimbConsts &c,
-                            const Twiddles &tw, hipStream_t st) {
+static hipError_t ring_mul_t(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, const LimbConsts &c,
+                             const Twiddles &tw, hipStream_t st) {
   if (np == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_ntt_fwd<LOGN, ELOG, true>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c,
-                     tw, ImgPtrs{}, 0u, mul);
+  hipLaunchKernelGGL((k_ring_mul<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, mul, c,
+                     tw);
   return hipGetLastError();
 }
 template <int LOGN, int ELOG>
@@ -232,9 +276,9 @@ hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint
   const ImgPtrs &t = tab ? *tab : none;
   HC_NTT_DISPATCH(fwd_t, in, out, np, c, tw, t, ppi, st)
 }
-hipError_t launch_ntt_fwd_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
-                              const uint32_t *mul, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
-  HC_NTT_DISPATCH(fwd_mul_t, in, out, np, mul, c, tw, st)
+hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
+                           const uint32_t *mul, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  HC_NTT_DISPATCH(ring_mul_t, in, out, np, mul, c, tw, st)
 }
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
