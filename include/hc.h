@@ -319,6 +319,18 @@ hc_status hc_check_residues(const hc_ctx *ctx, const uint32_t *polys, size_t npo
 hc_status hc_encrypt_online(const hc_layer *layer, const uint32_t *act, const uint32_t *ct_zero, uint32_t *ct_in,
                             uint32_t B, void *stream);
 
+/* The offline half of Algorithm 2: `count` private-key encryptions of zero
+ * (Table 2's private-key form with m = 0), ct_zero[c] = (-(a_c s + e_c) mod q, a_c).
+ * The random polynomials are inputs, drawn by the caller:
+ *   a   [count][L][N]  uniform residues (canonical, device)
+ *   sk  [L][N]         secret key residues s mod q_l (canonical, device)
+ *   e   [count][N]     int32 error coefficients, |e| < q_l (device)
+ *   ct_zero [count][2][L][N] output, must not overlap a or ws.
+ * a * s is the negacyclic product through the NTT (the kernel decryption uses).
+ * ws: at least (count + 1) L N words, 16-byte aligned. */
+hc_status hc_encrypt_zero(const hc_ctx *ctx, const uint32_t *a, const uint32_t *sk, const int32_t *e,
+                          uint32_t *ct_zero, uint32_t count, void *ws, size_t ws_bytes, void *stream);
+
 /* BFV decryption (eq. bfv_dec): m = round(t [c1 s + c0]_q / q) mod t, rounded
  * half up and exact for every phase (the RNS rounding carries 160 fraction bits;
  * q < 2^120). The secret key sk is given as its residues [L][N] (s mod q_l,

@@ -1,7 +1,8 @@
-// Client-side entry points of libhconv (include/hc.h): direct encoding with
-// online encryption of a layer's input (Algorithm 2, section "Moving
-// Data-independent Operations to Offline Phase") and BFV decryption
-// (eq. bfv_dec) of the masked convolution's outputs or of whole ciphertexts.
+// Client-side entry points of libhconv (include/hc.h): the offline encryptions
+// of zero and direct encoding with online encryption of a layer's input
+// (Algorithm 2, section "Moving Data-independent Operations to Offline
+// Phase"), and BFV decryption (eq. bfv_dec) of the masked convolution's outputs
+// or of whole ciphertexts.
 // Kernels live in hc_client.hip; decryption's ring product c1 * s is the
 // fused forward NTT / product / inverse NTT kernel of hc_ntt.hip.
 #include <hip/hip_runtime.h>
@@ -104,6 +105,25 @@ hc_status hc_encrypt_online(const hc_layer *ly, const uint32_t *act, const uint3
   hc::DeviceGuard dg(c.device);
   CL_HIP(hc::launch_encrypt_online(ly->geom, enc_geom(*ly), act, ct_zero, ct_in, B, !in_place, c.consts,
                                    (hipStream_t)stream));
+  return HC_OK;
+}
+
+hc_status hc_encrypt_zero(const hc_ctx *c, const uint32_t *a, const uint32_t *sk, const int32_t *e, uint32_t *ct_zero,
+                          uint32_t count, void *ws, size_t ws_bytes, void *stream) {
+  if (!c || (count && (!a || !sk || !e || !ct_zero || !ws))) return fail(HC_EINVAL, "null argument");
+  if (count == 0) return HC_OK;
+  const size_t np = (size_t)count * c->L;
+  if (ws_bytes < (np + c->L) * c->N * sizeof(uint32_t)) return fail(HC_EINVAL, "workspace too small");
+  if ((uintptr_t)ws & 15u) return fail(HC_EINVAL, "ws must be 16-byte aligned");
+  const size_t ct_words = 2 * np * c->N;
+  if (overlap(ct_zero, ct_words, a, np * c->N) || overlap(ct_zero, ct_words, (const uint32_t *)ws, np * c->N))
+    return fail(HC_EINVAL, "ct_zero overlaps a or ws");
+  uint32_t *as = (uint32_t *)ws, *s_hat = as + np * c->N;
+  hipStream_t st = (hipStream_t)stream;
+  hc::DeviceGuard dg(c->device);
+  hc_status s = ring_times_secret(*c, sk, a, as, np, s_hat, st);
+  if (s != HC_OK) return s;
+  CL_HIP(hc::launch_encrypt_zero(a, as, e, ct_zero, count, c->N, c->consts, st));
   return HC_OK;
 }
 

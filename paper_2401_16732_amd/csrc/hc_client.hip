@@ -70,6 +70,27 @@ __global__ __launch_bounds__(256) void k_encrypt_online(const uint32_t *__restri
   }
 }
 
+// Offline encryption of zero (private-key form): ct[c][0][l] = -(as[c][l] + e[c]) mod q_l,
+// ct[c][1][l] = a[c][l], with as = a * s already computed and e small signed integers.
+// Grid: x = ciphertext, y = chunk of 256 coefficients.
+__global__ __launch_bounds__(256) void k_encrypt_zero(const uint32_t *__restrict__ a,
+                                                       const uint32_t *__restrict__ as,
+                                                       const int32_t *__restrict__ e, uint32_t *__restrict__ ct,
+                                                       uint32_t N, LimbConsts c) {
+  const size_t cn = blockIdx.x;
+  const uint32_t k = blockIdx.y * 256 + threadIdx.x;
+  const int32_t ek = e[cn * N + k];
+  for (uint32_t l = 0; l < c.L; ++l) {
+    const uint32_t q = c.q[l];
+    // e mod q_l for |e| < q_l
+    const uint32_t el = ek < 0 ? q - (uint32_t)(-(int64_t)ek) : (uint32_t)ek;
+    const uint32_t sum = csub(as[(cn * c.L + l) * N + k] + csub(el, q), q);
+    const size_t w0 = ((cn * 2) * c.L + l) * N + k;
+    ct[w0] = sum == 0 ? 0 : q - sum;
+    ct[w0 + (size_t)c.L * N] = a[(cn * c.L + l) * N + k];
+  }
+}
+
 // ---------------------------------------------------------------- decryption
 __global__ void k_gather_c1(const uint32_t *__restrict__ ct, uint32_t *__restrict__ c1, size_t n_ct, size_t ln) {
   const size_t total = n_ct * ln;
@@ -161,6 +182,13 @@ hipError_t launch_encrypt_online(const ConvGeom &g, const EncGeom &e, const uint
   if (n_ct >= (1ull << 31) || g.N % 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_encrypt_online, dim3((uint32_t)n_ct, g.N / 1024), dim3(256), 0, st, act, ct0, ct, g, e,
                      copy_c1 ? 1u : 0u, c);
+  return hipGetLastError();
+}
+hipError_t launch_encrypt_zero(const uint32_t *a, const uint32_t *as, const int32_t *e, uint32_t *ct, size_t n_ct,
+                               uint32_t N, const LimbConsts &c, hipStream_t st) {
+  if (n_ct == 0) return hipSuccess;
+  if (n_ct >= (1ull << 31) || N % 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_encrypt_zero, dim3((uint32_t)n_ct, N / 256), dim3(256), 0, st, a, as, e, ct, N, c);
   return hipGetLastError();
 }
 hipError_t launch_gather_c1(const uint32_t *ct, uint32_t *c1, size_t n_ct, uint32_t L, uint32_t N, hipStream_t st) {

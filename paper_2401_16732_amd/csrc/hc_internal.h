@@ -140,6 +140,10 @@ struct EncGeom {
 // unless copy_c1 is false (ct == ct_zero).
 hipError_t launch_encrypt_online(const ConvGeom &g, const EncGeom &e, const uint32_t *act, const uint32_t *ct_zero,
                                  uint32_t *ct, uint32_t B, bool copy_c1, const LimbConsts &c, hipStream_t st);
+// ct [n_ct][2][L][N] <- (-(as + e) mod q_l, a) from a, as = a * s ([n_ct][L][N])
+// and e [n_ct][N] (signed, |e| < q_l).
+hipError_t launch_encrypt_zero(const uint32_t *a, const uint32_t *as, const int32_t *e, uint32_t *ct, size_t n_ct,
+                               uint32_t N, const LimbConsts &c, hipStream_t st);
 // c1[c][l][:] = ct[c][1][l][:] for n_ct ciphertexts [n_ct][2][L][N].
 hipError_t launch_gather_c1(const uint32_t *ct, uint32_t *c1, size_t n_ct, uint32_t L, uint32_t N, hipStream_t st);
 // m[b][i][oy][ox] = decode(c0_ext[b][i][:][oy][ox] + c1s[b][(i, tau)][:][e]).

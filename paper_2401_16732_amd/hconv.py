@@ -30,6 +30,7 @@ SYMBOLS = [
     "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
     "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
     "hc_check_residues", "hc_encrypt_online", "hc_decrypt_workspace_size", "hc_decrypt_extracted", "hc_decrypt",
+    "hc_encrypt_zero",
 ]
 
 
@@ -96,6 +97,7 @@ def load(path: str = LIB_PATH):
         "hc_decrypt_workspace_size": (I, [P, u32, P]),
         "hc_decrypt_extracted": (I, [P, P, P, P, P, u32, P, sz, P]),
         "hc_decrypt": (I, [P, P, P, P, u32, P, sz, P]),
+        "hc_encrypt_zero": (I, [P, P, P, P, P, u32, P, sz, P]),
         "hc_sync": (I, [P]),
         "hc_status_string": (ctypes.c_char_p, [I]),
         "hc_last_error": (ctypes.c_char_p, []),
@@ -214,6 +216,21 @@ class Context:
         _check(_lib.hc_check_residues(self.h, _dptr(polys, "polys", self.device), npolys, _stream(stream),
                                       ctypes.byref(n)), "hc_check_residues")
         return n.value
+
+    def encrypt_zero(self, a, sk, e, ct_zero, ws, stream=None):
+        """ct_zero [count][2][L][N] <- (-(a s + e), a) for a [count][L][N] residues,
+        sk [L][N] key residues and e [count][N] int32 errors (device tensors);
+        ws: (count + 1) L N words."""
+        ln = self.L * self.N
+        count = a.numel() // ln
+        if a.numel() != count * ln or sk.numel() != ln or e.numel() != count * self.N:
+            raise ValueError("a must hold count * L * N words, sk L * N, e count * N")
+        if ct_zero.numel() < 2 * count * ln or ws.numel() < (count + 1) * ln:
+            raise ValueError("ct_zero must hold 2 * count * L * N words, ws (count + 1) * L * N")
+        _check(_lib.hc_encrypt_zero(self.h, _dptr(a, "a", self.device), _dptr(sk, "sk", self.device),
+                                    _dptr(e, "e", self.device), _dptr(ct_zero, "ct_zero", self.device), count,
+                                    _dptr(ws, "ws", self.device), ws.numel() * 4, _stream(stream)),
+               "hc_encrypt_zero")
 
     def decrypt(self, ct, sk, m, ws, stream=None):
         """m [count][N] <- decryption of ct [count][2][L][N] under the key

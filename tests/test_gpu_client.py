@@ -102,6 +102,29 @@ def test_plaintext_modulus_must_be_below_twice_each_prime(hc):
     hc.Context(1024, 1, 2 * 12289 - 1, primes=[12289]).close()
 
 
+def _dev_i32(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).cuda()
+
+
+@pytest.mark.parametrize("N,L", [(1024, 3), (4096, 1)])
+def test_encrypt_zero_matches_oracle(hc, N, L):
+    """Offline [[0]] = (-(a s + e), a) against oracle.bfv.encrypt_zero."""
+    c = hc.Context(N, L, 2 ** 17)
+    g = W.rng(77 + L)
+    count = 3
+    s = bfv.sample_secret(g, N)
+    a = np.stack([bfv.sample_a(g, c.primes, N) for _ in range(count)]).astype(np.uint32)
+    e = np.stack([bfv.sample_error(g, N) for _ in range(count)])
+    e[0, :4] = [0, -1, 1, -19]
+    out = zeros((count, 2, L, N))
+    print(f"encrypt_zero N={N} L={L}", flush=True)
+    c.encrypt_zero(dev(a), dev(_sk_residues(s, c.primes)), _dev_i32(e), out, zeros(((count + 1) * L * N,)))
+    got = host(out)
+    for k in range(count):
+        assert (got[k] == bfv.encrypt_zero(s, a[k], e[k], c.primes)).all(), k
+
+
 @pytest.mark.parametrize("L,t", [(4, 2 ** 17), (3, 65537), (1, 2 ** 20), (4, 3)])
 def test_decrypt_rounding_is_exact_at_the_boundaries(hc, L, t):
     """c1 = 0, so the phase is c0: phases one below and at each rounding
@@ -194,9 +217,9 @@ def test_decrypt_extracted_matches_oracle(hc, N, L, t, shape):
 
 def test_client_server_client_loop_resnet50_layer(hc):
     """ResNet-50 conv2_x 3x3 layer (64 -> 64, 56 x 56) at N = 8192, 3 primes,
-    t = 2^17, two images, everything on the GPU: encryptions of zero (a s by
-    the library's ring product), online encryption, masked convolution,
-    decryption. The result is conv(a) + r mod t at every output pixel."""
+    t = 2^17, two images, every step on the GPU: offline encryptions of zero,
+    online encryption, masked convolution, decryption. The result is
+    conv(a) + r mod t at every output pixel."""
     N, L, t, B = 8192, 3, 2 ** 17, 2
     shape = (64, 64, 56, 56, 3, 1)
     c = hc.Context(N, L, t)
@@ -208,16 +231,12 @@ def test_client_server_client_loop_resnet50_layer(hc):
     sk = _sk_residues(s, c.primes)
     n_ct = B * P.G
     a_poly = W.gen_ct_limbs(g, (n_ct,), c.primes, N)                  # [n_ct][L][N]
-    a_s = zeros((n_ct, L, N))
-    c.poly_mul(dev(a_poly), dev(np.broadcast_to(sk, (n_ct, L, N))), a_s, zeros((2 * n_ct * L * N,)))
     e = np.stack([bfv.sample_error(g, N) for _ in range(n_ct)])      # [n_ct][N]
-    qs = np.array(c.primes, dtype=np.int64)[None, :, None]
-    c0z = (-(host(a_s).astype(np.int64) + e[:, None, :])) % qs
-    ct = np.stack([c0z, a_poly.astype(np.int64)], axis=1).astype(np.uint32).reshape(B, P.G, 2, L, N)
     act = W.gen_activations(g, W.ConvSpec(*shape), 0, 256, batch=B).astype(np.uint32)
     r = W.gen_mask(g, (B, P.c_o, P.ho, P.wo), t)
-    print("loop: encrypt_online", flush=True)
-    ct_d = dev(ct)
+    print("loop: encrypt_zero, encrypt_online", flush=True)
+    ct_d = zeros(ly.in_shape(B))
+    c.encrypt_zero(dev(a_poly), dev(sk), _dev_i32(e), ct_d, zeros(((n_ct + 1) * L * N,)))
     ly.encrypt_online(dev(act), ct_d, ct_d, B)
     c0, c1 = zeros(ly.c0_shape(B)), zeros(ly.c1_shape(B))
     print("loop: conv_masked", flush=True)
