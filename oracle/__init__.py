@@ -7,7 +7,8 @@ benchmark's CPU-baseline leg use it. It shares no code with the GPU library
 
 It is deliberately plain and slow: every function states the passage of the
 paper it follows, works in exact integers (Python ints or int64 numpy with
-explicit reductions), and uses no NTT. The paper's convolution (Algorithm 1)
+explicit reductions), and uses no NTT (batch encoding is interpolation at the
+slot points, written out). The paper's convolution (Algorithm 1)
 is a ring computation, so its result is unique given the ciphertext layout;
 the oracle computes that result directly from the definitions.
 
@@ -19,6 +20,8 @@ Modules:
   conv    - Algorithm 1, the weight polynomial, plain conv mod t, mask + extract,
             Freivalds combination
   calg1   - the same Algorithm 1 in plain C (int64 lazy accumulation)
+  batch   - batch (slot) encoding by interpolation, PMult, and the server steps
+            of the x^2 + x protocol
 
 Parity pins: every function is checked by the `-m "not gpu"` tests against
 closed forms, brute force or library routines (see tests/test_oracle_*.py).
