@@ -352,6 +352,50 @@ hc_status hc_decrypt_extracted(const hc_layer *layer, const uint32_t *c0_ext, co
 hc_status hc_decrypt(const hc_ctx *ctx, const uint32_t *ct, const uint32_t *sk, uint32_t *m, uint32_t count,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------ x^2 + x protocol
+ * Section "Proposed Secure Computation of Polynomial Activation Function": the
+ * client returns [[a + r]] under batch encoding, the server multiplies it slot
+ * by slot with 2r and hides the product with v (step 1); the client returns
+ * that vector re-encrypted under direct encoding, and the server combines it
+ * with [[a^2 + 2ar + r^2 + a + r]] into [[a^2 + a]] (step 2). r, v are the
+ * server's random vectors (inputs, drawn offline).
+ *
+ * Batch (slot) encoding needs a context whose t is a prime = 1 mod 2N (below
+ * 2^30); other contexts return HC_EUNSUPPORTED. R_t = Z_t[x]/(x^N + 1) splits
+ * into N slots, the evaluations at the roots of x^N + 1. Slot order (public, a
+ * convention the paper leaves open): slot k is the evaluation at
+ * psi^(2 brv(k) + 1), brv = bit reversal over log2 N bits, psi = the first
+ * x^((t-1)/2N), x = 2, 3, ..., whose N-th power is -1.
+ *
+ * hc_batch_encode: p [n][N] <- the plaintext polynomials with slots z [n][N]
+ *   (values in [0, t)); hc_batch_decode: z <- slots of p (z 16-byte aligned).
+ * hc_encrypt_plain: ct = ct_zero + Delta * p for plaintext polynomials p
+ *   [n][N] in [0, t) (Algorithm 2 for a batch-encoded message); ct_zero, ct
+ *   [n][2][L][N]; ct may be ct_zero, must not otherwise overlap it.
+ * Enqueued on `stream`; no allocation. */
+hc_status hc_batch_encode(const hc_ctx *ctx, const uint32_t *z, uint32_t *p, uint32_t n, void *stream);
+hc_status hc_batch_decode(const hc_ctx *ctx, const uint32_t *p, uint32_t *z, uint32_t n, void *stream);
+hc_status hc_encrypt_plain(const hc_ctx *ctx, const uint32_t *p, const uint32_t *ct_zero, uint32_t *ct, uint32_t n,
+                           void *stream);
+
+/* Step 1: ct_out = PMult(ct_batch, encode(2r)) + encode(v), i.e. [[2r (a + r) + v]]
+ * under batch encoding, for n_ct ciphertexts ct_batch [n_ct][2][L][N] with slot
+ * vectors r, v [n_ct][N] in [0, t). PMult multiplies both components by the
+ * centred plaintext polynomial in R_q (forward NTT, product, inverse NTT in one
+ * kernel). ct_out may be ct_batch, must not otherwise overlap it.
+ * ws: hc_act_workspace_size bytes ((L + 2) n_ct N words), 16-byte aligned. */
+hc_status hc_act_workspace_size(const hc_ctx *ctx, uint32_t n_ct, size_t *bytes);
+hc_status hc_act_pmult(const hc_ctx *ctx, const uint32_t *ct_batch, const uint32_t *r, const uint32_t *v,
+                       uint32_t *ct_out, uint32_t n_ct, void *ws, size_t ws_bytes, void *stream);
+/* Step 2, for the layer whose input the activation map is: ct_out = ct_x - ct_y
+ * + Delta * enc(r^2 - r + v mod t), where ct_x, ct_y [B][G][2][L][N] are the
+ * layer's direct-encoded input ciphertexts of a^2 + 2ar + r^2 + a + r and of
+ * 2ar + 2r^2 + v, enc is the layer's direct encoding (header comment) and r, v
+ * are [B][c_in][h][w] in [0, t); the result encrypts a^2 + a. ct_out may be
+ * ct_x or ct_y, must not otherwise overlap them. Any t; no allocation. */
+hc_status hc_act_combine(const hc_layer *layer, const uint32_t *ct_x, const uint32_t *ct_y, const uint32_t *r,
+                         const uint32_t *v, uint32_t *ct_out, uint32_t B, void *stream);
+
 /* Wait for all work on the context's device; reports earlier asynchronous faults. */
 hc_status hc_sync(hc_ctx *ctx);
 const char *hc_status_string(hc_status s);

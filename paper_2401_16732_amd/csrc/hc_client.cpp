@@ -1,8 +1,9 @@
-// Client-side entry points of libhconv (include/hc.h): the offline encryptions
-// of zero and direct encoding with online encryption of a layer's input
-// (Algorithm 2, section "Moving Data-independent Operations to Offline
-// Phase"), and BFV decryption (eq. bfv_dec) of the masked convolution's outputs
-// or of whole ciphertexts.
+// Entry points of libhconv (include/hc.h) for the steps around the
+// convolution: on the client side the offline encryptions of zero, direct
+// encoding with online encryption of a layer's input (Algorithm 2, section
+// "Moving Data-independent Operations to Offline Phase") and BFV decryption
+// (eq. bfv_dec); batch encoding and the server steps of the x^2 + x protocol
+// (section "Proposed Secure Computation of Polynomial Activation Function").
 // Kernels live in hc_client.hip; decryption's ring product c1 * s is the
 // fused forward NTT / product / inverse NTT kernel of hc_ntt.hip.
 #include <hip/hip_runtime.h>
@@ -64,7 +65,7 @@ hc_status ring_times_secret(const hc_ctx &c, const uint32_t *sk, const uint32_t 
                             uint32_t *s_hat, hipStream_t st) {
   const hc::Shapes sh = hc::shapes_for(c, 1);
   CL_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, sk, s_hat, c.L, c.consts, c.tw, st));
-  CL_HIP(hc::launch_ring_mul(c.logn, sh.ie, c1, c1s, np, s_hat, c.consts, c.tw, st));
+  CL_HIP(hc::launch_ring_mul(c.logn, sh.ie, c1, c1s, np, s_hat, 0, c.consts, c.tw, st));
   return HC_OK;
 }
 
@@ -168,5 +169,96 @@ hc_status hc_decrypt(const hc_ctx *c, const uint32_t *ct, const uint32_t *sk, ui
   hc_status s = ring_times_secret(*c, sk, c1s, c1s, np, s_hat, st);
   if (s != HC_OK) return s;
   CL_HIP(hc::launch_decrypt_full(ct, c1s, m, count, c->N, c->consts, c->dec, st));
+  return HC_OK;
+}
+
+// ------------------------------------------------------------- batch encoding, x^2 + x protocol
+namespace {
+hc_status need_batch(const hc_ctx *c) {
+  if (!c->batch_ok) return fail(HC_EUNSUPPORTED, "batch encoding needs a prime t = 1 mod 2N below 2^30");
+  return HC_OK;
+}
+}  // namespace
+
+hc_status hc_batch_encode(const hc_ctx *c, const uint32_t *z, uint32_t *p, uint32_t n, void *stream) {
+  if (!c || (n && (!z || !p))) return fail(HC_EINVAL, "null argument");
+  hc_status s = need_batch(c);
+  if (s != HC_OK || n == 0) return s;
+  hc::DeviceGuard dg(c->device);
+  CL_HIP(hc::launch_intt_full(c->logn, hc::shapes_for(*c, 1).ie, z, p, n, c->consts_t, c->tw_t,
+                              (hipStream_t)stream));
+  return HC_OK;
+}
+
+hc_status hc_batch_decode(const hc_ctx *c, const uint32_t *p, uint32_t *z, uint32_t n, void *stream) {
+  if (!c || (n && (!z || !p))) return fail(HC_EINVAL, "null argument");
+  hc_status s = need_batch(c);
+  if (s != HC_OK || n == 0) return s;
+  if ((uintptr_t)z & 15u) return fail(HC_EINVAL, "z must be 16-byte aligned");
+  hc::DeviceGuard dg(c->device);
+  CL_HIP(hc::launch_ntt_fwd(c->logn, hc::shapes_for(*c, 1).fe, p, z, n, c->consts_t, c->tw_t, (hipStream_t)stream));
+  return HC_OK;
+}
+
+hc_status hc_encrypt_plain(const hc_ctx *c, const uint32_t *p, const uint32_t *ct_zero, uint32_t *ct, uint32_t n,
+                           void *stream) {
+  if (!c || (n && (!p || !ct_zero || !ct))) return fail(HC_EINVAL, "null argument");
+  if (n == 0) return HC_OK;
+  const size_t words = (size_t)n * 2 * c->L * c->N;
+  if (ct != ct_zero && overlap(ct, words, ct_zero, words))
+    return fail(HC_EINVAL, "ct overlaps ct_zero without being the same buffer");
+  hipStream_t st = (hipStream_t)stream;
+  hc::DeviceGuard dg(c->device);
+  if (ct != ct_zero) CL_HIP(hipMemcpyAsync(ct, ct_zero, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  CL_HIP(hc::launch_add_plain(ct, p, n, c->N, c->consts, st));
+  return HC_OK;
+}
+
+hc_status hc_act_workspace_size(const hc_ctx *c, uint32_t n_ct, size_t *bytes) {
+  if (!c || !bytes) return fail(HC_EINVAL, "null argument");
+  *bytes = (size_t)n_ct * (c->L + 2) * c->N * sizeof(uint32_t);
+  return HC_OK;
+}
+
+hc_status hc_act_pmult(const hc_ctx *c, const uint32_t *ct_batch, const uint32_t *r, const uint32_t *v,
+                       uint32_t *ct_out, uint32_t n_ct, void *ws, size_t ws_bytes, void *stream) {
+  if (!c || (n_ct && (!ct_batch || !r || !v || !ct_out || !ws))) return fail(HC_EINVAL, "null argument");
+  hc_status s = need_batch(c);
+  if (s != HC_OK || n_ct == 0) return s;
+  size_t need = 0;
+  (void)hc_act_workspace_size(c, n_ct, &need);
+  if (ws_bytes < need) return fail(HC_EINVAL, "workspace too small");
+  if ((uintptr_t)ws & 15u) return fail(HC_EINVAL, "ws must be 16-byte aligned");
+  const size_t words = (size_t)n_ct * 2 * c->L * c->N;
+  if (ct_out != ct_batch && overlap(ct_out, words, ct_batch, words))
+    return fail(HC_EINVAL, "ct_out overlaps ct_batch without being the same buffer");
+  const size_t pw = (size_t)n_ct * c->N;
+  uint32_t *pr = (uint32_t *)ws, *pv = pr + pw, *lifted = pv + pw;
+  hipStream_t st = (hipStream_t)stream;
+  const hc::Shapes sh = hc::shapes_for(*c, 1);
+  hc::DeviceGuard dg(c->device);
+  // batch-encode r and v (inverse transforms modulo t; slot k = bit-reversed evaluation order)
+  CL_HIP(hc::launch_intt_full(c->logn, sh.ie, r, pr, n_ct, c->consts_t, c->tw_t, st));
+  CL_HIP(hc::launch_intt_full(c->logn, sh.ie, v, pv, n_ct, c->consts_t, c->tw_t, st));
+  // encode(2r) = 2 encode(r): lift to every limb, NTT, then PMult of both components
+  CL_HIP(hc::launch_lift_plain(pr, lifted, n_ct, c->N, 2, c->consts, st));
+  CL_HIP(hc::launch_ntt_fwd(c->logn, sh.fe, lifted, lifted, (size_t)n_ct * c->L, c->consts, c->tw, st));
+  CL_HIP(hc::launch_ring_mul(c->logn, sh.ie, ct_batch, ct_out, (size_t)n_ct * 2 * c->L, lifted, 2 * c->L, c->consts,
+                             c->tw, st));
+  CL_HIP(hc::launch_add_plain(ct_out, pv, n_ct, c->N, c->consts, st));
+  return HC_OK;
+}
+
+hc_status hc_act_combine(const hc_layer *ly, const uint32_t *ct_x, const uint32_t *ct_y, const uint32_t *r,
+                         const uint32_t *v, uint32_t *ct_out, uint32_t B, void *stream) {
+  if (!ly || (B && (!ct_x || !ct_y || !r || !v || !ct_out))) return fail(HC_EINVAL, "null argument");
+  if (B == 0) return HC_OK;
+  const hc_ctx &c = *ly->ctx;
+  const size_t words = (size_t)B * ly->lay.in_cts * 2 * c.L * c.N;
+  if ((ct_out != ct_x && overlap(ct_out, words, ct_x, words)) || (ct_out != ct_y && overlap(ct_out, words, ct_y, words)))
+    return fail(HC_EINVAL, "ct_out partly overlaps ct_x or ct_y");
+  hc::DeviceGuard dg(c.device);
+  CL_HIP(hc::launch_act_combine(ly->geom, enc_geom(*ly), ct_x, ct_y, r, v, ct_out, B, c.consts,
+                                (hipStream_t)stream));
   return HC_OK;
 }

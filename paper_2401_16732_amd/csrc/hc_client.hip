@@ -1,6 +1,8 @@
-// gfx950 kernels of the client-side steps around the convolution: direct
-// encoding with online encryption (Algorithm 2) of a layer's input, and BFV
-// decryption (eq. bfv_dec) of its extracted outputs or of whole ciphertexts.
+// gfx950 kernels of the steps around the convolution: on the client side the
+// offline encryptions of zero, direct encoding with online encryption
+// (Algorithm 2) of a layer's input and BFV decryption (eq. bfv_dec); on the
+// server side the x^2 + x protocol's PMult helpers (plaintext lift and
+// addition) and its final combination.
 // All of them are elementwise and bound by HBM traffic: dword accesses that
 // are consecutive across a wave's lanes, 2-D grids (ciphertext or channel x
 // chunk) so that no thread divides a 64-bit index. The ring product c1 * s of
@@ -11,17 +13,19 @@
 namespace hc {
 
 // ---------------------------------------------------------------- encryption
-// Plaintext value at coefficient k of input ciphertext gi of image b under
-// the direct-encoding layout: zero padding, c_n channels per ciphertext at
-// offsets (j mod c_n) F, or row tiles with f - 1 halo rows when F > N; with
-// client subsampling the encoded pixel (y, x) is act[j][sub y][sub x].
-__device__ __forceinline__ uint32_t encoded_value(const uint32_t *__restrict__ act, const ConvGeom &g,
-                                                  const EncGeom &e, size_t b, uint32_t gi, uint32_t k) {
+// Activation index [b][j][y][x] (into a [B][c_in][h][w] array) that coefficient
+// k of input ciphertext gi of image b holds under the direct-encoding layout:
+// zero padding, c_n channels per ciphertext at offsets (j mod c_n) F, or row
+// tiles with f - 1 halo rows when F > N; with client subsampling the encoded
+// pixel (y, x) is [j][sub y][sub x]. kNone for padding and empty slots.
+constexpr size_t kNone = ~(size_t)0;
+__device__ __forceinline__ size_t encoded_index(const ConvGeom &g, const EncGeom &e, size_t b, uint32_t gi,
+                                                uint32_t k) {
   uint32_t j, y, x;
   if (!g.tiled) {
     const uint32_t slot = k / g.F;
     j = gi * g.cn + slot;
-    if (slot >= g.cn || j >= g.c_in) return 0;
+    if (slot >= g.cn || j >= g.c_in) return kNone;
     const uint32_t pos = k - slot * g.F;
     y = pos / g.w_pad;
     x = pos - y * g.w_pad;
@@ -29,15 +33,23 @@ __device__ __forceinline__ uint32_t encoded_value(const uint32_t *__restrict__ a
     j = gi / g.T;
     const uint32_t tau = gi - j * g.T;
     const uint32_t yl = k / g.w_pad;
-    if (yl >= e.rows_per_ct) return 0;
+    if (yl >= e.rows_per_ct) return kNone;
     x = k - yl * g.w_pad;
     y = tau * g.r_o + yl;
-    if (y >= e.h_pad) return 0;
+    if (y >= e.h_pad) return kNone;
   }
-  if (y < e.pad || x < e.pad) return 0;
+  if (y < e.pad || x < e.pad) return kNone;
   const uint32_t ya = y - e.pad, xa = x - e.pad;
-  if (ya >= e.h_enc || xa >= e.w_enc) return 0;
-  return act[((b * g.c_in + j) * e.h + (size_t)ya * e.sub) * e.w + (size_t)xa * e.sub];
+  if (ya >= e.h_enc || xa >= e.w_enc) return kNone;
+  return ((b * g.c_in + j) * e.h + (size_t)ya * e.sub) * e.w + (size_t)xa * e.sub;
+}
+
+// Delta_l * (m mod q_l) for the centred plaintext value of m in [0, t)
+// (m <= t/2: m itself; else m - t + q, which t < 2 q_l keeps in [0, q_l)).
+__device__ __forceinline__ uint32_t delta_times(uint32_t m, const LimbConsts &c, uint32_t l) {
+  const uint32_t q = c.q[l];
+  const uint32_t mc = m > c.t / 2 ? m - c.t + q : m;
+  return csub(shoup_lazy(mc, c.delta[l], c.delta_p[l], q), q);
 }
 
 // Grid: x = input ciphertext (b * G + gi), y = chunk of 1024 coefficients;
@@ -51,21 +63,78 @@ __global__ __launch_bounds__(256) void k_encrypt_online(const uint32_t *__restri
   const uint32_t ctn = blockIdx.x;
   const uint32_t b = ctn / g.G, gi = ctn - b * g.G;
   const uint32_t k0 = blockIdx.y * 1024 + threadIdx.x;
-  const uint32_t half = c.t / 2;
   uint32_t m[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) m[j] = encoded_value(act, g, e, b, gi, k0 + 256 * j);
+  for (int j = 0; j < 4; ++j) {
+    const size_t idx = encoded_index(g, e, b, gi, k0 + 256 * j);
+    m[j] = idx == kNone ? 0u : act[idx];
+  }
   const size_t base = (size_t)ctn * 2 * g.L * g.N + k0;
   for (uint32_t l = 0; l < g.L; ++l) {
     const uint32_t q = c.q[l];
     const size_t w0 = base + (size_t)l * g.N, w1 = w0 + (size_t)g.L * g.N;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      // m <= t/2: m itself; else m - t + q (t < 2 q_l keeps both in [0, q_l))
-      const uint32_t mc = m[j] > half ? m[j] - c.t + q : m[j];
-      const uint32_t add = csub(shoup_lazy(mc, c.delta[l], c.delta_p[l], q), q);
-      ct[w0 + 256 * j] = csub(ct0[w0 + 256 * j] + add, q);
+      ct[w0 + 256 * j] = csub(ct0[w0 + 256 * j] + delta_times(m[j], c, l), q);
       if (copy_c1) ct[w1 + 256 * j] = ct0[w1 + 256 * j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- x^2 + x protocol, server steps
+// out[c][l][k] = centred(mult * p[c][k] mod t) mod q_l (p in [0, t), mult 1 or 2).
+// Grid: x = plaintext, y = chunk of 256 coefficients.
+__global__ __launch_bounds__(256) void k_lift_plain(const uint32_t *__restrict__ p, uint32_t *__restrict__ out,
+                                                     uint32_t N, uint32_t mult, LimbConsts c) {
+  const size_t cn = blockIdx.x;
+  const uint32_t k = blockIdx.y * 256 + threadIdx.x;
+  uint32_t v = p[cn * N + k];
+  if (mult == 2) v = csub(2 * v, c.t);
+  for (uint32_t l = 0; l < c.L; ++l)
+    out[(cn * c.L + l) * N + k] = v > c.t / 2 ? v - c.t + c.q[l] : v;
+}
+
+// c0 of ct[c] += Delta_l (centred p[c][k] mod q_l): plaintext addition.
+__global__ __launch_bounds__(256) void k_add_plain(uint32_t *__restrict__ ct, const uint32_t *__restrict__ p,
+                                                    uint32_t N, LimbConsts c) {
+  const size_t cn = blockIdx.x;
+  const uint32_t k = blockIdx.y * 256 + threadIdx.x;
+  const uint32_t m = p[cn * N + k];
+  for (uint32_t l = 0; l < c.L; ++l) {
+    const size_t w0 = ((cn * 2) * c.L + l) * N + k;
+    ct[w0] = csub(ct[w0] + delta_times(m, c, l), c.q[l]);
+  }
+}
+
+// ct = ct_x - ct_y + Delta * enc(r^2 - r + v mod t), direct encoding of the
+// layer's input. Grid as k_encrypt_online.
+__global__ __launch_bounds__(256) void k_act_combine(const uint32_t *ct_x, const uint32_t *ct_y,
+                                                      const uint32_t *__restrict__ r, const uint32_t *__restrict__ v,
+                                                      uint32_t *ct, ConvGeom g, EncGeom e, LimbConsts c) {
+  const uint32_t ctn = blockIdx.x;
+  const uint32_t b = ctn / g.G, gi = ctn - b * g.G;
+  const uint32_t k0 = blockIdx.y * 1024 + threadIdx.x;
+  uint32_t w[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const size_t idx = encoded_index(g, e, b, gi, k0 + 256 * j);
+    if (idx == kNone) {
+      w[j] = 0;
+    } else {
+      const uint64_t rr = r[idx];
+      w[j] = (uint32_t)((rr * (rr ? rr - 1 : 0) + v[idx]) % c.t);
+    }
+  }
+  const size_t base = (size_t)ctn * 2 * g.L * g.N + k0;
+  for (uint32_t l = 0; l < g.L; ++l) {
+    const uint32_t q = c.q[l];
+    const size_t w0 = base + (size_t)l * g.N, w1 = w0 + (size_t)g.L * g.N;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t d0 = csub(ct_x[w0 + 256 * j] + q - ct_y[w0 + 256 * j], q);
+      const uint32_t d1 = csub(ct_x[w1 + 256 * j] + q - ct_y[w1 + 256 * j], q);
+      ct[w0 + 256 * j] = csub(d0 + delta_times(w[j], c, l), q);
+      ct[w1 + 256 * j] = d1;
     }
   }
 }
@@ -182,6 +251,30 @@ hipError_t launch_encrypt_online(const ConvGeom &g, const EncGeom &e, const uint
   if (n_ct >= (1ull << 31) || g.N % 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_encrypt_online, dim3((uint32_t)n_ct, g.N / 1024), dim3(256), 0, st, act, ct0, ct, g, e,
                      copy_c1 ? 1u : 0u, c);
+  return hipGetLastError();
+}
+hipError_t launch_lift_plain(const uint32_t *p, uint32_t *out, size_t n, uint32_t N, uint32_t mult,
+                             const LimbConsts &c, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (n >= (1ull << 31) || N % 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lift_plain, dim3((uint32_t)n, N / 256), dim3(256), 0, st, p, out, N, mult, c);
+  return hipGetLastError();
+}
+hipError_t launch_add_plain(uint32_t *ct, const uint32_t *p, size_t n, uint32_t N, const LimbConsts &c,
+                            hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (n >= (1ull << 31) || N % 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_add_plain, dim3((uint32_t)n, N / 256), dim3(256), 0, st, ct, p, N, c);
+  return hipGetLastError();
+}
+hipError_t launch_act_combine(const ConvGeom &g, const EncGeom &e, const uint32_t *ct_x, const uint32_t *ct_y,
+                              const uint32_t *r, const uint32_t *v, uint32_t *ct, uint32_t B, const LimbConsts &c,
+                              hipStream_t st) {
+  const uint64_t n_ct = (uint64_t)B * g.G;
+  if (n_ct == 0) return hipSuccess;
+  if (n_ct >= (1ull << 31) || g.N % 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_act_combine, dim3((uint32_t)n_ct, g.N / 1024), dim3(256), 0, st, ct_x, ct_y, r, v, ct, g, e,
+                     c);
   return hipGetLastError();
 }
 hipError_t launch_encrypt_zero(const uint32_t *a, const uint32_t *as, const int32_t *e, uint32_t *ct, size_t n_ct,

@@ -100,6 +100,42 @@ uint32_t bitrev(uint32_t x, int bits) {
   return r;
 }
 
+// Transform tables of one prime q for ring degree N: fw[i] = {psi^brv(i), Shoup},
+// iw[i] = {psi^-brv(i), Shoup}, with psi the first x^((q-1)/2N), x = 2, 3, ...,
+// whose N-th power is -1; fills slot l of k with q and the inverse transform's
+// constants. Returns psi, or 0 when q has no primitive 2N-th root.
+uint32_t limb_tables(uint32_t q, uint32_t N, uint32_t logn, uint2 *fw, uint2 *iw, LimbConsts &k, uint32_t l) {
+  const uint64_t two_n = 2ull * N;
+  uint64_t psi = 0;
+  for (uint64_t x = 2; x < q; ++x) {
+    const uint64_t cand = powmod64(x, (q - 1) / two_n, q);
+    if (powmod64(cand, N, q) == q - 1) {
+      psi = cand;
+      break;
+    }
+  }
+  if (!psi) return 0;
+  const uint64_t ipsi = powmod64(psi, q - 2, q);
+  for (uint32_t i = 0; i < N; ++i) {
+    const uint32_t e = bitrev(i, (int)logn);
+    const uint32_t a = (uint32_t)powmod64(psi, e, q);
+    const uint32_t b = (uint32_t)powmod64(ipsi, e, q);
+    fw[i] = make_uint2(a, shoup_of(a, q));
+    iw[i] = make_uint2(b, shoup_of(b, q));
+  }
+  const uint32_t ninv = (uint32_t)powmod64(N, q - 2, q);
+  const uint32_t ninvw = (uint32_t)mulmod64(ninv, iw[1].x, q);
+  k.q[l] = q;
+  k.ninv[l] = ninv;
+  k.ninv_p[l] = shoup_of(ninv, q);
+  k.ninvw[l] = ninvw;
+  k.ninvw_p[l] = shoup_of(ninvw, q);
+  k.r2[l] = (uint32_t)((1ull << 32) % q);
+  k.r2_p[l] = shoup_of(k.r2[l], q);
+  k.one_p[l] = shoup_of(1, q);
+  return (uint32_t)psi;
+}
+
 }  // namespace
 
 constexpr int kChains = 4;  // concurrent chains of layers in a batch graph
@@ -405,40 +441,11 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
   for (uint32_t l = 0; l < L; ++l) {
     const uint32_t q = c->q[l];
     c->delta[l] = (uint32_t)(D % q);
-    // psi: a primitive 2N-th root of unity (psi^N = -1), smallest base first
-    uint64_t psi = 0;
-    for (uint64_t x = 2; x < q; ++x) {
-      const uint64_t cand = powmod64(x, (q - 1) / two_n, q);
-      if (powmod64(cand, N, q) == q - 1) {
-        psi = cand;
-        break;
-      }
-    }
-    if (!psi) {
+    c->psi[l] = limb_tables(q, N, c->logn, tw.data() + (size_t)l * N, tw.data() + ((size_t)L + l) * N, k, l);
+    if (!c->psi[l]) {
       delete c;
       return fail(HC_EINVAL, "no primitive 2N-th root of unity");
     }
-    c->psi[l] = (uint32_t)psi;
-    const uint64_t ipsi = powmod64(psi, q - 2, q);
-    uint2 *fw = tw.data() + (size_t)l * N;
-    uint2 *iw = tw.data() + ((size_t)L + l) * N;
-    for (uint32_t i = 0; i < N; ++i) {
-      const uint32_t e = bitrev(i, (int)c->logn);
-      const uint32_t a = (uint32_t)powmod64(psi, e, q);
-      const uint32_t b = (uint32_t)powmod64(ipsi, e, q);
-      fw[i] = make_uint2(a, shoup_of(a, q));
-      iw[i] = make_uint2(b, shoup_of(b, q));
-    }
-    const uint32_t ninv = (uint32_t)powmod64(N, q - 2, q);
-    const uint32_t ninvw = (uint32_t)mulmod64(ninv, iw[1].x, q);
-    k.q[l] = q;
-    k.ninv[l] = ninv;
-    k.ninv_p[l] = shoup_of(ninv, q);
-    k.ninvw[l] = ninvw;
-    k.ninvw_p[l] = shoup_of(ninvw, q);
-    k.r2[l] = (uint32_t)((1ull << 32) % q);
-    k.r2_p[l] = shoup_of(k.r2[l], q);
-    k.one_p[l] = shoup_of(1, q);
     k.delta[l] = c->delta[l];
     k.delta_p[l] = shoup_of(c->delta[l], q);
     // terms that fit between folds: fold leaves acc < 2^32 * r2 + 2^32; each
@@ -470,6 +477,25 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
   }
   c->tw.fwd = c->d_tw;
   c->tw.inv = c->d_tw + (size_t)L * N;
+  // batch (slot) encoding: transforms modulo t itself when t is a prime = 1 mod 2N
+  if (t < (1ull << 30) && t % two_n == 1 && is_prime(t)) {
+    std::vector<uint2> twt((size_t)2 * N);
+    LimbConsts &kt = c->consts_t;
+    std::memset(&kt, 0, sizeof(kt));
+    kt.L = 1;
+    kt.t = (uint32_t)t;
+    if (limb_tables((uint32_t)t, N, c->logn, twt.data(), twt.data() + N, kt, 0)) {
+      e = hipMalloc((void **)&c->d_tw_t, twt.size() * sizeof(uint2));
+      if (e == hipSuccess) e = hipMemcpy(c->d_tw_t, twt.data(), twt.size() * sizeof(uint2), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        hc_ctx_destroy(c);
+        return hip_fail(e, "batch-encoding twiddles");
+      }
+      c->tw_t.fwd = c->d_tw_t;
+      c->tw_t.inv = c->d_tw_t + N;
+      c->batch_ok = true;
+    }
+  }
   *out = c;
   return HC_OK;
 }
@@ -487,6 +513,7 @@ void hc_ctx_destroy(hc_ctx *c) {
   if (!c) return;
   DeviceGuard dg(c->device);
   if (c->d_tw) (void)hipFree(c->d_tw);
+  if (c->d_tw_t) (void)hipFree(c->d_tw_t);
   delete c;
 }
 

@@ -82,11 +82,14 @@ bool mac_offsets_fit(const ConvGeom &g, const MacShape &m);
 hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                           const LimbConsts &c, const Twiddles &tw, hipStream_t st, const ImgPtrs *tab = nullptr,
                           uint32_t ppi = 0);
-// out[p] = in[p] * s_(p mod L) mod (x^N + 1, q_(p mod L)) over [P][N], where
-// mul [L][N] holds NTT(s_l) as launch_ntt_fwd writes it (canonical, 16-byte
-// aligned): forward NTT, product and inverse NTT in one kernel (in place allowed).
+// out[p] = in[p] * s mod (x^N + 1, q_(p mod L)) over [P][N], where s is row
+// p / mul_div (row 0 for all p when mul_div is 0; mul_div a multiple of L) of
+// mul [..][L][N], which holds NTT(s) per limb as launch_ntt_fwd writes it
+// (canonical, 16-byte aligned): forward NTT, product and inverse NTT in one
+// kernel (in place allowed).
 hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
-                           const uint32_t *mul, const LimbConsts &c, const Twiddles &tw, hipStream_t st);
+                           const uint32_t *mul, uint32_t mul_div, const LimbConsts &c, const Twiddles &tw,
+                           hipStream_t st);
 // Full mode: in [P][N] -> out [P][N] (in place allowed).
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st);
@@ -144,6 +147,18 @@ hipError_t launch_encrypt_online(const ConvGeom &g, const EncGeom &e, const uint
 // and e [n_ct][N] (signed, |e| < q_l).
 hipError_t launch_encrypt_zero(const uint32_t *a, const uint32_t *as, const int32_t *e, uint32_t *ct, size_t n_ct,
                                uint32_t N, const LimbConsts &c, hipStream_t st);
+// Batch encoding helpers (x^2 + x protocol). lift: out[c][l][k] = centred(mult * p[c][k] mod t)
+// mod q_l for plaintexts p [n][N] in [0, t) (mult 1 or 2). add_plain: c0 of ct [n][2][L][N]
+// += Delta_l (centred p[c] mod q_l).
+hipError_t launch_lift_plain(const uint32_t *p, uint32_t *out, size_t n, uint32_t N, uint32_t mult,
+                             const LimbConsts &c, hipStream_t st);
+hipError_t launch_add_plain(uint32_t *ct, const uint32_t *p, size_t n, uint32_t N, const LimbConsts &c,
+                            hipStream_t st);
+// Server step 2 of the x^2 + x protocol: ct = ct_x - ct_y + Delta * enc(r^2 - r + v mod t)
+// under the layer's direct encoding, r and v [B][c_in][h][w] in [0, t) (ct may be ct_x or ct_y).
+hipError_t launch_act_combine(const ConvGeom &g, const EncGeom &e, const uint32_t *ct_x, const uint32_t *ct_y,
+                              const uint32_t *r, const uint32_t *v, uint32_t *ct, uint32_t B, const LimbConsts &c,
+                              hipStream_t st);
 // c1[c][l][:] = ct[c][1][l][:] for n_ct ciphertexts [n_ct][2][L][N].
 hipError_t launch_gather_c1(const uint32_t *ct, uint32_t *c1, size_t n_ct, uint32_t L, uint32_t N, hipStream_t st);
 // m[b][i][oy][ox] = decode(c0_ext[b][i][:][oy][ox] + c1s[b][(i, tau)][:][e]).

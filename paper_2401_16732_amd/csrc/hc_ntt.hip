@@ -73,14 +73,16 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
 }
 
 // Negacyclic product of each polynomial of in [P][N] (limb = poly mod L) with
-// the limb's polynomial whose NTT is mul [L][N] (bit-reversed evaluation order,
-// canonical, 16-byte aligned), in one pass over HBM: the forward transform,
+// the polynomial whose NTT is row poly / mul_div of mul [..][L][N] at the same
+// limb (row 0 for every polynomial when mul_div is 0; bit-reversed evaluation
+// order, canonical, 16-byte aligned), in one pass over HBM: the forward transform,
 // the pointwise product as the forward's last pass leaves its registers, one
 // LDS exchange into the inverse transform's first-pass layout, the inverse
 // transform, and a canonical store (in place allowed).
 template <int LOGN, int ELOG>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ring_mul(const uint32_t *in, uint32_t *out,
-                                                                  const uint32_t *mul, LimbConsts c, Twiddles tws) {
+                                                                  const uint32_t *mul, uint32_t mul_div,
+                                                                  LimbConsts c, Twiddles tws) {
   constexpr int N = 1 << LOGN, E = 1 << ELOG, NP = n_pass(LOGN, ELOG);
   __shared__ uint32_t lds[N + N / 32];
   const uint32_t tid = threadIdx.x;
@@ -100,7 +102,8 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ring_mul(const uint32_t 
   constexpr int EPL = pass_bits(LOGN, ELOG, NP - 1);
   static_assert(pass_lo_fwd(LOGN, ELOG, NP - 1) == 0 && EPL >= 2, "last forward pass covers the low bits");
   const uint32_t q2 = 2 * q;
-  const uint32_t *ml = mul + (size_t)l * N + gidx<LOGN, ELOG, 0, EPL>(tid, 0);
+  const size_t mrow = mul_div ? poly / mul_div : 0;
+  const uint32_t *ml = mul + (mrow * c.L + l) * N + gidx<LOGN, ELOG, 0, EPL>(tid, 0);
 #pragma unroll
   for (int u = 0; u < E; u += 4) {
     const uint4 s4 = *reinterpret_cast<const uint4 *>(ml + gidx<LOGN, ELOG, 0, EPL>(0, u));
@@ -232,11 +235,11 @@ static hipError_t fwd_t(const uint32_t *in, uint32_t *out, size_t np, const Limb
   return hipGetLastError();
 }
 template <int LOGN, int ELOG>
-static hipError_t ring_mul_t(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, const LimbConsts &c,
-                             const Twiddles &tw, hipStream_t st) {
+static hipError_t ring_mul_t(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, uint32_t mul_div,
+                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
   if (np == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_ring_mul<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, mul, c,
-                     tw);
+  hipLaunchKernelGGL((k_ring_mul<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, mul,
+                     mul_div, c, tw);
   return hipGetLastError();
 }
 template <int LOGN, int ELOG>
@@ -277,8 +280,10 @@ hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint
   HC_NTT_DISPATCH(fwd_t, in, out, np, c, tw, t, ppi, st)
 }
 hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
-                           const uint32_t *mul, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
-  HC_NTT_DISPATCH(ring_mul_t, in, out, np, mul, c, tw, st)
+                           const uint32_t *mul, uint32_t mul_div, const LimbConsts &c, const Twiddles &tw,
+                           hipStream_t st) {
+  if (mul_div && mul_div % c.L) return hipErrorInvalidValue;
+  HC_NTT_DISPATCH(ring_mul_t, in, out, np, mul, mul_div, c, tw, st)
 }
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {

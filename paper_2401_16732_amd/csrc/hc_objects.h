@@ -20,6 +20,11 @@ struct hc_ctx {
   hc_tuning tune{};        // 0 fields = defaults
   bool check_inputs = false;  // HC_CHECK_INPUTS=1 at creation: conv entry points validate their inputs
   hc::DecodeConsts dec{};     // exact decryption rounding (client side)
+  // batch (slot) encoding, present when t is a prime = 1 mod 2N: transforms modulo t
+  bool batch_ok = false;
+  hc::LimbConsts consts_t{};  // L = 1, q[0] = t
+  uint2 *d_tw_t = nullptr;    // [2][N]
+  hc::Twiddles tw_t{};
 };
 
 struct hc_layer {

@@ -30,7 +30,8 @@ SYMBOLS = [
     "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
     "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
     "hc_check_residues", "hc_encrypt_online", "hc_decrypt_workspace_size", "hc_decrypt_extracted", "hc_decrypt",
-    "hc_encrypt_zero",
+    "hc_encrypt_zero", "hc_batch_encode", "hc_batch_decode", "hc_encrypt_plain", "hc_act_workspace_size",
+    "hc_act_pmult", "hc_act_combine",
 ]
 
 
@@ -98,6 +99,12 @@ def load(path: str = LIB_PATH):
         "hc_decrypt_extracted": (I, [P, P, P, P, P, u32, P, sz, P]),
         "hc_decrypt": (I, [P, P, P, P, u32, P, sz, P]),
         "hc_encrypt_zero": (I, [P, P, P, P, P, u32, P, sz, P]),
+        "hc_batch_encode": (I, [P, P, P, u32, P]),
+        "hc_batch_decode": (I, [P, P, P, u32, P]),
+        "hc_encrypt_plain": (I, [P, P, P, P, u32, P]),
+        "hc_act_workspace_size": (I, [P, u32, P]),
+        "hc_act_pmult": (I, [P, P, P, P, P, u32, P, sz, P]),
+        "hc_act_combine": (I, [P, P, P, P, P, P, u32, P]),
         "hc_sync": (I, [P]),
         "hc_status_string": (ctypes.c_char_p, [I]),
         "hc_last_error": (ctypes.c_char_p, []),
@@ -232,6 +239,51 @@ class Context:
                                     _dptr(ws, "ws", self.device), ws.numel() * 4, _stream(stream)),
                "hc_encrypt_zero")
 
+    def _rows(self, t, name, per_row):
+        n = t.numel() // per_row
+        if n * per_row != t.numel():
+            raise ValueError(f"{name} must hold a whole number of {per_row}-word rows")
+        return n
+
+    def batch_encode(self, z, p, stream=None):
+        """p [n][N] <- plaintext polynomials whose slots are z [n][N] (t prime, = 1 mod 2N)."""
+        n = self._rows(z, "z", self.N)
+        if p.numel() < z.numel():
+            raise ValueError("p must hold n * N words")
+        _check(_lib.hc_batch_encode(self.h, _dptr(z, "z", self.device), _dptr(p, "p", self.device), n,
+                                    _stream(stream)), "hc_batch_encode")
+
+    def batch_decode(self, p, z, stream=None):
+        n = self._rows(p, "p", self.N)
+        if z.numel() < p.numel():
+            raise ValueError("z must hold n * N words")
+        _check(_lib.hc_batch_decode(self.h, _dptr(p, "p", self.device), _dptr(z, "z", self.device), n,
+                                    _stream(stream)), "hc_batch_decode")
+
+    def encrypt_plain(self, p, ct_zero, ct, stream=None):
+        """ct [n][2][L][N] <- ct_zero + Delta * p for plaintext polynomials p [n][N]."""
+        n = self._rows(p, "p", self.N)
+        if ct_zero.numel() < 2 * n * self.L * self.N or ct.numel() < 2 * n * self.L * self.N:
+            raise ValueError("ct_zero and ct must hold n * 2 * L * N words")
+        _check(_lib.hc_encrypt_plain(self.h, _dptr(p, "p", self.device), _dptr(ct_zero, "ct_zero", self.device),
+                                     _dptr(ct, "ct", self.device), n, _stream(stream)), "hc_encrypt_plain")
+
+    def act_workspace_words(self, n_ct: int) -> int:
+        b = ctypes.c_size_t()
+        _check(_lib.hc_act_workspace_size(self.h, n_ct, ctypes.byref(b)), "hc_act_workspace_size")
+        return (b.value + 3) // 4
+
+    def act_pmult(self, ct_batch, r, v, ct_out, ws, stream=None):
+        """Server step 1 of the x^2 + x protocol: ct_out <- PMult(ct_batch, encode(2r)) + encode(v)."""
+        n = self._rows(ct_batch, "ct_batch", 2 * self.L * self.N)
+        if r.numel() != n * self.N or v.numel() != n * self.N or ct_out.numel() < ct_batch.numel():
+            raise ValueError("r and v must hold n_ct * N slots, ct_out n_ct * 2 * L * N words")
+        if ws.numel() < self.act_workspace_words(n):
+            raise ValueError("ws too small (act_workspace_words)")
+        _check(_lib.hc_act_pmult(self.h, _dptr(ct_batch, "ct_batch", self.device), _dptr(r, "r", self.device),
+                                 _dptr(v, "v", self.device), _dptr(ct_out, "ct_out", self.device), n,
+                                 _dptr(ws, "ws", self.device), ws.numel() * 4, _stream(stream)), "hc_act_pmult")
+
     def decrypt(self, ct, sk, m, ws, stream=None):
         """m [count][N] <- decryption of ct [count][2][L][N] under the key
         residues sk [L][N] (all device int32 tensors); ws: (count + 1) L N words."""
@@ -358,6 +410,18 @@ class Layer:
         _check(_lib.hc_decrypt_extracted(self.h, _dptr(c0_ext, "c0_ext", d), _dptr(c1_out, "c1_out", d),
                                          _dptr(sk, "sk", d), _dptr(m, "m", d), B, _dptr(ws, "ws", d),
                                          ws.numel() * 4, _stream(stream)), "hc_decrypt_extracted")
+
+    def act_combine(self, ct_x, ct_y, r, v, ct_out, B: int, stream=None):
+        """Server step 2 of the x^2 + x protocol for this layer's input:
+        ct_out <- ct_x - ct_y + Delta * enc(r^2 - r + v)."""
+        d = self.ctx.device
+        for t_, name in ((ct_x, "ct_x"), (ct_y, "ct_y"), (ct_out, "ct_out")):
+            self._need(t_, self.in_shape(B), name)
+        self._need(r, self.act_shape(B), "r")
+        self._need(v, self.act_shape(B), "v")
+        _check(_lib.hc_act_combine(self.h, _dptr(ct_x, "ct_x", d), _dptr(ct_y, "ct_y", d), _dptr(r, "r", d),
+                                   _dptr(v, "v", d), _dptr(ct_out, "ct_out", d), B, _stream(stream)),
+               "hc_act_combine")
 
     def tuning(self):
         """(batch size, (fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups, mac_depth,
