@@ -20,6 +20,10 @@ masks) are resident in HBM before the timed region. Reported:
                        online encryption (Algorithm 2) of every layer's input
                        against HBM bandwidth, and decryption of every layer's
                        extracted outputs (its NTTs against the butterfly peak)
+  protocol             the x^2 + x protocol's server steps on every layer's
+                       activation map, timed apart: PMult of the batch-encoded
+                       a + r by 2r plus v (butterflies), and the combination
+                       into [[a^2 + a]] (HBM bytes)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -55,7 +59,10 @@ def parse():
     ap.add_argument("--cpu-fraction", type=float, default=1.0 / 16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-client", action="store_true", help="skip the client-side (encrypt/decrypt) timing")
+    ap.add_argument("--no-client", action="store_true",
+                    help="skip the client-side (encrypt/decrypt) and activation-protocol timing")
+    ap.add_argument("--t-batch", type=int, default=786433,
+                    help="prime plaintext modulus = 1 mod 2N for the protocol's batch-encoded step")
     ap.add_argument("--seed", type=int, default=50)
     ap.add_argument("--stage-passes", type=int, default=3, help="eager passes timed per kernel for the roofline")
     ap.add_argument("--copy-gib", type=float, default=4.0, help="size of the HBM stream-copy calibration")
@@ -183,7 +190,7 @@ def client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, passes=3, grap
     # decryption: forward and inverse NTT of every output ciphertext's c1
     dec_bfly = sum(2 * B * ly.layout.out_cts * L * (N // 2) * int(math.log2(N)) for ly in layers)
     if not graphs:
-        return None
+        return None, acts
     enc_s, dec_s = res["encrypt_online"] * 1e-3, res["decrypt_extracted"] * 1e-3
     return {
         "encrypt_online": {"ms_per_image": round(res["encrypt_online"] / B, 4), "launches": len(layers),
@@ -192,6 +199,76 @@ def client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, passes=3, grap
         "decrypt_extracted": {"ms_per_image": round(res["decrypt_extracted"] / B, 4), "launches": 4 * len(layers),
                               "butterflies": dec_bfly, "tbutterfly_per_s": round(dec_bfly / dec_s / 1e12, 4),
                               "alu_frac": round(dec_bfly / dec_s / BFLY_PEAK, 4)},
+    }, acts
+
+
+def protocol_pass(torch, dev, hconv, ctx, layers, ct_in, acts, B, tg, t_batch, passes=3, graphs=True):
+    """Times the server steps of the x^2 + x protocol over every layer's
+    activation map for B images. Step 1 (PMult of the batch-encoded a + r by
+    2r, plus v) needs a prime plaintext modulus = 1 mod 2N: it runs on a second
+    context with t = t_batch and the same primes, on B c_out ho wo slots per
+    layer packed N to a ciphertext. Step 2 (the combination) runs on each
+    layer's own input ciphertexts (x = ct_in, in place; y a buffer of its own)
+    with that layer's activation-shaped r and v."""
+    from paper_2401_16732_amd import workloads as W
+    N, L = ctx.N, ctx.L
+    cb = hconv.Context(N, L, t_batch, primes=ctx.primes)
+    n_ct = [-(-(B * ly.shape[1] * ly.layout.ho * ly.layout.wo) // N) for ly in layers]
+    mx = max(n_ct)
+    ct_b = W.gen_ct_limbs_torch(tg, (mx, 2), ctx.primes, N, dev)
+    r = torch.randint(0, t_batch, (mx, N), generator=tg, device=dev, dtype=torch.int32)
+    v = torch.randint(0, t_batch, (mx, N), generator=tg, device=dev, dtype=torch.int32)
+    out = torch.empty_like(ct_b)
+    ws = torch.empty((cb.act_workspace_words(mx),), dtype=torch.int32, device=dev)
+
+    def step1():
+        for n in n_ct:
+            cb.act_pmult(ct_b[:n], r[:n], v[:n], out[:n], ws)
+
+    ybuf = torch.empty((max(t_.numel() for t_ in ct_in),), dtype=torch.int32, device=dev)
+    ys = [ybuf[:t_.numel()].view(t_.shape) for t_ in ct_in]
+    for y_, x_ in zip(ys, ct_in):
+        y_.copy_(x_)  # canonical residues, at addresses of their own
+
+    def step2():
+        for k, ly in enumerate(layers):
+            ly.act_combine(ct_in[k], ys[k], acts[k], acts[k], ct_in[k], B)
+
+    res = {}
+    for name, fn in (("act_pmult", step1), ("act_combine", step2)):
+        fn()
+        torch.cuda.synchronize()
+        if not graphs:
+            continue
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            fn()
+        graph.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(passes):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / passes
+        del graph
+    cb.close()
+    if not graphs:
+        return None
+    # step 1 per ciphertext: PMult of 2L polynomials (two transforms each), batch
+    # encoding of r and v (one inverse transform mod t each), L forward transforms of 2r
+    per_ct = (4 * L + 2 + L) * (N // 2) * int(math.log2(N))
+    bfly = sum(n_ct) * per_ct
+    # step 2: read x and y, write the result (2 L N words each per ciphertext), read r and v
+    cbytes = sum(B * ly.layout.in_cts * 2 * L * N * 4 * 3 + 2 * math.prod(ly.act_shape(B)) * 4 for ly in layers)
+    s1, s2 = res["act_pmult"] * 1e-3, res["act_combine"] * 1e-3
+    return {
+        "t_batch": t_batch, "ciphertexts_step1": sum(n_ct),
+        "act_pmult": {"ms_per_image": round(res["act_pmult"] / B, 4), "butterflies": bfly,
+                      "tbutterfly_per_s": round(bfly / s1 / 1e12, 4), "alu_frac": round(bfly / s1 / BFLY_PEAK, 4)},
+        "act_combine": {"ms_per_image": round(res["act_combine"] / B, 4), "algorithmic_bytes": cbytes,
+                        "achieved_GBps": round(cbytes / s2 / 1e9, 1), "hbm_frac": round(cbytes / s2 / HBM_PEAK, 4)},
     }
 
 
@@ -326,9 +403,17 @@ def main():
         plain_ms = p0.elapsed_time(p1) / a.plain_images
         print(f"[bench] plain: {plain_ms:.3f} ms/image", file=sys.stderr, flush=True)
 
-    client = None
+    client = protocol = None
     if not a.no_client:
-        client = client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, graphs=a.steps > 0)
+        client, acts = client_pass(torch, dev, ctx, layers, ct_in, c0, c1, B, t, tg, graphs=a.steps > 0)
+        protocol = protocol_pass(torch, dev, hconv, ctx, layers, ct_in, acts, B, tg, a.t_batch,
+                                 graphs=a.steps > 0)
+        del acts
+    if protocol is not None:
+        print(f"[bench] protocol: step 1 {protocol['act_pmult']['ms_per_image']:.3f} ms/image "
+              f"({protocol['act_pmult']['tbutterfly_per_s']} T butterflies/s), step 2 "
+              f"{protocol['act_combine']['ms_per_image']:.3f} ms/image "
+              f"({protocol['act_combine']['achieved_GBps']} GB/s)", file=sys.stderr, flush=True)
     if client is not None:
         print(f"[bench] client: encrypt {client['encrypt_online']['ms_per_image']:.3f} ms/image "
               f"({client['encrypt_online']['achieved_GBps']} GB/s), decrypt "
@@ -400,6 +485,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "client": client,
+        "protocol": protocol,
     }
     print(json.dumps(out), flush=True)
     return 0
