@@ -225,10 +225,10 @@ def protocol_pass(torch, dev, hconv, ctx, layers, ct_in, acts, B, tg, t_batch, p
         for n in n_ct:
             cb.act_pmult(ct_b[:n], r[:n], v[:n], out[:n], ws)
 
-    ybuf = torch.empty((max(t_.numel() for t_ in ct_in),), dtype=torch.int32, device=dev)
+    # y: canonical residues (below every prime) at addresses of their own
+    ybuf = torch.randint(0, min(ctx.primes), (max(t_.numel() for t_ in ct_in),), generator=tg, device=dev,
+                         dtype=torch.int32)
     ys = [ybuf[:t_.numel()].view(t_.shape) for t_ in ct_in]
-    for y_, x_ in zip(ys, ct_in):
-        y_.copy_(x_)  # canonical residues, at addresses of their own
 
     def step2():
         for k, ly in enumerate(layers):
