@@ -159,3 +159,27 @@ def test_protocol_resnet50_layer_full_size(hc):
     c.decrypt(ct_x, dev(sk), m, zeros(((P.G + 1) * L * N,)))
     aa = a[0].astype(np.int64)
     assert (host(m) == layout.encode_input((aa * aa + aa) % t, P) % t).all()
+
+
+def test_largest_ring_batch_encoding_properties(hc):
+    """N = 16384 with t = 65537 (prime, 1 mod 2^15): decode(encode(z)) = z, and
+    the slot-wise product equals the library's ring product modulo t (PMult's
+    premise), on every slot. Properties that hold at any size; the oracle's
+    O(N^2) interpolation is pinned at the smaller sizes."""
+    N, L, t = 16384, 2, 65537
+    c = hc.Context(N, L, t)
+    ct_ = hc.Context(N, 1, t, primes=[t])   # the ring Z_t[x]/(x^N + 1) as a one-limb context
+    g = W.rng(16385)
+    z1 = g.integers(0, t, size=(1, N)).astype(np.uint32)
+    z2 = g.integers(0, t, size=(1, N)).astype(np.uint32)
+    p1, p2 = zeros((1, N)), zeros((1, N))
+    c.batch_encode(dev(z1), p1)
+    c.batch_encode(dev(z2), p2)
+    back = zeros((1, N))
+    c.batch_decode(p1, back)
+    assert (host(back) == z1).all()
+    prod = zeros((1, N))
+    ct_.poly_mul(p1, p2, prod, zeros((2 * N,)))
+    zz = zeros((1, N))
+    c.batch_decode(prod, zz)
+    assert (host(zz).astype(np.int64) == (z1.astype(np.int64) * z2) % t).all()

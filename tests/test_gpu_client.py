@@ -248,3 +248,32 @@ def test_client_server_client_loop_resnet50_layer(hc):
     for b in range(B):
         z = conv.plain_conv_mod_t(act[b], f, 1, t)
         assert (got[b] == (z + r[b]) % t).all(), b
+
+
+def test_largest_ring_encrypt_decrypt_round_trip(hc):
+    """N = 16384, 4 primes (q < 2^120, the exact rounding's largest case):
+    encryptions of zero, online encryption of a 7x7/2 stem input (row tiles)
+    and decryption of every coefficient give back the direct-encoded input;
+    one ciphertext's decryption is also compared with the oracle's."""
+    N, L, t, B = 16384, 4, 2 ** 24, 1
+    shape = (3, 8, 224, 224, 7, 2)
+    c = hc.Context(N, L, t)
+    P = layout.plan(N, *shape)
+    assert P.tiled
+    g = W.rng(16384)
+    ly = hc.Layer(c, *shape, W.gen_filters(g, W.ConvSpec(*shape)))
+    s = bfv.sample_secret(g, N)
+    sk = dev(_sk_residues(s, c.primes))
+    e = np.stack([bfv.sample_error(g, N) for _ in range(P.G)])
+    ct = zeros(ly.in_shape(B))
+    c.encrypt_zero(dev(W.gen_ct_limbs(g, (P.G,), c.primes, N)), sk, _dev_i32(e), ct,
+                   zeros(((P.G + 1) * L * N,)))
+    act = W.gen_mask(g, ly.act_shape(B), t)
+    ly.encrypt_online(dev(act), ct, ct, B)
+    m = zeros((P.G, N))
+    print(f"N=16384 round trip, G={P.G}", flush=True)
+    c.decrypt(ct, sk, m, zeros(((P.G + 1) * L * N,)))
+    got = host(m)
+    assert (got == layout.encode_input(act[0], P) % t).all()
+    one = host(ct)[0, P.G // 2]
+    assert (got[P.G // 2] == np.array(bfv.decrypt(one, s, c.primes, t), dtype=np.uint32)).all()
