@@ -93,3 +93,23 @@ def test_planner_rejects_bad_shapes():
     with pytest.raises(hconv.HcError) as e:
         hconv.plan_ring(4096, 0, 4, 8, 8, 3, 1)
     assert e.value.status == -1
+
+
+def test_client_and_protocol_entry_points_reject_null_handles():
+    """Argument checks that return before any device call: a null context or
+    layer is HC_EINVAL, with a message for hc_last_error."""
+    lib = hconv.load()
+    n = None
+    sz = ctypes.c_size_t()
+    assert lib.hc_encrypt_online(n, n, n, n, 1, n) == -1
+    assert lib.hc_encrypt_zero(n, n, n, n, n, 1, n, 0, n) == -1
+    assert lib.hc_decrypt(n, n, n, n, 1, n, 0, n) == -1
+    assert lib.hc_decrypt_extracted(n, n, n, n, n, 1, n, 0, n) == -1
+    assert lib.hc_decrypt_workspace_size(n, 1, ctypes.byref(sz)) == -1
+    assert lib.hc_batch_encode(n, n, n, 1, n) == -1
+    assert lib.hc_batch_decode(n, n, n, 1, n) == -1
+    assert lib.hc_encrypt_plain(n, n, n, n, 1, n) == -1
+    assert lib.hc_act_workspace_size(n, 1, ctypes.byref(sz)) == -1
+    assert lib.hc_act_pmult(n, n, n, n, n, 1, n, 0, n) == -1
+    assert lib.hc_act_combine(n, n, n, n, n, n, 1, n) == -1
+    assert lib.hc_last_error() != b""
