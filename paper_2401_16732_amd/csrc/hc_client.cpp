@@ -60,12 +60,13 @@ hc::EncGeom enc_geom(const hc_layer &ly) {
 }
 
 // NTT(s) into s_hat [L][N], then c1s [P][N] <- c1 * s for c1 [P][N] (c1 == c1s
-// allowed): forward NTT, product and inverse NTT in one kernel per polynomial.
+// allowed): forward NTT, product and inverse NTT in one kernel per polynomial;
+// with keep_bits < log2 N only the coefficients below 2^keep_bits are formed.
 hc_status ring_times_secret(const hc_ctx &c, const uint32_t *sk, const uint32_t *c1, uint32_t *c1s, size_t np,
-                            uint32_t *s_hat, hipStream_t st) {
+                            uint32_t *s_hat, hipStream_t st, uint32_t keep_bits = 32) {
   const hc::Shapes sh = hc::shapes_for(c, 1);
   CL_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, sk, s_hat, c.L, c.consts, c.tw, st));
-  CL_HIP(hc::launch_ring_mul(c.logn, sh.ie, c1, c1s, np, s_hat, 0, c.consts, c.tw, st));
+  CL_HIP(hc::launch_ring_mul(c.logn, sh.ie, c1, c1s, np, s_hat, 0, c.consts, c.tw, st, keep_bits));
   return HC_OK;
 }
 
@@ -149,7 +150,8 @@ hc_status hc_decrypt_extracted(const hc_layer *ly, const uint32_t *c0_ext, const
   uint32_t *c1s = (uint32_t *)ws, *s_hat = c1s + np * c.N;
   hipStream_t st = (hipStream_t)stream;
   hc::DeviceGuard dg(c.device);
-  hc_status s = ring_times_secret(c, sk, c1_out, c1s, np, s_hat, st);
+  // every extracted coefficient lies below 2^prune_bits
+  hc_status s = ring_times_secret(c, sk, c1_out, c1s, np, s_hat, st, ly->geom.prune_bits);
   if (s != HC_OK) return s;
   CL_HIP(hc::launch_decrypt_extracted(ly->geom, c0_ext, c1s, m, B, c.consts, c.dec, st));
   return HC_OK;

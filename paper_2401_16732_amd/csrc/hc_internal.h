@@ -86,10 +86,11 @@ hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint
 // p / mul_div (row 0 for all p when mul_div is 0; mul_div a multiple of L) of
 // mul [..][L][N], which holds NTT(s) per limb as launch_ntt_fwd writes it
 // (canonical, 16-byte aligned): forward NTT, product and inverse NTT in one
-// kernel (in place allowed).
+// kernel (in place allowed). keep_bits < logn: only outputs below 2^keep_bits
+// are computed and stored (the rest of out is left as it was).
 hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                            const uint32_t *mul, uint32_t mul_div, const LimbConsts &c, const Twiddles &tw,
-                           hipStream_t st);
+                           hipStream_t st, uint32_t keep_bits = 32);
 // Full mode: in [P][N] -> out [P][N] (in place allowed).
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st);

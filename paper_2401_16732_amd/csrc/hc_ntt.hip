@@ -78,8 +78,10 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
 // order, canonical, 16-byte aligned), in one pass over HBM: the forward transform,
 // the pointwise product as the forward's last pass leaves its registers, one
 // LDS exchange into the inverse transform's first-pass layout, the inverse
-// transform, and a canonical store (in place allowed).
-template <int LOGN, int ELOG>
+// transform, and a canonical store (in place allowed). PS > 0: only outputs
+// below 2^(LOGN - PS) are wanted; the inverse prunes its top PS stages (as the
+// masked inverse NTT does for c0) and the other outputs are not stored.
+template <int LOGN, int ELOG, int PS>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ring_mul(const uint32_t *in, uint32_t *out,
                                                                   const uint32_t *mul, uint32_t mul_div,
                                                                   LimbConsts c, Twiddles tws) {
@@ -120,14 +122,18 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ring_mul(const uint32_t 
   const uint2 *itw = tws.inv + (size_t)l * N;
   if constexpr (ELOG <= 4) {
     const EarlyTws<LOGN, ELOG, 0> t(itw, tid);
-    intt_passes<LOGN, ELOG, 0, 1, 0>(v, lds, tid, c, t, l);
+    intt_passes<LOGN, ELOG, PS, 1, 0>(v, lds, tid, c, t, l);
   } else {
-    intt_passes<LOGN, ELOG, 0, 1, 0>(v, lds, tid, c, MemTws<LOGN, ELOG, 0>{itw, tid}, l);
+    intt_passes<LOGN, ELOG, PS, 1, 0>(v, lds, tid, c, MemTws<LOGN, ELOG, 0>{itw, tid}, l);
   }
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
-  uint32_t *db = out + poly * N + gidx<LOGN, ELOG, LO, EP>(tid, 0);
+  const uint32_t base = gidx<LOGN, ELOG, LO, EP>(tid, 0);
+  uint32_t *db = out + poly * N + base;
 #pragma unroll
-  for (int u = 0; u < E; ++u) db[gidx<LOGN, ELOG, LO, EP>(0, u)] = csub(v[0][u], q);
+  for (int u = 0; u < E; ++u) {
+    const uint32_t j = gidx<LOGN, ELOG, LO, EP>(0, u);
+    if (PS == 0 || base + j < (uint32_t)(N >> PS)) db[j] = csub(v[0][u], q);
+  }
 }
 
 // ---------------------------------------------------------------- weight encoding
@@ -234,13 +240,25 @@ static hipError_t fwd_t(const uint32_t *in, uint32_t *out, size_t np, const Limb
                      tab, ppi);
   return hipGetLastError();
 }
-template <int LOGN, int ELOG>
-static hipError_t ring_mul_t(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, uint32_t mul_div,
-                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
-  if (np == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_ring_mul<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, mul,
+template <int LOGN, int ELOG, int PS>
+static hipError_t ring_mul_ps(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, uint32_t mul_div,
+                              const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  hipLaunchKernelGGL((k_ring_mul<LOGN, ELOG, PS>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, mul,
                      mul_div, c, tw);
   return hipGetLastError();
+}
+// Pruning fewer stages than allowed is exact: the largest instantiated count
+// not above ps (pruned forms exist for ELOG 4, the default shape).
+template <int LOGN, int ELOG>
+static hipError_t ring_mul_t(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, uint32_t mul_div,
+                             uint32_t ps, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  if (np == 0) return hipSuccess;
+  if constexpr (ELOG == 4) {
+    if (ps >= 7) return ring_mul_ps<LOGN, ELOG, 7>(in, out, np, mul, mul_div, c, tw, st);
+    if (ps >= 5) return ring_mul_ps<LOGN, ELOG, 5>(in, out, np, mul, mul_div, c, tw, st);
+    if (ps >= 3) return ring_mul_ps<LOGN, ELOG, 3>(in, out, np, mul, mul_div, c, tw, st);
+  }
+  return ring_mul_ps<LOGN, ELOG, 0>(in, out, np, mul, mul_div, c, tw, st);
 }
 template <int LOGN, int ELOG>
 static hipError_t inv_t(const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c, const Twiddles &tw,
@@ -281,9 +299,10 @@ hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint
 }
 hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
                            const uint32_t *mul, uint32_t mul_div, const LimbConsts &c, const Twiddles &tw,
-                           hipStream_t st) {
+                           hipStream_t st, uint32_t keep_bits) {
   if (mul_div && mul_div % c.L) return hipErrorInvalidValue;
-  HC_NTT_DISPATCH(ring_mul_t, in, out, np, mul, mul_div, c, tw, st)
+  const uint32_t ps = keep_bits >= logn ? 0 : logn - keep_bits;
+  HC_NTT_DISPATCH(ring_mul_t, in, out, np, mul, mul_div, ps, c, tw, st)
 }
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
