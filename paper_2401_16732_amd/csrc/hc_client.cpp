@@ -245,9 +245,9 @@ hc_status hc_act_pmult(const hc_ctx *c, const uint32_t *ct_batch, const uint32_t
   // encode(2r) = 2 encode(r): lift to every limb, NTT, then PMult of both components
   CL_HIP(hc::launch_lift_plain(pr, lifted, n_ct, c->N, 2, c->consts, st));
   CL_HIP(hc::launch_ntt_fwd(c->logn, sh.fe, lifted, lifted, (size_t)n_ct * c->L, c->consts, c->tw, st));
+  // PMult of both components, with + Delta * encode(v) on c0 as it is stored
   CL_HIP(hc::launch_ring_mul(c->logn, sh.ie, ct_batch, ct_out, (size_t)n_ct * 2 * c->L, lifted, 2 * c->L, c->consts,
-                             c->tw, st));
-  CL_HIP(hc::launch_add_plain(ct_out, pv, n_ct, c->N, c->consts, st));
+                             c->tw, st, 32, pv));
   return HC_OK;
 }
 

@@ -87,10 +87,12 @@ hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint
 // mul [..][L][N], which holds NTT(s) per limb as launch_ntt_fwd writes it
 // (canonical, 16-byte aligned): forward NTT, product and inverse NTT in one
 // kernel (in place allowed). keep_bits < logn: only outputs below 2^keep_bits
-// are computed and stored (the rest of out is left as it was).
+// are computed and stored (the rest of out is left as it was). addp: the
+// polynomials are whole ciphertexts [..][2][L][N], and c0 of ciphertext r
+// gains Delta (centred addp[r] mod q_l), addp [..][N] in [0, t) (no pruning).
 hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                            const uint32_t *mul, uint32_t mul_div, const LimbConsts &c, const Twiddles &tw,
-                           hipStream_t st, uint32_t keep_bits = 32);
+                           hipStream_t st, uint32_t keep_bits = 32, const uint32_t *addp = nullptr);
 // Full mode: in [P][N] -> out [P][N] (in place allowed).
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st);

@@ -81,10 +81,14 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t
 // transform, and a canonical store (in place allowed). PS > 0: only outputs
 // below 2^(LOGN - PS) are wanted; the inverse prunes its top PS stages (as the
 // masked inverse NTT does for c0) and the other outputs are not stored.
-template <int LOGN, int ELOG, int PS>
+// ADD: the polynomials are ciphertexts [..][2][L][N], and c0 of ciphertext r
+// gains Delta_l (centred addp[r][k] mod q_l) as it is stored (a plaintext
+// addition, addp [..][N] in [0, t)).
+template <int LOGN, int ELOG, int PS, bool ADD>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ring_mul(const uint32_t *in, uint32_t *out,
                                                                   const uint32_t *mul, uint32_t mul_div,
-                                                                  LimbConsts c, Twiddles tws) {
+                                                                  const uint32_t *addp, LimbConsts c,
+                                                                  Twiddles tws) {
   constexpr int N = 1 << LOGN, E = 1 << ELOG, NP = n_pass(LOGN, ELOG);
   __shared__ uint32_t lds[N + N / 32];
   const uint32_t tid = threadIdx.x;
@@ -129,6 +133,21 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ring_mul(const uint32_t 
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
   const uint32_t base = gidx<LOGN, ELOG, LO, EP>(tid, 0);
   uint32_t *db = out + poly * N + base;
+  if constexpr (ADD) {
+    if (((poly / c.L) & 1) == 0) {  // c0 of its ciphertext
+      const uint32_t *ap = addp + (poly / (2 * c.L)) * N + base;
+      const uint32_t half = c.t / 2;
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const uint32_t j = gidx<LOGN, ELOG, LO, EP>(0, u);
+        const uint32_t m = ap[j];
+        // Delta_l (centred m mod q_l): m <= t/2 is m itself, else m - t + q (t < 2 q_l)
+        const uint32_t mc = m > half ? m - c.t + q : m;
+        db[j] = csub(csub(v[0][u], q) + csub(shoup_lazy(mc, c.delta[l], c.delta_p[l], q), q), q);
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int u = 0; u < E; ++u) {
     const uint32_t j = gidx<LOGN, ELOG, LO, EP>(0, u);
@@ -240,25 +259,28 @@ static hipError_t fwd_t(const uint32_t *in, uint32_t *out, size_t np, const Limb
                      tab, ppi);
   return hipGetLastError();
 }
-template <int LOGN, int ELOG, int PS>
+template <int LOGN, int ELOG, int PS, bool ADD>
 static hipError_t ring_mul_ps(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, uint32_t mul_div,
-                              const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
-  hipLaunchKernelGGL((k_ring_mul<LOGN, ELOG, PS>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, mul,
-                     mul_div, c, tw);
+                              const uint32_t *addp, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+  hipLaunchKernelGGL((k_ring_mul<LOGN, ELOG, PS, ADD>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out,
+                     mul, mul_div, addp, c, tw);
   return hipGetLastError();
 }
 // Pruning fewer stages than allowed is exact: the largest instantiated count
-// not above ps (pruned forms exist for ELOG 4, the default shape).
+// not above ps (pruned forms exist for ELOG 4, the default shape). The
+// plaintext-adding form is unpruned.
 template <int LOGN, int ELOG>
 static hipError_t ring_mul_t(const uint32_t *in, uint32_t *out, size_t np, const uint32_t *mul, uint32_t mul_div,
-                             uint32_t ps, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+                             uint32_t ps, const uint32_t *addp, const LimbConsts &c, const Twiddles &tw,
+                             hipStream_t st) {
   if (np == 0) return hipSuccess;
+  if (addp) return ring_mul_ps<LOGN, ELOG, 0, true>(in, out, np, mul, mul_div, addp, c, tw, st);
   if constexpr (ELOG == 4) {
-    if (ps >= 7) return ring_mul_ps<LOGN, ELOG, 7>(in, out, np, mul, mul_div, c, tw, st);
-    if (ps >= 5) return ring_mul_ps<LOGN, ELOG, 5>(in, out, np, mul, mul_div, c, tw, st);
-    if (ps >= 3) return ring_mul_ps<LOGN, ELOG, 3>(in, out, np, mul, mul_div, c, tw, st);
+    if (ps >= 7) return ring_mul_ps<LOGN, ELOG, 7, false>(in, out, np, mul, mul_div, addp, c, tw, st);
+    if (ps >= 5) return ring_mul_ps<LOGN, ELOG, 5, false>(in, out, np, mul, mul_div, addp, c, tw, st);
+    if (ps >= 3) return ring_mul_ps<LOGN, ELOG, 3, false>(in, out, np, mul, mul_div, addp, c, tw, st);
   }
-  return ring_mul_ps<LOGN, ELOG, 0>(in, out, np, mul, mul_div, c, tw, st);
+  return ring_mul_ps<LOGN, ELOG, 0, false>(in, out, np, mul, mul_div, addp, c, tw, st);
 }
 template <int LOGN, int ELOG>
 static hipError_t inv_t(const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c, const Twiddles &tw,
@@ -299,10 +321,11 @@ hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint
 }
 hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
                            const uint32_t *mul, uint32_t mul_div, const LimbConsts &c, const Twiddles &tw,
-                           hipStream_t st, uint32_t keep_bits) {
+                           hipStream_t st, uint32_t keep_bits, const uint32_t *addp) {
   if (mul_div && mul_div % c.L) return hipErrorInvalidValue;
+  if (addp && np % (2 * c.L)) return hipErrorInvalidValue;  // whole ciphertexts
   const uint32_t ps = keep_bits >= logn ? 0 : logn - keep_bits;
-  HC_NTT_DISPATCH(ring_mul_t, in, out, np, mul, mul_div, ps, c, tw, st)
+  HC_NTT_DISPATCH(ring_mul_t, in, out, np, mul, mul_div, ps, addp, c, tw, st)
 }
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
                             const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
