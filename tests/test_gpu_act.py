@@ -183,3 +183,51 @@ def test_largest_ring_batch_encoding_properties(hc):
     zz = zeros((1, N))
     c.batch_decode(prod, zz)
     assert (host(zz).astype(np.int64) == (z1.astype(np.int64) * z2) % t).all()
+
+
+def test_client_and_protocol_steps_replay_as_graphs(hc):
+    """The client and protocol entry points enqueue kernels and copies only, so
+    they can be recorded in a HIP graph (as bench.py does to time them). Each
+    replay, with eager work and synchronisations between replays, must give
+    the eager result."""
+    import torch
+    N, L, t, B = 2048, 2, 65537, 2
+    shape = (6, 5, 20, 20, 3, 1)
+    c = hc.Context(N, L, t)
+    g = W.rng(777)
+    ly = hc.Layer(c, *shape, W.gen_filters(g, W.ConvSpec(*shape)))
+    P = layout.plan(N, *shape)
+    s = g.integers(-1, 2, size=N)
+    sk = dev(np.stack([np.mod(s, q) for q in c.primes]).astype(np.uint32))
+    act = dev(W.gen_mask(g, ly.act_shape(B), t))
+    ct0 = dev(W.gen_ct_limbs(g, (B, P.G, 2), c.primes, N))
+    c0 = dev(W.gen_ct_limbs(g, (B, P.c_o), c.primes, P.ho * P.wo))
+    c1 = dev(W.gen_ct_limbs(g, (B, P.O), c.primes, N))
+    n_ct = 3
+    ctb = dev(W.gen_ct_limbs(g, (n_ct, 2), c.primes, N))
+    r = dev(g.integers(0, t, size=(n_ct, N)).astype(np.uint32))
+    v = dev(g.integers(0, t, size=(n_ct, N)).astype(np.uint32))
+    enc, m, pm = zeros(ly.in_shape(B)), zeros(ly.mask_shape(B)), zeros((n_ct, 2, L, N))
+    wsd, wsa = zeros((ly.decrypt_workspace_words(B),)), zeros((c.act_workspace_words(n_ct),))
+
+    def work():
+        ly.encrypt_online(act, ct0, enc, B)
+        ly.decrypt_extracted(c0, c1, sk, m, B, wsd)
+        c.act_pmult(ctb, r, v, pm, wsa)
+
+    work()
+    torch.cuda.synchronize()
+    want = [host(x).copy() for x in (enc, m, pm)]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        work()
+    for k in range(3):
+        for x in (enc, m, pm):
+            x.zero_()
+        junk = torch.randint(0, 7, (1 << 20,), device="cuda", dtype=torch.int32).sum()  # eager work between
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for x, w_ in zip((enc, m, pm), want):
+            assert (host(x) == w_).all(), k
+        del junk
