@@ -11,6 +11,9 @@ masks) are resident in HBM before the timed region. Reported:
   ms_per_step_spread   median, p10 and p90 of the single-step times
   plain_ms_per_image   the same work per image with one launch sequence per
                        layer at B = 1 (stream order, no graph)
+  plain_hybrid_ms_per_image  the plain path with Flash's coefficient-domain
+                       conv (Algorithm 1 as written) on the layers where it
+                       beats the NTT path at one image
   speedup_vs_plain     plain / batched
   modmul_per_s         algorithmic modular multiplies (NTT butterflies + MAC)
                        per second, batched
@@ -383,7 +386,8 @@ def main():
     modmul = tot["bfly_fwd"] + tot["bfly_inv"] + tot["mac"] + tot["mask"]
 
     # plain path: one launch sequence per layer, one image at a time
-    plain_ms = None
+    plain_ms = plain_hybrid_ms = None
+    direct = []
     if not a.no_plain:
         wsw = max(ly.workspace_words(1, True) for ly in layers)
         ws = torch.empty((wsw,), dtype=torch.int32, device=dev)
@@ -402,6 +406,47 @@ def main():
         torch.cuda.synchronize()
         plain_ms = p0.elapsed_time(p1) / a.plain_images
         print(f"[bench] plain: {plain_ms:.3f} ms/image", file=sys.stderr, flush=True)
+
+        # the same plain path with Flash's coefficient-domain conv on the layers
+        # where it is faster at one image: tried where c_n f^2 <= 4 (untiled),
+        # kept where its events beat the NTT path's
+        def layer_ms(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        direct = []
+        for k, ly in enumerate(layers):
+            cand = not ly.layout.tiled and ly.layout.cn * ly.shape[4] ** 2 <= 4
+            if cand:
+                tn = layer_ms(lambda: ly.conv_masked(ct_in[k][0], mask[k][0], c0[k][0], c1[k][0], 1, ws))
+                td = layer_ms(lambda: ly.conv_masked_direct(ct_in[k][0], mask[k][0], c0[k][0], c1[k][0], 1))
+                if td < tn:
+                    direct.append(k)
+
+        def one_image_hybrid(b):
+            for k, ly in enumerate(layers):
+                if k in direct:
+                    ly.conv_masked_direct(ct_in[k][b], mask[k][b], c0[k][b], c1[k][b], 1)
+                else:
+                    ly.conv_masked(ct_in[k][b], mask[k][b], c0[k][b], c1[k][b], 1, ws)
+
+        one_image_hybrid(0)
+        torch.cuda.synchronize()
+        p0.record()
+        for b in range(a.plain_images):
+            one_image_hybrid(b % B)
+        p1.record()
+        torch.cuda.synchronize()
+        plain_hybrid_ms = p0.elapsed_time(p1) / a.plain_images
+        print(f"[bench] plain with the coefficient-domain conv on {len(direct)} layers: "
+              f"{plain_hybrid_ms:.3f} ms/image", file=sys.stderr, flush=True)
 
     client = protocol = None
     if not a.no_client:
@@ -476,6 +521,8 @@ def main():
         "modmul_per_s": round(modmul / (ms_step * 1e-3), 1),
         "plain_ms_per_image": None if plain_ms is None else round(plain_ms, 4),
         "speedup_vs_plain": None if plain_ms is None else round(plain_ms / per_img, 3),
+        "plain_hybrid_ms_per_image": None if plain_hybrid_ms is None else round(plain_hybrid_ms, 4),
+        "plain_hybrid_direct_layers": direct,
         "weight_encode_ms": round(encode_ms, 1),
         "autotune_ms": None if tune_ms is None else round(tune_ms, 1),
         "stage_ms_eager": [round(v, 3) for v in stage],

@@ -396,6 +396,16 @@ hc_status hc_act_pmult(const hc_ctx *ctx, const uint32_t *ct_batch, const uint32
 hc_status hc_act_combine(const hc_layer *layer, const uint32_t *ct_x, const uint32_t *ct_y, const uint32_t *r,
                          const uint32_t *v, uint32_t *ct_out, uint32_t B, void *stream);
 
+/* Flash's own coefficient-domain convolution (Algorithm 1 as written: CMult of
+ * DRot-ed inputs summed over taps and channels, in exact signed 64-bit sums,
+ * section "Employing Lazy Reduction in Convolution"), with the same outputs as
+ * hc_conv_masked, bit for bit. It reads the int8 filters instead of the
+ * resident NTT-domain weights and needs no workspace, so it pays where c_n f^2
+ * is small and the batch is small. Untiled layers with c_in f^2 <= 2^17
+ * (HC_EUNSUPPORTED otherwise). Enqueued on `stream`; no allocation. */
+hc_status hc_conv_masked_direct(const hc_layer *layer, const uint32_t *ct_in, const uint32_t *mask, uint32_t *c0_ext,
+                                uint32_t *c1_out, uint32_t B, void *stream);
+
 /* Wait for all work on the context's device; reports earlier asynchronous faults. */
 hc_status hc_sync(hc_ctx *ctx);
 const char *hc_status_string(hc_status s);

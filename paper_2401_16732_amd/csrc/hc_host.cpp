@@ -598,10 +598,18 @@ hc_status hc_layer_create(hc_ctx *c, const hc_conv_shape *s, const int8_t *filte
   if (e == hipSuccess)
     e = hc::launch_ntt_fwd(c->logn, shapes_for(*c, 1).fe, ly->d_w, ly->d_w, (size_t)s->c_out * lay.w_cts * c->L,
                            c->consts, c->tw, hs);
+  // int32 filter table for the coefficient-domain conv, rows padded to 16
+  ly->wt_rows = (s->c_out + 15u) / 16u * 16u;
+  const size_t taps = (size_t)s->f * s->f;
+  std::vector<int32_t> wt((size_t)ly->wt_rows * s->c_in * taps, 0);
+  for (size_t k = 0; k < (size_t)s->c_out * s->c_in * taps; ++k) wt[k] = filters[k];
+  if (e == hipSuccess) e = hipMalloc((void **)&ly->d_wt, wt.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemcpyAsync(ly->d_wt, wt.data(), wt.size() * sizeof(int32_t), hipMemcpyHostToDevice, hs);
   if (e == hipSuccess) e = hipStreamSynchronize(hs);
   if (d_f) (void)hipFree(d_f);
   if (e != hipSuccess) {
     (void)hipFree(ly->d_w);
+    if (ly->d_wt) (void)hipFree(ly->d_wt);
     delete ly;
     return hip_fail(e, "weight encoding");
   }
@@ -613,6 +621,7 @@ void hc_layer_destroy(hc_layer *ly) {
   if (!ly) return;
   DeviceGuard dg(ly->ctx->device);
   if (ly->d_w) (void)hipFree(ly->d_w);
+  if (ly->d_wt) (void)hipFree(ly->d_wt);
   delete ly;
 }
 
@@ -680,6 +689,25 @@ hc_status hc_mask_extract(const hc_layer *ly, const uint32_t *ct_out, const uint
   if (((uintptr_t)ct_out | (uintptr_t)c1_out) & 15u) return fail(HC_EINVAL, "ct_out and c1_out must be 16-byte aligned");
   DeviceGuard dg(ly->ctx->device);
   HC_HIP(hc::launch_mask_extract(ly->geom, ct_out, mask, c0_ext, c1_out, B, ly->ctx->consts, (hipStream_t)stream));
+  return HC_OK;
+}
+
+hc_status hc_conv_masked_direct(const hc_layer *ly, const uint32_t *ct_in, const uint32_t *mask, uint32_t *c0_ext,
+                                uint32_t *c1_out, uint32_t B, void *stream) {
+  if (!ly || (B && (!ct_in || !mask || !c0_ext || !c1_out))) return fail(HC_EINVAL, "null argument");
+  if (ly->lay.tiled) return fail(HC_EUNSUPPORTED, "the coefficient-domain conv covers untiled layers only");
+  if ((uint64_t)ly->shape.c_in * ly->shape.f * ly->shape.f > (1u << 17))
+    return fail(HC_EUNSUPPORTED, "c_in f^2 above 2^17 (64-bit sum bound)");
+  if ((uint64_t)B * ly->ctx->L > 65535) return fail(HC_EUNSUPPORTED, "B L above 65535");
+  if (B == 0) return HC_OK;
+  const hc_ctx &c = *ly->ctx;
+  DeviceGuard dg(c.device);
+  hc_status s = check_input(ly, ct_in, B, (hipStream_t)stream);
+  if (s != HC_OK) return s;
+  hc::DirectConsts d{};
+  for (uint32_t l = 0; l < c.L; ++l) d.bias[l] = (uint64_t)c.q[l] * (((1ull << 55) + c.q[l] - 1) / c.q[l]);
+  HC_HIP(hc::launch_conv_direct(ly->geom, ct_in, ly->d_wt, ly->wt_rows, mask, c0_ext, c1_out, B, d, c.consts,
+                                (hipStream_t)stream));
   return HC_OK;
 }
 

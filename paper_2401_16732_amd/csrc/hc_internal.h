@@ -162,6 +162,19 @@ hipError_t launch_add_plain(uint32_t *ct, const uint32_t *p, size_t n, uint32_t 
 hipError_t launch_act_combine(const ConvGeom &g, const EncGeom &e, const uint32_t *ct_x, const uint32_t *ct_y,
                               const uint32_t *r, const uint32_t *v, uint32_t *ct, uint32_t B, const LimbConsts &c,
                               hipStream_t st);
+// ---------------------------------------------------------------- coefficient-domain conv (hc_direct.hip)
+// bias[l] = q_l ceil(2^55 / q_l): added to a signed 64-bit sum |acc| < 2^54 it
+// gives a value in [0, 2^57) with the same residue.
+struct DirectConsts {
+  uint64_t bias[kMaxLimbs];
+};
+// Algorithm 1 in the coefficient domain for an untiled layer, with the mask
+// add and extraction: c0_ext and c1_out as launch_intt_masked writes them.
+// wt: int32 filters [wt_rows][c_in][f f], wt_rows a multiple of 16 >= c_out,
+// rows beyond c_out zero. Needs c_in f f <= 2^17 (the sum bound).
+hipError_t launch_conv_direct(const ConvGeom &g, const uint32_t *ct, const int32_t *wt, uint32_t wt_rows,
+                              const uint32_t *mask, uint32_t *c0, uint32_t *c1, uint32_t B, const DirectConsts &d,
+                              const LimbConsts &c, hipStream_t st);
 // c1[c][l][:] = ct[c][1][l][:] for n_ct ciphertexts [n_ct][2][L][N].
 hipError_t launch_gather_c1(const uint32_t *ct, uint32_t *c1, size_t n_ct, uint32_t L, uint32_t N, hipStream_t st);
 // m[b][i][oy][ox] = decode(c0_ext[b][i][:][oy][ox] + c1s[b][(i, tau)][:][e]).

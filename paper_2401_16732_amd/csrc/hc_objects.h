@@ -34,6 +34,8 @@ struct hc_layer {
   hc::ConvGeom geom{};
   uint32_t *d_w = nullptr;  // [c_out][w_cts][L][N], NTT domain
   size_t w_elems = 0;
+  int32_t *d_wt = nullptr;  // [wt_rows][c_in][f f] int32 filters (coefficient-domain conv)
+  uint32_t wt_rows = 0;     // c_out rounded up to a multiple of 16, extra rows zero
   hc_tuning tune{};         // per-layer launch shapes chosen by the autotuner ...
   uint32_t tune_B = 0;      // ... for this batch size (0: none)
 };

@@ -31,7 +31,7 @@ SYMBOLS = [
     "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
     "hc_check_residues", "hc_encrypt_online", "hc_decrypt_workspace_size", "hc_decrypt_extracted", "hc_decrypt",
     "hc_encrypt_zero", "hc_batch_encode", "hc_batch_decode", "hc_encrypt_plain", "hc_act_workspace_size",
-    "hc_act_pmult", "hc_act_combine",
+    "hc_act_pmult", "hc_act_combine", "hc_conv_masked_direct",
 ]
 
 
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
         "hc_act_workspace_size": (I, [P, u32, P]),
         "hc_act_pmult": (I, [P, P, P, P, P, u32, P, sz, P]),
         "hc_act_combine": (I, [P, P, P, P, P, P, u32, P]),
+        "hc_conv_masked_direct": (I, [P, P, P, P, P, u32, P]),
         "hc_sync": (I, [P]),
         "hc_status_string": (ctypes.c_char_p, [I]),
         "hc_last_error": (ctypes.c_char_p, []),
@@ -422,6 +423,18 @@ class Layer:
         _check(_lib.hc_act_combine(self.h, _dptr(ct_x, "ct_x", d), _dptr(ct_y, "ct_y", d), _dptr(r, "r", d),
                                    _dptr(v, "v", d), _dptr(ct_out, "ct_out", d), B, _stream(stream)),
                "hc_act_combine")
+
+    def conv_masked_direct(self, ct_in, mask, c0_ext, c1_out, B: int, stream=None):
+        """The same outputs as conv_masked, by the coefficient-domain convolution
+        (Algorithm 1 as written; untiled layers)."""
+        d = self.ctx.device
+        self._need(ct_in, self.in_shape(B), "ct_in")
+        self._need(mask, self.mask_shape(B), "mask")
+        self._need(c0_ext, self.c0_shape(B), "c0_ext")
+        self._need(c1_out, self.c1_shape(B), "c1_out")
+        _check(_lib.hc_conv_masked_direct(self.h, _dptr(ct_in, "ct_in", d), _dptr(mask, "mask", d),
+                                          _dptr(c0_ext, "c0_ext", d), _dptr(c1_out, "c1_out", d), B,
+                                          _stream(stream)), "hc_conv_masked_direct")
 
     def tuning(self):
         """(batch size, (fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups, mac_depth,
