@@ -93,6 +93,12 @@ hc::DecodeConsts hc::make_decode_consts(const uint32_t *q, uint32_t L, uint64_t 
   return d;
 }
 
+hc::DirectConsts hc::direct_consts(const hc_ctx &c) {
+  DirectConsts d{};
+  for (uint32_t l = 0; l < c.L; ++l) d.bias[l] = (uint64_t)c.q[l] * (((1ull << 55) + c.q[l] - 1) / c.q[l]);
+  return d;
+}
+
 hc_status hc_encrypt_online(const hc_layer *ly, const uint32_t *act, const uint32_t *ct_zero, uint32_t *ct_in,
                             uint32_t B, void *stream) {
   if (!ly || (B && (!act || !ct_zero || !ct_in))) return fail(HC_EINVAL, "null argument");

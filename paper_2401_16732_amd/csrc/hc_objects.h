@@ -36,6 +36,7 @@ struct hc_layer {
   size_t w_elems = 0;
   int32_t *d_wt = nullptr;  // [wt_rows][c_in][f f] int32 filters (coefficient-domain conv)
   uint32_t wt_rows = 0;     // c_out rounded up to a multiple of 16, extra rows zero
+  bool direct_one = false;  // the coefficient-domain conv is the faster path for one image
   hc_tuning tune{};         // per-layer launch shapes chosen by the autotuner ...
   uint32_t tune_B = 0;      // ... for this batch size (0: none)
 };
@@ -62,6 +63,9 @@ Shapes layer_shapes(const hc_layer *ly, uint32_t B);
 
 // Constants of the exact decryption rounding for primes q[0..L) and t.
 DecodeConsts make_decode_consts(const uint32_t *q, uint32_t L, uint64_t t);
+
+// Sum offsets of the coefficient-domain conv for the context's primes.
+DirectConsts direct_consts(const hc_ctx &c);
 
 // Device workspace of one layer's conv for B images (X-hat, plus Y-hat when masked).
 size_t ws_bytes_for(const hc_layer *ly, uint32_t B, bool masked);

@@ -371,8 +371,14 @@ hc_status hc_server_step(hc_server *s) {
       c1[b] = (uint32_t *)(base + np.off_c1[k]);
     }
     const uint32_t si = s->rr++ % (uint32_t)s->streams.size();
-    hc_status cs = hc::enqueue_conv_gather(ly, B, in, mk, c0, c1, s->ws[si], s->streams[si]);
-    if (cs != HC_OK) return cs;
+    if (B == 1 && ly->direct_one) {
+      // a lone image on a layer where the coefficient-domain conv is faster (same bits)
+      SV_HIP(hc::launch_conv_direct(ly->geom, in[0], ly->d_wt, ly->wt_rows, mk[0], c0[0], c1[0], 1,
+                                    hc::direct_consts(*ly->ctx), ly->ctx->consts, s->streams[si]));
+    } else {
+      hc_status cs = hc::enqueue_conv_gather(ly, B, in, mk, c0, c1, s->ws[si], s->streams[si]);
+      if (cs != HC_OK) return cs;
+    }
     int ev = ev_get(s);
     if (ev < 0) return fail(HC_EDEVICE, "event creation");
     SV_HIP(hipEventRecord(s->events[ev], s->streams[si]));
