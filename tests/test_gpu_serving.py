@@ -13,6 +13,10 @@ pytestmark = pytest.mark.gpu
 
 N, L, T = 8192, 3, 2 ** 20
 
+# network a: the first ResNet-18/CIFAR layers plus a 1x1 layer at 56 x 56 (c_n = 2, so a
+# group of one image takes the coefficient-domain conv and a larger group the NTT path)
+NET_A_EXTRA = [W.ConvSpec(8, 16, 56, 56, 1, 1, "a.1x1")]
+
 NET_B = [  # a small second network with other shapes: tiled 7x7/2 stem, 1x1/2, 5x5
     W.ConvSpec(3, 8, 64, 64, 7, 2, "b.stem"),
     W.ConvSpec(8, 16, 32, 32, 1, 2, "b.proj"),
@@ -29,7 +33,7 @@ def setup():
     ctx = hconv.Context(N, L, T)
     g = W.rng(99)
     nets = {}
-    for name, specs in (("a", W.resnet18_cifar()[:6]), ("b", NET_B)):
+    for name, specs in (("a", W.resnet18_cifar()[:6] + NET_A_EXTRA), ("b", NET_B)):
         filt = [W.gen_filters(g, s) for s in specs]
         layers = [hconv.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, f) for s, f in zip(specs, filt)]
         nets[name] = (specs, filt, layers)
