@@ -152,3 +152,95 @@ void oracle_alg1_points(uint32_t n, uint32_t L, const uint32_t *q, uint32_t c_i,
         val[r] = (uint32_t)(rr < 0 ? rr + ql : rr);
     }
 }
+
+/*
+ * Freivalds combination of one layer's outputs over output channels, for one
+ * image: for each tile tau, poly p and limb l,
+ *     z[tau][p][l][m] = sum_i rho[l][i] y_(i,tau)[p][l][m]   mod q_l.
+ * The tap positions e = o_j + s_k do not depend on i, so this equals the
+ * closed form above with the combined filter f'[j][k] = sum_i rho[l][i] f[i][j][k]
+ * mod q_l in place of f[i] (n a power of two):
+ *     z[m] = sum_j sum_k f'[j][k] (-1)^floor((m + e) / n) c_(j,tau)[(m + e) mod n]  mod q_l,
+ * which costs 1 / c_o of the layer. f' is no longer small, so products
+ * (< 2^60) are summed in uint64 and reduced every 8 terms.
+ *   rho : [L][c_o] residues
+ *   z   : [T][2][L][n]
+ */
+void oracle_freivalds(uint32_t n, uint32_t L, const uint32_t *q, uint32_t c_i, uint32_t c_o, uint32_t T,
+                      uint32_t n_taps, const uint32_t *tap_off, const uint32_t *chan_off,
+                      const uint32_t *in_ct, const int8_t *filters, const uint32_t *x,
+                      const uint32_t *rho, uint32_t *z)
+{
+    size_t nf = (size_t)c_i * n_taps;
+    uint64_t *fc = (uint64_t *)malloc(sizeof(uint64_t) * nf * L);
+    if (!fc)
+        abort();
+    for (uint32_t l = 0; l < L; ++l) {
+        uint64_t ql = q[l];
+        for (size_t jk = 0; jk < nf; ++jk) {
+            uint64_t acc = 0;
+            for (uint32_t i = 0; i < c_o; ++i) {
+                int64_t f = filters[(size_t)i * nf + jk];
+                uint64_t fm = f < 0 ? ql - (uint64_t)(-f) : (uint64_t)f;
+                acc = (acc + (uint64_t)rho[(size_t)l * c_o + i] % ql * fm) % ql;
+            }
+            fc[(size_t)l * nf + jk] = acc;
+        }
+    }
+    uint32_t logn = 0;
+    while ((1u << logn) < n)
+        ++logn;
+    const uint32_t MB = 256;  /* coefficients per work item */
+    int64_t blocks = (int64_t)((n + MB - 1) / MB);
+    int64_t items = (int64_t)T * 2 * L * blocks;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t it = 0; it < items; ++it) {
+        uint32_t mb = (uint32_t)(it % blocks);
+        uint32_t l = (uint32_t)((it / blocks) % L);
+        uint32_t p = (uint32_t)((it / (blocks * L)) % 2);
+        uint32_t tau = (uint32_t)(it / (blocks * L * 2));
+        uint64_t ql = q[l];
+        const uint64_t *fl = fc + (size_t)l * nf;
+        uint32_t m0 = mb * MB, m1 = m0 + MB < n ? m0 + MB : n;
+        uint64_t acc[256];
+        memset(acc, 0, sizeof(acc));
+        uint32_t terms = 0;
+        for (uint32_t j = 0; j < c_i; ++j) {
+            const uint32_t *c = x + (((size_t)in_ct[(size_t)j * T + tau] * 2 + p) * L + l) * n;
+            for (uint32_t k = 0; k < n_taps; ++k) {
+                uint64_t w = fl[(size_t)j * n_taps + k];
+                uint32_t e = chan_off[j] + tap_off[k];
+                for (uint32_t m = m0; m < m1; ++m) {
+                    uint32_t idx = m + e;
+                    uint64_t v = c[idx & (n - 1)];
+                    if (v >= ql)
+                        v %= ql;
+                    if (((idx >> logn) & 1u) && v != 0)
+                        v = ql - v;
+                    acc[m - m0] += w * v;
+                }
+                if (++terms == 8) {
+                    for (uint32_t m = m0; m < m1; ++m)
+                        acc[m - m0] %= ql;
+                    terms = 0;
+                }
+            }
+        }
+        for (uint32_t m = m0; m < m1; ++m)
+            z[(((size_t)tau * 2 + p) * L + l) * n + m] = (uint32_t)(acc[m - m0] % ql);
+    }
+    free(fc);
+}
+
+/* Cap the OpenMP threads of the calls above (n >= 1); returns the new count. */
+int oracle_set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads >= 1)
+        omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}

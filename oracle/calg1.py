@@ -1,7 +1,9 @@
 """ctypes front of oracle/alg1.c (oracle; test infrastructure only).
 
-build() compiles alg1.c with gcc into oracle/_alg1.so; load() builds it when
-it is missing or older than its source.
+build() compiles alg1.c with gcc (-O3 -march=native, OpenMP) into a shared
+library named for the host CPU (oracle/_alg1_<cpu>.so, since -march=native code
+only runs on the CPU it was built for); load() builds it when it is missing or
+older than its source.
 """
 from __future__ import annotations
 
@@ -16,14 +18,41 @@ from .layout import Plan
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "alg1.c")
-_LIB = os.path.join(_HERE, "_alg1.so")
 _lib = None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or 'unknown'."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_key() -> str:
+    import hashlib
+    flags = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("flags"):
+                flags = line
+                break
+    except OSError:
+        pass
+    return hashlib.sha256((cpu_model() + flags).encode()).hexdigest()[:12]
+
+
+_LIB = os.path.join(_HERE, f"_alg1_{_cpu_key()}.so")
+
+
 def build() -> str:
-    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c99", "-Wall", "-o", _LIB + ".tmp", _SRC]
+    tmp = f"{_LIB}.tmp{os.getpid()}"
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-shared", "-fPIC", "-std=c99", "-Wall", "-o", tmp, _SRC]
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
+    os.replace(tmp, _LIB)
     return _LIB
 
 
@@ -40,6 +69,10 @@ def load():
     lib.oracle_alg1_layer.argtypes = [u32, u32, P, u32, u32, u32, P, P, P, P, P, u32, P, P]
     lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
+    lib.oracle_set_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_freivalds.restype = None
+    lib.oracle_freivalds.argtypes = [u32, u32, P, u32, u32, u32, u32, P, P, P, P, P, P, P]
     lib.oracle_alg1_points.restype = None
     lib.oracle_alg1_points.argtypes = [u32, u32, P, u32, u32, u32, P, P, P, P, P, ctypes.c_uint64,
                                        P, P, P, P, P, P]
@@ -49,6 +82,11 @@ def load():
 
 def threads() -> int:
     return int(load().oracle_threads())
+
+
+def set_threads(n: int) -> int:
+    """Cap the OpenMP threads of the oracle's calls; returns the new count."""
+    return int(load().oracle_set_threads(int(n)))
 
 
 def _ptr(a: np.ndarray):
@@ -94,3 +132,21 @@ def alg1_points(x, filters, P: Plan, primes: Sequence[int], i, tau, p, l, m) -> 
     lib.oracle_alg1_points(P.n, len(primes), _ptr(q), P.c_i, P.T, len(taps), _ptr(taps), _ptr(chan),
                            _ptr(in_ct), _ptr(f), _ptr(x), npts, *[_ptr(c) for c in cols], _ptr(val))
     return val
+
+
+def freivalds_rhs(x, filters, rho, P: Plan, primes: Sequence[int]) -> np.ndarray:
+    """sum_i rho_i y_(i,tau) of one image's Algorithm 1 outputs, by the closed
+    form with the combined filter (C, OpenMP): same contract as
+    conv.freivalds_rhs, rho[l][i] residues mod q_l; returns [T][2][L][n]."""
+    lib = load()
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    assert x.shape == (P.G, 2, len(primes), P.n)
+    f = np.ascontiguousarray(np.asarray(filters, dtype=np.int8).reshape(P.c_o, P.c_i, P.f_w * P.f_w))
+    q = np.asarray(primes, dtype=np.uint32)
+    r = np.ascontiguousarray(np.asarray(rho, dtype=np.uint64) % q[:, None].astype(np.uint64), dtype=np.uint32)
+    assert r.shape == (len(primes), P.c_o)
+    in_ct, chan, taps = _layout_arrays(P)
+    z = np.empty((P.T, 2, len(primes), P.n), dtype=np.uint32)
+    lib.oracle_freivalds(P.n, len(primes), _ptr(q), P.c_i, P.c_o, P.T, len(taps), _ptr(taps), _ptr(chan),
+                         _ptr(in_ct), _ptr(f), _ptr(x), _ptr(r), _ptr(z))
+    return z

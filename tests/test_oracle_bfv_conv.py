@@ -201,6 +201,66 @@ def test_freivalds_combination(shape):
     assert not (conv.freivalds_lhs(y_bad, rho, P, primes) == conv.freivalds_rhs(x, f, rho, P, primes)).all()
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+def test_c_freivalds_equals_combined_outputs(shape):
+    """The C Freivalds combination equals sum_i rho_i y_i of the full Algorithm 1
+    outputs (and the numpy form), with rho spanning the whole residue range; a
+    single changed coefficient of one output changes the combination."""
+    n, ci, co, h, w, fw, s = shape
+    primes, t = _ctx(n, 2)
+    P = layout.plan(n, ci, co, h, w, fw, s)
+    g = W.rng(52 + hash(shape) % 1000)
+    f = W.gen_filters(g, W.ConvSpec(ci, co, h, w, fw, s))
+    x = W.gen_ct_limbs(g, (P.G, 2), primes, n)
+    rho = [g.integers(0, q, size=co) for q in primes]
+    rho[0][0] = primes[0] - 1  # the largest residue
+    y = calg1.alg1_layer(x, f, P, primes)
+    z = calg1.freivalds_rhs(x, f, rho, P, primes)
+    assert (z == conv.freivalds_lhs(y, rho, P, primes)).all()
+    assert (z == conv.freivalds_rhs(x, f, rho, P, primes)).all()
+    y_bad = y.copy()
+    y_bad[-1, 0, 1, n - 1] = (int(y_bad[-1, 0, 1, n - 1]) + 1) % primes[1]
+    assert not (conv.freivalds_lhs(y_bad, rho, P, primes) == z).all()
+
+
+def test_c_freivalds_many_terms_between_reductions():
+    """A layer with many (channel, tap) terms and rho, filters at their extremes
+    (f = -128 everywhere, rho = q - 1): the uint64 sums must not overflow."""
+    n = 64
+    primes = params.rns_primes(n, 2)
+    P = layout.plan(n, 9, 3, 2, 2, 3, 1)
+    f = np.full((3, 9, 3, 3), -128, dtype=np.int8)
+    g = W.rng(53)
+    x = W.gen_ct_limbs(g, (P.G, 2), primes, n)
+    x[..., :] = np.array(primes, dtype=np.uint32)[None, None, :, None] - 1  # the largest residues
+    rho = [np.full(3, q - 1) for q in primes]
+    y = calg1.alg1_layer(x, f, P, primes)
+    assert (calg1.freivalds_rhs(x, f, rho, P, primes) == conv.freivalds_lhs(y, rho, P, primes)).all()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mask_add_equals_mask_extract(shape):
+    """mask_add (one masked coefficient, what the sampled GPU checks use) gives
+    mask_extract's value at every extracted output, including masks at 0,
+    t/2, t/2 + 1 and t - 1 (the ends of the centred lift)."""
+    n, ci, co, h, w, fw, s = shape
+    primes, t = _ctx(n, 2, 2 ** 10)
+    P = layout.plan(n, ci, co, h, w, fw, s)
+    g = W.rng(54 + hash(shape) % 1000)
+    x = W.gen_ct_limbs(g, (P.O, 2), primes, n)
+    r = W.gen_mask(g, (co, P.ho, P.wo), t)
+    flat = r.reshape(-1)
+    flat[:4] = [0, t // 2, t // 2 + 1, t - 1][:flat.size]
+    c0e, _ = conv.mask_extract(x, r, P, primes, t)
+    for i in range(co):
+        for oy in range(P.ho):
+            for ox in range(P.wo):
+                tau, e = P.out_pos(oy, ox)
+                for l in range(len(primes)):
+                    got = conv.mask_add(int(x[P.out_ct(i, tau), 0, l, e]), int(r[i, oy, ox]), l, primes, t)
+                    assert got == int(c0e[i, l, oy, ox]), (i, oy, ox, l)
+
+
 def test_lazy_int64_accumulation_cannot_overflow_at_the_largest_layer():
     # |c| < 2^30, |f| <= 128, 49 taps (7x7), up to 2048 input channels
     assert (2 ** 30) * 128 * 49 * 2048 < 2 ** 63
