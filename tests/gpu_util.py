@@ -45,3 +45,43 @@ def check_layer_points(P, primes, t, x_img, f, mask_img, c0_img, c1_img, g, npts
                     for k in range(npts)], dtype=np.uint32)
     got = c0_img[i, l, oy, ox]
     assert (got == exp).all(), f"c0 mismatch at {np.nonzero(got != exp)[0][:5]}"
+
+
+def freivalds_check(P, primes, delta_mod_q, t, x_img, f, mask_img, c0_img, c1_img, g):
+    """Every output of one image against the oracle at once: for random rho
+    (one residue per output channel and limb), sum_i rho_i c1_(i,tau) must equal
+    the oracle's combination of Algorithm 1's c1 outputs at every coefficient,
+    and sum_i rho_i (c0_ext_i - Delta_l r_i) must equal its c0 combination at
+    every extracted coefficient (tolerance 0). A wrong value anywhere passes
+    with probability at most 1/q_l per compared coefficient.
+
+    x_img: host input ciphertexts [G][2][L][n]; mask_img, c0_img, c1_img: the
+    image's device tensors (int32 views of uint32). The combination on the
+    device side is test arithmetic in int64 torch ops; rhs comes from
+    oracle.calg1.freivalds_rhs."""
+    import torch
+    L = len(primes)
+    rho = [g.integers(0, q, size=P.c_o) for q in primes]
+    rhs = calg1.freivalds_rhs(x_img, f, rho, P, primes)  # [T][2][L][n]
+    dev = c1_img.device
+    u32 = lambda v: v.to(torch.int64) & 0xFFFFFFFF
+    c1 = u32(c1_img).view(P.c_o, P.T, L, P.n)
+    c0 = u32(c0_img).view(P.c_o, L, P.ho, P.wo)
+    r = u32(mask_img).view(P.c_o, P.ho, P.wo)
+    rc = torch.where(r > t // 2, r - t, r)  # centred lift of the mask
+    taus = np.zeros((P.ho, P.wo), dtype=np.int64)
+    es = np.zeros((P.ho, P.wo), dtype=np.int64)
+    for oy in range(P.ho):
+        for ox in range(P.wo):
+            taus[oy, ox], es[oy, ox] = P.out_pos(oy, ox)
+    for l, q in enumerate(primes):
+        rl = torch.tensor(rho[l], dtype=torch.int64, device=dev)
+        lhs1 = ((c1[:, :, l, :] * rl[:, None, None]) % q).sum(0) % q  # [T][n]
+        exp1 = rhs[:, 1, l, :].astype(np.int64)
+        got1 = lhs1.cpu().numpy()
+        assert (got1 == exp1).all(), f"c1 combination differs at limb {l}: {np.argwhere(got1 != exp1)[:4]}"
+        y0 = (c0[:, l] - (delta_mod_q[l] * (rc % q)) % q) % q  # c0 before the mask, [c_o][ho][wo]
+        lhs0 = ((y0 * rl[:, None, None]) % q).sum(0) % q
+        exp0 = rhs[taus, 0, l, es].astype(np.int64)
+        got0 = lhs0.cpu().numpy()
+        assert (got0 == exp0).all(), f"c0 combination differs at limb {l}: {np.argwhere(got0 != exp0)[:4]}"

@@ -1,15 +1,17 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
-times (all 53 ResNet-50 layers, 16 images, one HIP graph), and at the large
-ring (ResNet-18 224x224, N = 16384, 4 primes, 64 images): sampled outputs of
-every layer against the oracle's closed form (bit-exact), and graph replays
-against eager runs."""
+times (all 53 ResNet-50 layers, 16 images, autotuned launch shapes, one HIP
+graph), and at the large ring (ResNet-18 224x224, N = 16384, 4 primes, 64
+images, autotuned): every output of every layer of several images through a
+Freivalds combination over output channels against the oracle, sampled outputs
+against the oracle's closed form (bit-exact), and graph replays against eager
+runs."""
 import numpy as np
 import pytest
 
 from oracle import layout
 from paper_2401_16732_amd import workloads as W
 
-from gpu_util import check_layer_points, host
+from gpu_util import check_layer_points, freivalds_check, host
 
 pytestmark = pytest.mark.gpu
 
@@ -41,12 +43,23 @@ def _net_batch(hc, net, N, L, t, B, seed):
 
 
 def _check_net(ctx, specs, filters, ct_in, mask, c0, c1, images, t, g, npts):
+    """Every output of each image in `images` (Freivalds over output channels)
+    and npts sampled outputs by the closed form, for every layer."""
     for k, (s, f) in enumerate(zip(specs, filters)):
         P = layout.plan(ctx.N, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride)
         for b in images:
             print(f"  layer {k} {s.name} image {b}", flush=True)
-            check_layer_points(P, ctx.primes, t, host(ct_in[k][b]), f, host(mask[k][b]), host(c0[k][b]),
-                               host(c1[k][b]), g, npts=npts)
+            x = host(ct_in[k][b])
+            freivalds_check(P, ctx.primes, ctx.delta_mod_q, t, x, f, mask[k][b], c0[k][b], c1[k][b], g)
+            check_layer_points(P, ctx.primes, t, x, f, host(mask[k][b]), host(c0[k][b]), host(c1[k][b]), g,
+                               npts=npts)
+
+
+def _tuned_shapes(layers, B):
+    """Every layer carries an autotuned shape set for this batch size."""
+    for ly in layers:
+        tb, tv = ly.tuning()
+        assert tb == B, (tb, tv)
 
 
 def _free(*objs):
@@ -63,14 +76,20 @@ def _free(*objs):
 
 
 def test_resnet50_batch16_graph_matches_oracle(hc):
+    """The benchmark's configuration: ResNet-50 at B = 16, autotuned like
+    bench.py, replayed as the graph; every output of images 0, 7 and 15."""
     import torch
     N, L, t, B = 8192, 3, 2 ** 20, 16
-    print("resnet50_224 B=16 graph", flush=True)
+    print("resnet50_224 B=16 graph, autotuned", flush=True)
     ctx, specs, filters, layers, ct_in, mask, c0, c1 = _net_batch(hc, "resnet50_224", N, L, t, B, 50)
     bt = hc.Batch(ctx, layers, B)
+    bt.autotune(ct_in, mask, c0, c1)
+    _tuned_shapes(layers, B)
+    for v in c0 + c1:
+        v.zero_()
     bt.run(ct_in, mask, c0, c1)
     torch.cuda.synchronize()
-    _check_net(ctx, specs, filters, ct_in, mask, c0, c1, (0, B - 1), t, W.rng(7), npts=8)
+    _check_net(ctx, specs, filters, ct_in, mask, c0, c1, (0, 7, B - 1), t, W.rng(7), npts=8)
     del ct_in, mask, c0, c1
     _free(bt, layers)
 
@@ -114,9 +133,13 @@ def test_graph_replays_match_eager(hc):
 def test_resnet18_224_large_ring_batch64_matches_oracle(hc):
     import torch
     N, L, t, B = 16384, 4, 2 ** 24, 64
-    print("resnet18_224 N=16384 L=4 B=64 graph", flush=True)
+    print("resnet18_224 N=16384 L=4 B=64 graph, autotuned", flush=True)
     ctx, specs, filters, layers, ct_in, mask, c0, c1 = _net_batch(hc, "resnet18_224", N, L, t, B, 18)
     bt = hc.Batch(ctx, layers, B)
+    bt.autotune(ct_in, mask, c0, c1)
+    _tuned_shapes(layers, B)
+    for v in c0 + c1:
+        v.zero_()
     bt.run(ct_in, mask, c0, c1)
     torch.cuda.synchronize()
     _check_net(ctx, specs, filters, ct_in, mask, c0, c1, (0, 37, B - 1), t, W.rng(8), npts=8)

@@ -298,3 +298,80 @@ def test_mac_epilogue_stages_match_oracle(hc, spec):
             c0, c1 = host(c0), host(c1)
             for b in range(B):
                 assert (c0[b] == exp[b][0]).all() and (c1[b] == exp[b][1]).all(), (v, ie, npw, b)
+
+
+PRUNED = [  # (c_i, c_o, h, w, f, stride): top inverse stages of c0 the layer lets the kernel prune at N = 8192
+    W.ConvSpec(40, 9, 7, 7, 3, 1, "7x7"),     # largest extracted index 60: 7 stages
+    W.ConvSpec(20, 7, 4, 4, 3, 1, "4x4"),     # index 21: 8 allowed, 7 instantiated
+    W.ConvSpec(16, 5, 8, 8, 3, 2, "8x8s2"),   # index 66: 6 allowed, 5 instantiated
+]
+
+
+@pytest.mark.parametrize("spec", PRUNED, ids=lambda s: s.name)
+def test_pruned_inverse_shapes_every_output(hc, spec):
+    """Small-map layers at N = 8192 whose extracted coefficients let the masked
+    inverse NTT prune its top 5 or 7 stages, in every inverse shape the
+    autotuner can pick (2^3, 2^4, 2^5 coefficients per thread; one or two
+    polynomials per workgroup; with and without the MAC's epilogue stages),
+    B = 3 (the last two-polynomial workgroup half empty): every output against
+    the oracle."""
+    N, L, t, B = 8192, 3, 2 ** 20, 3
+    c = _ctx(hc, N, L, t)
+    P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+    g = W.rng(77)
+    f = W.gen_filters(g, spec)
+    x = W.gen_ct_limbs(g, (B, P.G, 2), c.primes, N)
+    r = W.gen_mask(g, (B, spec.c_o, P.ho, P.wo), t)
+    ly = hc.Layer(c, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride, f)
+    exp = [conv.mask_extract(calg1.alg1_layer(x[b], f, P, c.primes), r[b], P, c.primes, t) for b in range(B)]
+    dx, dr = dev(x), dev(r)
+    ws = zeros((ly.workspace_words(B, True),))
+    cases = [(0, ie, 0, 0, 0, 0, 0, 0, npw) for ie in (3, 4, 5) for npw in (1, 2) if ie <= 4 or npw == 1]
+    cases += [mac_tuning(v, ie, npw) for v in MAC_VARIANTS if v[6] for ie, npw in ((3, 2), (4, 2), (4, 1))]
+    for tune in cases:
+        print(f"{spec.name} tuning {tune}", flush=True)
+        c.set_tuning(*tune)
+        c0, c1 = zeros(ly.c0_shape(B)), zeros(ly.c1_shape(B))
+        ly.conv_masked(dx, dr, c0, c1, B, ws)
+        c0, c1 = host(c0), host(c1)
+        for b in range(B):
+            assert (c0[b] == exp[b][0]).all() and (c1[b] == exp[b][1]).all(), (tune, b)
+
+
+def test_resnet18_cifar_every_output(hc):
+    """ResNet-18/CIFAR at N = 8192, 3 primes, t = 2^20, one image, one launch
+    sequence per layer with launch shapes autotuned at B = 1 (as the benchmark's
+    plain leg): every output coefficient of every layer (c0_ext and c1_out)
+    against the oracle (Algorithm 1 in C, then mask and extraction)."""
+    import torch
+    N, L, t, B = 8192, 3, 2 ** 20, 1
+    c = _ctx(hc, N, L, t)
+    specs = W.resnet18_cifar()
+    g = W.rng(1818)
+    filters = [W.gen_filters(g, s) for s in specs]
+    layers = [hc.Layer(c, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, f) for s, f in zip(specs, filters)]
+    plans = [layout.plan(N, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride) for s in specs]
+    xs = [W.gen_ct_limbs(g, (B, P.G, 2), c.primes, N) for P in plans]
+    rs = [W.gen_mask(g, (B, s.c_o, P.ho, P.wo), t) for s, P in zip(specs, plans)]
+    dx, dr = [dev(x) for x in xs], [dev(r) for r in rs]
+    c0 = [zeros(ly.c0_shape(B)) for ly in layers]
+    c1 = [zeros(ly.c1_shape(B)) for ly in layers]
+    bt = hc.Batch(c, layers, B)
+    print("autotune at B=1", flush=True)
+    bt.autotune(dx, dr, c0, c1)
+    bt.close()
+    ws = zeros((max(ly.workspace_words(B, True) for ly in layers),))
+    for k, (s, ly, P) in enumerate(zip(specs, layers, plans)):
+        assert ly.tuning()[0] == B
+        c0[k].zero_()
+        c1[k].zero_()
+        ly.conv_masked(dx[k], dr[k], c0[k], c1[k], B, ws)
+    torch.cuda.synchronize()
+    for k, (s, f, P) in enumerate(zip(specs, filters, plans)):
+        print(f"r18-cifar layer {k} {s.name}: every output", flush=True)
+        y = calg1.alg1_layer(xs[k][0], f, P, c.primes)
+        e0, e1 = conv.mask_extract(y, rs[k][0], P, c.primes, t)
+        assert (host(c0[k])[0] == e0).all(), f"layer {k}: c0_ext differs"
+        assert (host(c1[k])[0] == e1).all(), f"layer {k}: c1_out differs"
+    for ly in layers:
+        ly.close()
