@@ -14,11 +14,20 @@ masks) are resident in HBM before the timed region. Reported:
   plain_hybrid_ms_per_image  the plain path with Flash's coefficient-domain
                        conv (Algorithm 1 as written) on the layers where it
                        beats the NTT path at one image
-  speedup_vs_plain     plain / batched
+  speedup_vs_plain     best plain leg / batched (both legs autotuned for their
+                       own batch size)
   modmul_per_s         algorithmic modular multiplies (NTT butterflies + MAC)
                        per second, batched
+  valu_probe           register-only VALU rates measured on the device
+                       (hc_valu_probe): the lane rates behind the ALU peak
   roofline             the dominant kernel against the VALU / HBM ceiling
-  cpu_baseline         the CPU oracle (Algorithm 1 in C, OpenMP) on a sample
+  configs              the other workloads, each timed apart: ResNet-18/CIFAR
+                       on the plain per-layer path (one image), the serving
+                       sweep (Poisson arrivals of a ResNet-18/ResNet-50 mix),
+                       and ResNet-18 224x224 at N = 16384, 4 primes, 64 images
+                       as the batched graph
+  cpu_baseline         the CPU oracle (Algorithm 1 in C, OpenMP) on a sample,
+                       all host threads and one thread
   client               the client-side steps around the step, timed apart:
                        online encryption (Algorithm 2) of every layer's input
                        against HBM bandwidth, and decryption of every layer's
@@ -41,10 +50,16 @@ import time
 
 HBM_PEAK = 8.0e12                     # bytes/s, MI355X HBM3E
 CUS, CLK = 256, 2.4e9                 # compute units, peak engine clock
-SIMPLE_LANES, MUL_LANES = 128, 64     # 32-bit lane-ops per clock per CU: add/sub/cmp, and integer multiply
-# Ideal Harvey butterfly: 3 multiplies (mul_hi, 2 mul_lo: Shoup) + 5 simple ops.
-BFLY_PEAK = CUS * CLK / (3.0 / MUL_LANES + 5.0 / SIMPLE_LANES)
-# Ideal MAC term: one v_mad_u64_u32.
+# 32-bit lane-ops per clock per CU: add/sub/min, and integer multiply (mul_lo,
+# mul_hi, mad_u64_u32). The valu_probe object checks them on the device.
+SIMPLE_LANES, MUL_LANES = 128, 64
+# The inverse NTT's butterfly as compiled (Gentleman-Sande with a Shoup
+# twiddle, lazy [0, 2q)): 3 multiplies (mul_hi, 2 mul_lo) + 6 simple ops (sum,
+# its conditional subtraction as sub + min, difference + 2q as add + sub, and
+# the Shoup subtraction).
+BFLY_MULS, BFLY_SIMPLE = 3, 6
+BFLY_PEAK = CUS * CLK / (BFLY_MULS / MUL_LANES + BFLY_SIMPLE / SIMPLE_LANES)
+# MAC term: one v_mad_u64_u32.
 MAC_PEAK = CUS * CLK * MUL_LANES
 
 
@@ -72,6 +87,13 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="use the context's default launch shapes")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: layers found there are not re-timed, new results are appended")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (ResNet-18/CIFAR plain, serving, ResNet-18 224 at N=16384)")
+    ap.add_argument("--serve-rates", default="0.5,1.0", help="serving: offered load, fractions of saturation")
+    ap.add_argument("--serve-duration", type=float, default=1.5, help="serving: seconds of arrivals per rate")
+    ap.add_argument("--large-batch", type=int, default=64, help="ResNet-18 224x224 at N=16384: images per step")
+    ap.add_argument("--large-steps", type=int, default=10)
+    ap.add_argument("--no-probe", action="store_true", help="skip the register-only VALU probe")
     return ap.parse_args()
 
 
@@ -275,30 +297,188 @@ def protocol_pass(torch, dev, hconv, ctx, layers, ct_in, acts, B, tg, t_batch, p
     }
 
 
-def cpu_baseline(specs, N, L, t, frac, seed):
+def cpu_baseline(specs, N, L, t, frac, seed, frac_single=None):
     """The oracle (Algorithm 1 in C, OpenMP) on every layer for one image over
     the first ceil(frac * c_out) output channels; Algorithm 1's work is the same
-    for every output channel, so the time scales by c_out / sampled."""
+    for every output channel, so the time scales by c_out / sampled. Then the
+    same on one thread over ceil(frac_single * c_out) channels."""
     import numpy as np
     from oracle import calg1, layout, params
     from paper_2401_16732_amd import workloads as W
     primes = params.rns_primes(N, L)
-    g = W.rng(seed + 1)
-    total_s, sampled, full = 0.0, 0, 0
-    for spec in specs:
-        P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
-        f = W.gen_filters(g, spec)
-        x = W.gen_ct_limbs(g, (P.G, 2), primes, N)
-        n = max(1, math.ceil(frac * spec.c_o))
-        t0 = time.perf_counter()
-        calg1.alg1_layer(x, f, P, primes, outputs=np.arange(n))
-        dt = time.perf_counter() - t0
-        total_s += dt * spec.c_o / n
-        sampled += n
-        full += spec.c_o
-    return {"value": round(total_s * 1e3, 1), "unit": "ms/image", "cores": calg1.threads(), "kind": "oracle",
-            "sample": f"1 image, every layer, first {sampled} of {full} output channels "
-                      f"(~{frac:.4f} of the Algorithm 1 work), scaled by c_out/sampled per layer"}
+
+    def run(fr):
+        g = W.rng(seed + 1)
+        total_s, sampled, full = 0.0, 0, 0
+        for spec in specs:
+            P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+            f = W.gen_filters(g, spec)
+            x = W.gen_ct_limbs(g, (P.G, 2), primes, N)
+            n = max(1, math.ceil(fr * spec.c_o))
+            t0 = time.perf_counter()
+            calg1.alg1_layer(x, f, P, primes, outputs=np.arange(n))
+            dt = time.perf_counter() - t0
+            total_s += dt * spec.c_o / n
+            sampled += n
+            full += spec.c_o
+        return total_s, sampled, full
+
+    threads = calg1.threads()
+    total_s, sampled, full = run(frac)
+    out = {"value": round(total_s * 1e3, 1), "unit": "ms/image", "cores": threads, "kind": "oracle",
+           "sample": f"1 image, every layer, first {sampled} of {full} output channels "
+                     f"(~{sampled / full:.4f} of the Algorithm 1 work), scaled by c_out/sampled per layer",
+           "nproc": os.cpu_count(), "cpu_model": calg1.cpu_model(), "build": "gcc -O3 -march=native -fopenmp"}
+    if frac_single:
+        calg1.set_threads(1)
+        try:
+            s1, sampled1, _ = run(frac_single)
+        finally:
+            calg1.set_threads(threads)
+        out["single_thread"] = {"value": round(s1 * 1e3, 1), "unit": "ms/image", "cores": 1,
+                                "sample": f"first {sampled1} of {full} output channels, scaled the same way"}
+    return out
+
+
+def event_ms(torch, fn, reps):
+    """Mean ms of fn() over reps back-to-back calls on the current stream
+    (one untimed call first)."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def roofline_of(stage, tot, nlayers, bfly_peak, mac_peak):
+    """The dominant kernel (largest eager stage time) against its ceiling."""
+    names = [("ntt_fwd", stage[0], tot["bfly_fwd"], tot["bytes_fwd"]),
+             ("mac", stage[1], tot["mac"], tot["bytes_mac"]),
+             ("intt_mask_extract", stage[2], tot["bfly_inv"], tot["bytes_inv"])]
+    kname, kms, kops, kbytes = max(names, key=lambda r: r[1])
+    ops_peak = mac_peak if kname == "mac" else bfly_peak
+    t_alu, t_hbm = kops / ops_peak, kbytes / HBM_PEAK
+    if t_alu >= t_hbm:
+        ach = kops / (kms * 1e-3)
+        roof = {"bound": "alu", "achieved": round(ach / 1e12, 4), "peak": round(ops_peak / 1e12, 4),
+                "unit": "Tmac/s" if kname == "mac" else "Tbutterfly/s"}
+    else:
+        ach = kbytes / (kms * 1e-3)
+        roof = {"bound": "hbm", "achieved": round(ach / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["algorithmic_bytes_per_launch"] = round(kbytes / nlayers)
+    roof["kernel"] = kname
+    roof["launches"] = nlayers
+    roof["ms_total"] = round(kms, 3)
+    roof["algorithmic_ops"] = kops
+    roof["algorithmic_bytes"] = kbytes
+    roof["alu_frac"] = round(kops / (kms * 1e-3) / ops_peak, 4)
+    roof["hbm_frac"] = round(kbytes / (kms * 1e-3) / HBM_PEAK, 4)
+    return roof
+
+
+def autotune_single(hconv, ctx, layers, ct_in, mask, c0, c1):
+    """Autotune every layer for one image (the plain legs' batch size) on the
+    first image of the given buffers; the layers keep their other tunings."""
+    bt1 = hconv.Batch(ctx, layers, 1)
+    bt1.autotune([x[:1] for x in ct_in], [m[:1] for m in mask], [v[:1] for v in c0], [v[:1] for v in c1])
+    bt1.close()
+
+
+def cfg_resnet18_cifar(torch, dev, hconv, W, a, ctx, probe_peaks):
+    """ResNet-18/CIFAR at N = 8192, 3 primes, t = 2^20, one image, one launch
+    sequence per layer (the plain per-layer path), launch shapes autotuned for
+    one image. Returns the result object and the layers (kept for serving)."""
+    N, L, t = ctx.N, ctx.L, ctx.t
+    specs = W.resnet18_cifar()
+    g = W.rng(a.seed + 18)
+    layers = [hconv.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, W.gen_filters(g, s)) for s in specs]
+    tg = torch.Generator(device=dev)
+    tg.manual_seed(a.seed + 18)
+    B = 1
+    ct_in = [W.gen_ct_limbs_torch(tg, ly.in_shape(B)[:3], ctx.primes, N, dev) for ly in layers]
+    mask = [torch.randint(0, t, ly.mask_shape(B), generator=tg, device=dev, dtype=torch.int32) for ly in layers]
+    c0 = [torch.empty(ly.c0_shape(B), dtype=torch.int32, device=dev) for ly in layers]
+    c1 = [torch.empty(ly.c1_shape(B), dtype=torch.int32, device=dev) for ly in layers]
+    autotune_single(hconv, ctx, layers, ct_in, mask, c0, c1)
+    ws = torch.empty((max(ly.workspace_words(B, True) for ly in layers),), dtype=torch.int32, device=dev)
+
+    def one_image():
+        for k, ly in enumerate(layers):
+            ly.conv_masked(ct_in[k], mask[k], c0[k], c1[k], B, ws)
+
+    ms = event_ms(torch, one_image, 10)
+    tot = {}
+    for ly in layers:
+        for k, v in layer_counts(ly, B, N, L).items():
+            tot[k] = tot.get(k, 0) + v
+    bfly, mac = tot["bfly_fwd"] + tot["bfly_inv"], tot["mac"]
+    sec = ms * 1e-3
+    bytes_ = tot["bytes_path"] + tot["bytes_w"]
+    res = {"workload": "resnet18_cifar HE convolution, 20 conv layers, one image, per-layer launches",
+           "N": N, "L": L, "t": t, "batch": B, "layers": len(layers), "ms_per_image": round(ms, 4),
+           "modmul_per_s": round((bfly + mac + tot["mask"]) / sec, 1),
+           "alu_frac": round((bfly / probe_peaks[0] + mac / probe_peaks[1]) / sec, 4),
+           "hbm_frac": round(bytes_ / sec / HBM_PEAK, 4), "path_bytes": bytes_}
+    del ct_in, mask, c0, c1, ws
+    return res, layers
+
+
+def cfg_resnet18_224_large(torch, dev, hconv, W, a, probe_peaks):
+    """ResNet-18 224x224 at N = 16384, 4 primes, t = 2^24, B images as the
+    batched graph (mask add and extraction fused into the inverse NTT),
+    autotuned; ms per image and the dominant kernel's roofline."""
+    N, L, t, B = 16384, 4, 2 ** 24, a.large_batch
+    ctx = hconv.Context(N, L, t)
+    specs = W.resnet18_224()
+    g = W.rng(a.seed + 224)
+    t0 = time.perf_counter()
+    layers = [hconv.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, W.gen_filters(g, s)) for s in specs]
+    torch.cuda.synchronize()
+    enc_ms = (time.perf_counter() - t0) * 1e3
+    tg = torch.Generator(device=dev)
+    tg.manual_seed(a.seed + 224)
+    ct_in = [W.gen_ct_limbs_torch(tg, ly.in_shape(B)[:3], ctx.primes, N, dev) for ly in layers]
+    mask = [torch.randint(0, t, ly.mask_shape(B), generator=tg, device=dev, dtype=torch.int32) for ly in layers]
+    c0 = [torch.empty(ly.c0_shape(B), dtype=torch.int32, device=dev) for ly in layers]
+    c1 = [torch.empty(ly.c1_shape(B), dtype=torch.int32, device=dev) for ly in layers]
+    bt = hconv.Batch(ctx, layers, B)
+    t1 = time.perf_counter()
+    bt.autotune(ct_in, mask, c0, c1)
+    tune_ms = (time.perf_counter() - t1) * 1e3
+    ms = event_ms(torch, lambda: bt.run(ct_in, mask, c0, c1), a.large_steps)
+    acc = [0.0, 0.0, 0.0]
+    for _ in range(max(1, a.stage_passes)):
+        acc = [x + y for x, y in zip(acc, bt.run_timed(ct_in, mask, c0, c1))]
+    stage = [x / max(1, a.stage_passes) for x in acc]
+    tot = {}
+    for ly in layers:
+        for k, v in layer_counts(ly, B, N, L).items():
+            tot[k] = tot.get(k, 0) + v
+    bfly, mac = tot["bfly_fwd"] + tot["bfly_inv"], tot["mac"]
+    sec = ms * 1e-3
+    roof = roofline_of(stage, tot, len(layers), probe_peaks[0], probe_peaks[1])
+    res = {"workload": "resnet18_224 HE convolution, 20 conv layers, batched HIP graph",
+           "N": N, "L": L, "primes": ctx.primes, "t": t, "batch": B, "layers": len(layers),
+           "ms_per_step": round(ms, 3), "ms_per_image": round(ms / B, 4), "steps": a.large_steps,
+           "weight_encode_ms": round(enc_ms, 1), "autotune_ms": round(tune_ms, 1),
+           "stage_ms_eager": [round(v, 3) for v in stage],
+           "modmul_per_s": round((bfly + mac + tot["mask"]) / sec, 1),
+           "alu_frac": round((bfly / probe_peaks[0] + mac / probe_peaks[1]) / sec, 4),
+           "path_hbm_frac": round((tot["bytes_path"] + tot["bytes_w"]) / sec / HBM_PEAK, 4),
+           "roofline": roof}
+    bt.close()
+    for ly in layers:
+        ly.close()
+    del ct_in, mask, c0, c1
+    ctx.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -310,10 +490,33 @@ def main():
         return 2
     import torch
     from paper_2401_16732_amd import hconv
+    from paper_2401_16732_amd import serve as S
     from paper_2401_16732_amd import workloads as W
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    log = lambda s: print(f"[bench] {s}", file=sys.stderr, flush=True)
+
+    # register-only VALU rates of this device: the lane rates the ALU peaks assume
+    probe = None
+    if not a.no_probe:
+        r = hconv.valu_probe(0)
+        unit = CUS * CLK
+        probe = {"simple_lanes_per_clk_cu": round(r["simple_ops_per_s"] / unit, 2),
+                 "mul_lanes_per_clk_cu": round(r["mul_ops_per_s"] / unit, 2),
+                 "mad64_lanes_per_clk_cu": round(r["mad64_ops_per_s"] / unit, 2),
+                 "butterflies_per_s": round(r["butterflies_per_s"], 1),
+                 "butterfly_frac_of_peak": round(r["butterflies_per_s"] / BFLY_PEAK, 4),
+                 "mad64_per_s": round(r["mad64_ops_per_s"], 1),
+                 "device_compute_units": r["compute_units"], "device_clock_hz": r["clock_hz"],
+                 "assumed": {"simple_lanes_per_clk_cu": SIMPLE_LANES, "mul_lanes_per_clk_cu": MUL_LANES,
+                             "butterfly": f"{BFLY_MULS} multiplies + {BFLY_SIMPLE} simple ops",
+                             "bfly_peak": BFLY_PEAK, "mac_peak": MAC_PEAK}}
+        log(f"VALU probe: simple {probe['simple_lanes_per_clk_cu']} mul {probe['mul_lanes_per_clk_cu']} "
+            f"mad64 {probe['mad64_lanes_per_clk_cu']} lanes/clk/CU; butterflies {r['butterflies_per_s'] / 1e12:.3f} T/s "
+            f"({probe['butterfly_frac_of_peak']:.3f} of {BFLY_PEAK / 1e12:.3f} T)")
+    peaks = (BFLY_PEAK, MAC_PEAK)
+
     N, L, t, B = a.N, a.L, a.t, a.batch
     ctx = hconv.Context(N, L, t)
     specs = W.NETS[a.net]()
@@ -325,7 +528,7 @@ def main():
     layers = [hconv.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, W.gen_filters(g, s)) for s in specs]
     torch.cuda.synchronize()
     encode_ms = (time.perf_counter() - t0) * 1e3
-    print(f"[bench] {a.net}: {len(layers)} layers encoded in {encode_ms:.0f} ms", file=sys.stderr, flush=True)
+    log(f"{a.net}: {len(layers)} layers encoded in {encode_ms:.0f} ms")
 
     tg = torch.Generator(device=dev)
     tg.manual_seed(a.seed)
@@ -335,14 +538,13 @@ def main():
     c1 = [torch.empty(ly.c1_shape(B), dtype=torch.int32, device=dev) for ly in layers]
     bt = hconv.Batch(ctx, layers, B)
     torch.cuda.synchronize()
-    print(f"[bench] inputs resident; batch workspace {bt.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr,
-          flush=True)
+    log(f"inputs resident; batch workspace {bt.workspace_bytes / 2**30:.1f} GiB")
     tune_ms = None
     if not a.no_autotune:
         t1 = time.perf_counter()
         bt.autotune(ct_in, mask, c0, c1, cache_path=a.tune_cache)
         tune_ms = (time.perf_counter() - t1) * 1e3
-        print(f"[bench] autotuned {len(layers)} layers in {tune_ms:.0f} ms", file=sys.stderr, flush=True)
+        log(f"autotuned {len(layers)} layers in {tune_ms:.0f} ms")
 
     for _ in range(a.warmup):
         bt.run(ct_in, mask, c0, c1)
@@ -364,8 +566,7 @@ def main():
         per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps))
         q = lambda f: per[min(len(per) - 1, int(round(f * (len(per) - 1))))]
         spread = {"median": round(q(0.5), 3), "p10": round(q(0.1), 3), "p90": round(q(0.9), 3)}
-        print(f"[bench] batched: {ms_step:.2f} ms/step ({ms_step / B:.3f} ms/image), wall {wall_ms:.2f}",
-              file=sys.stderr, flush=True)
+        log(f"batched: {ms_step:.2f} ms/step ({ms_step / B:.3f} ms/image), wall {wall_ms:.2f}")
 
     # per-kernel stage times (eager, events around every launch on its stream)
     acc = [0.0, 0.0, 0.0]
@@ -374,10 +575,9 @@ def main():
         acc = [x + y for x, y in zip(acc, st)]
     stage = [x / max(1, a.stage_passes) for x in acc]
     torch.cuda.synchronize()
-    print(f"[bench] stages (eager, ms): fwd {stage[0]:.2f} mac {stage[1]:.2f} inv {stage[2]:.2f}",
-          file=sys.stderr, flush=True)
+    log(f"stages (eager, ms): fwd {stage[0]:.2f} mac {stage[1]:.2f} inv {stage[2]:.2f}")
     copy = hbm_copy(torch, dev, a.copy_gib)
-    print(f"[bench] HBM copy: {copy['GBps']} GB/s", file=sys.stderr, flush=True)
+    log(f"HBM copy: {copy['GBps']} GB/s")
 
     tot = {}
     for ly in layers:
@@ -385,10 +585,16 @@ def main():
             tot[k] = tot.get(k, 0) + v
     modmul = tot["bfly_fwd"] + tot["bfly_inv"] + tot["mac"] + tot["mask"]
 
-    # plain path: one launch sequence per layer, one image at a time
+    # plain path: one launch sequence per layer, one image at a time, with
+    # launch shapes autotuned for one image (the layers keep their B-image
+    # shapes for the batched graph)
     plain_ms = plain_hybrid_ms = None
     direct = []
     if not a.no_plain:
+        if not a.no_autotune:
+            t1 = time.perf_counter()
+            autotune_single(hconv, ctx, layers, ct_in, mask, c0, c1)
+            log(f"autotuned {len(layers)} layers for one image in {(time.perf_counter() - t1) * 1e3:.0f} ms")
         wsw = max(ly.workspace_words(1, True) for ly in layers)
         ws = torch.empty((wsw,), dtype=torch.int32, device=dev)
 
@@ -405,28 +611,17 @@ def main():
         p1.record()
         torch.cuda.synchronize()
         plain_ms = p0.elapsed_time(p1) / a.plain_images
-        print(f"[bench] plain: {plain_ms:.3f} ms/image", file=sys.stderr, flush=True)
+        log(f"plain: {plain_ms:.3f} ms/image")
 
         # the same plain path with Flash's coefficient-domain conv on the layers
         # where it is faster at one image: tried where c_n f^2 <= 4 (untiled),
         # kept where its events beat the NTT path's
-        def layer_ms(fn, reps=5):
-            fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                fn()
-            e1.record()
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / reps
-
         direct = []
         for k, ly in enumerate(layers):
             cand = not ly.layout.tiled and ly.layout.cn * ly.shape[4] ** 2 <= 4
             if cand:
-                tn = layer_ms(lambda: ly.conv_masked(ct_in[k][0], mask[k][0], c0[k][0], c1[k][0], 1, ws))
-                td = layer_ms(lambda: ly.conv_masked_direct(ct_in[k][0], mask[k][0], c0[k][0], c1[k][0], 1))
+                tn = event_ms(torch, lambda: ly.conv_masked(ct_in[k][0], mask[k][0], c0[k][0], c1[k][0], 1, ws), 5)
+                td = event_ms(torch, lambda: ly.conv_masked_direct(ct_in[k][0], mask[k][0], c0[k][0], c1[k][0], 1), 5)
                 if td < tn:
                     direct.append(k)
 
@@ -445,8 +640,8 @@ def main():
         p1.record()
         torch.cuda.synchronize()
         plain_hybrid_ms = p0.elapsed_time(p1) / a.plain_images
-        print(f"[bench] plain with the coefficient-domain conv on {len(direct)} layers: "
-              f"{plain_hybrid_ms:.3f} ms/image", file=sys.stderr, flush=True)
+        log(f"plain with the coefficient-domain conv on {len(direct)} layers: {plain_hybrid_ms:.3f} ms/image")
+        del ws
 
     client = protocol = None
     if not a.no_client:
@@ -455,51 +650,65 @@ def main():
                                  graphs=a.steps > 0)
         del acts
     if protocol is not None:
-        print(f"[bench] protocol: step 1 {protocol['act_pmult']['ms_per_image']:.3f} ms/image "
-              f"({protocol['act_pmult']['tbutterfly_per_s']} T butterflies/s), step 2 "
-              f"{protocol['act_combine']['ms_per_image']:.3f} ms/image "
-              f"({protocol['act_combine']['achieved_GBps']} GB/s)", file=sys.stderr, flush=True)
+        log(f"protocol: step 1 {protocol['act_pmult']['ms_per_image']:.3f} ms/image "
+            f"({protocol['act_pmult']['tbutterfly_per_s']} T butterflies/s), step 2 "
+            f"{protocol['act_combine']['ms_per_image']:.3f} ms/image ({protocol['act_combine']['achieved_GBps']} GB/s)")
     if client is not None:
-        print(f"[bench] client: encrypt {client['encrypt_online']['ms_per_image']:.3f} ms/image "
-              f"({client['encrypt_online']['achieved_GBps']} GB/s), decrypt "
-              f"{client['decrypt_extracted']['ms_per_image']:.3f} ms/image", file=sys.stderr, flush=True)
+        log(f"client: encrypt {client['encrypt_online']['ms_per_image']:.3f} ms/image "
+            f"({client['encrypt_online']['achieved_GBps']} GB/s), decrypt "
+            f"{client['decrypt_extracted']['ms_per_image']:.3f} ms/image")
 
     # roofline of the dominant kernel (largest stage time)
-    names = [("ntt_fwd", stage[0], tot["bfly_fwd"], tot["bytes_fwd"]),
-             ("mac", stage[1], tot["mac"], tot["bytes_mac"]),
-             ("intt_mask_extract", stage[2], tot["bfly_inv"], tot["bytes_inv"])]
-    kname, kms, kops, kbytes = max(names, key=lambda r: r[1])
-    ops_peak = MAC_PEAK if kname == "mac" else BFLY_PEAK
-    t_alu, t_hbm = kops / ops_peak, kbytes / HBM_PEAK
-    if t_alu >= t_hbm:
-        ach = kops / (kms * 1e-3)
-        roof = {"bound": "alu", "achieved": round(ach / 1e12, 4), "peak": round(ops_peak / 1e12, 4),
-                "unit": "Tmac/s" if kname == "mac" else "Tbutterfly/s"}
-    else:
-        ach = kbytes / (kms * 1e-3)
-        roof = {"bound": "hbm", "achieved": round(ach / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    traffic = measured_traffic(kname, f"resnet50_b{B}") if a.net == "resnet50_224" else None
+    roof = roofline_of(stage, tot, len(layers), *peaks)
+    traffic = measured_traffic(roof["kernel"], f"resnet50_b{B}") if a.net == "resnet50_224" else None
     roof["traffic"] = None if traffic is None else round(traffic)
     roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-    roof["algorithmic_bytes_per_launch"] = round(kbytes / len(layers))
-    roof["kernel"] = kname
-    roof["launches"] = len(layers)
-    roof["ms_total"] = round(kms, 3)
-    roof["algorithmic_ops"] = kops
-    roof["algorithmic_bytes"] = kbytes
-    roof["alu_frac"] = round(kops / (kms * 1e-3) / ops_peak, 4)
-    roof["hbm_frac"] = round(kbytes / (kms * 1e-3) / HBM_PEAK, 4)
+    if probe is not None:
+        kpeak = probe["mad64_per_s"] if roof["kernel"] == "mac" else probe["butterflies_per_s"]
+        ach = roof["algorithmic_ops"] / (roof["ms_total"] * 1e-3)
+        roof["frac_of_probe"] = round(ach / kpeak, 4)
+    whole_alu = ((tot["bfly_fwd"] + tot["bfly_inv"]) / peaks[0] + tot["mac"] / peaks[1]) / (ms_step * 1e-3)
+
+    # the other workloads, after the headline's buffers are released
+    configs = None
+    if not a.no_configs and a.steps > 0 and a.net == "resnet50_224":
+        bt.close()
+        del ct_in, mask, c0, c1
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        configs = {}
+        r18, r18_layers = cfg_resnet18_cifar(torch, dev, hconv, W, a, ctx, peaks)
+        configs["resnet18_cifar_plain"] = r18
+        log(f"resnet18_cifar plain: {r18['ms_per_image']:.3f} ms/image")
+        sv = S.sweep(hconv, W, ctx, {"resnet18_cifar": r18_layers, "resnet50_224": layers}, mix=0.5,
+                     rates=[float(v) for v in a.serve_rates.split(",")], duration=a.serve_duration,
+                     arena_gib=48.0, max_batch=16, streams=4, max_inflight=8, burst=32, sets=2, seed=a.seed,
+                     bfly_peak=peaks[0], mac_peak=peaks[1])
+        sv["workload"] = ("serving: Poisson arrivals, 50% ResNet-50 224x224 / 50% ResNet-18 32x32 requests, "
+                          "N=8192, 3 primes, continuous batching")
+        configs["serving"] = sv
+        log(f"serving: saturation {sv['saturation']['requests_per_s']} req/s; " + ", ".join(
+            f"{r['rate_fraction']}x: p50 {r['p50_ms']} p99 {r['p99_ms']} ms" for r in sv["rates"]))
+        for ly in r18_layers + layers:
+            ly.close()
+        layers = []
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        big = cfg_resnet18_224_large(torch, dev, hconv, W, a, peaks)
+        configs["resnet18_224_n16384"] = big
+        log(f"resnet18_224 N=16384 B={big['batch']}: {big['ms_per_image']:.3f} ms/image, "
+            f"{big['roofline']['kernel']} {big['roofline']['frac']}")
 
     cpu = None
     if not a.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(specs, N, L, t, a.cpu_fraction, a.seed)
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(specs, N, L, t, a.cpu_fraction, a.seed, frac_single=a.cpu_fraction / 16)
 
     per_img = ms_step / B
     if a.steps == 0:
         print(json.dumps({"profile_pass": True, "stage_ms_eager": stage, "hbm_copy": copy}), flush=True)
         return 0
+    best_plain = min(v for v in (plain_ms, plain_hybrid_ms) if v is not None) if plain_ms is not None else None
     out = {
         "metric": "HE-conv ms per ResNet-50 image + NTT modmul/s vs roofline, batched vs plain",
         "value": round(per_img, 4),
@@ -514,25 +723,29 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{a.net} HE convolution, all {len(layers)} conv layers, batched HIP graph",
-                   "N": N, "L": L, "primes": ctx.primes, "t": t, "batch": B, "layers": len(layers),
+        "config": {"workload": f"{a.net} HE convolution, all {len(specs)} conv layers, batched HIP graph",
+                   "N": N, "L": L, "primes": ctx.primes, "t": t, "batch": B, "layers": len(specs),
                    "parallelism": "single GPU"},
         "images_per_s": round(1e3 / per_img, 2),
         "modmul_per_s": round(modmul / (ms_step * 1e-3), 1),
+        "whole_step_alu_frac": round(whole_alu, 4),
         "plain_ms_per_image": None if plain_ms is None else round(plain_ms, 4),
-        "speedup_vs_plain": None if plain_ms is None else round(plain_ms / per_img, 3),
         "plain_hybrid_ms_per_image": None if plain_hybrid_ms is None else round(plain_hybrid_ms, 4),
         "plain_hybrid_direct_layers": direct,
+        "speedup_vs_plain": None if best_plain is None else round(best_plain / per_img, 3),
+        "speedup_vs_plain_ntt_only": None if plain_ms is None else round(plain_ms / per_img, 3),
         "weight_encode_ms": round(encode_ms, 1),
         "autotune_ms": None if tune_ms is None else round(tune_ms, 1),
         "stage_ms_eager": [round(v, 3) for v in stage],
         "path_bytes_per_step": tot["bytes_path"] + tot["bytes_w"],
         "path_hbm_frac": round((tot["bytes_path"] + tot["bytes_w"]) / (ms_step * 1e-3) / HBM_PEAK, 4),
         "hbm_copy": copy,
+        "valu_probe": probe,
         "roofline": roof,
         "cpu_baseline": cpu,
         "client": client,
         "protocol": protocol,
+        "configs": configs,
     }
     print(json.dumps(out), flush=True)
     return 0

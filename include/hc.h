@@ -219,8 +219,14 @@ void hc_batch_destroy(hc_batch *batch);
 hc_status hc_batch_autotune(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
                             uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream, const char *cache_path);
 /* A layer's autotuned shapes and the batch size they apply to (0: none); clearing
- * returns the layer to the context's shapes. */
+ * removes every stored set and returns the layer to the context's shapes. */
 hc_status hc_layer_get_tuning(const hc_layer *layer, uint32_t *batch_size, hc_tuning *out);
+/* A layer keeps up to 4 autotuned shape sets, one per batch size (e.g. the
+ * batched graph's and a single image's); runs of B images use the set tuned
+ * for B, if any, else the context's. hc_layer_get_tuning gives the set stored
+ * last; hc_layer_get_tuning_for the one for `batch_size` (HC_ESTATE and an
+ * all-zero *out when there is none). */
+hc_status hc_layer_get_tuning_for(const hc_layer *layer, uint32_t batch_size, hc_tuning *out);
 hc_status hc_layer_clear_tuning(hc_layer *layer);
 
 /* hc_batch_run_eager with a HIP event recorded on `stream` before and after
@@ -405,6 +411,28 @@ hc_status hc_act_combine(const hc_layer *layer, const uint32_t *ct_x, const uint
  * (HC_EUNSUPPORTED otherwise). Enqueued on `stream`; no allocation. */
 hc_status hc_conv_masked_direct(const hc_layer *layer, const uint32_t *ct_in, const uint32_t *mask, uint32_t *c0_ext,
                                 uint32_t *c1_out, uint32_t B, void *stream);
+
+/* ------------------------------------------------------------ measurement
+ * Register-only VALU rate probes on HIP device `hip_device`, the ceilings the
+ * kernels' roofline is priced against: independent chains of one instruction
+ * class in registers, no memory traffic in the timed loop, 8 four-wave
+ * workgroups per compute unit; one warm-up launch, then one launch timed with
+ * HIP events. Rates are lane-operations (or butterflies) per second over the
+ * whole device:
+ *   simple_ops_per_s   32-bit integer add / sub
+ *   mul_ops_per_s      32-bit integer multiply, low and high halves
+ *   mad64_ops_per_s    v_mad_u64_u32 (the multiply-accumulate's instruction)
+ *   butterflies_per_s  the inverse NTT's butterfly (Gentleman-Sande, Shoup
+ *                      twiddle, lazy [0, 2q) range), compiled from the same
+ *                      code as the inverse NTT kernels
+ * compute_units and clock_hz are the device's reported unit count and peak
+ * engine clock. Synchronous; allocates and frees a few bytes of device memory. */
+typedef struct {
+    double simple_ops_per_s, mul_ops_per_s, mad64_ops_per_s, butterflies_per_s;
+    uint32_t compute_units;
+    double clock_hz;
+} hc_valu_rates;
+hc_status hc_valu_probe(int hip_device, hc_valu_rates *out);
 
 /* Wait for all work on the context's device; reports earlier asynchronous faults. */
 hc_status hc_sync(hc_ctx *ctx);

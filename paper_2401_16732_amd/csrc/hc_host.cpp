@@ -273,10 +273,29 @@ hc::Shapes hc::shapes_for(const hc_ctx &c, uint32_t B) {
   return s;
 }
 
+const hc_tuning *hc::layer_tuning_for(const hc_layer *ly, uint32_t B) {
+  if (B == 0) return nullptr;
+  for (const auto &sl : ly->tunes)
+    if (sl.B == B) return &sl.t;
+  return nullptr;
+}
+
+void hc::layer_set_tuning(hc_layer *ly, uint32_t B, const hc_tuning &t) {
+  int k = -1;
+  for (int i = 0; i < hc_layer::kTuneSlots && k < 0; ++i)
+    if (ly->tunes[i].B == B) k = i;
+  for (int i = 0; i < hc_layer::kTuneSlots && k < 0; ++i)
+    if (ly->tunes[i].B == 0) k = i;
+  if (k < 0) k = (ly->tune_last + 1) % hc_layer::kTuneSlots;  // slots fill in order: the next is the oldest
+  ly->tunes[k].B = B;
+  ly->tunes[k].t = t;
+  ly->tune_last = k;
+}
+
 hc::Shapes hc::layer_shapes(const hc_layer *ly, uint32_t B) {
   hc::Shapes s = shapes_for(*ly->ctx, B);
-  if (ly->tune_B == B) {
-    const hc_tuning &t = ly->tune;
+  if (const hc_tuning *tp = layer_tuning_for(ly, B)) {
+    const hc_tuning &t = *tp;
     if (t.fwd_elog) s.fe = t.fwd_elog;
     if (t.inv_elog) s.ie = t.inv_elog;
     if (t.inv_polys) s.ipw = t.inv_polys;
@@ -994,8 +1013,7 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
       if (hc::ntt_variant_ok(c.logn, t.fwd_elog) &&
           hc::intt_masked_ok(c.logn, t.inv_elog, t.inv_polys ? t.inv_polys : 1, t.mac_pre) &&
           hc::mac_variant_ok(hc::mac_of(t)) && hc::mac_offsets_fit(ly->geom, hc::mac_of(t))) {
-        ly->tune = t;
-        ly->tune_B = B;
+        hc::layer_set_tuning(ly, B, t);
         continue;
       }
     }
@@ -1049,8 +1067,7 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
       }
       if (mac_ms + inv_ms < best_total) best_total = mac_ms + inv_ms, best = t;
     }
-    ly->tune = best;
-    ly->tune_B = B;
+    hc::layer_set_tuning(ly, B, best);
     char buf[128];
     std::snprintf(buf, sizeof(buf), "|%u %u %u %u %u %u %u %u %u %u\n", best.fwd_elog, best.inv_elog,
                   best.mac_rows, best.mac_cols, best.mac_row_groups, best.mac_col_groups, best.mac_depth,
@@ -1073,15 +1090,27 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
 
 hc_status hc_layer_get_tuning(const hc_layer *ly, uint32_t *B, hc_tuning *out) {
   if (!ly || !B || !out) return fail(HC_EINVAL, "null argument");
-  *B = ly->tune_B;
-  *out = ly->tune;
+  if (ly->tune_last < 0) {
+    *B = 0;
+    *out = hc_tuning{};
+  } else {
+    *B = ly->tunes[ly->tune_last].B;
+    *out = ly->tunes[ly->tune_last].t;
+  }
   return HC_OK;
+}
+
+hc_status hc_layer_get_tuning_for(const hc_layer *ly, uint32_t B, hc_tuning *out) {
+  if (!ly || !out) return fail(HC_EINVAL, "null argument");
+  const hc_tuning *t = hc::layer_tuning_for(ly, B);
+  *out = t ? *t : hc_tuning{};
+  return t ? HC_OK : HC_ESTATE;
 }
 
 hc_status hc_layer_clear_tuning(hc_layer *ly) {
   if (!ly) return fail(HC_EINVAL, "null argument");
-  ly->tune = hc_tuning{};
-  ly->tune_B = 0;
+  for (auto &sl : ly->tunes) sl = hc_layer::TuneSlot{};
+  ly->tune_last = -1;
   return HC_OK;
 }
 

@@ -115,6 +115,10 @@ hipError_t launch_mask_extract(const ConvGeom &g, const uint32_t *ct_out, const 
 // that are >= the prime of their limb.
 hipError_t launch_count_noncanonical(const uint32_t *p, size_t np, uint32_t N, const LimbConsts &k,
                                      unsigned long long *count, hipStream_t st);
+// Register-only VALU probe `kind` (0 simple add/sub, 1 mul_lo/mul_hi, 2
+// mad_u64_u32, 3 inverse butterflies) over nwg workgroups of 256 threads.
+hipError_t launch_probe(int kind, uint32_t nwg, uint32_t iters, uint32_t q, const uint2 *tw, uint32_t *out,
+                        hipStream_t st);
 hipError_t launch_pointwise_mul(const uint32_t *a, const uint32_t *b, uint32_t *c, size_t npolys, uint32_t N,
                                 const LimbConsts &k, hipStream_t st);
 

@@ -37,8 +37,14 @@ struct hc_layer {
   int32_t *d_wt = nullptr;  // [wt_rows][c_in][f f] int32 filters (coefficient-domain conv)
   uint32_t wt_rows = 0;     // c_out rounded up to a multiple of 16, extra rows zero
   bool direct_one = false;  // the coefficient-domain conv is the faster path for one image
-  hc_tuning tune{};         // per-layer launch shapes chosen by the autotuner ...
-  uint32_t tune_B = 0;      // ... for this batch size (0: none)
+  // per-layer launch shapes chosen by the autotuner, one set per batch size
+  // (a few sizes: e.g. the batched graph's and one image's)
+  static constexpr int kTuneSlots = 4;
+  struct TuneSlot {
+    uint32_t B = 0;  // 0: empty
+    hc_tuning t{};
+  } tunes[kTuneSlots];
+  int tune_last = -1;  // slot set most recently
 };
 
 
@@ -60,6 +66,10 @@ inline MacShape mac_of(const hc_tuning &t) {
 }
 // The layer's autotuned shapes when tuned for B images, else the context's.
 Shapes layer_shapes(const hc_layer *ly, uint32_t B);
+// The layer's tuning for B images (nullptr: none); storing one for B replaces
+// an earlier one for B, else takes a free slot, else the oldest.
+const hc_tuning *layer_tuning_for(const hc_layer *ly, uint32_t B);
+void layer_set_tuning(hc_layer *ly, uint32_t B, const hc_tuning &t);
 
 // Constants of the exact decryption rounding for primes q[0..L) and t.
 DecodeConsts make_decode_consts(const uint32_t *q, uint32_t L, uint64_t t);

@@ -29,6 +29,7 @@ SYMBOLS = [
     "hc_server_create", "hc_server_add_net", "hc_server_request_bytes", "hc_server_submit", "hc_server_step",
     "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
     "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
+    "hc_layer_get_tuning_for", "hc_valu_probe",
     "hc_check_residues", "hc_encrypt_online", "hc_decrypt_workspace_size", "hc_decrypt_extracted", "hc_decrypt",
     "hc_encrypt_zero", "hc_batch_encode", "hc_batch_decode", "hc_encrypt_plain", "hc_act_workspace_size",
     "hc_act_pmult", "hc_act_combine", "hc_conv_masked_direct",
@@ -128,6 +129,8 @@ def load(path: str = LIB_PATH):
         "hc_batch_autotune": (I, [P, P, P, P, P, P, ctypes.c_char_p]),
         "hc_layer_get_tuning": (I, [P, P, P]),
         "hc_layer_clear_tuning": (I, [P]),
+        "hc_layer_get_tuning_for": (I, [P, u32, P]),
+        "hc_valu_probe": (I, [I, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -167,6 +170,23 @@ def plan_ring(N, c_in, c_out, h, w, f, stride=1) -> Layout:
     sh = ConvShape(c_in, c_out, h, w, f, stride)
     _check(_lib.hc_plan_ring(N, ctypes.byref(sh), ctypes.byref(lay)), "hc_plan_ring")
     return lay
+
+
+class ValuRates(ctypes.Structure):
+    _fields_ = [("simple_ops_per_s", ctypes.c_double), ("mul_ops_per_s", ctypes.c_double),
+                ("mad64_ops_per_s", ctypes.c_double), ("butterflies_per_s", ctypes.c_double),
+                ("compute_units", ctypes.c_uint32), ("clock_hz", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def valu_probe(device: int = 0) -> dict:
+    """Register-only VALU rates of the device (hc_valu_probe)."""
+    load()
+    r = ValuRates()
+    _check(_lib.hc_valu_probe(device, ctypes.byref(r)), "hc_valu_probe")
+    return r.as_dict()
 
 
 def ring_params(N: int, L: int, t: int):
@@ -436,13 +456,20 @@ class Layer:
                                           _dptr(c0_ext, "c0_ext", d), _dptr(c1_out, "c1_out", d), B,
                                           _stream(stream)), "hc_conv_masked_direct")
 
-    def tuning(self):
+    def tuning(self, B: Optional[int] = None):
         """(batch size, (fwd_elog, inv_elog, mac_rows, mac_cols, mac_row_groups, mac_col_groups, mac_depth,
-        mac_lds, inv_polys, mac_pre)) or (0, ...)."""
-        B = ctypes.c_uint32()
+        mac_lds, inv_polys, mac_pre)) of the set stored last, or of the set for B images when B is given;
+        (0, (0, ...)) when there is none."""
         t = Tuning()
-        _check(_lib.hc_layer_get_tuning(self.h, ctypes.byref(B), ctypes.byref(t)), "hc_layer_get_tuning")
-        return B.value, t.as_tuple()
+        if B is not None:
+            st = _lib.hc_layer_get_tuning_for(self.h, B, ctypes.byref(t))
+            if st == -5:
+                return 0, t.as_tuple()
+            _check(st, "hc_layer_get_tuning_for")
+            return B, t.as_tuple()
+        Bv = ctypes.c_uint32()
+        _check(_lib.hc_layer_get_tuning(self.h, ctypes.byref(Bv), ctypes.byref(t)), "hc_layer_get_tuning")
+        return Bv.value, t.as_tuple()
 
     def clear_tuning(self):
         _check(_lib.hc_layer_clear_tuning(self.h), "hc_layer_clear_tuning")
