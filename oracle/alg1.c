@@ -244,3 +244,23 @@ int oracle_set_threads(int nthreads)
     return 1;
 #endif
 }
+
+/*
+ * Schoolbook negacyclic product c = a b mod (x^n + 1, q) of residue vectors
+ * (a[i], b[j] < q < 2^31): c_k = sum_{i+j=k} a_i b_j - sum_{i+j=k+n} a_i b_j,
+ * summed in unsigned 128-bit integers (positive and negative parts apart) and
+ * reduced once per coefficient.
+ */
+void oracle_negacyclic_mul(uint32_t n, uint64_t q, const uint64_t *a, const uint64_t *b, uint64_t *c)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < (int64_t)n; ++k) {
+        unsigned __int128 pos = 0, neg = 0;
+        for (uint32_t i = 0; i <= (uint32_t)k; ++i)
+            pos += (unsigned __int128)a[i] * b[k - i];
+        for (uint32_t i = (uint32_t)k + 1; i < n; ++i)
+            neg += (unsigned __int128)a[i] * b[(uint32_t)k + n - i];
+        uint64_t p = (uint64_t)(pos % q), m = (uint64_t)(neg % q);
+        c[k] = p >= m ? p - m : p + q - m;
+    }
+}

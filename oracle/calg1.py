@@ -50,7 +50,7 @@ _LIB = os.path.join(_HERE, f"_alg1_{_cpu_key()}.so")
 
 def build() -> str:
     tmp = f"{_LIB}.tmp{os.getpid()}"
-    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-shared", "-fPIC", "-std=c99", "-Wall", "-o", tmp, _SRC]
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-shared", "-fPIC", "-std=gnu99", "-Wall", "-o", tmp, _SRC]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
     return _LIB
@@ -73,6 +73,8 @@ def load():
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_freivalds.restype = None
     lib.oracle_freivalds.argtypes = [u32, u32, P, u32, u32, u32, u32, P, P, P, P, P, P, P]
+    lib.oracle_negacyclic_mul.restype = None
+    lib.oracle_negacyclic_mul.argtypes = [u32, ctypes.c_uint64, P, P, P]
     lib.oracle_alg1_points.restype = None
     lib.oracle_alg1_points.argtypes = [u32, u32, P, u32, u32, u32, P, P, P, P, P, ctypes.c_uint64,
                                        P, P, P, P, P, P]
@@ -150,3 +152,15 @@ def freivalds_rhs(x, filters, rho, P: Plan, primes: Sequence[int]) -> np.ndarray
     lib.oracle_freivalds(P.n, len(primes), _ptr(q), P.c_i, P.c_o, P.T, len(taps), _ptr(taps), _ptr(chan),
                          _ptr(in_ct), _ptr(f), _ptr(x), _ptr(r), _ptr(z))
     return z
+
+
+def negacyclic_mul(a, b, q: int) -> np.ndarray:
+    """Schoolbook a(x) b(x) mod (x^n + 1, q) (C, 128-bit sums): the same
+    definition as ring.negacyclic_mul, faster for n in the thousands."""
+    lib = load()
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int64) % q, dtype=np.uint64)
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.int64) % q, dtype=np.uint64)
+    assert a.shape == b.shape and a.ndim == 1
+    c = np.empty_like(a)
+    lib.oracle_negacyclic_mul(a.shape[0], int(q), _ptr(a), _ptr(b), _ptr(c))
+    return c.astype(np.int64)

@@ -27,7 +27,8 @@ Readings (the paper leaves these open):
   * the digits are taken of c1 before the automorphism (the paper's order:
     decompose, transform, automorphism, key switch), so one decomposition
     serves every rotation of a ciphertext.
-Products are the schoolbook negacyclic product (oracle.ring); no NTT.
+Products are the schoolbook negacyclic product (the C form of oracle.ring's,
+oracle.calg1.negacyclic_mul); no NTT.
 """
 from __future__ import annotations
 
@@ -36,8 +37,8 @@ from typing import List, Sequence
 import numpy as np
 
 from .batch import slot_root
+from .calg1 import negacyclic_mul
 from .params import centred, modulus
-from .ring import negacyclic_mul
 
 
 # ---------------------------------------------------------------- slots in rotation order

@@ -14,7 +14,7 @@ the mathematics fixes, not against a retyping of itself:
 import numpy as np
 import pytest
 
-from oracle import batch, bfv, conv, hrot, params, ring
+from oracle import batch, bfv, calg1, conv, hrot, params, ring
 from paper_2401_16732_amd import workloads as W
 
 
@@ -38,6 +38,17 @@ def test_slot_exponents_and_rotation_order_match_batch_slots(n, t):
     assert (hrot.rot_encode(zr, t, n) == p).all()
     z = g.integers(0, t, size=(2, n // 2))
     assert (hrot.rot_decode(hrot.rot_encode(z, t, n), t, n) == z).all()
+
+
+@pytest.mark.parametrize("n", [16, 64, 1024])
+def test_c_negacyclic_product_equals_schoolbook(n):
+    """The C product the HRot oracle uses equals ring.negacyclic_mul (pinned to
+    sympy and brute force elsewhere), also at the largest residues."""
+    q = _primes(max(n, 64), 1)[0]
+    g = W.rng(n + 7)
+    a, b = g.integers(0, q, size=n), g.integers(0, q, size=n)
+    a[0] = b[-1] = q - 1
+    assert (calg1.negacyclic_mul(a, b, q) == ring.negacyclic_mul(a, b, q)).all()
 
 
 @pytest.mark.parametrize("n", [64, 128])
