@@ -24,8 +24,9 @@ masks) are resident in HBM before the timed region. Reported:
   configs              the other workloads, each timed apart: ResNet-18/CIFAR
                        on the plain per-layer path (one image), the serving
                        sweep (Poisson arrivals of a ResNet-18/ResNet-50 mix),
-                       and ResNet-18 224x224 at N = 16384, 4 primes, 64 images
-                       as the batched graph
+                       ResNet-18 224x224 at N = 16384, 4 primes, 64 images
+                       as the batched graph, and the conventional (HRot/PMult)
+                       convolution against this path on Table 9's layer shapes
   cpu_baseline         the CPU oracle (Algorithm 1 in C, OpenMP) on a sample,
                        all host threads and one thread
   client               the client-side steps around the step, timed apart:
@@ -94,6 +95,8 @@ def parse():
     ap.add_argument("--large-batch", type=int, default=64, help="ResNet-18 224x224 at N=16384: images per step")
     ap.add_argument("--large-steps", type=int, default=10)
     ap.add_argument("--no-probe", action="store_true", help="skip the register-only VALU probe")
+    ap.add_argument("--no-conventional", action="store_true",
+                    help="skip the conventional (HRot/PMult) convolution's Table 9 comparison")
     return ap.parse_args()
 
 
@@ -481,6 +484,65 @@ def cfg_resnet18_224_large(torch, dev, hconv, W, a, probe_peaks):
     return res
 
 
+# Table 9 layer shapes (H x W, c_in, c_out, f) whose image fits one slot row at N = 8192
+TABLE9 = [((64, 64), 64, 64, 3), ((64, 64), 3, 64, 7), ((56, 56), 256, 256, 3), ((32, 32), 16, 16, 3),
+          ((32, 32), 128, 128, 3), ((28, 28), 512, 512, 3), ((16, 16), 64, 64, 3), ((16, 16), 256, 256, 3),
+          ((8, 8), 128, 128, 3), ((8, 8), 512, 512, 3), ((4, 4), 512, 512, 3)]
+# the paper's conventional / best-DRot time ratio for the same shapes (CPU, n = 2048)
+TABLE9_PAPER_RATIO = [55.7, 29.4, 94.3, 92.7, 78.5, 93.5, 30.6, 33.3, 10.2, 12.6, 4.0]
+
+
+def conventional_vs_drot(torch, dev, hconv, W, a):
+    """The conventional convolution (batch encoding, HRot with 10-bit digit key
+    switching, PMult) against this library's direct-encoding convolution on
+    Table 9's layer shapes at N = 8192, 3 primes, t = 786433, one image: ms per
+    layer and their ratio, next to the paper's CPU ratio."""
+    N, L, t, T = 8192, 3, 786433, 10
+    ctx = hconv.Context(N, L, t)
+    rows = []
+    g = W.rng(a.seed + 9)
+    tg = torch.Generator(device=dev)
+    tg.manual_seed(a.seed + 9)
+    for ((h, w), ci, co, f), paper in zip(TABLE9, TABLE9_PAPER_RATIO):
+        filt = g.integers(-128, 128, size=(co, ci, f, f)).astype("int8")
+        cc = hconv.CConv(ctx, ci, co, h, w, f, filt, T)
+        R, LD = cc.layout.rotations, cc.layout.digits
+        s = torch.randint(-1, 2, (N,), generator=tg, device=dev, dtype=torch.int64)
+        sk = torch.stack([torch.remainder(s, q) for q in ctx.primes]).to(torch.int32).contiguous()
+        keys = torch.empty((cc.keys_words(),), dtype=torch.int32, device=dev)
+        ka = W.gen_ct_limbs_torch(tg, (R * LD,), ctx.primes, N, dev)
+        ke = torch.randint(-8, 9, (R * LD, N), generator=tg, device=dev, dtype=torch.int32)
+        kws = torch.empty((cc.keygen_workspace_words(),), dtype=torch.int32, device=dev)
+        cc.keygen(sk, ka, ke, keys, kws)
+        del ka, ke, kws
+        ct = W.gen_ct_limbs_torch(tg, (1, cc.layout.g_in, 2), ctx.primes, N, dev)
+        out = torch.empty((1, cc.layout.g_out, 2, L, N), dtype=torch.int32, device=dev)
+        ws = torch.empty((cc.workspace_words(1),), dtype=torch.int32, device=dev)
+        conv_ms = event_ms(torch, lambda: cc.run(keys, ct, out, 1, ws), 3)
+        del ct, out, ws, keys
+        cc.close()
+        ly = hconv.Layer(ctx, ci, co, h, w, f, 1, filt)
+        x = W.gen_ct_limbs_torch(tg, ly.in_shape(1)[:3], ctx.primes, N, dev)
+        m = torch.randint(0, t, ly.mask_shape(1), generator=tg, device=dev, dtype=torch.int32)
+        c0 = torch.empty(ly.c0_shape(1), dtype=torch.int32, device=dev)
+        c1 = torch.empty(ly.c1_shape(1), dtype=torch.int32, device=dev)
+        lws = torch.empty((ly.workspace_words(1, True),), dtype=torch.int32, device=dev)
+        drot_ms = event_ms(torch, lambda: ly.conv_masked(x, m, c0, c1, 1, lws), 5)
+        if not ly.layout.tiled and ci * f * f <= 2 ** 17:
+            drot_ms = min(drot_ms, event_ms(torch, lambda: ly.conv_masked_direct(x, m, c0, c1, 1), 5))
+        ly.close()
+        del x, m, c0, c1, lws
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        rows.append({"hw": [h, w], "c_in": ci, "c_out": co, "f": f, "rotations": R,
+                     "conventional_ms": round(conv_ms, 4), "drot_ms": round(drot_ms, 4),
+                     "ratio": round(conv_ms / drot_ms, 2), "paper_cpu_ratio": paper})
+    ctx.close()
+    return {"workload": "Table 9 layer shapes (h w <= N/2), one image, N=8192, 3 primes, t=786433, "
+                        "10-bit digits; DRot path = the faster of the NTT path and the coefficient-domain conv",
+            "rows": rows}
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -509,10 +571,12 @@ def main():
                  "butterfly_frac_of_peak": round(r["butterflies_per_s"] / BFLY_PEAK, 4),
                  "mad64_per_s": round(r["mad64_ops_per_s"], 1),
                  "device_compute_units": r["compute_units"], "device_clock_hz": r["clock_hz"],
+                 "measured_clock_hz": round(r["measured_clock_hz"], 1),
                  "assumed": {"simple_lanes_per_clk_cu": SIMPLE_LANES, "mul_lanes_per_clk_cu": MUL_LANES,
                              "butterfly": f"{BFLY_MULS} multiplies + {BFLY_SIMPLE} simple ops",
                              "bfly_peak": BFLY_PEAK, "mac_peak": MAC_PEAK}}
-        log(f"VALU probe: simple {probe['simple_lanes_per_clk_cu']} mul {probe['mul_lanes_per_clk_cu']} "
+        log(f"VALU probe: clock {r['measured_clock_hz'] / 1e9:.3f} GHz; simple {probe['simple_lanes_per_clk_cu']} "
+            f"mul {probe['mul_lanes_per_clk_cu']} "
             f"mad64 {probe['mad64_lanes_per_clk_cu']} lanes/clk/CU; butterflies {r['butterflies_per_s'] / 1e12:.3f} T/s "
             f"({probe['butterfly_frac_of_peak']:.3f} of {BFLY_PEAK / 1e12:.3f} T)")
     peaks = (BFLY_PEAK, MAC_PEAK)
@@ -698,6 +762,11 @@ def main():
         configs["resnet18_224_n16384"] = big
         log(f"resnet18_224 N=16384 B={big['batch']}: {big['ms_per_image']:.3f} ms/image, "
             f"{big['roofline']['kernel']} {big['roofline']['frac']}")
+        if not a.no_conventional:
+            cv = conventional_vs_drot(torch, dev, hconv, W, a)
+            configs["conventional_vs_drot"] = cv
+            log("conventional / DRot path: " + ", ".join(
+                f"{r['hw'][0]}^2 {r['c_in']}->{r['c_out']} {r['ratio']}x" for r in cv["rows"]))
 
     cpu = None
     if not a.no_cpu_baseline:

@@ -45,8 +45,11 @@
  * library trusts them, unless the environment variable HC_CHECK_INPUTS=1 is
  * set when a context is created: hc_conv and hc_conv_masked on its layers
  * then count the input ciphertexts' non-canonical words first (a device pass
- * and a wait for the stream) and return HC_EINVAL if there are any.
- * hc_check_residues does the same count on demand.
+ * and a wait for the stream, on a counter the context allocated; checks on one
+ * context run one at a time) and return HC_EINVAL if there are any. That wait
+ * cannot be recorded into a graph: with the check on, these calls return
+ * HC_ESTATE on a stream under capture. hc_check_residues does the same count
+ * on demand.
  *
  * Errors: every call returns hc_status. Argument and shape errors are
  * synchronous (HC_EINVAL / HC_EUNSUPPORTED); kernel faults are asynchronous and
@@ -207,6 +210,20 @@ hc_status hc_batch_run(hc_batch *batch, const uint32_t *const *ct_in, const uint
 hc_status hc_batch_run_eager(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
                              uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream);
 void hc_batch_destroy(hc_batch *batch);
+
+/* The batch's work as a two-stream pipeline over chunks of output channels,
+ * launched kernel by kernel (no graph): per layer, the forward NTT, then for
+ * each chunk of about chunk_bytes of multiply-accumulate output (a multiple of
+ * the MAC's channel tile) the MAC on one stream and the inverse NTT with mask
+ * and extraction of that chunk on a second stream, which waits for it; nbuf
+ * (2..8) chunk buffers rotate, so the MAC of the next chunks (and layers) runs
+ * beside the inverse NTT of earlier ones and a chunk's products can still be
+ * in the last-level cache when they are read. Same outputs as hc_batch_run.
+ * Allocates its own workspace on first use (and when a larger one is needed);
+ * `stream` waits for the whole batch. Not for graph capture. */
+hc_status hc_batch_run_pipelined(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                                 uint32_t *const *c0_ext, uint32_t *const *c1_out, uint64_t chunk_bytes,
+                                 uint32_t nbuf, void *stream);
 
 /* Autotuner: for every layer of the batch, time each supported launch shape
  * of each stage (forward NTT threads per polynomial, MAC tile, inverse NTT
@@ -412,6 +429,80 @@ hc_status hc_act_combine(const hc_layer *layer, const uint32_t *ct_x, const uint
 hc_status hc_conv_masked_direct(const hc_layer *layer, const uint32_t *ct_in, const uint32_t *mask, uint32_t *c0_ext,
                                 uint32_t *c1_out, uint32_t B, void *stream);
 
+/* ------------------------------------------------------------ conventional convolution
+ * The convolution the paper compares Flash's against (section "Conventional
+ * Convolution"; HRot and eq. keySwitching in "Background: Homomorphic
+ * Encryption"), for measuring that comparison (Table 9) on this GPU: batch
+ * encoding, slot rotations by automorphism plus key switching, PMult by
+ * plaintexts of weights, HAdd. Needs a context whose t is a prime = 1 mod 2N
+ * (below 2^30), stride 1 and h w <= N/2 (HC_EUNSUPPORTED otherwise).
+ *
+ * Slots in rotation order (a convention the paper leaves open): two rows of
+ * N/2; slot (r, c) is the evaluation at psi^(3^c) (row 0) or psi^(-3^c)
+ * (row 1), psi as for hc_batch_encode; vectors are [2][N/2], row 0 first.
+ * The automorphism x -> x^(3^k) shifts both rows left by k (the paper's
+ * left-cyclic HRot), x -> x^(-1) exchanges them.
+ *
+ * Layout: c_r = the largest power of two with c_r h w <= N/2 channels per slot
+ * row, each in a block of `block` = (N/2)/c_r slots (row-major pixels, the
+ * rest zero); c_n = 2 c_r channels per ciphertext (input channel j of
+ * ciphertext j / c_n at row (j mod c_n) / c_r, block (j mod c_n) mod c_r);
+ * the output ciphertexts hold the output channels the same way (packed).
+ * Rotations r = 0 .. c_n f^2 - 1 in the order (swap, d, ky, kx), swap slowest:
+ * exchange the rows when swap, then shift left by d block + (ky - p) w + (kx - p)
+ * (mod N/2); its Galois element is hc_cconv_info's galois[r]. Output ciphertext
+ * o = sum over input ciphertexts g and rotations r of PMult(HRot(in_g, r),
+ * pt(o, g, r)), where pt holds at each output slot the weight that the
+ * rotated input's channel and pixel there carry (0 where the tap reads the
+ * zero padding or a channel is absent). A rotation with element 1 is the
+ * identity (no key switch).
+ *
+ * Key switching: c1 is split into D = ceil(30 / decomp_bits) digits of
+ * decomp_bits bits per RNS limb (L D digits, digit (l, d) weighted by the CRT
+ * basis element of limb l times 2^(decomp_bits d)); the digits go through the
+ * automorphism and are multiplied by the switching keys (swk0, swk1) of the
+ * rotation: c0' = c0(x^g) + sum_i swk0_i c1^(i)(x^g), c1' = sum_i swk1_i c1^(i)(x^g).
+ * Keys are made on the client from the secret: swk0_i = -a_i s + e_i +
+ * w_i s(x^g), swk1_i = a_i (hc_cconv_keygen).
+ *
+ * Buffers (uint32 residues unless stated, device, caller-owned):
+ *   keys     [rotations][L D][2][L][N]  NTT domain (hc_cconv_keygen's output)
+ *   ct_in    [B][g_in][2][L][N]   batch-encoded inputs, coefficient domain, canonical
+ *   ct_out   [B][g_out][2][L][N]  coefficient domain, canonical
+ * The layer owns its weight plaintexts (g_out g_in rotations L N words, NTT
+ * domain) until hc_cconv_destroy. */
+typedef struct hc_cconv hc_cconv;
+typedef struct {
+    uint32_t c_r, block, c_n;   /* channels per slot row, slots per channel block, channels per ciphertext */
+    uint32_t g_in, g_out;       /* input / output ciphertexts per image */
+    uint32_t rotations;         /* c_n f^2 */
+    uint32_t decomp_bits, digits; /* bits per digit; digits per key (L D) */
+} hc_cconv_layout;
+hc_status hc_cconv_create(hc_ctx *ctx, const hc_conv_shape *shape, const int8_t *filters_host, uint32_t decomp_bits,
+                          void *stream, hc_cconv **out);
+void hc_cconv_destroy(hc_cconv *layer);
+/* galois: NULL, or room for `rotations` values. */
+hc_status hc_cconv_info(const hc_cconv *layer, hc_cconv_layout *out, uint32_t *galois);
+hc_status hc_cconv_keys_size(const hc_cconv *layer, size_t *bytes);
+hc_status hc_cconv_keygen_workspace_size(const hc_cconv *layer, size_t *bytes);
+/* Client side: keys from the secret's residues sk [L][N], uniform residues
+ * a [rotations][L D][L][N] and int32 errors e [rotations][L D][N] (|e| < q_l),
+ * all drawn by the caller. ws: hc_cconv_keygen_workspace_size bytes. */
+hc_status hc_cconv_keygen(const hc_cconv *layer, const uint32_t *sk, const uint32_t *a, const int32_t *e,
+                          uint32_t *keys, void *ws, size_t ws_bytes, void *stream);
+hc_status hc_cconv_workspace_size(const hc_cconv *layer, uint32_t B, size_t *bytes);
+/* The convolution of B images. ws: hc_cconv_workspace_size bytes. Enqueued on
+ * `stream`; no allocation. */
+hc_status hc_cconv_run(const hc_cconv *layer, const uint32_t *keys, const uint32_t *ct_in, uint32_t *ct_out,
+                       uint32_t B, void *ws, size_t ws_bytes, void *stream);
+/* Rotation-order batch encoding of n slot vectors z [n][N] (values in [0, t))
+ * into plaintext polynomials p [n][N], and decoding back (ws: n N words,
+ * 16-byte aligned). z and p must not overlap. These two calls allocate a small
+ * table and wait for the stream. */
+hc_status hc_rot_encode(const hc_ctx *ctx, const uint32_t *z, uint32_t *p, uint32_t n, void *stream);
+hc_status hc_rot_decode(const hc_ctx *ctx, const uint32_t *p, uint32_t *z, uint32_t n, void *ws, size_t ws_bytes,
+                        void *stream);
+
 /* ------------------------------------------------------------ measurement
  * Register-only VALU rate probes on HIP device `hip_device`, the ceilings the
  * kernels' roofline is priced against: independent chains of one instruction
@@ -426,11 +517,15 @@ hc_status hc_conv_masked_direct(const hc_layer *layer, const uint32_t *ct_in, co
  *                      twiddle, lazy [0, 2q) range), compiled from the same
  *                      code as the inverse NTT kernels
  * compute_units and clock_hz are the device's reported unit count and peak
- * engine clock. Synchronous; allocates and frees a few bytes of device memory. */
+ * engine clock; measured_clock_hz is the engine clock during the simple-op
+ * probe (shader cycle counter of its longest workgroup over the launch's
+ * duration; every workgroup is resident for the whole launch). Synchronous;
+ * allocates and frees a few kilobytes of device memory. */
 typedef struct {
     double simple_ops_per_s, mul_ops_per_s, mad64_ops_per_s, butterflies_per_s;
     uint32_t compute_units;
     double clock_hz;
+    double measured_clock_hz;
 } hc_valu_rates;
 hc_status hc_valu_probe(int hip_device, hc_valu_rates *out);
 

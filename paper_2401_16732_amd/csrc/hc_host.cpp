@@ -151,6 +151,12 @@ struct hc_batch {
   hipEvent_t fork = nullptr, join[kChains] = {};
   hipGraphExec_t exec = nullptr;
   std::vector<const void *> key;  // pointers the graph was recorded with
+  // chunked two-stream pipeline (hc_batch_run_pipelined): its own workspace
+  // (X-hat of the largest layer + Y-hat chunk buffers), streams and events
+  void *pws = nullptr;
+  size_t pws_bytes = 0;
+  hipStream_t pa = nullptr, pb = nullptr;
+  std::vector<hipEvent_t> pev;  // one per chunk and direction, recorded once per run
 };
 
 namespace {
@@ -496,6 +502,12 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
   }
   c->tw.fwd = c->d_tw;
   c->tw.inv = c->d_tw + (size_t)L * N;
+  // the input check's counter
+  e = hipMalloc((void **)&c->d_count, sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    hc_ctx_destroy(c);
+    return fail(HC_ENOMEM, "counter allocation");
+  }
   // batch (slot) encoding: transforms modulo t itself when t is a prime = 1 mod 2N
   if (t < (1ull << 30) && t % two_n == 1 && is_prime(t)) {
     std::vector<uint2> twt((size_t)2 * N);
@@ -533,6 +545,7 @@ void hc_ctx_destroy(hc_ctx *c) {
   DeviceGuard dg(c->device);
   if (c->d_tw) (void)hipFree(c->d_tw);
   if (c->d_tw_t) (void)hipFree(c->d_tw_t);
+  if (c->d_count) (void)hipFree(c->d_count);
   delete c;
 }
 
@@ -662,15 +675,22 @@ hc_status hc_workspace_size(const hc_layer *ly, uint32_t B, int masked, size_t *
 namespace {
 // Number of non-canonical words in npolys polynomials [..][L][N], counted on
 // the device; the call waits for the stream.
+// It uses the context's counter (allocated with the context): no allocation
+// here, and calls on one context are serialised. Refused (HC_ESTATE) while
+// the stream is being captured into a graph, since it waits for the stream.
 hc_status count_noncanonical(const hc_ctx &c, const uint32_t *p, size_t npolys, hipStream_t st, uint64_t *n_bad) {
-  unsigned long long *d = nullptr;
-  HC_HIP(hipMalloc((void **)&d, sizeof(*d)));
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HC_HIP(hipStreamIsCapturing(st, &cap));
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(HC_ESTATE, "the residue check waits for its stream and cannot run under graph capture");
+  std::lock_guard<std::mutex> lk(*c.count_mu);
+  unsigned long long *d = c.d_count;
+  static const unsigned long long zero = 0;
   unsigned long long h = 0;
-  hipError_t e = hipMemsetAsync(d, 0, sizeof(*d), st);
+  hipError_t e = hipMemcpyAsync(d, &zero, sizeof(zero), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hc::launch_count_noncanonical(p, npolys, c.N, c.consts, d, st);
   if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(d);
   if (e != hipSuccess) return hip_fail(e, "residue check");
   *n_bad = h;
   return HC_OK;
@@ -684,6 +704,17 @@ hc_status check_input(const hc_layer *ly, const uint32_t *ct_in, uint32_t B, hip
   return bad ? fail(HC_EINVAL, "input ciphertext word not below its prime") : HC_OK;
 }
 }  // namespace
+
+}  // extern "C"
+
+hc_status hc::conv_masked_on(const hc_layer *ly, const uint32_t *ct_in, const uint32_t *mask, uint32_t *c0_ext,
+                             uint32_t *c1_out, uint32_t B, void *ws, hipStream_t st) {
+  hc_status s = check_input(ly, ct_in, B, st);
+  if (s != HC_OK) return s;
+  return enqueue_conv(ly, ct_in, nullptr, mask, c0_ext, c1_out, B, ws, true, st);
+}
+
+extern "C" {
 
 hc_status hc_check_residues(const hc_ctx *c, const uint32_t *polys, size_t npolys, void *stream, uint64_t *n_bad) {
   if (!c || !n_bad || (npolys && !polys)) return fail(HC_EINVAL, "null argument");
@@ -737,9 +768,7 @@ hc_status hc_conv_masked(const hc_layer *ly, const uint32_t *ct_in, const uint32
   if (B == 0) return HC_OK;
   if (ws_bytes < ws_bytes_for(ly, B, true)) return fail(HC_EINVAL, "workspace too small");
   DeviceGuard dg(ly->ctx->device);
-  hc_status s = check_input(ly, ct_in, B, (hipStream_t)stream);
-  if (s != HC_OK) return s;
-  return enqueue_conv(ly, ct_in, nullptr, mask, c0_ext, c1_out, B, ws, true, (hipStream_t)stream);
+  return hc::conv_masked_on(ly, ct_in, mask, c0_ext, c1_out, B, ws, (hipStream_t)stream);
 }
 
 hc_status hc_poly_mul(const hc_ctx *c, const uint32_t *a, const uint32_t *b, uint32_t *out, uint32_t count, void *ws,
@@ -922,6 +951,123 @@ hc_status hc_batch_run_timed(hc_batch *bt, const uint32_t *const *ct_in, const u
   }
   for (int k = 0; k < 6; ++k) (void)hipEventDestroy(tm.ev[k]);
   return out;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Output channels per chunk of layer ly for the pipelined run: about
+// chunk_bytes of Y-hat, a multiple of the MAC's channel tile, at least one tile.
+uint32_t chunk_channels(const hc_layer *ly, uint32_t B, uint64_t chunk_bytes) {
+  const hc_ctx &c = *ly->ctx;
+  const hc::ConvGeom &g = ly->geom;
+  const uint64_t per_ch = (uint64_t)B * g.T * 2 * c.L * c.N * 4;
+  const hc::Shapes sh = hc::layer_shapes(ly, B);
+  const uint32_t tile = sh.mac.cg * sh.mac.ct;
+  uint64_t n = chunk_bytes / per_ch;
+  n = n / tile * tile;
+  if (n < tile) n = tile;
+  return (uint32_t)std::min<uint64_t>(n, g.c_out);
+}
+
+}  // namespace
+
+extern "C" {
+
+hc_status hc_batch_run_pipelined(hc_batch *bt, const uint32_t *const *ct_in, const uint32_t *const *mask,
+                                 uint32_t *const *c0, uint32_t *const *c1, uint64_t chunk_bytes, uint32_t nbuf,
+                                 void *stream) {
+  hc_status s = batch_check(bt, ct_in, mask, c0, c1);
+  if (s != HC_OK) return s;
+  if (chunk_bytes == 0 || nbuf < 2 || nbuf > 8) return fail(HC_EINVAL, "chunk_bytes > 0 and 2 <= nbuf <= 8");
+  const hc_ctx &c = *bt->ctx;
+  DeviceGuard dg(c.device);
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t B = bt->B;
+  const size_t n = bt->layers.size();
+  // workspace: X-hat of the largest layer, then nbuf chunk buffers of the largest chunk
+  size_t xbytes = 0, ybytes = 0, nchunks = 0;
+  std::vector<uint32_t> nch(n);
+  for (size_t k = 0; k < n; ++k) {
+    const hc_layer *ly = bt->layers[k];
+    const hc::ConvGeom &g = ly->geom;
+    nch[k] = chunk_channels(ly, B, chunk_bytes);
+    xbytes = std::max(xbytes, (size_t)B * g.G * 2 * c.L * c.N * 4);
+    ybytes = std::max(ybytes, (size_t)B * nch[k] * g.T * 2 * c.L * c.N * 4);
+    nchunks += (g.c_out + nch[k] - 1) / nch[k];
+  }
+  xbytes = (xbytes + 255) & ~(size_t)255;
+  ybytes = (ybytes + 255) & ~(size_t)255;
+  const size_t need = xbytes + nbuf * ybytes;
+  if (bt->pws_bytes < need) {
+    HC_HIP(hipDeviceSynchronize());
+    if (bt->pws) (void)hipFree(bt->pws);
+    bt->pws = nullptr;
+    bt->pws_bytes = 0;
+    if (hipMalloc(&bt->pws, need) != hipSuccess) return fail(HC_ENOMEM, "pipeline workspace allocation");
+    bt->pws_bytes = need;
+  }
+  if (!bt->pa) HC_HIP(hipStreamCreateWithFlags(&bt->pa, hipStreamNonBlocking));
+  if (!bt->pb) HC_HIP(hipStreamCreateWithFlags(&bt->pb, hipStreamNonBlocking));
+  // events: 2 per chunk (MAC done, inverse done) + start + 2 ends
+  const size_t nev = 2 * nchunks + 3;
+  while (bt->pev.size() < nev) {
+    hipEvent_t ev = nullptr;
+    HC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    bt->pev.push_back(ev);
+  }
+  hipEvent_t ev_start = bt->pev[2 * nchunks], ev_ea = bt->pev[2 * nchunks + 1], ev_eb = bt->pev[2 * nchunks + 2];
+  hipStream_t sa = bt->pa, sb = bt->pb;
+  HC_HIP(hipEventRecord(ev_start, st));
+  HC_HIP(hipStreamWaitEvent(sa, ev_start, 0));
+  HC_HIP(hipStreamWaitEvent(sb, ev_start, 0));
+  uint32_t *xhat = (uint32_t *)bt->pws;
+  size_t ci = 0;  // running chunk index over all layers
+  for (size_t k = 0; k < n; ++k) {
+    const hc_layer *ly = bt->layers[k];
+    const hc::ConvGeom &g = ly->geom;
+    const Shapes sh = hc::layer_shapes(ly, B);
+    const size_t npin = (size_t)B * g.G * 2 * c.L;
+    // stream A: the layer's forward NTT (after the previous layer's last MAC, in stream order)
+    HC_HIP(hc::launch_ntt_fwd(c.logn, sh.fe, ct_in[k], xhat, npin, c.consts, c.tw, sa));
+    const size_t hw = (size_t)g.ho * g.wo;
+    for (uint32_t i0 = 0; i0 < g.c_out; i0 += nch[k], ++ci) {
+      const uint32_t nc = std::min(nch[k], g.c_out - i0);
+      hc::ConvGeom gc = g;
+      gc.c_out = nc;
+      gc.O = nc * g.T;
+      uint32_t *ybuf = (uint32_t *)((char *)bt->pws + xbytes + (ci % nbuf) * ybytes);
+      hipEvent_t mac_done = bt->pev[2 * ci], inv_done = bt->pev[2 * ci + 1];
+      if (ci >= nbuf) HC_HIP(hipStreamWaitEvent(sa, bt->pev[2 * (ci - nbuf) + 1], 0));  // buffer free again
+      if (!hc::mac_offsets_fit(gc, sh.mac)) return fail(HC_EUNSUPPORTED, "layer too large for the MAC tile");
+      HC_HIP(hc::launch_mac(gc, sh.mac, xhat, ly->d_w + (size_t)i0 * g.G_w * c.L * c.N, ybuf, B, c.consts, c.tw,
+                            sa));
+      HC_HIP(hipEventRecord(mac_done, sa));
+      HC_HIP(hipStreamWaitEvent(sb, mac_done, 0));
+      // inverse NTT + mask + extraction of the chunk, at most kMaxTab images per launch
+      for (uint32_t b0 = 0; b0 < B; b0 += hc::kMaxTab) {
+        const uint32_t nb = std::min<uint32_t>(hc::kMaxTab, B - b0);
+        hc::OutPtrs out{};
+        out.n = nb;
+        for (uint32_t b = 0; b < nb; ++b) {
+          const size_t bi = b0 + b;
+          out.mask[b] = (uint64_t)(uintptr_t)(mask[k] + (bi * g.c_out + i0) * hw);
+          out.c0[b] = (uint64_t)(uintptr_t)(c0[k] + (bi * g.c_out + i0) * c.L * hw);
+          out.c1[b] = (uint64_t)(uintptr_t)(c1[k] + (bi * g.O + (size_t)i0 * g.T) * c.L * c.N);
+        }
+        const uint32_t *ysrc = ybuf + (size_t)b0 * gc.O * 2 * c.L * c.N;
+        HC_HIP(hc::launch_intt_masked(gc, c.logn, sh.ie, sh.ipw, sh.mac.pre, ysrc, nullptr, nullptr, nullptr, nb,
+                                      c.consts, c.tw, sb, &out));
+      }
+      HC_HIP(hipEventRecord(inv_done, sb));
+    }
+  }
+  HC_HIP(hipEventRecord(ev_ea, sa));
+  HC_HIP(hipEventRecord(ev_eb, sb));
+  HC_HIP(hipStreamWaitEvent(st, ev_ea, 0));
+  HC_HIP(hipStreamWaitEvent(st, ev_eb, 0));
+  return HC_OK;
 }
 
 }  // extern "C"
@@ -1117,6 +1263,12 @@ hc_status hc_layer_clear_tuning(hc_layer *ly) {
 void hc_batch_destroy(hc_batch *bt) {
   if (!bt) return;
   DeviceGuard dg(bt->ctx->device);
+  if (bt->pa) (void)hipStreamSynchronize(bt->pa);
+  if (bt->pb) (void)hipStreamSynchronize(bt->pb);
+  for (hipEvent_t ev : bt->pev) (void)hipEventDestroy(ev);
+  if (bt->pa) (void)hipStreamDestroy(bt->pa);
+  if (bt->pb) (void)hipStreamDestroy(bt->pb);
+  if (bt->pws) (void)hipFree(bt->pws);
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
   for (int s = 0; s < kChains; ++s) {
     if (bt->side[s]) (void)hipStreamDestroy(bt->side[s]);

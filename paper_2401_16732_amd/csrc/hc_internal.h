@@ -188,4 +188,37 @@ hipError_t launch_decrypt_extracted(const ConvGeom &g, const uint32_t *c0_ext, c
 hipError_t launch_decrypt_full(const uint32_t *ct, const uint32_t *c1s, uint32_t *m, size_t n_ct, uint32_t N,
                                const LimbConsts &c, const DecodeConsts &d, hipStream_t st);
 
+// ---------------------------------------------------------------- conventional convolution (hc_cconv.hip)
+// Slot layout of the conventional (batch-encoded) convolution: images of h w
+// <= N/2 pixels in blocks of bsz = (N/2)/c_r slots of one slot row, c_r
+// channels per row, c_n = 2 c_r per ciphertext; R = c_n f^2 rotations.
+struct CcGeom {
+  uint32_t N, logn, c_in, c_out, h, w, f, p;
+  uint32_t c_r, bsz, c_n, g_in, R;
+};
+// dig [n_ct][L D][L][N] <- the T-bit digits of c1 of ct [n_ct][2][L][N]
+// (coefficient domain), each digit polynomial repeated in every limb.
+hipError_t launch_cc_digits(const uint32_t *ct, uint32_t *dig, size_t n_ct, uint32_t N, uint32_t L, uint32_t T,
+                            uint32_t D, hipStream_t st);
+// out [n_ct][R][2][L][N] <- the automorphism x -> x^gal[r] and key switching
+// of each ciphertext (NTT domain: xh its forward NTT, dh its digits' forward
+// NTTs) with keys [R][LD][2][L][N]; gal[r] = 1 copies the ciphertext.
+hipError_t launch_cc_keyswitch(const uint32_t *xh, const uint32_t *dh, const uint32_t *keys, const uint32_t *gal,
+                               uint32_t *out, size_t n_ct, uint32_t R, uint32_t LD, uint32_t logn,
+                               const LimbConsts &c, hipStream_t st);
+// z [n_pt][N] <- the weight slot values (mod t) of plaintexts p0 .. p0 + n_pt
+// - 1, in the batch encoding's slot order.
+hipError_t launch_cc_weight_slots(const int8_t *filt, const uint32_t *rot_tab, const uint32_t *pow3, uint32_t *z,
+                                  const CcGeom &cg, size_t p0, size_t n_pt, uint32_t t, hipStream_t st);
+// Rotation-order slots (dir 0) to the batch encoding's order, or back (dir 1).
+hipError_t launch_cc_slot_perm(const uint32_t *in, uint32_t *out, const uint32_t *pow3, size_t n, uint32_t logn,
+                               int dir, hipStream_t st);
+// keys [R][LD][2][L][N] (NTT domain) from ah, eh [R][LD][L][N] and sh [L][N].
+hipError_t launch_cc_keygen(const uint32_t *ah, const uint32_t *eh, const uint32_t *sh, const uint32_t *gal,
+                            uint32_t *keys, uint32_t R, uint32_t LD, uint32_t D, uint32_t T, uint32_t logn,
+                            const LimbConsts &c, hipStream_t st);
+// out [n][L][N] <- signed e [n][N] (|e| < q_l) as residues.
+hipError_t launch_cc_lift_signed(const int32_t *e, uint32_t *out, size_t n, uint32_t N, const LimbConsts &c,
+                                 hipStream_t st);
+
 }  // namespace hc

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <memory>
+#include <mutex>
 #include <string>
 
 #include "../../include/hc.h"
@@ -19,6 +21,8 @@ struct hc_ctx {
   hc::Twiddles tw{};
   hc_tuning tune{};        // 0 fields = defaults
   bool check_inputs = false;  // HC_CHECK_INPUTS=1 at creation: conv entry points validate their inputs
+  unsigned long long *d_count = nullptr;  // the input check's device counter ...
+  std::unique_ptr<std::mutex> count_mu{new std::mutex};  // ... used by one call at a time
   hc::DecodeConsts dec{};     // exact decryption rounding (client side)
   // batch (slot) encoding, present when t is a prime = 1 mod 2N: transforms modulo t
   bool batch_ok = false;
@@ -90,6 +94,12 @@ struct DeviceGuard {
     if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
+
+// hc_conv_masked after its argument checks, on the device already current:
+// the input check (when the context has it on), then forward NTT, MAC and
+// masked inverse NTT with X-hat and Y-hat in ws (ws_bytes_for(ly, B, true)).
+hc_status conv_masked_on(const hc_layer *ly, const uint32_t *ct_in, const uint32_t *mask, uint32_t *c0_ext,
+                         uint32_t *c1_out, uint32_t B, void *ws, hipStream_t st);
 
 // Forward NTT, MAC and masked inverse NTT of one layer for a group of images
 // whose buffers are given per image (at most kMaxTab).

@@ -15,7 +15,12 @@ namespace hc {
 
 constexpr int kProbeChains = 16;
 
+// The simple-op probe also reads the shader clock counter at its start and
+// end: thread 0 of each workgroup stores the elapsed cycles at out[1 + block]
+// (all workgroups are resident at once at this register count, so the
+// elapsed cycles over the launch's duration give the engine clock under load).
 __global__ __launch_bounds__(256) void k_probe_simple(uint32_t *out, uint32_t iters, uint32_t a, uint32_t b) {
+  const uint64_t c0 = clock64();
   uint32_t x[kProbeChains];
 #pragma unroll
   for (int k = 0; k < kProbeChains; ++k) x[k] = threadIdx.x + k;
@@ -29,6 +34,8 @@ __global__ __launch_bounds__(256) void k_probe_simple(uint32_t *out, uint32_t it
 #pragma unroll
   for (int k = 0; k < kProbeChains; ++k) s ^= x[k];
   if (s == 0x9e3779b9u) out[0] = s;  // keeps the chains live; practically never stores
+  const uint64_t c1 = clock64();
+  if (threadIdx.x == 0) out[1 + blockIdx.x] = (uint32_t)(c1 - c0);
 }
 
 __global__ __launch_bounds__(256) void k_probe_mul(uint32_t *out, uint32_t iters, uint32_t a, uint32_t b) {
@@ -119,7 +126,9 @@ hipError_t launch_probe(int kind, uint32_t nwg, uint32_t iters, uint32_t q, cons
 }  // namespace hc
 
 // ---------------------------------------------------------------- host entry point
+#include <algorithm>
 #include <vector>
+
 #include "hc_objects.h"
 
 namespace {
@@ -160,7 +169,7 @@ extern "C" hc_status hc_valu_probe(int hip_device, hc_valu_rates *out) {
   uint32_t *dout = nullptr;
   hipStream_t st = nullptr;
   e = hipMalloc((void **)&dtw, 64 * sizeof(uint2));
-  if (e == hipSuccess) e = hipMalloc((void **)&dout, 64);
+  if (e == hipSuccess) e = hipMalloc((void **)&dout, (size_t)(1 + nwg) * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemcpy(dtw, htw.data(), 64 * sizeof(uint2), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreate(&st);
   // lane operations per thread per loop turn: 2 x 16 chains (simple, mul),
@@ -168,10 +177,18 @@ extern "C" hc_status hc_valu_probe(int hip_device, hc_valu_rates *out) {
   const uint32_t iters[4] = {4096, 2048, 2048, 512};
   const double per_turn[4] = {32.0, 32.0, 16.0, 32.0};
   double rate[4] = {0, 0, 0, 0};
+  double clock_meas = 0.0;
   for (int k = 0; k < 4 && e == hipSuccess; ++k) {
     float ms = 0.f;
     e = time_probe(k, nwg, iters[k], q, dtw, dout, st, &ms);
     if (e == hipSuccess) rate[k] = (double)nwg * 256.0 * iters[k] * per_turn[k] / (ms * 1e-3);
+    if (e == hipSuccess && k == 0) {
+      std::vector<uint32_t> cyc(nwg);
+      e = hipMemcpy(cyc.data(), dout + 1, nwg * sizeof(uint32_t), hipMemcpyDeviceToHost);
+      double mx = 0;
+      for (uint32_t c : cyc) mx = std::max(mx, (double)c);
+      if (e == hipSuccess && ms > 0) clock_meas = mx / (ms * 1e-3);
+    }
   }
   if (st) (void)hipStreamDestroy(st);
   if (dtw) (void)hipFree(dtw);
@@ -183,5 +200,6 @@ extern "C" hc_status hc_valu_probe(int hip_device, hc_valu_rates *out) {
   out->butterflies_per_s = rate[3];
   out->compute_units = cus;
   out->clock_hz = (double)prop.clockRate * 1e3;
+  out->measured_clock_hz = clock_meas;
   return HC_OK;
 }

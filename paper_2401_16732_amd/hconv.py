@@ -29,7 +29,9 @@ SYMBOLS = [
     "hc_server_create", "hc_server_add_net", "hc_server_request_bytes", "hc_server_submit", "hc_server_step",
     "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
     "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
-    "hc_layer_get_tuning_for", "hc_valu_probe",
+    "hc_layer_get_tuning_for", "hc_valu_probe", "hc_batch_run_pipelined",
+    "hc_cconv_create", "hc_cconv_destroy", "hc_cconv_info", "hc_cconv_keys_size", "hc_cconv_keygen_workspace_size",
+    "hc_cconv_keygen", "hc_cconv_workspace_size", "hc_cconv_run", "hc_rot_encode", "hc_rot_decode",
     "hc_check_residues", "hc_encrypt_online", "hc_decrypt_workspace_size", "hc_decrypt_extracted", "hc_decrypt",
     "hc_encrypt_zero", "hc_batch_encode", "hc_batch_decode", "hc_encrypt_plain", "hc_act_workspace_size",
     "hc_act_pmult", "hc_act_combine", "hc_conv_masked_direct",
@@ -131,6 +133,17 @@ def load(path: str = LIB_PATH):
         "hc_layer_clear_tuning": (I, [P]),
         "hc_layer_get_tuning_for": (I, [P, u32, P]),
         "hc_valu_probe": (I, [I, P]),
+        "hc_batch_run_pipelined": (I, [P, P, P, P, P, u64, u32, P]),
+        "hc_cconv_create": (I, [P, P, P, u32, P, P]),
+        "hc_cconv_destroy": (None, [P]),
+        "hc_cconv_info": (I, [P, P, P]),
+        "hc_cconv_keys_size": (I, [P, P]),
+        "hc_cconv_keygen_workspace_size": (I, [P, P]),
+        "hc_cconv_keygen": (I, [P, P, P, P, P, P, sz, P]),
+        "hc_cconv_workspace_size": (I, [P, u32, P]),
+        "hc_cconv_run": (I, [P, P, P, P, u32, P, sz, P]),
+        "hc_rot_encode": (I, [P, P, P, u32, P]),
+        "hc_rot_decode": (I, [P, P, P, u32, P, sz, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -175,7 +188,8 @@ def plan_ring(N, c_in, c_out, h, w, f, stride=1) -> Layout:
 class ValuRates(ctypes.Structure):
     _fields_ = [("simple_ops_per_s", ctypes.c_double), ("mul_ops_per_s", ctypes.c_double),
                 ("mad64_ops_per_s", ctypes.c_double), ("butterflies_per_s", ctypes.c_double),
-                ("compute_units", ctypes.c_uint32), ("clock_hz", ctypes.c_double)]
+                ("compute_units", ctypes.c_uint32), ("clock_hz", ctypes.c_double),
+                ("measured_clock_hz", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -280,6 +294,23 @@ class Context:
             raise ValueError("z must hold n * N words")
         _check(_lib.hc_batch_decode(self.h, _dptr(p, "p", self.device), _dptr(z, "z", self.device), n,
                                     _stream(stream)), "hc_batch_decode")
+
+    def rot_encode(self, z, p, stream=None):
+        """p [n][N] <- the plaintext polynomials whose slots in rotation order
+        (two rows of N/2, row 0 first) are z [n][N] (values in [0, t))."""
+        n = self._rows(z, "z", self.N)
+        if p.numel() < n * self.N:
+            raise ValueError("p must hold n * N words")
+        _check(_lib.hc_rot_encode(self.h, _dptr(z, "z", self.device), _dptr(p, "p", self.device), n,
+                                  _stream(stream)), "hc_rot_encode")
+
+    def rot_decode(self, p, z, ws, stream=None):
+        """z [n][N] <- the rotation-order slots of plaintext polynomials p [n][N]; ws: n N words."""
+        n = self._rows(p, "p", self.N)
+        if z.numel() < n * self.N or ws.numel() < n * self.N:
+            raise ValueError("z and ws must hold n * N words")
+        _check(_lib.hc_rot_decode(self.h, _dptr(p, "p", self.device), _dptr(z, "z", self.device), n,
+                                  _dptr(ws, "ws", self.device), ws.numel() * 4, _stream(stream)), "hc_rot_decode")
 
     def encrypt_plain(self, p, ct_zero, ct, stream=None):
         """ct [n][2][L][N] <- ct_zero + Delta * p for plaintext polynomials p [n][N]."""
@@ -505,6 +536,87 @@ class Layer:
             pass
 
 
+class CConvLayout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in ("c_r", "block", "c_n", "g_in", "g_out", "rotations",
+                                               "decomp_bits", "digits")]
+
+
+class CConv:
+    """The conventional convolution (batch encoding, HRot with key switching,
+    PMult; hc_cconv_*) of one layer, with its weight plaintexts resident on the
+    device. Stride 1, h w <= N/2, a context whose t is a prime = 1 mod 2N."""
+
+    def __init__(self, ctx: Context, c_in, c_out, h, w, f, filters: np.ndarray, decomp_bits: int = 10,
+                 stream=None):
+        load()
+        self.ctx = ctx
+        self.h = None
+        f8 = np.ascontiguousarray(np.asarray(filters, dtype=np.int8))
+        if f8.shape != (c_out, c_in, f, f):
+            raise ValueError(f"filters must be [c_out][c_in][f][f] = {(c_out, c_in, f, f)}")
+        sh = ConvShape(c_in, c_out, h, w, f, 1)
+        h_ = ctypes.c_void_p()
+        _check(_lib.hc_cconv_create(ctx.h, ctypes.byref(sh), f8.ctypes.data_as(ctypes.c_void_p), decomp_bits,
+                                    _stream(stream), ctypes.byref(h_)), "hc_cconv_create")
+        self.h = h_
+        lay = CConvLayout()
+        _check(_lib.hc_cconv_info(self.h, ctypes.byref(lay), None), "hc_cconv_info")
+        gal = (ctypes.c_uint32 * lay.rotations)()
+        _check(_lib.hc_cconv_info(self.h, ctypes.byref(lay), gal), "hc_cconv_info")
+        self.layout = lay
+        self.galois = list(gal)
+
+    def _size(self, fn, *args):
+        b = ctypes.c_size_t()
+        _check(fn(self.h, *args, ctypes.byref(b)), fn.__name__)
+        return (b.value + 3) // 4
+
+    def keys_words(self) -> int:
+        return self._size(_lib.hc_cconv_keys_size)
+
+    def keygen_workspace_words(self) -> int:
+        return self._size(_lib.hc_cconv_keygen_workspace_size)
+
+    def workspace_words(self, B: int) -> int:
+        return self._size(_lib.hc_cconv_workspace_size, B)
+
+    def keygen(self, sk, a, e, keys, ws, stream=None):
+        """Switching keys [rotations][digits][2][L][N] (NTT domain) from the key
+        residues sk [L][N], uniform a [rotations][digits][L][N] and int32 errors
+        e [rotations][digits][N]."""
+        d, L, N = self.ctx.device, self.ctx.L, self.ctx.N
+        R, LD = self.layout.rotations, self.layout.digits
+        if sk.numel() != L * N or a.numel() != R * LD * L * N or e.numel() != R * LD * N:
+            raise ValueError("sk [L][N], a [rotations][digits][L][N], e [rotations][digits][N]")
+        if keys.numel() < self.keys_words() or ws.numel() < self.keygen_workspace_words():
+            raise ValueError("keys or workspace too small")
+        _check(_lib.hc_cconv_keygen(self.h, _dptr(sk, "sk", d), _dptr(a, "a", d), _dptr(e, "e", d),
+                                    _dptr(keys, "keys", d), _dptr(ws, "ws", d), ws.numel() * 4, _stream(stream)),
+               "hc_cconv_keygen")
+
+    def run(self, keys, ct_in, ct_out, B: int, ws, stream=None):
+        """ct_out [B][g_out][2][L][N] <- the convolution of ct_in [B][g_in][2][L][N]."""
+        d, L, N = self.ctx.device, self.ctx.L, self.ctx.N
+        if ct_in.numel() != B * self.layout.g_in * 2 * L * N or ct_out.numel() != B * self.layout.g_out * 2 * L * N:
+            raise ValueError("ct_in [B][g_in][2][L][N], ct_out [B][g_out][2][L][N]")
+        if keys.numel() < self.keys_words() or ws.numel() < self.workspace_words(B):
+            raise ValueError("keys or workspace too small")
+        _check(_lib.hc_cconv_run(self.h, _dptr(keys, "keys", d), _dptr(ct_in, "ct_in", d),
+                                 _dptr(ct_out, "ct_out", d), B, _dptr(ws, "ws", d), ws.numel() * 4,
+                                 _stream(stream)), "hc_cconv_run")
+
+    def close(self):
+        if self.h is not None and _lib is not None:
+            _lib.hc_cconv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _ptr_array(ts, name, device):
     arr = (ctypes.c_void_p * len(ts))()
     for k, t in enumerate(ts):
@@ -545,6 +657,12 @@ class Batch:
     def run_eager(self, ct_in, mask, c0, c1, stream=None):
         a = self._args(ct_in, mask, c0, c1)
         _check(_lib.hc_batch_run_eager(self.h, *a, _stream(stream)), "hc_batch_run_eager")
+
+    def run_pipelined(self, ct_in, mask, c0, c1, chunk_bytes=64 << 20, nbuf=3, stream=None):
+        """The batch as a two-stream pipeline over output-channel chunks (eager)."""
+        a = self._args(ct_in, mask, c0, c1)
+        _check(_lib.hc_batch_run_pipelined(self.h, *a, int(chunk_bytes), int(nbuf), _stream(stream)),
+               "hc_batch_run_pipelined")
 
     def autotune(self, ct_in, mask, c0, c1, cache_path=None, stream=None):
         """Pick each layer's launch shapes by timing every candidate on these buffers."""

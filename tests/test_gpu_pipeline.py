@@ -1,0 +1,75 @@
+"""The batch as a two-stream pipeline over output-channel chunks
+(hc_batch_run_pipelined) gives the graph's outputs bit for bit: ResNet-50
+layers at B = 16 (tiled stem, stride-2 and 1x1 layers) with small chunks, so
+that many chunks rotate through 2 or 3 buffers across layer boundaries, and
+ResNet-18 224x224 layers at N = 16384 with B = 64 (more images than one
+inverse-NTT launch takes per chunk)."""
+import pytest
+
+from paper_2401_16732_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_16732_amd import hconv
+    hconv.load()
+    return hconv
+
+
+def _case(hc, net, names, N, L, t, B, seed):
+    import torch
+    ctx = hc.Context(N, L, t)
+    specs = [s for s in W.NETS[net]() if s.name in names]
+    g = W.rng(seed)
+    layers = [hc.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, W.gen_filters(g, s)) for s in specs]
+    tg = torch.Generator(device="cuda")
+    tg.manual_seed(seed)
+    ct_in = [W.gen_ct_limbs_torch(tg, ly.in_shape(B)[:3], ctx.primes, N, "cuda") for ly in layers]
+    mask = [torch.randint(0, t, ly.mask_shape(B), generator=tg, device="cuda", dtype=torch.int32) for ly in layers]
+    outs = lambda: ([torch.zeros(ly.c0_shape(B), dtype=torch.int32, device="cuda") for ly in layers],
+                    [torch.zeros(ly.c1_shape(B), dtype=torch.int32, device="cuda") for ly in layers])
+    return ctx, layers, ct_in, mask, outs
+
+
+@pytest.mark.parametrize("chunk_mib,nbuf", [(8, 2), (20, 3)])
+def test_pipelined_equals_graph_resnet50(hc, chunk_mib, nbuf):
+    import torch
+    N, L, t, B = 8192, 3, 2 ** 20, 16
+    ctx, layers, ct_in, mask, outs = _case(hc, "resnet50_224", ("stem", "s1.b0.c2", "s2.b0.c2", "s2.b0.proj",
+                                                                 "s3.b1.c1", "s4.b0.c3"), N, L, t, B, 61)
+    bt = hc.Batch(ctx, layers, B)
+    g0, g1 = outs()
+    bt.run(ct_in, mask, g0, g1)
+    for rep in range(2):
+        print(f"pipelined chunk {chunk_mib} MiB x{nbuf}, run {rep}", flush=True)
+        p0, p1 = outs()
+        bt.run_pipelined(ct_in, mask, p0, p1, chunk_bytes=chunk_mib << 20, nbuf=nbuf)
+        torch.cuda.synchronize()
+        for k in range(len(layers)):
+            assert torch.equal(p0[k], g0[k]) and torch.equal(p1[k], g1[k]), (rep, k)
+    bt.close()
+    for ly in layers:
+        ly.close()
+
+
+def test_pipelined_equals_graph_large_ring_b64(hc):
+    import torch
+    N, L, t, B = 16384, 4, 2 ** 24, 64
+    ctx, layers, ct_in, mask, outs = _case(hc, "resnet18_224", ("stem", "s2.b1.c1", "s4.b2.c2"), N, L, t, B, 62)
+    bt = hc.Batch(ctx, layers, B)
+    g0, g1 = outs()
+    bt.run(ct_in, mask, g0, g1)
+    print("pipelined N=16384 B=64", flush=True)
+    p0, p1 = outs()
+    bt.run_pipelined(ct_in, mask, p0, p1, chunk_bytes=96 << 20, nbuf=3)
+    torch.cuda.synchronize()
+    for k in range(len(layers)):
+        assert torch.equal(p0[k], g0[k]) and torch.equal(p1[k], g1[k]), k
+    bt.close()
+    for ly in layers:
+        ly.close()
