@@ -529,6 +529,23 @@ typedef struct {
 } hc_valu_rates;
 hc_status hc_valu_probe(int hip_device, hc_valu_rates *out);
 
+/* ------------------------------------------------------------ no allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * hc_conv_masked without a workspace argument. Its scratch (the NTT-domain
+ * inputs and products of one call, hc_workspace_size(layer, B, 1) bytes) is a
+ * fixed device array of HC_NOALLOC_SCRATCH_BYTES per device, held by the
+ * library until the process ends; the call allocates nothing and returns
+ * HC_EINVAL when the layer needs more for B images (call it with fewer images,
+ * or use hc_conv_masked). Every call on one device shares that device's array
+ * and overwrites it completely before reading it: calls that overlap in time
+ * on one device (other streams, other host threads) race and give wrong
+ * results; order them on one stream. Same outputs as hc_conv_masked, bit for
+ * bit. Asynchronous on `stream`. */
+#define HC_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+hc_status hc_conv_masked_noalloc(const hc_layer *layer, const uint32_t *ct_in, const uint32_t *mask,
+                                 uint32_t *c0_ext, uint32_t *c1_out, uint32_t B, void *stream);
+
 /* Wait for all work on the context's device; reports earlier asynchronous faults. */
 hc_status hc_sync(hc_ctx *ctx);
 const char *hc_status_string(hc_status s);

@@ -24,7 +24,7 @@ LIB = os.path.join(HERE, "libhconv.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("hc_host.cpp", "hc_server.cpp", "hc_client.cpp", "hc_ntt.hip",
                                            "hc_mac.hip", "hc_client.hip", "hc_direct.hip", "hc_intt_masked_small.hip",
                                            "hc_intt_masked_8k.hip", "hc_intt_masked_16k.hip", "hc_probe.hip",
-                                           "hc_cconv.hip", "hc_cconv.cpp")]
+                                           "hc_noalloc.hip", "hc_cconv.hip", "hc_cconv.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -508,6 +508,9 @@ hc_status hc_ctx_create(uint32_t N, uint32_t L, const uint32_t *primes, uint64_t
     hc_ctx_destroy(c);
     return fail(HC_ENOMEM, "counter allocation");
   }
+  // hc_conv_masked_noalloc's scratch address on this device; a failure here
+  // only affects that entry point, which looks again and reports it
+  (void)hc::noalloc_init(hip_device);
   // batch (slot) encoding: transforms modulo t itself when t is a prime = 1 mod 2N
   if (t < (1ull << 30) && t % two_n == 1 && is_prime(t)) {
     std::vector<uint2> twt((size_t)2 * N);

@@ -101,6 +101,10 @@ struct DeviceGuard {
 hc_status conv_masked_on(const hc_layer *ly, const uint32_t *ct_in, const uint32_t *mask, uint32_t *c0_ext,
                          uint32_t *c1_out, uint32_t B, void *ws, hipStream_t st);
 
+// Looks up the device address of hc_conv_masked_noalloc's scratch array on
+// `device` (which must be current) once; later calls return at once.
+hc_status noalloc_init(int device);
+
 // Forward NTT, MAC and masked inverse NTT of one layer for a group of images
 // whose buffers are given per image (at most kMaxTab).
 hc_status enqueue_conv_gather(const hc_layer *ly, uint32_t B, const uint32_t *const *ct_in,

@@ -29,7 +29,7 @@ SYMBOLS = [
     "hc_server_create", "hc_server_add_net", "hc_server_request_bytes", "hc_server_submit", "hc_server_step",
     "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
     "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
-    "hc_layer_get_tuning_for", "hc_valu_probe", "hc_batch_run_pipelined",
+    "hc_layer_get_tuning_for", "hc_valu_probe", "hc_conv_masked_noalloc", "hc_batch_run_pipelined",
     "hc_cconv_create", "hc_cconv_destroy", "hc_cconv_info", "hc_cconv_keys_size", "hc_cconv_keygen_workspace_size",
     "hc_cconv_keygen", "hc_cconv_workspace_size", "hc_cconv_run", "hc_rot_encode", "hc_rot_decode",
     "hc_check_residues", "hc_encrypt_online", "hc_decrypt_workspace_size", "hc_decrypt_extracted", "hc_decrypt",
@@ -133,6 +133,7 @@ def load(path: str = LIB_PATH):
         "hc_layer_clear_tuning": (I, [P]),
         "hc_layer_get_tuning_for": (I, [P, u32, P]),
         "hc_valu_probe": (I, [I, P]),
+        "hc_conv_masked_noalloc": (I, [P, P, P, P, P, u32, P]),
         "hc_batch_run_pipelined": (I, [P, P, P, P, P, u64, u32, P]),
         "hc_cconv_create": (I, [P, P, P, u32, P, P]),
         "hc_cconv_destroy": (None, [P]),
@@ -474,6 +475,21 @@ class Layer:
         _check(_lib.hc_act_combine(self.h, _dptr(ct_x, "ct_x", d), _dptr(ct_y, "ct_y", d), _dptr(r, "r", d),
                                    _dptr(v, "v", d), _dptr(ct_out, "ct_out", d), B, _stream(stream)),
                "hc_act_combine")
+
+    NOALLOC_SCRATCH_BYTES = 128 << 20  # HC_NOALLOC_SCRATCH_BYTES
+
+    def conv_masked_noalloc(self, ct_in, mask, c0_ext, c1_out, B: int, stream=None):
+        """conv_masked without a workspace: the library's fixed per-device
+        scratch array (NOALLOC_SCRATCH_BYTES) holds the intermediate values; no
+        allocation. Calls that overlap on one device race."""
+        d = self.ctx.device
+        self._need(ct_in, self.in_shape(B), "ct_in")
+        self._need(mask, self.mask_shape(B), "mask")
+        self._need(c0_ext, self.c0_shape(B), "c0_ext")
+        self._need(c1_out, self.c1_shape(B), "c1_out")
+        _check(_lib.hc_conv_masked_noalloc(self.h, _dptr(ct_in, "ct_in", d), _dptr(mask, "mask", d),
+                                           _dptr(c0_ext, "c0_ext", d), _dptr(c1_out, "c1_out", d), B,
+                                           _stream(stream)), "hc_conv_masked_noalloc")
 
     def conv_masked_direct(self, ct_in, mask, c0_ext, c1_out, B: int, stream=None):
         """The same outputs as conv_masked, by the coefficient-domain convolution
