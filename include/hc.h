@@ -281,6 +281,7 @@ typedef struct {
     uint64_t submitted, admitted, completed, groups, images;  /* cumulative */
     uint64_t queued;       /* waiting for arena space */
     uint64_t arena_used, arena_bytes;
+    uint64_t direct_groups;  /* cumulative: groups of one image run by the coefficient-domain conv */
 } hc_server_stats;
 
 hc_status hc_server_create(hc_ctx *ctx, const hc_server_config *cfg, hc_server **out);

@@ -375,6 +375,7 @@ hc_status hc_server_step(hc_server *s) {
       // a lone image on a layer where the coefficient-domain conv is faster (same bits)
       SV_HIP(hc::launch_conv_direct(ly->geom, in[0], ly->d_wt, ly->wt_rows, mk[0], c0[0], c1[0], 1,
                                     hc::direct_consts(*ly->ctx), ly->ctx->consts, s->streams[si]));
+      s->st.direct_groups++;
     } else {
       hc_status cs = hc::enqueue_conv_gather(ly, B, in, mk, c0, c1, s->ws[si], s->streams[si]);
       if (cs != HC_OK) return cs;

@@ -713,7 +713,7 @@ class ServerConfig(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "admitted", "completed", "groups", "images", "queued",
-                                               "arena_used", "arena_bytes")]
+                                               "arena_used", "arena_bytes", "direct_groups")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

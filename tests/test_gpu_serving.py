@@ -49,8 +49,11 @@ def _inputs(ctx, specs, layers, g):
     return xs, ms
 
 
-def _run(srv, plan):
-    """plan: list of (submit_at_step, net_id, ct_in, mask). Returns {index: request id}."""
+def _run(srv, plan, lockstep=False):
+    """plan: list of (submit_at_step, net_id, ct_in, mask). Returns {index: request id}.
+    lockstep: wait for the server's streams after every step, so that requests
+    admitted in one step are ready together and every launched group finishes
+    before the next step (groups then never split)."""
     ids = {}
     done = set()
     step = 0
@@ -59,6 +62,8 @@ def _run(srv, plan):
             if at == step:
                 ids[k] = srv.submit(net, x, m)
         srv.step()
+        if lockstep:
+            srv.sync()
         done.update(srv.poll())
         step += 1
         assert step < 100000, "server made no progress"
@@ -77,11 +82,15 @@ def test_request_alone_equals_request_in_mix(setup):
     srv = hconv.Server(ctx, arena_bytes=8 << 30, max_batch=16, streams=2)
     na, nb = srv.add_net(layers_a), srv.add_net(layers_b)
     rid = _run(srv, [(0, na, dxa, dma)])[0]
+    # alone, its 1x1 layer at 56 x 56 (c_n f^2 = 2) ran through the coefficient-domain conv
+    assert srv.stats()["direct_groups"] == 1, srv.stats()
     alone = [srv.outputs(rid, k, na) for k in range(len(layers_a))]
     alone = [(host(c0).copy(), host(c1).copy()) for c0, c1 in alone]
     srv.release(rid)
     srv.close()
-    # in a mix: other requests of both networks arrive before, with and after it
+    # in a mix: five other requests of network a are submitted in the same step as
+    # it (so all six go through every layer as one group: the 1x1 layer takes the
+    # NTT path), and requests of network b arrive before, with and after it
     print("serving: request in a mix", flush=True)
     plan = []
     others = []
@@ -89,13 +98,16 @@ def test_request_alone_equals_request_in_mix(setup):
         net, specs, layers = (na, specs_a, layers_a) if k % 3 else (nb, specs_b, layers_b)
         x, m = _inputs(ctx, specs, layers, g)
         others.append((net, [dev(v) for v in x], [dev(v) for v in m]))
-        plan.append((k // 2, net, others[-1][1], others[-1][2]))
+        plan.append((1 if net == na else k // 2, net, others[-1][1], others[-1][2]))
     plan.insert(4, (1, na, dxa, dma))
     srv = hconv.Server(ctx, arena_bytes=8 << 30, max_batch=16, streams=3, max_inflight=3)
     assert srv.add_net(layers_a) == na and srv.add_net(layers_b) == nb
-    ids = _run(srv, plan)
+    ids = _run(srv, plan, lockstep=True)
     st = srv.stats()
     assert st["completed"] == len(plan) and st["groups"] < st["images"], st  # some layers were batched
+    # no group of network a had one image: the request's 1x1 layer ran in a group, by the NTT
+    # path, and network b has no layer that takes the coefficient-domain conv
+    assert st["direct_groups"] == 0, st
     for k in range(len(layers_a)):
         c0, c1 = srv.outputs(ids[4], k, na)
         assert (host(c0) == alone[k][0]).all() and (host(c1) == alone[k][1]).all(), f"layer {k} differs in the mix"
