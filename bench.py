@@ -746,7 +746,7 @@ def main():
         log(f"resnet18_cifar plain: {r18['ms_per_image']:.3f} ms/image")
         sv = S.sweep(hconv, W, ctx, {"resnet18_cifar": r18_layers, "resnet50_224": layers}, mix=0.5,
                      rates=[float(v) for v in a.serve_rates.split(",")], duration=a.serve_duration,
-                     arena_gib=48.0, max_batch=16, streams=4, max_inflight=8, burst=32, sets=2, seed=a.seed,
+                     arena_gib=128.0, max_batch=16, streams=4, max_inflight=8, burst=64, sets=2, seed=a.seed,
                      bfly_peak=peaks[0], mac_peak=peaks[1])
         sv["workload"] = ("serving: Poisson arrivals, 50% ResNet-50 224x224 / 50% ResNet-18 32x32 requests, "
                           "N=8192, 3 primes, continuous batching")
