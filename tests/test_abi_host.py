@@ -113,3 +113,28 @@ def test_client_and_protocol_entry_points_reject_null_handles():
     assert lib.hc_act_pmult(n, n, n, n, n, 1, n, 0, n) == -1
     assert lib.hc_act_combine(n, n, n, n, n, n, 1, n) == -1
     assert lib.hc_last_error() != b""
+
+
+def test_new_entry_points_reject_null_handles():
+    """The conventional convolution, rotation-order encoding, pipelined batch,
+    no-allocation conv, per-batch-size tuning and VALU probe entry points
+    refuse null handles and outputs before any device call."""
+    lib = hconv.load()
+    n = None
+    sz = ctypes.c_size_t()
+    assert lib.hc_cconv_create(n, n, n, 10, n, n) == -1
+    assert lib.hc_cconv_info(n, n, n) == -1
+    assert lib.hc_cconv_keys_size(n, ctypes.byref(sz)) == -1
+    assert lib.hc_cconv_keygen_workspace_size(n, ctypes.byref(sz)) == -1
+    assert lib.hc_cconv_keygen(n, n, n, n, n, n, 0, n) == -1
+    assert lib.hc_cconv_workspace_size(n, 1, ctypes.byref(sz)) == -1
+    assert lib.hc_cconv_run(n, n, n, n, 1, n, 0, n) == -1
+    lib.hc_cconv_destroy(n)  # a no-op
+    assert lib.hc_rot_encode(n, n, n, 1, n) == -1
+    assert lib.hc_rot_decode(n, n, n, 1, n, 0, n) == -1
+    assert lib.hc_batch_run_pipelined(n, n, n, n, n, 1 << 20, 3, n) == -1
+    assert lib.hc_conv_masked_noalloc(n, n, n, n, n, 1, n) == -1
+    t = hconv.Tuning()
+    assert lib.hc_layer_get_tuning_for(n, 1, ctypes.byref(t)) == -1
+    assert lib.hc_valu_probe(0, n) == -1
+    assert lib.hc_last_error() != b""
