@@ -55,10 +55,11 @@ CUS, CLK = 256, 2.4e9                 # compute units, peak engine clock
 # mul_hi, mad_u64_u32). The valu_probe object checks them on the device.
 SIMPLE_LANES, MUL_LANES = 128, 64
 # The inverse NTT's butterfly as compiled (Gentleman-Sande with a Shoup
-# twiddle, lazy [0, 2q)): 3 multiplies (mul_hi, 2 mul_lo) + 6 simple ops (sum,
-# its conditional subtraction as sub + min, difference + 2q as add + sub, and
-# the Shoup subtraction).
-BFLY_MULS, BFLY_SIMPLE = 3, 6
+# twiddle, lazy [0, 2q)): 3 multiplier operations (mul_hi, then two
+# mad_u64_u32 whose low word is the Shoup product, with no subtraction) + 5
+# simple ops (sum, its conditional subtraction as sub + min, difference + 2q
+# as add + sub).
+BFLY_MULS, BFLY_SIMPLE = 3, 5
 BFLY_PEAK = CUS * CLK / (BFLY_MULS / MUL_LANES + BFLY_SIMPLE / SIMPLE_LANES)
 # MAC term: one v_mad_u64_u32.
 MAC_PEAK = CUS * CLK * MUL_LANES

@@ -28,6 +28,36 @@ __device__ __forceinline__ uint32_t shoup_lazy(uint32_t a, uint32_t w, uint32_t 
 }
 __device__ __forceinline__ uint32_t csub(uint32_t a, uint32_t m) { return a >= m ? a - m : a; }
 
+// v_mad_u64_u32 (a * b + c over 64 bits) issues at the rate of a 32-bit
+// multiply. Shoup's product a w - floor(a w' / 2^32) q only needs its low 32
+// bits, which equal those of (a w) + floor(a w' / 2^32) (2^32 - q): written
+// with two of these the subtraction disappears (3 multiplier operations, no
+// simple one). Inline assembly, because the compiler narrows a 64-bit product
+// whose high half is unused back to v_mul_lo_u32 + v_add_u32. The carry-out
+// mask goes to a scalar pair that nothing reads. SB: b is wave-uniform (a
+// scalar register); otherwise b is a per-lane value.
+template <bool SB>
+__device__ __forceinline__ uint64_t mul64(uint32_t a, uint32_t b) {
+  uint64_t r, carry;
+  if constexpr (SB)
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=s"(carry) : "v"(a), "s"(b));
+  else
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=s"(carry) : "v"(a), "v"(b));
+  return r;
+}
+// low 32 bits of hi * nq + c, nq wave-uniform
+__device__ __forceinline__ uint32_t mad_lo_s(uint32_t hi, uint32_t nq, uint64_t c) {
+  uint64_t r, carry;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(hi), "s"(nq), "v"(c));
+  return (uint32_t)r;
+}
+// shoup_lazy(a, w, wp, q) with nq = 2^32 - q (wave-uniform): the same value
+template <bool SW>
+__device__ __forceinline__ uint32_t shoup_mad(uint32_t a, uint32_t w, uint32_t wp, uint32_t nq) {
+  const uint32_t hi = __umulhi(a, wp);
+  return mad_lo_s(hi, nq, mul64<SW>(a, w));
+}
+
 // acc < 2^64 -> acc mod q, q < 2^30.
 __device__ __forceinline__ uint32_t reduce64(uint64_t acc, uint32_t q, uint32_t r2, uint32_t r2p, uint32_t onep) {
   uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
@@ -45,6 +75,13 @@ __device__ __forceinline__ uint32_t reduce64(uint64_t acc, uint32_t q, uint32_t 
 __host__ __device__ constexpr int n_pass(int logn, int elog) { return (logn + elog - 1) / elog; }
 __host__ __device__ constexpr int pass_bits(int logn, int elog, int k) {
   return logn / n_pass(logn, elog) + (k < logn % n_pass(logn, elog) ? 1 : 0);
+}
+// Waves per SIMD an NTT kernel is compiled for (the compiler then keeps its
+// registers within 512 / waves): one polynomial per workgroup at 16
+// coefficients per thread fits 64 registers (8 waves), at 32 fits 128 (4);
+// other shapes keep the compiler's choice.
+__host__ __device__ constexpr int ntt_min_waves(int elog, int m) {
+  return m == 1 && elog == 4 ? 8 : m == 1 && elog == 5 ? 4 : 1;
 }
 // Forward passes walk the index bits from the top down (stage s touches bit
 // LOGN-1-s); inverse passes walk them from the bottom up.
@@ -151,7 +188,8 @@ struct RegTw {
 template <int LOGN, int ELOG, int LO, int EP, class TW>
 __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], const TW &tws, uint32_t q) {
   constexpr int E = 1 << ELOG;
-  const uint32_t q2 = 2 * q;
+  constexpr bool kUniTw = LO >= 6;  // wave-uniform twiddles (scalar registers)
+  const uint32_t q2 = 2 * q, nq = 0u - q;
 #pragma unroll
   for (int bb = EP - 1; bb >= 0; --bb) {
     // butterflies side by side, one operation at a time (as in inv_pass);
@@ -166,7 +204,7 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], const TW &tws
     for (int k = 0; k < E / 2; ++k) {
       const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
       const uint32_t X = csub(v[u], q2);
-      const uint32_t T = v[u2] * tws(bb, u).x - hi[k] * q;  // Shoup: in [0, 2q)
+      const uint32_t T = mad_lo_s(hi[k], nq, mul64<kUniTw>(v[u2], tws(bb, u).x));  // Shoup: in [0, 2q)
       v[u] = X + T;
       v[u2] = X - T + q2;
     }
@@ -188,7 +226,10 @@ template <int LOGN, int ELOG, int LO, int EP, int PS, int M, class TW>
 __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &tws, uint32_t q, uint32_t ninv,
                                          uint32_t ninvp, uint32_t ninvw, uint32_t ninvwp) {
   constexpr int E = 1 << ELOG;
-  const uint32_t q2 = 2 * q;
+  // twiddles of a pass starting at bit 6 or above are the same for a whole
+  // wave (scalar registers)
+  constexpr bool kUniTw = LO >= 6;
+  const uint32_t q2 = 2 * q, nq = 0u - q;
 #pragma unroll
   for (int bb = 0; bb < EP; ++bb) {
     const int b = LO + bb;
@@ -221,8 +262,8 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &
 #pragma unroll
         for (int k = 0; k < E / 2; ++k) {
           const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
-          v[m][u] = a[m][k] * ninv - ha[m][k] * q;
-          if (!sum_only) v[m][u2] = d[m][k] * ninvw - hd[m][k] * q;
+          v[m][u] = mad_lo_s(ha[m][k], nq, mul64<true>(a[m][k], ninv));
+          if (!sum_only) v[m][u2] = mad_lo_s(hd[m][k], nq, mul64<true>(d[m][k], ninvw));
         }
     } else if (sum_only) {
 #pragma unroll
@@ -255,7 +296,7 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &
 #pragma unroll
         for (int k = 0; k < E / 2; ++k) {
           const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
-          v[m][u2] = d[m][k] * tws(bb, u).x - hi[m][k] * q;  // in [0, 2q)
+          v[m][u2] = mad_lo_s(hi[m][k], nq, mul64<kUniTw>(d[m][k], tws(bb, u).x));  // in [0, 2q)
         }
     }
   }

@@ -32,7 +32,7 @@ using gu32 = __attribute__((address_space(1))) uint32_t;
 // slot 0 and store nothing. PRE: the stages on index bits below PRE were done
 // by the multiply-accumulate (Yhat holds their output).
 template <int LOGN, int ELOG, int PS, int M, int PRE>
-__global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_masked(const uint32_t *yhat, const uint32_t *mask,
+__global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per_eu(ntt_min_waves(ELOG, M)))) void k_intt_masked(const uint32_t *yhat, const uint32_t *mask,
                                                                      uint32_t *c0_ext, uint32_t *c1_out, ConvGeom g,
                                                                      uint32_t B, LimbConsts c, Twiddles tws,
                                                                      OutPtrs out) {

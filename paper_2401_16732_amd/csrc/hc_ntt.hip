@@ -54,7 +54,7 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
 
 // Full mode: [P][N] -> [P][N] canonical (in place allowed).
 template <int LOGN, int ELOG>
-__global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_intt_full(const uint32_t *in, uint32_t *out, LimbConsts c,
+__global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per_eu(ntt_min_waves(ELOG, 1)))) void k_intt_full(const uint32_t *in, uint32_t *out, LimbConsts c,
                                                                    Twiddles tws) {
   constexpr int N = 1 << LOGN, E = 1 << ELOG, NP = n_pass(LOGN, ELOG);
   __shared__ uint32_t lds[N + N / 32];

@@ -8,7 +8,8 @@
 //   mad64  : v_mad_u64_u32, the multiply-accumulate's instruction
 //   bfly   : the inverse NTT's Gentleman-Sande butterfly with a Shoup twiddle,
 //            compiled from the same inv_pass template as the inverse kernels
-//            (16 coefficients per thread, 4 stages per pass, twiddles in registers)
+//            (16 coefficients per thread, 4 stages per pass, per-lane twiddles
+//            in registers)
 #include "hc_device.h"
 
 namespace hc {
@@ -73,9 +74,14 @@ __global__ __launch_bounds__(256) void k_probe_mad64(uint32_t *out, uint32_t ite
 }
 
 // Twiddles for the butterfly probe: {w, floor(w 2^32 / q)} pairs, any w < q.
+// Two per stage, in registers (per-lane values, as in the first inverse
+// passes): the instruction sequence is that of the kernels, and the probe
+// needs few enough registers for 8 waves per SIMD.
 struct ProbeTw {
-  uint32_t w[4][16], wp[4][16];
-  __device__ __forceinline__ uint2 operator()(int bb, int u) const { return make_uint2(w[bb][u], wp[bb][u]); }
+  uint32_t w[4][2], wp[4][2];
+  __device__ __forceinline__ uint2 operator()(int bb, int u) const {
+    return make_uint2(w[bb][(u >> 1) & 1], wp[bb][(u >> 1) & 1]);
+  }
 };
 
 __global__ __launch_bounds__(256) void k_probe_bfly(uint32_t *out, uint32_t iters, uint32_t q, const uint2 *tw) {
@@ -83,8 +89,8 @@ __global__ __launch_bounds__(256) void k_probe_bfly(uint32_t *out, uint32_t iter
 #pragma unroll
   for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const uint2 v = tw[(bb * 16 + u + threadIdx.x) & 63];
+    for (int u = 0; u < 2; ++u) {
+      const uint2 v = tw[(bb * 2 + u + threadIdx.x) & 63];
       t.w[bb][u] = v.x;
       t.wp[bb][u] = v.y;
     }
