@@ -51,6 +51,12 @@ __device__ __forceinline__ uint32_t mad_lo_s(uint32_t hi, uint32_t nq, uint64_t 
   asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(hi), "s"(nq), "v"(c));
   return (uint32_t)r;
 }
+// a * b + c over 64 bits, b wave-uniform
+__device__ __forceinline__ uint64_t mad64_s(uint32_t a, uint32_t b, uint64_t c) {
+  uint64_t r, carry;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
 // shoup_lazy(a, w, wp, q) with nq = 2^32 - q (wave-uniform): the same value
 template <bool SW>
 __device__ __forceinline__ uint32_t shoup_mad(uint32_t a, uint32_t w, uint32_t wp, uint32_t nq) {
@@ -64,6 +70,22 @@ __device__ __forceinline__ uint32_t reduce64(uint64_t acc, uint32_t q, uint32_t 
   uint32_t r = shoup_lazy(hi, r2, r2p, q) + shoup_lazy(lo, 1u, onep, q);  // [0, 4q)
   r = csub(r, 2 * q);
   return csub(r, q);
+}
+
+// acc < 2^64 -> a value in [0, 2q) congruent to acc mod q (q < 2^30), for
+// wave-uniform q and r2 = 2^32 mod q. With acc = hi 2^32 + lo, the value
+// hi r2 + lo - (floor(hi r2p / 2^32) + floor(lo onep / 2^32)) q is the sum of
+// two Shoup remainders, so it lies in [0, 4q) and is exact mod 2^32: the
+// first v_mad_u64_u32 takes acc itself as its addend (its low word is lo),
+// the second subtracts the quotients' multiple of q. Seven operations where
+// the canonical reduce64 takes about twelve; every inverse-NTT input accepts
+// [0, 2q).
+__device__ __forceinline__ uint32_t reduce64_lazy(uint64_t acc, uint32_t q, uint32_t r2, uint32_t r2p,
+                                                  uint32_t onep) {
+  const uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
+  const uint32_t Q = __umulhi(hi, r2p) + __umulhi(lo, onep);
+  const uint32_t r = mad_lo_s(Q, 0u - q, mad64_s(hi, r2, acc));
+  return csub(r, 2 * q);
 }
 
 // ---------------------------------------------------------------- NTT shape

@@ -5,6 +5,34 @@
 namespace hc {
 
 // ---------------------------------------------------------------- multiply-accumulate
+// A wave's tile of sums leaves as Yhat values in [0, 2q) (the inverse NTT's
+// input range): nc channels x nb images x 2 polynomials, 64 coefficients from
+// kb 64, lane `lane4 / 4` storing one. Each polynomial segment is a raw buffer
+// store whose base (wave-uniform, scalar registers) is the segment and whose
+// lane offset is lane4, so the stores need no vector address arithmetic.
+template <int CT, int BT>
+__device__ __forceinline__ void store_tile(const uint64_t (&acc)[CT][BT][2], uint32_t *Y, const ConvGeom &g,
+                                           uint32_t b0, uint32_t i0, uint32_t tau, uint32_t l, uint32_t kb,
+                                           uint32_t nc, uint32_t nb, uint32_t lane4, uint32_t q, uint32_t r2,
+                                           uint32_t r2p, uint32_t onep) {
+  const size_t LN = (size_t)g.L * g.N;
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc) {
+    if ((uint32_t)cc >= nc) continue;
+    const uint32_t o = (i0 + cc) * g.T + tau;
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) {
+      if ((uint32_t)bb >= nb) continue;
+      uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + (size_t)kb * 64;
+      const __amdgpu_buffer_rsrc_t yr =
+          __builtin_amdgcn_make_buffer_rsrc((void *)y, (short)0, (int)0xffffffffu, (int)kBufferWord3);
+      __builtin_amdgcn_raw_buffer_store_b32(reduce64_lazy(acc[cc][bb][0], q, r2, r2p, onep), yr, lane4, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(reduce64_lazy(acc[cc][bb][1], q, r2, r2p, onep), yr, lane4,
+                                            (uint32_t)(LN * 4), 0);
+    }
+  }
+}
+
 // Yhat[b][o][p][l][k] = sum_{gw < G_w} What[i][gw][l][k] * Xhat[b][gw T + tau][p][l][k]  mod q_l,
 // o = i T + tau.
 // Register-tiled form: one thread owns coefficient k and CT output channels
@@ -102,7 +130,7 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
   // ciphertext, and sets past the end get zero weights. Every fold / NS turns
   // (at most fold terms) the accumulators are folded, exactly mod q; that
   // branch is uniform and does no loads, so both of its paths leave the same
-  // loads in flight. The last partial chunk needs no fold: reduce64 takes any
+  // loads in flight. The last partial chunk needs no fold: the final reduction takes any
   // 64-bit value. NS * (CT + 2 BT) loads in flight must stay within the
   // 63 that the vector memory counter can track.
   uint32_t ws[NS][CT], xs[NS][BT][2];
@@ -148,19 +176,7 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
     }
   }
   const uint32_t r2p = c.r2_p[l], onep = c.one_p[l];
-  const uint32_t k = kb * 64 + lane;
-#pragma unroll
-  for (int cc = 0; cc < CT; ++cc) {
-    if ((uint32_t)cc >= nc) continue;
-    const uint32_t o = (i0 + cc) * g.T + tau;
-#pragma unroll
-    for (int bb = 0; bb < BT; ++bb) {
-      if ((uint32_t)bb >= nb) continue;
-      uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + k;
-      y[0] = reduce64(acc[cc][bb][0], q, r2, r2p, onep);
-      y[LN] = reduce64(acc[cc][bb][1], q, r2, r2p, onep);
-    }
-  }
+  store_tile<CT, BT>(acc, Y, g, b0, i0, tau, l, kb, nc, nb, lane4, q, r2, r2p, onep);
 }
 
 // LDS-staged form of the same register tile. Per input ciphertext ("step")
@@ -362,19 +378,7 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__rest
   if constexpr (PRE == 0) {
     if (i0 >= g.c_out || b0 >= B) return;
     const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
-    const uint32_t k = kb * 64 + lane;
-#pragma unroll
-    for (int cc = 0; cc < CT; ++cc) {
-      if ((uint32_t)cc >= nc) continue;
-      const uint32_t o = (i0 + cc) * g.T + tau;
-#pragma unroll
-      for (int bb = 0; bb < BT; ++bb) {
-        if ((uint32_t)bb >= nb) continue;
-        uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + o) * 2) * LN + (size_t)l * g.N + k;
-        y[0] = reduce64(acc[cc][bb][0], q, r2, r2p, onep);
-        y[LN] = reduce64(acc[cc][bb][1], q, r2, r2p, onep);
-      }
-    }
+    store_tile<CT, BT>(acc, Y, g, b0, i0, tau, l, kb, nc, nb, lane * 4u, q, r2, r2p, onep);
   } else {
     // every wave takes part in the epilogue's barriers, also one whose tile
     // is absent (it stores nothing)
@@ -384,7 +388,7 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__rest
 #pragma unroll
       for (int bb = 0; bb < BT; ++bb)
 #pragma unroll
-        for (int pp = 0; pp < 2; ++pp) val[cc][bb][pp] = reduce64(acc[cc][bb][pp], q, r2, r2p, onep);
+        for (int pp = 0; pp < 2; ++pp) val[cc][bb][pp] = reduce64_lazy(acc[cc][bb][pp], q, r2, r2p, onep);
     // polynomial P = (cc BT + bb) 2 + pp of the wave's tile is row P of the
     // wave's LDS region
     uint32_t *region = (uint32_t *)stage + wave * RWW;
