@@ -116,9 +116,11 @@ typedef struct {
     uint32_t mac_row_groups;  /* waves per workgroup along images */
     uint32_t mac_col_groups;  /* waves per workgroup along output channels */
     uint32_t mac_depth;       /* input ciphertexts whose loads are in flight (2..4 as the tile
-                                 allows; 0 = 2) */
+                                 allows; 0 = 2); with mac_lds = 2 the LDS stages (3, 4 or 6) */
     uint32_t mac_lds;         /* 1: the workgroup stages each input ciphertext's tile through LDS
-                                 with 16-byte loads; 0: every wave loads its operands itself */
+                                 with 16-byte loads into registers; 2: the same tile loaded
+                                 straight into LDS (buffer loads to LDS, no staging registers);
+                                 0: every wave loads its operands itself */
     uint32_t inv_polys;       /* masked inverse NTT: polynomials per workgroup, sharing each twiddle
                                  load (1, or 2 when inv_elog <= 4; 0 = 1) */
     uint32_t mac_pre;         /* masked conv: inverse NTT stages the LDS-staged MAC applies to its

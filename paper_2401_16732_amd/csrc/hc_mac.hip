@@ -460,6 +460,165 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__rest
   }
 }
 
+// s_waitcnt that waits until at most n vector memory operations of this wave
+// are outstanding and leaves the other counters alone (gfx9 encoding: vmcnt
+// in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(n >= 0 && n < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
+
+// One buffer load of `W` bytes per lane into LDS: lane i's bytes land at the
+// wave-uniform LDS address `lds` + i W. (Device pass only: the host pass
+// sees an empty body, since the host target has no such builtin.)
+template <int W>
+__device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, char *lds, uint32_t voff) {
+  static_assert(W == 4 || W == 16, "4- or 16-byte lanes");
+#if defined(__HIP_DEVICE_COMPILE__)
+  using lds_ptr = __attribute__((address_space(3))) void *;
+  if constexpr (W == 16)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)lds, 16, voff, 0, 0, 0);
+  else
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)lds, 4, voff, 0, 0, 0);
+#endif
+}
+
+// DMA-staged form of the same register tile. The step's segments (as in
+// k_mac_lds) go from global memory straight into LDS: buffer loads with the
+// LDS flag, which write lane i's 4 or 16 bytes at a wave-uniform LDS base
+// + i * width, the position the LDS-staged form stores them at. S stages deep:
+// S - 1 steps are in flight and none of them occupies registers. Per step g:
+// wait until this thread's loads of step g have landed (its later steps'
+// loads may stay outstanding), one barrier (then every thread's have, and
+// every wave has finished reading the stage that the next loads refill),
+// issue the loads of step g + S - 1, read the operands from stage g mod S
+// and multiply-accumulate.
+template <int BT, int CT, int RG, int CG, int S>
+__global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__restrict__ X,
+                                                          const uint32_t *__restrict__ Wt,
+                                                          uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
+                                                          uint32_t nib, uint32_t nkb, LimbConsts c) {
+  constexpr int NT = 64 * RG * CG;
+  constexpr int NX = RG * BT * 2, NW = CG * CT;          // segments per step
+  constexpr int XB = NX * 256 / NT, WB = NW * 256 / NT;  // bytes per thread per step
+  static_assert(NX * 256 % NT == 0 && NW * 256 % NT == 0 && XB % 4 == 0 && WB % 4 == 0, "shares must be whole");
+  constexpr int XW = XB % 16 == 0 ? 16 : 4, WWD = WB % 16 == 0 ? 16 : 4;  // access widths
+  constexpr int KX = XB / XW, KW = WB / WWD;                              // accesses per thread per step
+  constexpr int LPS = KX + KW;
+  static_assert(S >= 2 && (S - 1) * LPS <= 63, "loads in flight beyond the vector memory counter");
+  constexpr uint32_t BUFB = (NX + NW) * 256;  // bytes per stage
+  __shared__ uint4 stage4[S * BUFB / 16];
+  char *stage = (char *)stage4;
+  const uint32_t nwg = gridDim.x;
+  uint32_t wg = blockIdx.x;
+  if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
+  // image tiles vary fastest (as in k_mac_lds)
+  const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
+  const uint32_t bt = wg % nbt;
+  uint32_t r = wg / nbt;
+  const uint32_t ib = r % nib;
+  r /= nib;
+  const uint32_t tau = r % g.T;
+  r /= g.T;
+  const uint32_t kb = r % nkb;
+  const uint32_t l = r / nkb;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t lane = tid & 63u;
+  const uint32_t rg = wave % RG, cg = wave / RG;
+  const uint32_t bw = bt * RG * BT, iw = ib * CG * CT;
+  if (bw >= B || iw >= g.c_out) return;  // uniform over the workgroup
+  const uint32_t nbw = min((uint32_t)(RG * BT), B - bw), ncw = min((uint32_t)(CG * CT), g.c_out - iw);
+  const uint32_t LN = g.L * g.N;
+  // per-thread global byte offsets of its accesses, fixed for the whole loop
+  // (absent images and channels read image / channel 0 of the tile)
+  uint32_t xoff[KX], woff[KW];
+#pragma unroll
+  for (int k = 0; k < KX; ++k) {
+    const uint32_t e = (tid + k * NT) * XW, seg = e >> 8, i = seg >> 1;
+    xoff[k] = (((i < nbw ? i : 0u) * g.G * 2 + (seg & 1u)) * LN) * 4u + (e & 255u);
+  }
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const uint32_t e = (tid + k * NT) * WWD, cc = e >> 8;
+    woff[k] = ((cc < ncw ? cc : 0u) * g.G_w * LN) * 4u + (e & 255u);
+  }
+  const char *xbase = (const char *)(X + ((size_t)bw * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const char *wbase = (const char *)(Wt + (size_t)iw * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
+  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
+  const uint32_t G_w = g.G_w, last = G_w - 1;
+  // step gw into stage st: access k of this thread lands at byte (tid + k NT) width
+  // of its operand's part of the stage = wave-uniform (wave 64 + k NT) width + lane width
+  auto issue = [&](uint32_t gw, uint32_t st) {
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(xbase + gw * xstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+    const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(wbase + gw * wstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+    char *sb = stage + st * BUFB;
+#pragma unroll
+    for (int k = 0; k < KX; ++k) load_to_lds<XW>(xr, sb + (wave * 64 + k * NT) * XW, xoff[k]);
+#pragma unroll
+    for (int k = 0; k < KW; ++k) load_to_lds<WWD>(wr, sb + NX * 256 + (wave * 64 + k * NT) * WWD, woff[k]);
+  };
+  const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
+  uint64_t acc[CT][BT][2];
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+  // this wave's operands inside a stage (words)
+  const uint32_t *xs0 = (const uint32_t *)stage + (rg * BT * 2) * 64 + lane;
+  const uint32_t *ws0 = (const uint32_t *)stage + (NX + cg * CT) * 64 + lane;
+  constexpr uint32_t BUFW = BUFB / 4;
+#pragma unroll
+  for (int j = 0; j < S - 1; ++j) issue(min((uint32_t)j, last), (uint32_t)j);
+  uint32_t since_fold = 0;
+  for (uint32_t g0 = 0; g0 < G_w; g0 += S) {
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const uint32_t gw = g0 + j;
+      if (gw >= G_w) break;  // uniform
+      wait_vmcnt<(S - 2) * LPS>();
+      asm volatile("s_barrier" ::: "memory");
+      issue(min(gw + S - 1, last), (uint32_t)((j + S - 1) % S));
+      const uint32_t *xs = xs0 + j * BUFW, *wsp = ws0 + j * BUFW;
+      uint32_t w[CT], x[BT][2];
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc) w[cc] = wsp[cc * 64];
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) {
+        x[bb][0] = xs[(bb * 2) * 64];
+        x[bb][1] = xs[(bb * 2 + 1) * 64];
+      }
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+        for (int bb = 0; bb < BT; ++bb) {
+          acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
+          acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
+        }
+      if (++since_fold == fold) {
+        since_fold = 0;
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+          for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+            for (int pp = 0; pp < 2; ++pp)
+              acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+      }
+    }
+  }
+  // the redundant loads past the last step must land before the workgroup's
+  // LDS is released
+  wait_vmcnt<0>();
+  const uint32_t i0 = iw + cg * CT, b0 = bw + rg * BT;
+  if (i0 >= g.c_out || b0 >= B) return;
+  const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
+  store_tile<CT, BT>(acc, Y, g, b0, i0, tau, l, kb, nc, nb, lane * 4u, q, r2, c.r2_p[l], c.one_p[l]);
+}
+
 template <int BT, int CT, int RG, int CG, int NS, int LDS, int PRE>
 static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
                         const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
@@ -469,7 +628,10 @@ static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w,
   const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
   const size_t nwg = (size_t)nib * g.T * nkb * g.L * nbt;
   if (nwg == 0) return hipSuccess;
-  if constexpr (LDS != 0)
+  if constexpr (LDS == 2)
+    hipLaunchKernelGGL((k_mac_dma<BT, CT, RG, CG, NS>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y, g,
+                       B, nib, nkb, c);
+  else if constexpr (LDS == 1)
     hipLaunchKernelGGL((k_mac_lds<BT, CT, RG, CG, NS, PRE>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w,
                        y, g, B, nib, nkb, c, tw.inv);
   else
@@ -487,7 +649,8 @@ bool mac_offsets_fit(const ConvGeom &g, const MacShape &m) {
 }
 
 // (images per thread, channels per thread, image groups, channel groups,
-//  loads in flight (register sets), LDS-staged, inverse stages in the epilogue)
+//  loads in flight (register sets; LDS stages for the DMA-staged form),
+//  0 register tile / 1 LDS-staged / 2 DMA-staged, inverse stages in the epilogue)
 #define HC_MAC_VARIANTS(X)                                                                                      \
   X(1, 8, 1, 4, 2, 0, 0) X(1, 4, 1, 4, 2, 0, 0) X(2, 4, 1, 4, 2, 0, 0) X(4, 4, 1, 4, 2, 0, 0)                   \
   X(4, 2, 1, 4, 2, 0, 0) X(8, 2, 1, 4, 2, 0, 0) X(4, 4, 4, 2, 2, 0, 0) X(4, 8, 4, 2, 2, 0, 0)                   \
@@ -496,7 +659,9 @@ bool mac_offsets_fit(const ConvGeom &g, const MacShape &m) {
   X(1, 8, 2, 4, 4, 0, 0) X(2, 4, 4, 4, 4, 0, 0) X(1, 8, 1, 4, 4, 0, 0) X(4, 8, 4, 2, 2, 1, 0)                   \
   X(4, 8, 4, 2, 3, 1, 0) X(4, 8, 2, 2, 2, 1, 0) X(4, 8, 2, 2, 3, 1, 0) X(2, 8, 4, 2, 3, 1, 0)                   \
   X(4, 4, 4, 2, 3, 1, 0) X(2, 8, 2, 2, 3, 1, 0) X(4, 8, 4, 2, 2, 1, 5) X(4, 8, 2, 2, 2, 1, 5)                   \
-  X(4, 8, 2, 2, 3, 1, 5)
+  X(4, 8, 2, 2, 3, 1, 5) X(4, 8, 2, 2, 3, 2, 0) X(4, 8, 2, 2, 4, 2, 0) X(4, 8, 2, 2, 6, 2, 0)                   \
+  X(4, 8, 4, 2, 3, 2, 0) X(4, 8, 4, 2, 4, 2, 0) X(2, 8, 4, 2, 4, 2, 0) X(4, 4, 4, 2, 4, 2, 0)                   \
+  X(2, 8, 2, 2, 4, 2, 0) X(4, 4, 2, 2, 4, 2, 0)
 
 bool mac_variant_ok(const MacShape &m) {
 #define HC_MAC_OK(B_, C_, R_, G_, S_, D_, P_)                                                                 \
