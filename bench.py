@@ -122,8 +122,8 @@ def hbm_copy(torch, dev, gib, reps=5):
     return {"bytes_per_copy": 2 * n * 4, "ms": round(ms, 3), "GBps": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
 
 
-# stage -> kernels launched for it (the MAC has a register-tiled and an LDS-staged form)
-STAGE_KERNELS = {"ntt_fwd": ("k_ntt_fwd",), "mac": ("k_mac_tiled", "k_mac_lds"), "intt_mask_extract": ("k_intt_masked",)}
+# stage -> kernels launched for it (the MAC has register-tiled, LDS-staged and DMA-staged forms)
+STAGE_KERNELS = {"ntt_fwd": ("k_ntt_fwd",), "mac": ("k_mac_tiled", "k_mac_lds", "k_mac_dma"), "intt_mask_extract": ("k_intt_masked",)}
 
 
 def measured_traffic(kernel: str, tag: str):
