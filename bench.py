@@ -469,7 +469,7 @@ def cfg_resnet18_224_large(torch, dev, hconv, W, a, probe_peaks):
     res = {"workload": "resnet18_224 HE convolution, 20 conv layers, batched HIP graph",
            "N": N, "L": L, "primes": ctx.primes, "t": t, "batch": B, "layers": len(layers),
            "ms_per_step": round(ms, 3), "ms_per_image": round(ms / B, 4), "steps": a.large_steps,
-           "weight_encode_ms": round(enc_ms, 1), "autotune_ms": round(tune_ms, 1),
+           "weight_encode_ms": round(enc_ms, 1), "autotune_ms": round(tune_ms, 1), "mac_grid_cap": bt.mac_cap,
            "stage_ms_eager": [round(v, 3) for v in stage],
            "modmul_per_s": round((bfly + mac + tot["mask"]) / sec, 1),
            "alu_frac": round((bfly / probe_peaks[0] + mac / probe_peaks[1]) / sec, 4),
@@ -609,7 +609,7 @@ def main():
         t1 = time.perf_counter()
         bt.autotune(ct_in, mask, c0, c1, cache_path=a.tune_cache)
         tune_ms = (time.perf_counter() - t1) * 1e3
-        log(f"autotuned {len(layers)} layers in {tune_ms:.0f} ms")
+        log(f"autotuned {len(layers)} layers in {tune_ms:.0f} ms; graph MAC grid cap {bt.mac_cap}")
 
     for _ in range(a.warmup):
         bt.run(ct_in, mask, c0, c1)
@@ -734,6 +734,7 @@ def main():
         roof["frac_of_probe"] = round(ach / kpeak, 4)
     whole_alu = ((tot["bfly_fwd"] + tot["bfly_inv"]) / peaks[0] + tot["mac"] / peaks[1]) / (ms_step * 1e-3)
 
+    mac_cap = bt.mac_cap
     # the other workloads, after the headline's buffers are released
     configs = None
     if not a.no_configs and a.steps > 0 and a.net == "resnet50_224":
@@ -806,6 +807,7 @@ def main():
         "speedup_vs_plain_ntt_only": None if plain_ms is None else round(plain_ms / per_img, 3),
         "weight_encode_ms": round(encode_ms, 1),
         "autotune_ms": None if tune_ms is None else round(tune_ms, 1),
+        "mac_grid_cap": mac_cap,
         "stage_ms_eager": [round(v, 3) for v in stage],
         "path_bytes_per_step": tot["bytes_path"] + tot["bytes_w"],
         "path_hbm_frac": round((tot["bytes_path"] + tot["bytes_w"]) / (ms_step * 1e-3) / HBM_PEAK, 4),

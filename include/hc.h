@@ -237,6 +237,15 @@ hc_status hc_batch_run_pipelined(hc_batch *batch, const uint32_t *const *ct_in, 
  * re-records its graph. The buffers are overwritten. */
 hc_status hc_batch_autotune(hc_batch *batch, const uint32_t *const *ct_in, const uint32_t *const *mask,
                             uint32_t *const *c0_ext, uint32_t *const *c1_out, void *stream, const char *cache_path);
+/* Grid cap of the batch graph's multiply-accumulate launches (DMA-staged form,
+ * mac_lds = 2; other forms ignore it): 0 launches one workgroup per tile;
+ * cap >= 8 launches at most cap workgroups (rounded down to a multiple of 8),
+ * each looping over its tiles, which leaves room on every compute unit for
+ * the other chains' kernels. A new batch starts at 4 workgroups per compute
+ * unit. Same outputs either way. The next hc_batch_run re-records its graph.
+ * Set returns HC_EINVAL for 1..7. */
+hc_status hc_batch_get_mac_cap(const hc_batch *batch, uint32_t *cap);
+hc_status hc_batch_set_mac_cap(hc_batch *batch, uint32_t cap);
 /* A layer's autotuned shapes and the batch size they apply to (0: none); clearing
  * removes every stored set and returns the layer to the context's shapes. */
 hc_status hc_layer_get_tuning(const hc_layer *layer, uint32_t *batch_size, hc_tuning *out);

@@ -151,6 +151,10 @@ struct hc_batch {
   hipEvent_t fork = nullptr, join[kChains] = {};
   hipGraphExec_t exec = nullptr;
   std::vector<const void *> key;  // pointers the graph was recorded with
+  // grid cap of the graph's DMA-staged MAC launches (0: one workgroup per
+  // tile): capped, a MAC leaves room on every compute unit for the kernels
+  // of the other chains; 4 per compute unit by default
+  uint32_t mac_cap = 0;
   // chunked two-stream pipeline (hc_batch_run_pipelined): its own workspace
   // (X-hat of the largest layer + Y-hat chunk buffers), streams and events
   void *pws = nullptr;
@@ -323,7 +327,7 @@ struct StageTimer {
 // A2 -> A4 (+A5 when masked) for one layer on B images.
 hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_out, const uint32_t *mask,
                        uint32_t *c0_ext, uint32_t *c1_out, uint32_t B, void *ws, bool masked, hipStream_t st,
-                       StageTimer *tm = nullptr) {
+                       StageTimer *tm = nullptr, uint32_t mac_cap = 0) {
   const hc_ctx &c = *ly->ctx;
   const ConvGeom &g = ly->geom;
   const bool timed = tm && tm->on;
@@ -343,7 +347,7 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
   } else {
     uint32_t *yhat = xhat + npin * c.N;
     if (timed) HC_HIP(hipEventRecord(tm->ev[2], st));
-    HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, c.tw, st));
+    HC_HIP(hc::launch_mac(g, sh.mac, xhat, ly->d_w, yhat, B, c.consts, c.tw, st, mac_cap));
     if (timed) HC_HIP(hipEventRecord(tm->ev[3], st));
     if (timed) HC_HIP(hipEventRecord(tm->ev[4], st));
     HC_HIP(hc::launch_intt_masked(g, c.logn, sh.ie, sh.ipw, sh.mac.pre, yhat, mask, c0_ext, c1_out, B, c.consts,
@@ -832,10 +836,15 @@ hc_status hc_batch_create(hc_ctx *c, const hc_layer *const *layers, uint32_t n, 
     e = hipStreamCreateWithFlags(&bt->side[s], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->join[s], hipEventDisableTiming);
   }
+  // the graph's MAC launches: at most 4 workgroups per compute unit, each
+  // looping over its tiles (hc_batch_set_mac_cap)
+  int cus = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e != hipSuccess) {
     hc_batch_destroy(bt);
     return hip_fail(e, "batch streams");
   }
+  bt->mac_cap = 4 * (uint32_t)cus;
   *out = bt;
   return HC_OK;
 }
@@ -886,6 +895,7 @@ hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_lds);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.inv_polys);
   key.push_back((const void *)(uintptr_t)bt->ctx->tune.mac_pre);
+  key.push_back((const void *)(uintptr_t)bt->mac_cap);
   for (size_t k = 0; k < n; ++k) {
     key.push_back(ct_in[k]);
     key.push_back(mask[k]);
@@ -909,7 +919,7 @@ hc_status hc_batch_run(hc_batch *bt, const uint32_t *const *ct_in, const uint32_
     hc_status cs = HC_OK;
     for (size_t k = 0; k < n && e == hipSuccess && cs == HC_OK; ++k)
       cs = enqueue_conv(bt->layers[k], ct_in[k], nullptr, mask[k], c0[k], c1[k], bt->B,
-                        (char *)bt->ws + bt->ws_off[k], true, bt->side[k % kChains]);
+                        (char *)bt->ws + bt->ws_off[k], true, bt->side[k % kChains], nullptr, bt->mac_cap);
     for (int sd = 0; sd < kChains && e == hipSuccess; ++sd) {
       e = hipEventRecord(bt->join[sd], bt->side[sd]);
       if (e == hipSuccess) e = hipStreamWaitEvent(cap, bt->join[sd], 0);
@@ -1236,6 +1246,19 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     (void)hipGraphExecDestroy(bt->exec);
     bt->exec = nullptr;
   }
+  return HC_OK;
+}
+
+hc_status hc_batch_get_mac_cap(const hc_batch *bt, uint32_t *cap) {
+  if (!bt || !cap) return fail(HC_EINVAL, "null argument");
+  *cap = bt->mac_cap;
+  return HC_OK;
+}
+
+hc_status hc_batch_set_mac_cap(hc_batch *bt, uint32_t cap) {
+  if (!bt) return fail(HC_EINVAL, "null argument");
+  if (cap != 0 && cap < 8) return fail(HC_EINVAL, "a MAC grid cap is 0 or at least 8");
+  bt->mac_cap = cap;
   return HC_OK;
 }
 

@@ -104,8 +104,11 @@ hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, u
                               const uint32_t *yhat,
                               const uint32_t *mask, uint32_t *c0_ext, uint32_t *c1_out, uint32_t B,
                               const LimbConsts &c, const Twiddles &tw, hipStream_t st, const OutPtrs *tab = nullptr);
+// max_wgs > 0 caps the grid of the DMA-staged form (its workgroups then loop
+// over the tiles); the other forms ignore it.
 hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *xhat, const uint32_t *what,
-                      uint32_t *yhat, uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st);
+                      uint32_t *yhat, uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st,
+                      uint32_t max_wgs = 0);
 hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *filters, uint32_t *w, const LimbConsts &c,
                                  hipStream_t st);
 hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st);

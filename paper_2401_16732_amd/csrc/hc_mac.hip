@@ -494,11 +494,18 @@ __device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, char *lds,
 // every wave has finished reading the stage that the next loads refill),
 // issue the loads of step g + S - 1, read the operands from stage g mod S
 // and multiply-accumulate.
+// The grid may be smaller than the ntiles tiles: each workgroup then loops
+// over its share, so that a capped launch leaves room on every compute unit
+// for the workgroups of a kernel running beside it on another stream. With
+// the grid and ntiles multiples of 8, workgroup w (on XCD w mod 8) takes the
+// tiles (w mod 8) ntiles/8 + w/8 + k grid/8: the workgroups of one XCD work
+// on consecutive tiles, as the full launch's remap arranges.
 template <int BT, int CT, int RG, int CG, int S>
 __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__restrict__ X,
                                                           const uint32_t *__restrict__ Wt,
                                                           uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
-                                                          uint32_t nib, uint32_t nkb, LimbConsts c) {
+                                                          uint32_t nib, uint32_t nkb, LimbConsts c,
+                                                          uint32_t ntiles) {
   constexpr int NT = 64 * RG * CG;
   constexpr int NX = RG * BT * 2, NW = CG * CT;          // segments per step
   constexpr int XB = NX * 256 / NT, WB = NW * 256 / NT;  // bytes per thread per step
@@ -508,129 +515,146 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
   constexpr int LPS = KX + KW;
   static_assert(S >= 2 && (S - 1) * LPS <= 63, "loads in flight beyond the vector memory counter");
   constexpr uint32_t BUFB = (NX + NW) * 256;  // bytes per stage
+  constexpr uint32_t BUFW = BUFB / 4;
   __shared__ uint4 stage4[S * BUFB / 16];
   char *stage = (char *)stage4;
-  const uint32_t nwg = gridDim.x;
-  uint32_t wg = blockIdx.x;
-  if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
-  // image tiles vary fastest (as in k_mac_lds)
-  const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
-  const uint32_t bt = wg % nbt;
-  uint32_t r = wg / nbt;
-  const uint32_t ib = r % nib;
-  r /= nib;
-  const uint32_t tau = r % g.T;
-  r /= g.T;
-  const uint32_t kb = r % nkb;
-  const uint32_t l = r / nkb;
+  const uint32_t G = gridDim.x;
+  const bool xcd = (ntiles & 7u) == 0 && (G & 7u) == 0;
   const uint32_t tid = threadIdx.x;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t lane = tid & 63u;
   const uint32_t rg = wave % RG, cg = wave / RG;
-  const uint32_t bw = bt * RG * BT, iw = ib * CG * CT;
-  if (bw >= B || iw >= g.c_out) return;  // uniform over the workgroup
-  const uint32_t nbw = min((uint32_t)(RG * BT), B - bw), ncw = min((uint32_t)(CG * CT), g.c_out - iw);
   const uint32_t LN = g.L * g.N;
-  // per-thread global byte offsets of its accesses, fixed for the whole loop
-  // (absent images and channels read image / channel 0 of the tile)
-  uint32_t xoff[KX], woff[KW];
-#pragma unroll
-  for (int k = 0; k < KX; ++k) {
-    const uint32_t e = (tid + k * NT) * XW, seg = e >> 8, i = seg >> 1;
-    xoff[k] = (((i < nbw ? i : 0u) * g.G * 2 + (seg & 1u)) * LN) * 4u + (e & 255u);
-  }
-#pragma unroll
-  for (int k = 0; k < KW; ++k) {
-    const uint32_t e = (tid + k * NT) * WWD, cc = e >> 8;
-    woff[k] = ((cc < ncw ? cc : 0u) * g.G_w * LN) * 4u + (e & 255u);
-  }
-  const char *xbase = (const char *)(X + ((size_t)bw * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
-  const char *wbase = (const char *)(Wt + (size_t)iw * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
-  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
   const uint32_t G_w = g.G_w, last = G_w - 1;
-  // step gw into stage st: access k of this thread lands at byte (tid + k NT) width
-  // of its operand's part of the stage = wave-uniform (wave 64 + k NT) width + lane width
-  auto issue = [&](uint32_t gw, uint32_t st) {
-    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(xbase + gw * xstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
-    const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(wbase + gw * wstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
-    char *sb = stage + st * BUFB;
-#pragma unroll
-    for (int k = 0; k < KX; ++k) load_to_lds<XW>(xr, sb + (wave * 64 + k * NT) * XW, xoff[k]);
-#pragma unroll
-    for (int k = 0; k < KW; ++k) load_to_lds<WWD>(wr, sb + NX * 256 + (wave * 64 + k * NT) * WWD, woff[k]);
-  };
-  const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
-  uint64_t acc[CT][BT][2];
-#pragma unroll
-  for (int cc = 0; cc < CT; ++cc)
-#pragma unroll
-    for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
   // this wave's operands inside a stage (words)
   const uint32_t *xs0 = (const uint32_t *)stage + (rg * BT * 2) * 64 + lane;
   const uint32_t *ws0 = (const uint32_t *)stage + (NX + cg * CT) * 64 + lane;
-  constexpr uint32_t BUFW = BUFB / 4;
+  for (uint32_t it = 0;; ++it) {
+    uint32_t wg;
+    if (xcd) {
+      const uint32_t m = (blockIdx.x >> 3) + it * (G >> 3);
+      if (m >= (ntiles >> 3)) break;
+      wg = (blockIdx.x & 7u) * (ntiles >> 3) + m;
+    } else {
+      wg = blockIdx.x + it * G;
+      if (wg >= ntiles) break;
+    }
+    // image tiles vary fastest (as in k_mac_lds)
+    const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
+    const uint32_t bt = wg % nbt;
+    uint32_t r = wg / nbt;
+    const uint32_t ib = r % nib;
+    r /= nib;
+    const uint32_t tau = r % g.T;
+    r /= g.T;
+    const uint32_t kb = r % nkb;
+    const uint32_t l = r / nkb;
+    const uint32_t bw = bt * RG * BT, iw = ib * CG * CT;
+    if (bw >= B || iw >= g.c_out) continue;  // uniform over the workgroup
+    const uint32_t nbw = min((uint32_t)(RG * BT), B - bw), ncw = min((uint32_t)(CG * CT), g.c_out - iw);
+    // per-thread global byte offsets of its accesses, fixed for the tile
+    // (absent images and channels read image / channel 0 of the tile)
+    uint32_t xoff[KX], woff[KW];
 #pragma unroll
-  for (int j = 0; j < S - 1; ++j) issue(min((uint32_t)j, last), (uint32_t)j);
-  uint32_t since_fold = 0;
-  for (uint32_t g0 = 0; g0 < G_w; g0 += S) {
+    for (int k = 0; k < KX; ++k) {
+      const uint32_t e = (tid + k * NT) * XW, seg = e >> 8, i = seg >> 1;
+      xoff[k] = (((i < nbw ? i : 0u) * g.G * 2 + (seg & 1u)) * LN) * 4u + (e & 255u);
+    }
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const uint32_t gw = g0 + j;
-      if (gw >= G_w) break;  // uniform
-      wait_vmcnt<(S - 2) * LPS>();
-      asm volatile("s_barrier" ::: "memory");
-      issue(min(gw + S - 1, last), (uint32_t)((j + S - 1) % S));
-      const uint32_t *xs = xs0 + j * BUFW, *wsp = ws0 + j * BUFW;
-      uint32_t w[CT], x[BT][2];
+    for (int k = 0; k < KW; ++k) {
+      const uint32_t e = (tid + k * NT) * WWD, cc = e >> 8;
+      woff[k] = ((cc < ncw ? cc : 0u) * g.G_w * LN) * 4u + (e & 255u);
+    }
+    const char *xbase = (const char *)(X + ((size_t)bw * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
+    const char *wbase = (const char *)(Wt + (size_t)iw * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
+    // step gw into stage st: access k of this thread lands at byte (tid + k NT) width
+    // of its operand's part of the stage = wave-uniform (wave 64 + k NT) width + lane width
+    auto issue = [&](uint32_t gw, uint32_t st) {
+      const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(xbase + gw * xstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+      const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(wbase + gw * wstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+      char *sb = stage + st * BUFB;
 #pragma unroll
-      for (int cc = 0; cc < CT; ++cc) w[cc] = wsp[cc * 64];
+      for (int k = 0; k < KX; ++k) load_to_lds<XW>(xr, sb + (wave * 64 + k * NT) * XW, xoff[k]);
 #pragma unroll
-      for (int bb = 0; bb < BT; ++bb) {
-        x[bb][0] = xs[(bb * 2) * 64];
-        x[bb][1] = xs[(bb * 2 + 1) * 64];
-      }
+      for (int k = 0; k < KW; ++k) load_to_lds<WWD>(wr, sb + NX * 256 + (wave * 64 + k * NT) * WWD, woff[k]);
+    };
+    const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
+    uint64_t acc[CT][BT][2];
 #pragma unroll
-      for (int cc = 0; cc < CT; ++cc)
+    for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+#pragma unroll
+    for (int j = 0; j < S - 1; ++j) issue(min((uint32_t)j, last), (uint32_t)j);
+    uint32_t since_fold = 0;
+    for (uint32_t g0 = 0; g0 < G_w; g0 += S) {
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const uint32_t gw = g0 + j;
+        if (gw >= G_w) break;  // uniform
+        wait_vmcnt<(S - 2) * LPS>();
+        asm volatile("s_barrier" ::: "memory");
+        issue(min(gw + S - 1, last), (uint32_t)((j + S - 1) % S));
+        const uint32_t *xs = xs0 + j * BUFW, *wsp = ws0 + j * BUFW;
+        uint32_t w[CT], x[BT][2];
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc) w[cc] = wsp[cc * 64];
 #pragma unroll
         for (int bb = 0; bb < BT; ++bb) {
-          acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
-          acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
+          x[bb][0] = xs[(bb * 2) * 64];
+          x[bb][1] = xs[(bb * 2 + 1) * 64];
         }
-      if (++since_fold == fold) {
-        since_fold = 0;
 #pragma unroll
         for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-          for (int bb = 0; bb < BT; ++bb)
+          for (int bb = 0; bb < BT; ++bb) {
+            acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
+            acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
+          }
+        if (++since_fold == fold) {
+          since_fold = 0;
 #pragma unroll
-            for (int pp = 0; pp < 2; ++pp)
-              acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+          for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+            for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+              for (int pp = 0; pp < 2; ++pp)
+                acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+        }
       }
     }
+    // the redundant loads past the last step must land, and every wave must
+    // be done with the stages, before the next tile's loads (or the release
+    // of the workgroup's LDS)
+    wait_vmcnt<0>();
+    asm volatile("s_barrier" ::: "memory");
+    const uint32_t i0 = iw + cg * CT, b0 = bw + rg * BT;
+    if (i0 < g.c_out && b0 < B) {
+      const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
+      store_tile<CT, BT>(acc, Y, g, b0, i0, tau, l, kb, nc, nb, lane * 4u, q, r2, c.r2_p[l], c.one_p[l]);
+    }
   }
-  // the redundant loads past the last step must land before the workgroup's
-  // LDS is released
-  wait_vmcnt<0>();
-  const uint32_t i0 = iw + cg * CT, b0 = bw + rg * BT;
-  if (i0 >= g.c_out || b0 >= B) return;
-  const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
-  store_tile<CT, BT>(acc, Y, g, b0, i0, tau, l, kb, nc, nb, lane * 4u, q, r2, c.r2_p[l], c.one_p[l]);
 }
 
 template <int BT, int CT, int RG, int CG, int NS, int LDS, int PRE>
 static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
-                        const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+                        const LimbConsts &c, const Twiddles &tw, hipStream_t st, uint32_t max_wgs) {
   if (!mac_offsets_fit(g, MacShape{BT, CT, RG, CG, NS, LDS, PRE})) return hipErrorInvalidValue;
   const uint32_t nkb = g.N / 64;
   const uint32_t nib = (g.c_out + CG * CT - 1) / (CG * CT);
   const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
   const size_t nwg = (size_t)nib * g.T * nkb * g.L * nbt;
   if (nwg == 0) return hipSuccess;
-  if constexpr (LDS == 2)
-    hipLaunchKernelGGL((k_mac_dma<BT, CT, RG, CG, NS>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w, y, g,
-                       B, nib, nkb, c);
+  if constexpr (LDS == 2) {
+    // a cap (a multiple of 8, so that the XCD arrangement holds) turns the
+    // launch into workgroups that loop over the tiles
+    const size_t cap = max_wgs >= 8 ? (size_t)(max_wgs & ~7u) : nwg;
+    hipLaunchKernelGGL((k_mac_dma<BT, CT, RG, CG, NS>), dim3((uint32_t)std::min(nwg, cap)), dim3(64 * RG * CG), 0,
+                       st, x, w, y, g, B, nib, nkb, c, (uint32_t)nwg);
+  }
   else if constexpr (LDS == 1)
     hipLaunchKernelGGL((k_mac_lds<BT, CT, RG, CG, NS, PRE>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w,
                        y, g, B, nib, nkb, c, tw.inv);
@@ -673,11 +697,11 @@ bool mac_variant_ok(const MacShape &m) {
 }
 
 hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *x, const uint32_t *w, uint32_t *y,
-                      uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
+                      uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st, uint32_t max_wgs) {
   if (m.pre && g.N < 4096) return hipErrorInvalidValue;  // the epilogue's twiddle layout needs N >= 4096
 #define HC_MAC_CASE(B_, C_, R_, G_, S_, D_, P_)                                                               \
   if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_ && m.pre == P_) \
-    return mac_t<B_, C_, R_, G_, S_, D_, P_>(g, x, w, y, B, c, tw, st);
+    return mac_t<B_, C_, R_, G_, S_, D_, P_>(g, x, w, y, B, c, tw, st, max_wgs);
   HC_MAC_VARIANTS(HC_MAC_CASE)
 #undef HC_MAC_CASE
   return hipErrorInvalidValue;

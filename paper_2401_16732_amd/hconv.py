@@ -30,6 +30,7 @@ SYMBOLS = [
     "hc_server_poll", "hc_server_outputs", "hc_server_release", "hc_server_get_stats", "hc_server_sync",
     "hc_server_destroy", "hc_batch_autotune", "hc_layer_get_tuning", "hc_layer_clear_tuning",
     "hc_layer_get_tuning_for", "hc_valu_probe", "hc_conv_masked_noalloc", "hc_batch_run_pipelined",
+    "hc_batch_get_mac_cap", "hc_batch_set_mac_cap",
     "hc_cconv_create", "hc_cconv_destroy", "hc_cconv_info", "hc_cconv_keys_size", "hc_cconv_keygen_workspace_size",
     "hc_cconv_keygen", "hc_cconv_workspace_size", "hc_cconv_run", "hc_rot_encode", "hc_rot_decode",
     "hc_check_residues", "hc_encrypt_online", "hc_decrypt_workspace_size", "hc_decrypt_extracted", "hc_decrypt",
@@ -135,6 +136,8 @@ def load(path: str = LIB_PATH):
         "hc_valu_probe": (I, [I, P]),
         "hc_conv_masked_noalloc": (I, [P, P, P, P, P, u32, P]),
         "hc_batch_run_pipelined": (I, [P, P, P, P, P, u64, u32, P]),
+        "hc_batch_get_mac_cap": (I, [P, P]),
+        "hc_batch_set_mac_cap": (I, [P, u32]),
         "hc_cconv_create": (I, [P, P, P, u32, P, P]),
         "hc_cconv_destroy": (None, [P]),
         "hc_cconv_info": (I, [P, P, P]),
@@ -685,6 +688,17 @@ class Batch:
         a = self._args(ct_in, mask, c0, c1)
         cp = None if cache_path is None else str(cache_path).encode()
         _check(_lib.hc_batch_autotune(self.h, *a, _stream(stream), cp), "hc_batch_autotune")
+
+    @property
+    def mac_cap(self):
+        """Grid cap of the graph's DMA-staged MAC launches (0: none)."""
+        v = ctypes.c_uint32()
+        _check(_lib.hc_batch_get_mac_cap(self.h, ctypes.byref(v)), "hc_batch_get_mac_cap")
+        return v.value
+
+    @mac_cap.setter
+    def mac_cap(self, cap):
+        _check(_lib.hc_batch_set_mac_cap(self.h, int(cap)), "hc_batch_set_mac_cap")
 
     def run_timed(self, ct_in, mask, c0, c1, stream=None):
         """Eager run with HIP events around every kernel; returns milliseconds

@@ -117,8 +117,8 @@ def test_client_and_protocol_entry_points_reject_null_handles():
 
 def test_new_entry_points_reject_null_handles():
     """The conventional convolution, rotation-order encoding, pipelined batch,
-    no-allocation conv, per-batch-size tuning and VALU probe entry points
-    refuse null handles and outputs before any device call."""
+    no-allocation conv, per-batch-size tuning, MAC grid cap and VALU probe entry
+    points refuse null handles and outputs before any device call."""
     lib = hconv.load()
     n = None
     sz = ctypes.c_size_t()
@@ -137,4 +137,7 @@ def test_new_entry_points_reject_null_handles():
     t = hconv.Tuning()
     assert lib.hc_layer_get_tuning_for(n, 1, ctypes.byref(t)) == -1
     assert lib.hc_valu_probe(0, n) == -1
+    cap = ctypes.c_uint32()
+    assert lib.hc_batch_get_mac_cap(n, ctypes.byref(cap)) == -1
+    assert lib.hc_batch_set_mac_cap(n, 0) == -1
     assert lib.hc_last_error() != b""

@@ -3,7 +3,8 @@
 layers at B = 16 (tiled stem, stride-2 and 1x1 layers) with small chunks, so
 that many chunks rotate through 2 or 3 buffers across layer boundaries, and
 ResNet-18 224x224 layers at N = 16384 with B = 64 (more images than one
-inverse-NTT launch takes per chunk)."""
+inverse-NTT launch takes per chunk). The batch graph with a grid cap on its
+MAC launches gives the same outputs as without."""
 import pytest
 
 from paper_2401_16732_amd import workloads as W
@@ -71,5 +72,42 @@ def test_pipelined_equals_graph_large_ring_b64(hc):
     for k in range(len(layers)):
         assert torch.equal(p0[k], g0[k]) and torch.equal(p1[k], g1[k]), k
     bt.close()
+    for ly in layers:
+        ly.close()
+
+
+@pytest.mark.parametrize("tile", [(4, 8, 2, 2, 4, 2), (2, 8, 4, 2, 4, 2)])
+def test_mac_grid_cap_equals_uncapped(hc, tile):
+    """The batch graph with its DMA-staged MAC launches capped (workgroups that
+    loop over the tiles; 8 workgroups take hundreds of tiles each, 13 rounds
+    down to 8, 264 is not a power of two, and the default of 4 per compute
+    unit) gives the uncapped graph's outputs. One batch per cap, each
+    recording its graph once."""
+    import torch
+    N, L, t, B = 8192, 3, 2 ** 20, 16
+    ctx, layers, ct_in, mask, outs = _case(hc, "resnet50_224", ("stem", "s1.b0.c2", "s2.b0.proj", "s4.b0.c3"),
+                                           N, L, t, B, 67)
+    ctx.set_tuning(0, 0, *tile)
+    ref = hc.Batch(ctx, layers, B)
+    default_cap = ref.mac_cap
+    assert default_cap >= 8 and default_cap % 8 == 0
+    ref.mac_cap = 0
+    g0, g1 = outs()
+    ref.run(ct_in, mask, g0, g1)
+    torch.cuda.synchronize()
+    ref.close()
+    for cap in (8, 13, 264, default_cap):
+        print(f"MAC tile {tile}, grid cap {cap}", flush=True)
+        bt = hc.Batch(ctx, layers, B)
+        bt.mac_cap = cap
+        assert bt.mac_cap == cap
+        p0, p1 = outs()
+        bt.run(ct_in, mask, p0, p1)
+        torch.cuda.synchronize()
+        for k in range(len(layers)):
+            assert torch.equal(p0[k], g0[k]) and torch.equal(p1[k], g1[k]), (cap, k)
+        with pytest.raises(hc.HcError):
+            bt.mac_cap = 5
+        bt.close()
     for ly in layers:
         ly.close()
