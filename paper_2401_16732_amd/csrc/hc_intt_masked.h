@@ -94,13 +94,38 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per
     const gu32 *mrow = out.n ? (const gu32 *)out.mask[b] + i * hw : (const gu32 *)mask + (b * g.c_out + i) * hw;
     gu32 *orow = out.n ? (gu32 *)out.c0[b] + ((size_t)i * g.L + l) * hw
                        : (gu32 *)c0_ext + ((b * g.c_out + i) * g.L + l) * hw;
-    for (uint32_t idx = tid; idx < count; idx += NT) {
-      const uint32_t oy = oy0 + idx / g.wo, ox = idx % g.wo;
-      const uint32_t e = (g.s * oy - tau * g.r_o) * g.w_pad + g.s * ox;
-      const uint32_t r = mrow[oy * g.wo + ox];
-      const uint32_t rc = r > half ? r - t + q : r;  // centred lift of r, taken mod q
-      const uint32_t add = csub(shoup_lazy(rc, dl, dlp, q), q);
-      orow[oy * g.wo + ox] = csub(csub(lm[lpad(e)], q) + add, q);
+    // Output idx of the tile (row oy0 + idx / wo, column idx % wo) is word
+    // idx of the mask and output rows from row oy0, and coefficient
+    // e = s w_pad (idx / wo) + s (idx % wo) of the polynomial (s oy0 is the
+    // tile's first input row, tau r_o). A thread's outputs idx = tid + j NT
+    // step their (row, column) by (NT / wo, NT % wo) with one carry, so no
+    // division per output; their mask words are loaded U at a time, before
+    // any of them is used.
+    constexpr int U = 4;
+    const gu32 *mr = mrow + (size_t)oy0 * g.wo;
+    gu32 *orr = orow + (size_t)oy0 * g.wo;
+    const uint32_t dy = NT / g.wo, dx = NT % g.wo, sw = g.s * g.w_pad;
+    uint32_t ry = tid / g.wo, ox = tid % g.wo;
+    for (uint32_t idx = tid; idx < count; idx += U * NT) {
+      uint32_t rv[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const uint32_t ij = idx + j * NT;
+        rv[j] = ij < count ? mr[ij] : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const uint32_t ij = idx + j * NT;
+        if (ij < count) {
+          const uint32_t e = sw * ry + g.s * ox;
+          const uint32_t rc = rv[j] > half ? rv[j] - t + q : rv[j];  // centred lift of r, taken mod q
+          const uint32_t add = csub(shoup_lazy(rc, dl, dlp, q), q);
+          orr[ij] = csub(csub(lm[lpad(e)], q) + add, q);
+        }
+        ox += dx;
+        ry += dy;
+        if (ox >= g.wo) ox -= g.wo, ++ry;
+      }
     }
   }
 }
