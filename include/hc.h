@@ -123,7 +123,7 @@ typedef struct {
                                  0: every wave loads its operands itself */
     uint32_t inv_polys;       /* masked inverse NTT: polynomials per workgroup, sharing each twiddle
                                  load (1, or 2 when inv_elog <= 4; 0 = 1) */
-    uint32_t mac_pre;         /* masked conv: inverse NTT stages the LDS-staged MAC applies to its
+    uint32_t mac_pre;         /* masked conv: inverse NTT stages the LDS- or DMA-staged MAC applies to its
                                  outputs before storing them (0, or 5 for 4x8 tiles, N >= 4096) */
 } hc_tuning;
 

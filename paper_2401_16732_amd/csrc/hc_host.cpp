@@ -1127,7 +1127,8 @@ const uint32_t kMacCand[][7] = {
     {4, 4, 4, 2, 3, 1, 0}, {2, 8, 2, 2, 3, 1, 0}, {4, 8, 4, 2, 2, 1, 5}, {4, 8, 2, 2, 2, 1, 5},
     {4, 8, 2, 2, 3, 1, 5}, {4, 8, 2, 2, 3, 2, 0}, {4, 8, 2, 2, 4, 2, 0}, {4, 8, 2, 2, 6, 2, 0},
     {4, 8, 4, 2, 3, 2, 0}, {4, 8, 4, 2, 4, 2, 0}, {2, 8, 4, 2, 4, 2, 0}, {4, 4, 4, 2, 4, 2, 0},
-    {2, 8, 2, 2, 4, 2, 0}, {4, 4, 2, 2, 4, 2, 0}};
+    {2, 8, 2, 2, 4, 2, 0}, {4, 4, 2, 2, 4, 2, 0}, {4, 8, 2, 2, 3, 2, 5}, {4, 8, 2, 2, 4, 2, 5},
+    {4, 8, 4, 2, 4, 2, 5}};
 
 }  // namespace
 

@@ -179,6 +179,103 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
   store_tile<CT, BT>(acc, Y, g, b0, i0, tau, l, kb, nc, nb, lane4, q, r2, r2p, onep);
 }
 
+// Epilogue of the LDS- and DMA-staged MACs with PRE (= 5) inverse stages:
+// the wave's 64 sums (one polynomial per lane slot: 2 BT CT = 64) leave in
+// [0, 2q) after the inverse NTT's stages on index bits 0 .. PRE-1, which act
+// within the tile's block of 64 coefficients. In two rounds, one per half of
+// the block, each wave moves its 64 polynomials x 32 coefficients through its
+// LDS region (64 x 36 words from `stage`) so that a lane holds 32 consecutive
+// coefficients of one polynomial, runs the stages in registers with twiddles
+// that are the same for every lane (scalar loads), and goes back through LDS
+// so that every store writes two whole 128-byte runs. Every wave of the
+// workgroup calls it (its barriers), also one whose tile is absent (it stores
+// nothing).
+template <int CT, int BT, int PRE>
+__device__ __forceinline__ void pre_epilogue(const uint64_t (&acc)[CT][BT][2], uint32_t *stage, uint32_t wave,
+                                             uint32_t lane, uint32_t *Y, const ConvGeom &g, uint32_t B,
+                                             uint32_t b0, uint32_t i0, uint32_t tau, uint32_t l, uint32_t kb,
+                                             uint32_t q, uint32_t r2, uint32_t r2p, uint32_t onep,
+                                             const uint2 *__restrict__ twinv) {
+  static_assert(PRE == 5 && 2 * BT * CT == 64, "epilogue stages need one polynomial per lane");
+  constexpr uint32_t RWW = 64 * 36;  // words per wave (64 x (32 + 4 pad))
+  const size_t LN = (size_t)g.L * g.N;
+  uint32_t val[CT][BT][2];
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) val[cc][bb][pp] = reduce64_lazy(acc[cc][bb][pp], q, r2, r2p, onep);
+  // polynomial P = (cc BT + bb) 2 + pp of the wave's tile is row P of the
+  // wave's LDS region
+  uint32_t *region = stage + wave * RWW;
+  const uint32_t q2 = 2 * q, nq = 0u - q;
+  const uint32_t LOGN = 31 - __builtin_clz(g.N);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();  // the staging buffers, or the previous round's region, are free
+    if ((lane >> 5) == (uint32_t)h) {
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+        for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+          for (int pp = 0; pp < 2; ++pp) region[((cc * BT + bb) * 2 + pp) * 36 + (lane & 31u)] = val[cc][bb][pp];
+    }
+    __syncthreads();
+    uint32_t v[32];
+    const uint4 *r4 = (const uint4 *)(region + lane * 36);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint4 t4 = r4[k];
+      v[4 * k] = t4.x, v[4 * k + 1] = t4.y, v[4 * k + 2] = t4.z, v[4 * k + 3] = t4.w;
+    }
+    // stages on bits 0 .. PRE-1 of j = kb 64 + h 32 + u; twiddle index
+    // 2^(LOGN-1-b) + (j >> (b+1)), the same for every lane of the wave
+    const uint32_t j0 = kb * 64 + h * 32;
+#pragma unroll
+    for (int b = 0; b < PRE; ++b) {
+      const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1 - b)) + (j0 >> (b + 1)));
+      // the stage's 16 butterflies side by side, one operation at a time
+      // (pair k is (u, u + 2^b), u = k with a zero inserted at bit b)
+      uint32_t d[16], hi[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
+        const uint32_t X = v[u], Yv = v[u2];
+        d[k] = X - Yv + q2;
+        v[u] = csub(X + Yv, q2);
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) hi[k] = __umulhi(d[k], (uint32_t)(tw[k >> b] >> 32));
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
+        v[u2] = mad_lo_s(hi[k], nq, mul64<true>(d[k], (uint32_t)tw[k >> b]));  // Shoup: in [0, 2q)
+      }
+    }
+    // back through the wave's region so that every store instruction
+    // writes two whole 128-byte runs: lanes 0-31 coefficient (lane) of
+    // polynomial 2 jp, lanes 32-63 the same of polynomial 2 jp + 1
+    uint4 *w4 = (uint4 *)(region + lane * 36);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w4[k] = make_uint4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t half = lane >> 5, kk = lane & 31u;
+#pragma unroll
+    for (int jp = 0; jp < 32; ++jp) {
+      const uint32_t P = 2 * jp + half;  // this lane's polynomial for the jp-th store
+      const uint32_t scc = P / (2 * BT), sbb = (P >> 1) % BT, spp = P & 1u;
+      const uint32_t x = region[P * 36 + kk];
+      if (i0 + scc < g.c_out && b0 + sbb < B)
+        Y[(((size_t)(b0 + sbb) * g.O + (i0 + scc) * g.T + tau) * 2 + spp) * LN + (size_t)l * g.N + kb * 64 +
+          h * 32 + kk] = x;
+    }
+  }
+}
+
 // LDS-staged form of the same register tile. Per input ciphertext ("step")
 // the workgroup needs NX = RG BT 2 input segments and NW = CG CT weight
 // segments of 64 coefficients (256 bytes). They are loaded once per
@@ -213,14 +310,9 @@ struct Chunk<16> {
 };
 
 // PRE > 0 (tiles with one output polynomial per lane, 2 BT CT = 64): before
-// storing, the epilogue applies the inverse NTT's first PRE Gentleman-Sande
-// stages (index bits 0 .. PRE-1), which act within the workgroup's block of 64
-// coefficients. In two rounds, one per half of the block, each wave moves its
-// 64 polynomials x 32 coefficients through LDS so that a lane holds 32
-// consecutive coefficients of one polynomial, runs the stages in registers
-// with twiddles that are the same for every lane (scalar loads, shared by the
-// whole workgroup), and goes back through LDS so that the stores are
-// coalesced. The masked inverse NTT then starts at bit PRE.
+// storing, the epilogue (pre_epilogue) applies the inverse NTT's first PRE
+// Gentleman-Sande stages (index bits 0 .. PRE-1); the masked inverse NTT then
+// starts at bit PRE.
 template <int BT, int CT, int RG, int CG, int R, int PRE>
 __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__restrict__ X,
                                                           const uint32_t *__restrict__ Wt,
@@ -380,83 +472,8 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__rest
     const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
     store_tile<CT, BT>(acc, Y, g, b0, i0, tau, l, kb, nc, nb, lane * 4u, q, r2, r2p, onep);
   } else {
-    // every wave takes part in the epilogue's barriers, also one whose tile
-    // is absent (it stores nothing)
-    uint32_t val[CT][BT][2];
-#pragma unroll
-    for (int cc = 0; cc < CT; ++cc)
-#pragma unroll
-      for (int bb = 0; bb < BT; ++bb)
-#pragma unroll
-        for (int pp = 0; pp < 2; ++pp) val[cc][bb][pp] = reduce64_lazy(acc[cc][bb][pp], q, r2, r2p, onep);
-    // polynomial P = (cc BT + bb) 2 + pp of the wave's tile is row P of the
-    // wave's LDS region
-    uint32_t *region = (uint32_t *)stage + wave * RWW;
-    const uint32_t q2 = 2 * q;
-    const uint32_t LOGN = 31 - __builtin_clz(g.N);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      __syncthreads();  // the staging buffers, or the previous round's region, are free
-      if ((lane >> 5) == (uint32_t)h) {
-#pragma unroll
-        for (int cc = 0; cc < CT; ++cc)
-#pragma unroll
-          for (int bb = 0; bb < BT; ++bb)
-#pragma unroll
-            for (int pp = 0; pp < 2; ++pp) region[((cc * BT + bb) * 2 + pp) * 36 + (lane & 31u)] = val[cc][bb][pp];
-      }
-      __syncthreads();
-      uint32_t v[32];
-      const uint4 *r4 = (const uint4 *)(region + lane * 36);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const uint4 t4 = r4[k];
-        v[4 * k] = t4.x, v[4 * k + 1] = t4.y, v[4 * k + 2] = t4.z, v[4 * k + 3] = t4.w;
-      }
-      // stages on bits 0 .. PRE-1 of j = kb 64 + h 32 + u; twiddle index
-      // 2^(LOGN-1-b) + (j >> (b+1)), the same for every lane of the wave
-      const uint32_t j0 = kb * 64 + h * 32;
-#pragma unroll
-      for (int b = 0; b < PRE; ++b) {
-        const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1 - b)) + (j0 >> (b + 1)));
-        // the stage's 16 butterflies side by side, one operation at a time
-        // (pair k is (u, u + 2^b), u = k with a zero inserted at bit b)
-        uint32_t d[16], hi[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
-          const uint32_t X = v[u], Yv = v[u2];
-          d[k] = X - Yv + q2;
-          v[u] = csub(X + Yv, q2);
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) hi[k] = __umulhi(d[k], (uint32_t)(tw[k >> b] >> 32));
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
-          v[u2] = d[k] * (uint32_t)tw[k >> b] - hi[k] * q;  // Shoup: in [0, 2q)
-        }
-      }
-      // back through the wave's region so that every store instruction
-      // writes two whole 128-byte runs: lanes 0-31 coefficient (lane) of
-      // polynomial 2 jp, lanes 32-63 the same of polynomial 2 jp + 1
-      uint4 *w4 = (uint4 *)(region + lane * 36);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) w4[k] = make_uint4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const uint32_t half = lane >> 5, kk = lane & 31u;
-#pragma unroll
-      for (int jp = 0; jp < 32; ++jp) {
-        const uint32_t P = 2 * jp + half;  // this lane's polynomial for the jp-th store
-        const uint32_t scc = P / (2 * BT), sbb = (P >> 1) % BT, spp = P & 1u;
-        const uint32_t x = region[P * 36 + kk];
-        if (i0 + scc < g.c_out && b0 + sbb < B)
-          Y[(((size_t)(b0 + sbb) * g.O + (i0 + scc) * g.T + tau) * 2 + spp) * LN + (size_t)l * g.N + kb * 64 +
-            h * 32 + kk] = x;
-      }
-    }
+    pre_epilogue<CT, BT, PRE>(acc, (uint32_t *)stage, wave, lane, Y, g, B, b0, i0, tau, l, kb, q, r2, r2p, onep,
+                              twinv);
   }
 }
 
@@ -500,12 +517,13 @@ __device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, char *lds,
 // the grid and ntiles multiples of 8, workgroup w (on XCD w mod 8) takes the
 // tiles (w mod 8) ntiles/8 + w/8 + k grid/8: the workgroups of one XCD work
 // on consecutive tiles, as the full launch's remap arranges.
-template <int BT, int CT, int RG, int CG, int S>
+// PRE: as in k_mac_lds (pre_epilogue; its region reuses the stages).
+template <int BT, int CT, int RG, int CG, int S, int PRE>
 __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__restrict__ X,
                                                           const uint32_t *__restrict__ Wt,
                                                           uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
                                                           uint32_t nib, uint32_t nkb, LimbConsts c,
-                                                          uint32_t ntiles) {
+                                                          uint32_t ntiles, const uint2 *__restrict__ twinv) {
   constexpr int NT = 64 * RG * CG;
   constexpr int NX = RG * BT * 2, NW = CG * CT;          // segments per step
   constexpr int XB = NX * 256 / NT, WB = NW * 256 / NT;  // bytes per thread per step
@@ -516,7 +534,9 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
   static_assert(S >= 2 && (S - 1) * LPS <= 63, "loads in flight beyond the vector memory counter");
   constexpr uint32_t BUFB = (NX + NW) * 256;  // bytes per stage
   constexpr uint32_t BUFW = BUFB / 4;
-  __shared__ uint4 stage4[S * BUFB / 16];
+  static_assert(PRE == 0 || (PRE == 5 && 2 * BT * CT == 64), "epilogue stages need one polynomial per lane");
+  constexpr uint32_t EPB = PRE ? RG * CG * 64 * 36 * 4 : 0;  // pre_epilogue's regions
+  __shared__ uint4 stage4[(S * BUFB > EPB ? S * BUFB : EPB) / 16];
   char *stage = (char *)stage4;
   const uint32_t G = gridDim.x;
   const bool xcd = (ntiles & 7u) == 0 && (G & 7u) == 0;
@@ -632,9 +652,16 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
     wait_vmcnt<0>();
     asm volatile("s_barrier" ::: "memory");
     const uint32_t i0 = iw + cg * CT, b0 = bw + rg * BT;
-    if (i0 < g.c_out && b0 < B) {
-      const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
-      store_tile<CT, BT>(acc, Y, g, b0, i0, tau, l, kb, nc, nb, lane * 4u, q, r2, c.r2_p[l], c.one_p[l]);
+    if constexpr (PRE == 0) {
+      if (i0 < g.c_out && b0 < B) {
+        const uint32_t nc = min((uint32_t)CT, g.c_out - i0), nb = min((uint32_t)BT, B - b0);
+        store_tile<CT, BT>(acc, Y, g, b0, i0, tau, l, kb, nc, nb, lane * 4u, q, r2, c.r2_p[l], c.one_p[l]);
+      }
+    } else {
+      pre_epilogue<CT, BT, PRE>(acc, (uint32_t *)stage, wave, lane, Y, g, B, b0, i0, tau, l, kb, q, r2, c.r2_p[l],
+                                c.one_p[l], twinv);
+      // the regions overlap the stages that the next tile's loads refill
+      __syncthreads();
     }
   }
 }
@@ -652,8 +679,8 @@ static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w,
     // a cap (a multiple of 8, so that the XCD arrangement holds) turns the
     // launch into workgroups that loop over the tiles
     const size_t cap = max_wgs >= 8 ? (size_t)(max_wgs & ~7u) : nwg;
-    hipLaunchKernelGGL((k_mac_dma<BT, CT, RG, CG, NS>), dim3((uint32_t)std::min(nwg, cap)), dim3(64 * RG * CG), 0,
-                       st, x, w, y, g, B, nib, nkb, c, (uint32_t)nwg);
+    hipLaunchKernelGGL((k_mac_dma<BT, CT, RG, CG, NS, PRE>), dim3((uint32_t)std::min(nwg, cap)), dim3(64 * RG * CG),
+                       0, st, x, w, y, g, B, nib, nkb, c, (uint32_t)nwg, tw.inv);
   }
   else if constexpr (LDS == 1)
     hipLaunchKernelGGL((k_mac_lds<BT, CT, RG, CG, NS, PRE>), dim3((uint32_t)nwg), dim3(64 * RG * CG), 0, st, x, w,
@@ -685,7 +712,8 @@ bool mac_offsets_fit(const ConvGeom &g, const MacShape &m) {
   X(4, 4, 4, 2, 3, 1, 0) X(2, 8, 2, 2, 3, 1, 0) X(4, 8, 4, 2, 2, 1, 5) X(4, 8, 2, 2, 2, 1, 5)                   \
   X(4, 8, 2, 2, 3, 1, 5) X(4, 8, 2, 2, 3, 2, 0) X(4, 8, 2, 2, 4, 2, 0) X(4, 8, 2, 2, 6, 2, 0)                   \
   X(4, 8, 4, 2, 3, 2, 0) X(4, 8, 4, 2, 4, 2, 0) X(2, 8, 4, 2, 4, 2, 0) X(4, 4, 4, 2, 4, 2, 0)                   \
-  X(2, 8, 2, 2, 4, 2, 0) X(4, 4, 2, 2, 4, 2, 0)
+  X(2, 8, 2, 2, 4, 2, 0) X(4, 4, 2, 2, 4, 2, 0) X(4, 8, 2, 2, 3, 2, 5) X(4, 8, 2, 2, 4, 2, 5)                   \
+  X(4, 8, 4, 2, 4, 2, 5)
 
 bool mac_variant_ok(const MacShape &m) {
 #define HC_MAC_OK(B_, C_, R_, G_, S_, D_, P_)                                                                 \

@@ -190,7 +190,8 @@ MAC_VARIANTS = [(1, 8, 1, 4, 2, 0, 0), (1, 4, 1, 4, 2, 0, 0), (2, 4, 1, 4, 2, 0,
                 (4, 4, 4, 2, 3, 1, 0), (2, 8, 2, 2, 3, 1, 0), (4, 8, 4, 2, 2, 1, 5), (4, 8, 2, 2, 2, 1, 5),
                 (4, 8, 2, 2, 3, 1, 5), (4, 8, 2, 2, 3, 2, 0), (4, 8, 2, 2, 4, 2, 0), (4, 8, 2, 2, 6, 2, 0),
                 (4, 8, 4, 2, 3, 2, 0), (4, 8, 4, 2, 4, 2, 0), (2, 8, 4, 2, 4, 2, 0), (4, 4, 4, 2, 4, 2, 0),
-                (2, 8, 2, 2, 4, 2, 0), (4, 4, 2, 2, 4, 2, 0)]
+                (2, 8, 2, 2, 4, 2, 0), (4, 4, 2, 2, 4, 2, 0), (4, 8, 2, 2, 3, 2, 5), (4, 8, 2, 2, 4, 2, 5),
+                (4, 8, 4, 2, 4, 2, 5)]
 
 
 def mac_tuning(v, inv_elog=0, inv_polys=0):
