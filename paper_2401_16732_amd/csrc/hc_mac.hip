@@ -498,6 +498,8 @@ __device__ __forceinline__ void load_to_lds(__amdgpu_buffer_rsrc_t r, char *lds,
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)lds, 16, voff, 0, 0, 0);
   else
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)lds, 4, voff, 0, 0, 0);
+#else
+  (void)r, (void)lds, (void)voff;
 #endif
 }
 
