@@ -233,13 +233,29 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << ELOG], const TW &tws
   }
 }
 
+// Pruned stages keep only the outputs that wanted outputs depend on. With
+// A = LOGN - PS (wanted outputs: index < 2^A), the sum a stage on bit b >= A
+// leaves at index j is needed only if bits A..b of j are zero: going back
+// from the last stage, each pruned stage frees one more index bit. The
+// register part of j (gidx(0, u)) is known at compile time, so sums whose
+// register part has such a bit set are not computed at all. (Testing the
+// thread part too, to let whole waves skip a pass, costs the kernels a third
+// more registers, and occupancy, for the branch.)
+template <int LOGN, int ELOG, int LO, int EP, int PS>
+__device__ __forceinline__ bool pruned_sum_needed(int u, int b) {
+  const uint32_t mask = ((2u << b) - 1u) & ~((1u << (LOGN - PS)) - 1u);  // bits A..b
+  return (gidx<LOGN, ELOG, LO, EP>(0, u) & mask) == 0;
+}
+
 // Inverse (Gentleman-Sande, bit-reversed -> natural) stages of one pass; the
 // last stage (s = 0) also multiplies by N^-1.
 // Pruning: when only outputs below 2^(LOGN - PS) are wanted, every stage on a
 // bit b >= LOGN - PS feeds wanted outputs from its lower (sum) half only - all
 // wanted indices have those bits clear - so the difference half, with its
-// twiddle multiply, is skipped there. PS = 0 computes the full transform. PS
-// is a compile-time constant, so no stage carries a run-time branch.
+// twiddle multiply, is skipped there, and of the sums only those that wanted
+// outputs depend on are computed (pruned_sum_needed). PS = 0 computes the
+// full transform. PS is a compile-time constant, so no stage carries a
+// run-time branch.
 // M polynomials of one limb go through the stages together (v[m]): each
 // twiddle is loaded once for all of them.
 // tws(bb, u): twiddle {w, w'} of stage bit LO + bb for register slot u
@@ -269,13 +285,16 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &
 #pragma unroll
         for (int k = 0; k < E / 2; ++k) {
           const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+          if (sum_only && !pruned_sum_needed<LOGN, ELOG, LO, EP, PS>(u, b)) continue;
           a[m][k] = v[m][u] + v[m][u2];
-          d[m][k] = v[m][u] - v[m][u2] + q2;
+          if (!sum_only) d[m][k] = v[m][u] - v[m][u2] + q2;
         }
 #pragma unroll
       for (int m = 0; m < M; ++m)
 #pragma unroll
         for (int k = 0; k < E / 2; ++k) {
+          const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1));
+          if (sum_only && !pruned_sum_needed<LOGN, ELOG, LO, EP, PS>(u, b)) continue;
           ha[m][k] = __umulhi(a[m][k], ninvp);
           if (!sum_only) hd[m][k] = __umulhi(d[m][k], ninvwp);
         }
@@ -284,6 +303,7 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &
 #pragma unroll
         for (int k = 0; k < E / 2; ++k) {
           const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+          if (sum_only && !pruned_sum_needed<LOGN, ELOG, LO, EP, PS>(u, b)) continue;
           v[m][u] = mad_lo_s(ha[m][k], nq, mul64<true>(a[m][k], ninv));
           if (!sum_only) v[m][u2] = mad_lo_s(hd[m][k], nq, mul64<true>(d[m][k], ninvw));
         }
@@ -293,6 +313,7 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &
 #pragma unroll
         for (int k = 0; k < E / 2; ++k) {
           const int u = ((k >> bb) << (bb + 1)) | (k & ((1 << bb) - 1)), u2 = u | (1 << bb);
+          if (!pruned_sum_needed<LOGN, ELOG, LO, EP, PS>(u, b)) continue;
           v[m][u] = csub(v[m][u] + v[m][u2], q2);
         }
     } else {
@@ -448,6 +469,8 @@ struct InvPasses {
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
+      // a pass above the wanted bits whose thread part is not wanted (whole
+      // waves, where those bits come from the wave index) computes nothing
       inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, t, q, a, ap, b, bp);
     } else {
 #pragma unroll
