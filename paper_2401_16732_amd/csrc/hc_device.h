@@ -469,8 +469,6 @@ struct InvPasses {
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
-      // a pass above the wanted bits whose thread part is not wanted (whole
-      // waves, where those bits come from the wave index) computes nothing
       inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, t, q, a, ap, b, bp);
     } else {
 #pragma unroll
