@@ -248,7 +248,9 @@ __device__ __forceinline__ bool pruned_sum_needed(int u, int b) {
 }
 
 // Inverse (Gentleman-Sande, bit-reversed -> natural) stages of one pass; the
-// last stage (s = 0) also multiplies by N^-1.
+// last stage (s = 0) also multiplies by N^-1, unless SC is false (inputs that
+// already carry the factor N^-1: the convolution's weights are stored scaled
+// by it, so its sums do), when it is an ordinary stage.
 // Pruning: when only outputs below 2^(LOGN - PS) are wanted, every stage on a
 // bit b >= LOGN - PS feeds wanted outputs from its lower (sum) half only - all
 // wanted indices have those bits clear - so the difference half, with its
@@ -260,7 +262,7 @@ __device__ __forceinline__ bool pruned_sum_needed(int u, int b) {
 // twiddle is loaded once for all of them.
 // tws(bb, u): twiddle {w, w'} of stage bit LO + bb for register slot u
 // (MemTw, RegTw).
-template <int LOGN, int ELOG, int LO, int EP, int PS, int M, class TW>
+template <int LOGN, int ELOG, int LO, int EP, int PS, int M, bool SC = true, class TW>
 __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &tws, uint32_t q, uint32_t ninv,
                                          uint32_t ninvp, uint32_t ninvw, uint32_t ninvwp) {
   constexpr int E = 1 << ELOG;
@@ -277,7 +279,7 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[M][1 << ELOG], const TW &
     // that independent instructions follow each other rather than each
     // butterfly's dependent chain (Shoup: a w - umulhi(a, w') q). Pair k
     // is (u, u + 2^bb) with u = k with a zero inserted at bit bb.
-    if (s == 0) {
+    if (s == 0 && SC) {
       // N^-1 on the sum; N^-1 psi^-brv(1) on the difference (or nothing: pruned)
       uint32_t a[M][E / 2], d[M][E / 2], ha[M][E / 2], hd[M][E / 2];
 #pragma unroll
@@ -449,7 +451,7 @@ struct EarlyTws {
   }
 };
 
-template <int LOGN, int ELOG, int K, int PS, int M, int PRE>
+template <int LOGN, int ELOG, int K, int PS, int M, int PRE, bool SC = true>
 struct InvPasses {
   template <class TWS>
   static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *lds, uint32_t tid,
@@ -457,7 +459,7 @@ struct InvPasses {
                                              uint32_t bp) {
     constexpr int LO = inv_lo(LOGN, ELOG, PRE, K), EP = inv_ep(LOGN, ELOG, PRE, K);
     constexpr int PLO = inv_lo(LOGN, ELOG, PRE, K - 1), PEP = inv_ep(LOGN, ELOG, PRE, K - 1);
-    InvPasses<LOGN, ELOG, K - 1, PS, M, PRE>::run(v, lds, tid, tws, q, a, ap, b, bp);
+    InvPasses<LOGN, ELOG, K - 1, PS, M, PRE, SC>::run(v, lds, tid, tws, q, a, ap, b, bp);
 #pragma unroll
     for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, PLO, PEP>(v[m], lds + m * lds_words(LOGN), tid);
     __syncthreads();
@@ -469,22 +471,22 @@ struct InvPasses {
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
-      inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, t, q, a, ap, b, bp);
+      inv_pass<LOGN, ELOG, LO, EP, PS, M, SC>(v, t, q, a, ap, b, bp);
     } else {
 #pragma unroll
       for (int m = 0; m < M; ++m) lds_to_regs<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);
-      inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tws.template pass<K>(), q, a, ap, b, bp);
+      inv_pass<LOGN, ELOG, LO, EP, PS, M, SC>(v, tws.template pass<K>(), q, a, ap, b, bp);
     }
   }
 };
-template <int LOGN, int ELOG, int PS, int M, int PRE>
-struct InvPasses<LOGN, ELOG, 0, PS, M, PRE> {
+template <int LOGN, int ELOG, int PS, int M, int PRE, bool SC>
+struct InvPasses<LOGN, ELOG, 0, PS, M, PRE, SC> {
   // pass 0 (bits [PRE, PRE + EP)) expects its inputs already in registers
   template <class TWS>
   static __device__ __forceinline__ void run(uint32_t (&v)[M][1 << ELOG], uint32_t *, uint32_t, const TWS &tws,
                                              uint32_t q, uint32_t a, uint32_t ap, uint32_t b, uint32_t bp) {
     constexpr int LO = inv_lo(LOGN, ELOG, PRE, 0), EP = inv_ep(LOGN, ELOG, PRE, 0);
-    inv_pass<LOGN, ELOG, LO, EP, PS, M>(v, tws.template pass<0>(), q, a, ap, b, bp);
+    inv_pass<LOGN, ELOG, LO, EP, PS, M, SC>(v, tws.template pass<0>(), q, a, ap, b, bp);
   }
 };
 
@@ -526,17 +528,18 @@ __device__ __forceinline__ void load_first(uint32_t (&v)[1 << ELOG], const uint3
 
 // The inverse passes over registers already loaded (load_first), with
 // twiddles from tws: the result is in registers, laid out for the last pass.
-template <int LOGN, int ELOG, int PS, int M, int PRE, class TWS>
+// SC: whether the last stage multiplies by N^-1 (see inv_pass).
+template <int LOGN, int ELOG, int PS, int M, int PRE, bool SC = true, class TWS>
 __device__ __forceinline__ void intt_passes(uint32_t (&v)[M][1 << ELOG], uint32_t *lds, uint32_t tid,
                                             const LimbConsts &c, const TWS &tws, uint32_t l) {
-  InvPasses<LOGN, ELOG, inv_np(LOGN, ELOG, PRE) - 1, PS, M, PRE>::run(v, lds, tid, tws, c.q[l], c.ninv[l],
-                                                                      c.ninv_p[l], c.ninvw[l], c.ninvw_p[l]);
+  InvPasses<LOGN, ELOG, inv_np(LOGN, ELOG, PRE) - 1, PS, M, PRE, SC>::run(v, lds, tid, tws, c.q[l], c.ninv[l],
+                                                                          c.ninv_p[l], c.ninvw[l], c.ninvw_p[l]);
 }
 
 // PS: top stages pruned (see inv_pass); 0 for the whole transform. M
 // polynomials src[m] of one limb, LDS of M * lds_words(LOGN) words. PRE:
 // stages on bits below PRE already done.
-template <int LOGN, int ELOG, int PS, int M, int PRE>
+template <int LOGN, int ELOG, int PS, int M, int PRE, bool SC = true>
 __device__ __forceinline__ void intt_core(const uint32_t *const (&src)[M], uint32_t (&v)[M][1 << ELOG],
                                           uint32_t *lds, uint32_t tid, const LimbConsts &c, const uint2 *tw,
                                           uint32_t l) {
@@ -546,9 +549,9 @@ __device__ __forceinline__ void intt_core(const uint32_t *const (&src)[M], uint3
   // cost it occupancy
   if constexpr (ELOG <= 4) {
     const EarlyTws<LOGN, ELOG, PRE> tws(tw, tid);
-    intt_passes<LOGN, ELOG, PS, M, PRE>(v, lds, tid, c, tws, l);
+    intt_passes<LOGN, ELOG, PS, M, PRE, SC>(v, lds, tid, c, tws, l);
   } else {
-    intt_passes<LOGN, ELOG, PS, M, PRE>(v, lds, tid, c, MemTws<LOGN, ELOG, PRE>{tw, tid}, l);
+    intt_passes<LOGN, ELOG, PS, M, PRE, SC>(v, lds, tid, c, MemTws<LOGN, ELOG, PRE>{tw, tid}, l);
   }
 }
 

@@ -343,7 +343,8 @@ hc_status enqueue_conv(const hc_layer *ly, const uint32_t *ct_in, uint32_t *ct_o
     hc::MacShape m = sh.mac;
     m.pre = 0;  // the full inverse NTT runs every stage
     HC_HIP(hc::launch_mac(g, m, xhat, ly->d_w, ct_out, B, c.consts, c.tw, st));
-    HC_HIP(hc::launch_intt_full(c.logn, sh.ie, ct_out, ct_out, (size_t)B * g.O * 2 * c.L, c.consts, c.tw, st));
+    HC_HIP(hc::launch_intt_full(c.logn, sh.ie, ct_out, ct_out, (size_t)B * g.O * 2 * c.L, c.consts, c.tw, st,
+                                false));  // the weights carry N^-1
   } else {
     uint32_t *yhat = xhat + npin * c.N;
     if (timed) HC_HIP(hipEventRecord(tm->ev[2], st));
@@ -637,6 +638,9 @@ hc_status hc_layer_create(hc_ctx *c, const hc_conv_shape *s, const int8_t *filte
   if (e == hipSuccess)
     e = hc::launch_ntt_fwd(c->logn, shapes_for(*c, 1).fe, ly->d_w, ly->d_w, (size_t)s->c_out * lay.w_cts * c->L,
                            c->consts, c->tw, hs);
+  // stored times N^-1: every sum then carries the inverse NTT's final factor,
+  // and the inverse NTT of the convolution skips it
+  if (e == hipSuccess) e = hc::launch_scale_ninv(ly->d_w, ly->w_elems, c->N, c->consts, hs);
   // int32 filter table for the coefficient-domain conv, rows padded to 16.
   // At one image it beats the NTT path where c_n f^2 <= 2 (measured on the
   // ResNet-50 layer mix at N = 8192: exactly those layers win, all others lose).

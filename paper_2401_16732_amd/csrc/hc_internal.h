@@ -93,9 +93,12 @@ hipError_t launch_ntt_fwd(uint32_t logn, uint32_t elog, const uint32_t *in, uint
 hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
                            const uint32_t *mul, uint32_t mul_div, const LimbConsts &c, const Twiddles &tw,
                            hipStream_t st, uint32_t keep_bits = 32, const uint32_t *addp = nullptr);
-// Full mode: in [P][N] -> out [P][N] (in place allowed).
+// Full mode: in [P][N] -> out [P][N] (in place allowed). scale = false for
+// inputs that carry the factor N^-1 already (the convolution's sums).
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t npolys,
-                            const LimbConsts &c, const Twiddles &tw, hipStream_t st);
+                            const LimbConsts &c, const Twiddles &tw, hipStream_t st, bool scale = true);
+// p [..][L][N] (n words) *= N^-1 mod q_l, canonical.
+hipError_t launch_scale_ninv(uint32_t *p, size_t n, uint32_t N, const LimbConsts &c, hipStream_t st);
 // Masked mode: in = Yhat [B][O][2][L][N]; c1 polys go to c1_out [B][O][L][N],
 // c0 polys are extracted with the mask into c0_ext [B][c_out][L][ho][wo].
 // tab: optional per-image output tables (tab->n == B). npw: polynomials per

@@ -30,7 +30,9 @@ using gu32 = __attribute__((address_space(1))) uint32_t;
 // ciphertext) indices bo with the same half p and limb l; workgroup w is
 // ((pair 2 + p) L + l), bo = pair M + m. Slots past B O compute a copy of
 // slot 0 and store nothing. PRE: the stages on index bits below PRE were done
-// by the multiply-accumulate (Yhat holds their output).
+// by the multiply-accumulate (Yhat holds their output). Yhat carries the
+// factor N^-1 already (the weights are stored scaled by it), so the last stage
+// does not multiply by it.
 template <int LOGN, int ELOG, int PS, int M, int PRE>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per_eu(ntt_min_waves(ELOG, M)))) void k_intt_masked(const uint32_t *yhat, const uint32_t *mask,
                                                                      uint32_t *c0_ext, uint32_t *c1_out, ConvGeom g,
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per
   constexpr int LO = inv_lo(LOGN, ELOG, PRE, NP - 1), EP = inv_ep(LOGN, ELOG, PRE, NP - 1);
   const uint2 *tw = tws.inv + (size_t)l * N;
   if (p == 1) {
-    intt_core<LOGN, ELOG, 0, M, PRE>(src, v, lds, tid, c, tw, l);
+    intt_core<LOGN, ELOG, 0, M, PRE, false>(src, v, lds, tid, c, tw, l);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       if (!valid[m]) continue;
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per
     return;
   }
   // c0 needs only its extracted coefficients
-  intt_core<LOGN, ELOG, PS, M, PRE>(src, v, lds, tid, c, tw, l);
+  intt_core<LOGN, ELOG, PS, M, PRE, false>(src, v, lds, tid, c, tw, l);
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < M; ++m) regs_to_lds<LOGN, ELOG, LO, EP>(v[m], lds + m * lds_words(LOGN), tid);

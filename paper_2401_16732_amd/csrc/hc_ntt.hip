@@ -52,8 +52,9 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) void k_ntt_fwd(const uint32_t *
   (void)NT;
 }
 
-// Full mode: [P][N] -> [P][N] canonical (in place allowed).
-template <int LOGN, int ELOG>
+// Full mode: [P][N] -> [P][N] canonical (in place allowed). SC: the last
+// stage multiplies by N^-1 (false for inputs that carry it already).
+template <int LOGN, int ELOG, bool SC>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per_eu(ntt_min_waves(ELOG, 1)))) void k_intt_full(const uint32_t *in, uint32_t *out, LimbConsts c,
                                                                    Twiddles tws) {
   constexpr int N = 1 << LOGN, E = 1 << ELOG, NP = n_pass(LOGN, ELOG);
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per
   const uint32_t l = (uint32_t)(poly % c.L);
   uint32_t v[1][E];
   const uint32_t *const src[1] = {in + poly * N};
-  intt_core<LOGN, ELOG, 0, 1, 0>(src, v, lds, tid, c, tws.inv + (size_t)l * N, l);
+  intt_core<LOGN, ELOG, 0, 1, 0, SC>(src, v, lds, tid, c, tws.inv + (size_t)l * N, l);
   constexpr int LO = pass_lo_inv(LOGN, ELOG, NP - 1), EP = pass_bits(LOGN, ELOG, NP - 1);
   uint32_t *dst = out + poly * N;
   const uint32_t q = c.q[l];
@@ -284,10 +285,14 @@ static hipError_t ring_mul_t(const uint32_t *in, uint32_t *out, size_t np, const
 }
 template <int LOGN, int ELOG>
 static hipError_t inv_t(const uint32_t *in, uint32_t *out, size_t np, const LimbConsts &c, const Twiddles &tw,
-                        hipStream_t st) {
+                        hipStream_t st, bool scale) {
   if (np == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_intt_full<LOGN, ELOG>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in, out, c,
-                     tw);
+  if (scale)
+    hipLaunchKernelGGL((k_intt_full<LOGN, ELOG, true>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in,
+                       out, c, tw);
+  else
+    hipLaunchKernelGGL((k_intt_full<LOGN, ELOG, false>), dim3((uint32_t)np), dim3(1 << (LOGN - ELOG)), 0, st, in,
+                       out, c, tw);
   return hipGetLastError();
 }
 // (LOGN, ELOG) instances: 2^(LOGN - ELOG) threads per polynomial.
@@ -328,8 +333,24 @@ hipError_t launch_ring_mul(uint32_t logn, uint32_t elog, const uint32_t *in, uin
   HC_NTT_DISPATCH(ring_mul_t, in, out, np, mul, mul_div, ps, addp, c, tw, st)
 }
 hipError_t launch_intt_full(uint32_t logn, uint32_t elog, const uint32_t *in, uint32_t *out, size_t np,
-                            const LimbConsts &c, const Twiddles &tw, hipStream_t st) {
-  HC_NTT_DISPATCH(inv_t, in, out, np, c, tw, st)
+                            const LimbConsts &c, const Twiddles &tw, hipStream_t st, bool scale) {
+  HC_NTT_DISPATCH(inv_t, in, out, np, c, tw, st, scale)
+}
+
+// p [..][L][N] *= N^-1 mod q_l, canonical out (the convolution's resident
+// weights, so that the inverse NTT of its sums needs no final scaling).
+__global__ __launch_bounds__(256) void k_scale_ninv(uint32_t *p, size_t n, uint32_t N, LimbConsts c) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t l = (uint32_t)((i / N) % c.L);
+    const uint32_t q = c.q[l];
+    p[i] = csub(shoup_lazy(p[i], c.ninv[l], c.ninv_p[l], q), q);
+  }
+}
+hipError_t launch_scale_ninv(uint32_t *p, size_t n, uint32_t N, const LimbConsts &c, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_scale_ninv, dim3((uint32_t)blocks), dim3(256), 0, st, p, n, N, c);
+  return hipGetLastError();
 }
 
 bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre) {
