@@ -156,7 +156,8 @@ hc_status hc_plan_ring(uint32_t N, const hc_conv_shape *shape, hc_layout *out);
 hc_status hc_ring_params(uint32_t N, uint32_t L, uint64_t t, uint32_t *primes_out, uint32_t *delta_mod_q_out);
 
 /* Offline weight encoding (Algorithm 1's filters as W_{i,g}, then the forward
- * NTT). filters_host: int8 [c_out][c_in][f][f] in host memory, read during
+ * NTT, stored times N^-1 so that the convolution's inverse NTT needs no final
+ * scaling). filters_host: int8 [c_out][c_in][f][f] in host memory, read during
  * the call. The NTT-domain weights stay resident in device memory owned by the
  * layer until hc_layer_destroy. `stream` is a hipStream_t (NULL = default);
  * the call returns after the encoding has been enqueued and the filters copied. */
