@@ -4,7 +4,8 @@ layers at B = 16 (tiled stem, stride-2 and 1x1 layers) with small chunks, so
 that many chunks rotate through 2 or 3 buffers across layer boundaries, and
 ResNet-18 224x224 layers at N = 16384 with B = 64 (more images than one
 inverse-NTT launch takes per chunk). The batch graph with a grid cap on its
-MAC launches gives the same outputs as without."""
+MAC launches gives the same outputs as without, for every DMA-staged MAC tile
+also on ragged tiles and short reductions."""
 import pytest
 
 from paper_2401_16732_amd import workloads as W
@@ -108,6 +109,54 @@ def test_mac_grid_cap_equals_uncapped(hc, tile):
             assert torch.equal(p0[k], g0[k]) and torch.equal(p1[k], g1[k]), (cap, k)
         with pytest.raises(hc.HcError):
             bt.mac_cap = 5
+        bt.close()
+    for ly in layers:
+        ly.close()
+
+
+DMA_TILES = [(4, 8, 2, 2, 3, 2), (4, 8, 2, 2, 4, 2), (4, 8, 2, 2, 6, 2), (4, 8, 4, 2, 3, 2), (4, 8, 4, 2, 4, 2),
+             (2, 8, 4, 2, 4, 2), (4, 4, 4, 2, 4, 2), (2, 8, 2, 2, 4, 2), (4, 4, 2, 2, 4, 2)]
+
+
+@pytest.mark.parametrize("cap", [8, 64, 0])
+def test_dma_mac_tile_loop_ragged(hc, cap):
+    """Every DMA-staged MAC tile without epilogue stages, its workgroups
+    looping over many tiles (caps 8 and 64) or taking one each (0), on layers
+    whose tiles are ragged in both directions (20 output channels, 5 images)
+    and whose reductions take 1, 2, 3, 5 and 6 input ciphertexts (fewer steps
+    than the staging depth, as many, and more). The outputs equal the
+    register-tiled MAC's (no LDS, uncapped)."""
+    import torch
+    N, L, t, B = 8192, 3, 2 ** 20, 5
+    ctx = hc.Context(N, L, t)
+    # 3x3 on 16x16: 25 channels per ciphertext, so c_i = 20, 30, 60, 110, 130
+    # gives 1, 2, 3, 5, 6 input ciphertexts
+    specs = [W.ConvSpec(ci, 20, 16, 16, 3, 1) for ci in (20, 30, 60, 110, 130)]
+    g = W.rng(68)
+    layers = [hc.Layer(ctx, s.c_i, s.c_o, s.h, s.w, s.f_w, s.stride, W.gen_filters(g, s)) for s in specs]
+    assert [ly.layout.w_cts for ly in layers] == [1, 2, 3, 5, 6]
+    tg = torch.Generator(device="cuda")
+    tg.manual_seed(68)
+    ct_in = [W.gen_ct_limbs_torch(tg, ly.in_shape(B)[:3], ctx.primes, N, "cuda") for ly in layers]
+    mask = [torch.randint(0, t, ly.mask_shape(B), generator=tg, device="cuda", dtype=torch.int32) for ly in layers]
+    outs = lambda: ([torch.zeros(ly.c0_shape(B), dtype=torch.int32, device="cuda") for ly in layers],
+                    [torch.zeros(ly.c1_shape(B), dtype=torch.int32, device="cuda") for ly in layers])
+    ctx.set_tuning(0, 0, 4, 4, 1, 4, 2, 0)
+    ref = hc.Batch(ctx, layers, B)
+    g0, g1 = outs()
+    ref.run(ct_in, mask, g0, g1)
+    torch.cuda.synchronize()
+    ref.close()
+    for tile in DMA_TILES:
+        print(f"DMA MAC tile {tile}, grid cap {cap}", flush=True)
+        ctx.set_tuning(0, 0, *tile)
+        bt = hc.Batch(ctx, layers, B)
+        bt.mac_cap = cap
+        p0, p1 = outs()
+        bt.run(ct_in, mask, p0, p1)
+        torch.cuda.synchronize()
+        for k in range(len(layers)):
+            assert torch.equal(p0[k], g0[k]) and torch.equal(p1[k], g1[k]), (tile, cap, k)
         bt.close()
     for ly in layers:
         ly.close()
