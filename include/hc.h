@@ -242,8 +242,8 @@ hc_status hc_batch_autotune(hc_batch *batch, const uint32_t *const *ct_in, const
  * mac_lds = 2; other forms ignore it): 0 launches one workgroup per tile;
  * cap >= 8 launches at most cap workgroups (rounded down to a multiple of 8),
  * each looping over its tiles, which leaves room on every compute unit for
- * the other chains' kernels. A new batch starts at 4 workgroups per compute
- * unit. Same outputs either way. The next hc_batch_run re-records its graph.
+ * the other chains' kernels. A new batch starts at 0. Same outputs either
+ * way. The next hc_batch_run re-records its graph.
  * Set returns HC_EINVAL for 1..7. */
 hc_status hc_batch_get_mac_cap(const hc_batch *batch, uint32_t *cap);
 hc_status hc_batch_set_mac_cap(hc_batch *batch, uint32_t cap);

@@ -31,7 +31,7 @@ struct hc_cconv {
   uint32_t *d_gal = nullptr;     // [R]
   uint32_t *d_rot = nullptr;     // [R][4] (swap, d, ky, kx)
   uint32_t *d_pow3 = nullptr;    // [N/2] 3^c mod 2N
-  uint32_t *d_pt = nullptr;      // [g_out][g_in R][L][N] NTT-domain weight plaintexts
+  uint32_t *d_pt = nullptr;      // NTT-domain weight plaintexts, g_out x g_in R, blocked as launch_weight_block
   hc::MacShape mac{};
   hc::ConvGeom mg{};             // the multiply-accumulate's view: c_out = g_out, G = G_w = g_in R, T = 1
 };
@@ -138,6 +138,7 @@ hc_status hc_cconv_create(hc_ctx *c, const hc_conv_shape *s, const int8_t *filte
   mg.T = 1;
   mg.G = mg.G_w = g.g_in * g.R;
   mg.O = g_out;
+  mg.w_ld = g_out;
   const hc::MacShape cands[] = {{1, 8, 1, 4, 2, 0, 0}, {1, 4, 1, 4, 2, 0, 0}, {1, 8, 2, 4, 2, 0, 0}};
   bool found = false;
   for (const auto &m : cands)
@@ -179,7 +180,13 @@ hc_status hc_cconv_create(hc_ctx *c, const hc_conv_shape *s, const int8_t *filte
     if (e == hipSuccess) e = hc::launch_lift_plain(d_z, dst, np, c->N, 1, c->consts, st);
     if (e == hipSuccess) e = hc::launch_ntt_fwd(c->logn, sh.fe, dst, dst, np * c->L, c->consts, c->tw, st);
   }
+  // the multiply-accumulate's blocked layout
+  uint32_t *d_blk = nullptr;
+  if (e == hipSuccess) e = hipMalloc((void **)&d_blk, n_pt * LN * 4);
+  if (e == hipSuccess) e = hc::launch_weight_block(cc->d_pt, d_blk, g_out, (uint32_t)(g.g_in * R), c->L, c->N, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(cc->d_pt);
+  cc->d_pt = d_blk;
   (void)hipFree(d_f);
   (void)hipFree(d_z);
   if (e != hipSuccess) {

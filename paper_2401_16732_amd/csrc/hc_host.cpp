@@ -253,6 +253,7 @@ ConvGeom geom_of(const hc_ctx &c, const hc_conv_shape &s, const hc_layout &o) {
   uint32_t pb = 0;
   while ((1ull << pb) <= e_max) ++pb;
   g.prune_bits = std::min(pb, c.logn);
+  g.w_ld = s.c_out;
   return g;
 }
 
@@ -641,6 +642,11 @@ hc_status hc_layer_create(hc_ctx *c, const hc_conv_shape *s, const int8_t *filte
   // stored times N^-1: every sum then carries the inverse NTT's final factor,
   // and the inverse NTT of the convolution skips it
   if (e == hipSuccess) e = hc::launch_scale_ninv(ly->d_w, ly->w_elems, c->N, c->consts, hs);
+  // then in the multiply-accumulate's blocked layout (runs of channels per
+  // coefficient block and input ciphertext)
+  uint32_t *d_wb = nullptr;
+  if (e == hipSuccess) e = hipMalloc((void **)&d_wb, ly->w_elems * sizeof(uint32_t));
+  if (e == hipSuccess) e = hc::launch_weight_block(ly->d_w, d_wb, s->c_out, lay.w_cts, c->L, c->N, hs);
   // int32 filter table for the coefficient-domain conv, rows padded to 16.
   // At one image it beats the NTT path where c_n f^2 <= 2 (measured on the
   // ResNet-50 layer mix at N = 8192: exactly those layers win, all others lose).
@@ -653,8 +659,10 @@ hc_status hc_layer_create(hc_ctx *c, const hc_conv_shape *s, const int8_t *filte
   if (e == hipSuccess) e = hipMemcpyAsync(ly->d_wt, wt.data(), wt.size() * sizeof(int32_t), hipMemcpyHostToDevice, hs);
   if (e == hipSuccess) e = hipStreamSynchronize(hs);
   if (d_f) (void)hipFree(d_f);
+  (void)hipFree(ly->d_w);  // the natural-layout copy
+  ly->d_w = d_wb;
   if (e != hipSuccess) {
-    (void)hipFree(ly->d_w);
+    if (ly->d_w) (void)hipFree(ly->d_w);
     if (ly->d_wt) (void)hipFree(ly->d_wt);
     delete ly;
     return hip_fail(e, "weight encoding");
@@ -840,15 +848,11 @@ hc_status hc_batch_create(hc_ctx *c, const hc_layer *const *layers, uint32_t n, 
     e = hipStreamCreateWithFlags(&bt->side[s], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->join[s], hipEventDisableTiming);
   }
-  // the graph's MAC launches: at most 4 workgroups per compute unit, each
-  // looping over its tiles (hc_batch_set_mac_cap)
-  int cus = 0;
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e != hipSuccess) {
     hc_batch_destroy(bt);
     return hip_fail(e, "batch streams");
   }
-  bt->mac_cap = 4 * (uint32_t)cus;
+  bt->mac_cap = 0;  // one workgroup per MAC tile (hc_batch_set_mac_cap)
   *out = bt;
   return HC_OK;
 }
@@ -1058,8 +1062,7 @@ hc_status hc_batch_run_pipelined(hc_batch *bt, const uint32_t *const *ct_in, con
       hipEvent_t mac_done = bt->pev[2 * ci], inv_done = bt->pev[2 * ci + 1];
       if (ci >= nbuf) HC_HIP(hipStreamWaitEvent(sa, bt->pev[2 * (ci - nbuf) + 1], 0));  // buffer free again
       if (!hc::mac_offsets_fit(gc, sh.mac)) return fail(HC_EUNSUPPORTED, "layer too large for the MAC tile");
-      HC_HIP(hc::launch_mac(gc, sh.mac, xhat, ly->d_w + (size_t)i0 * g.G_w * c.L * c.N, ybuf, B, c.consts, c.tw,
-                            sa));
+      HC_HIP(hc::launch_mac(gc, sh.mac, xhat, ly->d_w + (size_t)i0 * 64, ybuf, B, c.consts, c.tw, sa));
       HC_HIP(hipEventRecord(mac_done, sa));
       HC_HIP(hipStreamWaitEvent(sb, mac_done, 0));
       // inverse NTT + mask + extraction of the chunk, at most kMaxTab images per launch

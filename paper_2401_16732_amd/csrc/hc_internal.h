@@ -42,6 +42,7 @@ struct ConvGeom {
   uint32_t w_pad, F;
   uint32_t ho, wo;
   uint32_t prune_bits;  // every extracted c0 coefficient index is below 2^prune_bits
+  uint32_t w_ld;        // NTT-domain weights: channels per (limb, coefficient block, input ciphertext) block
 };
 
 // Per-image buffer tables (kernel arguments by value) for groups of up to
@@ -107,13 +108,22 @@ hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, u
                               const uint32_t *yhat,
                               const uint32_t *mask, uint32_t *c0_ext, uint32_t *c1_out, uint32_t B,
                               const LimbConsts &c, const Twiddles &tw, hipStream_t st, const OutPtrs *tab = nullptr);
-// max_wgs > 0 caps the grid of the DMA-staged form (its workgroups then loop
-// over the tiles); the other forms ignore it.
+// what: weights in the blocked layout of launch_weight_block, g.w_ld channels
+// per block (a launch over channels [i0, i0 + g.c_out) of a larger layer
+// passes what + 64 i0 and keeps the layer's w_ld). max_wgs > 0 caps the grid
+// of the DMA-staged form (its workgroups then loop over the tiles); the other
+// forms ignore it.
 hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *xhat, const uint32_t *what,
                       uint32_t *yhat, uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st,
                       uint32_t max_wgs = 0);
 hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *filters, uint32_t *w, const LimbConsts &c,
                                  hipStream_t st);
+// NTT-domain weights from [c][g][l][N] (c_out channels, G_w polynomials each)
+// to the multiply-accumulate's blocked layout [l][kb][g][c][64] (kb < N / 64;
+// w_ld = c_out): per input ciphertext, the 64-coefficient blocks of
+// consecutive channels are one run. dst must not overlap src.
+hipError_t launch_weight_block(const uint32_t *src, uint32_t *dst, uint32_t c_out, uint32_t G_w, uint32_t L,
+                               uint32_t N, hipStream_t st);
 hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st);
 hipError_t launch_mask_extract(const ConvGeom &g, const uint32_t *ct_out, const uint32_t *mask, uint32_t *c0_ext,
                                uint32_t *c1_out, uint32_t B, const LimbConsts &c, hipStream_t st);

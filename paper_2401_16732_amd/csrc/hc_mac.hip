@@ -34,7 +34,9 @@ __device__ __forceinline__ void store_tile(const uint64_t (&acc)[CT][BT][2], uin
 }
 
 // Yhat[b][o][p][l][k] = sum_{gw < G_w} What[i][gw][l][k] * Xhat[b][gw T + tau][p][l][k]  mod q_l,
-// o = i T + tau.
+// o = i T + tau. The weights are stored blocked, What[l][k / 64][gw][i][k mod 64]
+// with g.w_ld channels per block (launch_weight_block): the 64 coefficients of
+// a tile's consecutive channels for one input ciphertext are one run.
 // Register-tiled form: one thread owns coefficient k and CT output channels
 // (same row tile tau) for BT images x 2 polynomials, so each input value it
 // loads is used CT times and each weight 2 BT times. A workgroup is RG x CG
@@ -77,11 +79,11 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
   const uint32_t LN = g.L * g.N;
   // Scalar bases advance by one input ciphertext per step; each (image,
   // polynomial) and each channel adds a wave-uniform byte offset (32-bit;
-  // the host guarantees BT*G*2*L*N*4 and CT*G_w*L*N*4 < 2^32), and every
-  // lane the same 4 * lane.
+  // the host guarantees BT*G*2*L*N*4 < 2^32; in the weights' block a channel
+  // is the next 256 bytes), and every lane the same 4 * lane.
   const char *xbase = (const char *)(X + ((size_t)b0 * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
-  const char *wbase = (const char *)(Wt + (size_t)i0 * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
-  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
+  const char *wbase = (const char *)(Wt + (((size_t)l * nkb + kb) * g.G_w * g.w_ld + i0) * 64);
+  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)256 * g.w_ld;  // bytes
   const uint32_t lane4 = lane * 4u;
   uint32_t xo[BT][2], wo[CT];
 #pragma unroll
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_tiled(const uint32_t *__re
   }
 #pragma unroll
   for (int cc = 0; cc < CT; ++cc)
-    wo[cc] = __builtin_amdgcn_readfirstlane(((uint32_t)cc < nc ? (uint32_t)cc : 0u) * g.G_w * LN * 4u);
+    wo[cc] = __builtin_amdgcn_readfirstlane(((uint32_t)cc < nc ? (uint32_t)cc : 0u) * 256u);
   const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
   uint64_t acc[CT][BT][2];
 #pragma unroll
@@ -370,11 +372,11 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_lds(const uint32_t *__rest
 #pragma unroll
   for (int k = 0; k < KW; ++k) {
     const uint32_t e = (tid + k * NT) * WWD, cc = e >> 8;
-    woff[k] = ((cc < ncw ? cc : 0u) * g.G_w * LN) * 4u + (e & 255u);
+    woff[k] = (cc < ncw ? cc : 0u) * 256u + (e & 255u);
   }
   const char *xbase = (const char *)(X + ((size_t)bw * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
-  const char *wbase = (const char *)(Wt + (size_t)iw * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
-  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
+  const char *wbase = (const char *)(Wt + (((size_t)l * nkb + kb) * g.G_w * g.w_ld + iw) * 64);
+  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)256 * g.w_ld;  // bytes
   const uint32_t G_w = g.G_w, last = G_w - 1;
   using CX = Chunk<XW>;
   using CW = Chunk<WWD>;
@@ -548,7 +550,7 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
   const uint32_t rg = wave % RG, cg = wave / RG;
   const uint32_t LN = g.L * g.N;
   const uint32_t G_w = g.G_w, last = G_w - 1;
-  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)4 * LN;  // bytes
+  const size_t xstep = (size_t)8 * LN * g.T, wstep = (size_t)256 * g.w_ld;  // bytes
   // this wave's operands inside a stage (words)
   const uint32_t *xs0 = (const uint32_t *)stage + (rg * BT * 2) * 64 + lane;
   const uint32_t *ws0 = (const uint32_t *)stage + (NX + cg * CT) * 64 + lane;
@@ -586,10 +588,10 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
       const uint32_t e = (tid + k * NT) * WWD, cc = e >> 8;
-      woff[k] = ((cc < ncw ? cc : 0u) * g.G_w * LN) * 4u + (e & 255u);
+      woff[k] = (cc < ncw ? cc : 0u) * 256u + (e & 255u);
     }
     const char *xbase = (const char *)(X + ((size_t)bw * g.G + tau) * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
-    const char *wbase = (const char *)(Wt + (size_t)iw * g.G_w * LN + (size_t)l * g.N + (size_t)kb * 64);
+    const char *wbase = (const char *)(Wt + (((size_t)l * nkb + kb) * g.G_w * g.w_ld + iw) * 64);
     // step gw into stage st: access k of this thread lands at byte (tid + k NT) width
     // of its operand's part of the stage = wave-uniform (wave 64 + k NT) width + lane width
     auto issue = [&](uint32_t gw, uint32_t st) {
@@ -693,12 +695,13 @@ static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w,
   return hipGetLastError();
 }
 
-// The register tile's 32-bit offsets span BT images and CT channels; the
-// LDS-staged form's span the workgroup's RG BT images and CG CT channels.
+// The register tile's 32-bit input offsets span BT images; the LDS-staged
+// form's span the workgroup's RG BT images. (The weight offsets stay inside
+// one block of channels.)
 bool mac_offsets_fit(const ConvGeom &g, const MacShape &m) {
   const uint64_t ln = (uint64_t)g.L * g.N * 4;
-  const uint64_t bi = m.lds ? (uint64_t)m.rg * m.bt : m.bt, ch = m.lds ? (uint64_t)m.cg * m.ct : m.ct;
-  return bi * g.G * 2 * ln < (1ull << 32) && ch * g.G_w * ln < (1ull << 32);
+  const uint64_t bi = m.lds ? (uint64_t)m.rg * m.bt : m.bt;
+  return bi * g.G * 2 * ln < (1ull << 32) && g.w_ld >= g.c_out;
 }
 
 // (images per thread, channels per thread, image groups, channel groups,

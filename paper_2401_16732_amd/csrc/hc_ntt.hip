@@ -184,6 +184,25 @@ __global__ void k_weight_scatter(const int8_t *__restrict__ f, uint32_t *__restr
   }
 }
 
+// [c][gw][l][N] -> [l][kb][gw][c][64], 16 bytes per thread: both sides move
+// whole 256-byte runs.
+__global__ __launch_bounds__(256) void k_weight_block(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                      uint32_t c_out, uint32_t G_w, uint32_t L, uint32_t N,
+                                                      size_t n4) {
+  const uint32_t nkb = N / 64;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t j4 = (uint32_t)(i & 15u);
+    size_t r = i >> 4;
+    const uint32_t ch = (uint32_t)(r % c_out);
+    r /= c_out;
+    const uint32_t gw = (uint32_t)(r % G_w);
+    r /= G_w;
+    const uint32_t kb = (uint32_t)(r % nkb);
+    const uint32_t l = (uint32_t)(r / nkb);
+    dst[i] = src[((((size_t)ch * G_w + gw) * L + l) * N + (size_t)kb * 64) / 4 + j4];
+  }
+}
+
 __global__ void k_fill_zero(uint32_t *p, size_t n) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -380,6 +399,16 @@ hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *f, uint32_t *w
   const size_t total = (size_t)g.c_out * g.c_in * g.f * g.f;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_weight_scatter, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, f, w, g, c);
+  return hipGetLastError();
+}
+hipError_t launch_weight_block(const uint32_t *src, uint32_t *dst, uint32_t c_out, uint32_t G_w, uint32_t L,
+                               uint32_t N, hipStream_t st) {
+  const size_t n4 = (size_t)c_out * G_w * L * N / 4;
+  if (n4 == 0) return hipSuccess;
+  if (N % 64 != 0) return hipErrorInvalidValue;
+  const size_t blocks = std::min<size_t>((n4 + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_weight_block, dim3((uint32_t)blocks), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst,
+                     c_out, G_w, L, N, n4);
   return hipGetLastError();
 }
 hipError_t launch_fill_zero(uint32_t *p, size_t n, hipStream_t st) {

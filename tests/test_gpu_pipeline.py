@@ -81,8 +81,8 @@ def test_pipelined_equals_graph_large_ring_b64(hc):
 def test_mac_grid_cap_equals_uncapped(hc, tile):
     """The batch graph with its DMA-staged MAC launches capped (workgroups that
     loop over the tiles; 8 workgroups take hundreds of tiles each, 13 rounds
-    down to 8, 264 is not a power of two, and the default of 4 per compute
-    unit) gives the uncapped graph's outputs. One batch per cap, each
+    down to 8, 264 is not a power of two, and 4 per compute unit) gives the
+    uncapped graph's outputs (a new batch's default). One batch per cap, each
     recording its graph once."""
     import torch
     N, L, t, B = 8192, 3, 2 ** 20, 16
@@ -90,14 +90,13 @@ def test_mac_grid_cap_equals_uncapped(hc, tile):
                                            N, L, t, B, 67)
     ctx.set_tuning(0, 0, *tile)
     ref = hc.Batch(ctx, layers, B)
-    default_cap = ref.mac_cap
-    assert default_cap >= 8 and default_cap % 8 == 0
-    ref.mac_cap = 0
+    assert ref.mac_cap == 0
     g0, g1 = outs()
     ref.run(ct_in, mask, g0, g1)
     torch.cuda.synchronize()
     ref.close()
-    for cap in (8, 13, 264, default_cap):
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for cap in (8, 13, 264, 4 * cus):
         print(f"MAC tile {tile}, grid cap {cap}", flush=True)
         bt = hc.Batch(ctx, layers, B)
         bt.mac_cap = cap
