@@ -123,7 +123,10 @@ def hbm_copy(torch, dev, gib, reps=5):
 
 
 # stage -> kernels launched for it (the MAC has register-tiled, LDS-staged and DMA-staged forms)
-STAGE_KERNELS = {"ntt_fwd": ("k_ntt_fwd",), "mac": ("k_mac_tiled", "k_mac_lds", "k_mac_dma"), "intt_mask_extract": ("k_intt_masked",)}
+# (on layers whose MAC also carries out c0's transform, k_mac_c0x, the inverse
+# NTT transforms c1 only and k_c0_finish adds the splits and the mask)
+STAGE_KERNELS = {"ntt_fwd": ("k_ntt_fwd",), "mac": ("k_mac_tiled", "k_mac_lds", "k_mac_dma", "k_mac_c0x"),
+                 "intt_mask_extract": ("k_intt_masked", "k_c0_finish")}
 
 
 def measured_traffic(kernel: str, tag: str):
@@ -148,22 +151,36 @@ def measured_traffic(kernel: str, tag: str):
     return val if got == cur else None
 
 
+def c0_in_mac(ly, B):
+    """Whether the layer's shapes for B images have the MAC carry out c0's
+    transform (mac_pre = 6)."""
+    return ly.tuning(B)[1][9] == 6
+
+
 def layer_counts(ly, B, N, L):
-    """Algorithmic work of one layer on B images (no scratch round trips)."""
+    """Algorithmic work of one layer on B images (no scratch round trips).
+    Inverse-NTT butterflies are counted as full transforms of every output
+    polynomial (c0's pruned stages included); where the MAC carries out c0's
+    transform they are counted in the MAC stage (bfly_c0_mac), and the
+    inverse NTT stage counts c1's only."""
     lay = ly.layout
     c_out = ly.shape[1]
     logn = int(math.log2(N))
     pin = B * lay.in_cts * 2 * L
     pout = B * lay.out_cts * 2 * L
+    pc0 = pout // 2 if c0_in_mac(ly, B) else 0
     return {
         "bfly_fwd": pin * (N // 2) * logn,
-        "bfly_inv": pout * (N // 2) * logn,
+        "bfly_inv": (pout - pc0) * (N // 2) * logn,
+        "bfly_c0_mac": pc0 * (N // 2) * logn,
         "mac": B * lay.out_cts * lay.w_cts * 2 * L * N,
         "mask": B * c_out * lay.ho * lay.wo * L,
         # bytes each kernel must move through its interface
         "bytes_fwd": pin * N * 4 * 2,
-        "bytes_mac": (c_out * lay.w_cts * L * N + B * lay.in_cts * 2 * L * N + B * lay.out_cts * 2 * L * N) * 4,
-        "bytes_inv": (B * lay.out_cts * 2 * L * N + B * lay.out_cts * L * N + B * c_out * L * lay.ho * lay.wo
+        # (Yhat: c1 only where the MAC carries out c0's transform; its partial
+        # sums, under 1% of those bytes, are left out)
+        "bytes_mac": (c_out * lay.w_cts * L * N + B * lay.in_cts * 2 * L * N + (pout - pc0) * N) * 4,
+        "bytes_inv": ((pout - pc0) * N + B * lay.out_cts * L * N + B * c_out * L * lay.ho * lay.wo
                       + B * c_out * lay.ho * lay.wo) * 4,
         # whole-path algorithmic bytes: weights once + inputs + c1 out + c0_ext out + mask
         "bytes_path": (B * (lay.in_cts * 2 * L * N + lay.out_cts * L * N + c_out * L * lay.ho * lay.wo
@@ -420,7 +437,7 @@ def cfg_resnet18_cifar(torch, dev, hconv, W, a, ctx, probe_peaks):
     for ly in layers:
         for k, v in layer_counts(ly, B, N, L).items():
             tot[k] = tot.get(k, 0) + v
-    bfly, mac = tot["bfly_fwd"] + tot["bfly_inv"], tot["mac"]
+    bfly, mac = tot["bfly_fwd"] + tot["bfly_inv"] + tot["bfly_c0_mac"], tot["mac"]
     sec = ms * 1e-3
     bytes_ = tot["bytes_path"] + tot["bytes_w"]
     res = {"workload": "resnet18_cifar HE convolution, 20 conv layers, one image, per-layer launches",
@@ -463,7 +480,7 @@ def cfg_resnet18_224_large(torch, dev, hconv, W, a, probe_peaks):
     for ly in layers:
         for k, v in layer_counts(ly, B, N, L).items():
             tot[k] = tot.get(k, 0) + v
-    bfly, mac = tot["bfly_fwd"] + tot["bfly_inv"], tot["mac"]
+    bfly, mac = tot["bfly_fwd"] + tot["bfly_inv"] + tot["bfly_c0_mac"], tot["mac"]
     sec = ms * 1e-3
     roof = roofline_of(stage, tot, len(layers), probe_peaks[0], probe_peaks[1])
     res = {"workload": "resnet18_224 HE convolution, 20 conv layers, batched HIP graph",
@@ -648,7 +665,7 @@ def main():
     for ly in layers:
         for k, v in layer_counts(ly, B, N, L).items():
             tot[k] = tot.get(k, 0) + v
-    modmul = tot["bfly_fwd"] + tot["bfly_inv"] + tot["mac"] + tot["mask"]
+    modmul = tot["bfly_fwd"] + tot["bfly_inv"] + tot["bfly_c0_mac"] + tot["mac"] + tot["mask"]
 
     # plain path: one launch sequence per layer, one image at a time, with
     # launch shapes autotuned for one image (the layers keep their B-image
@@ -732,7 +749,7 @@ def main():
         kpeak = probe["mad64_per_s"] if roof["kernel"] == "mac" else probe["butterflies_per_s"]
         ach = roof["algorithmic_ops"] / (roof["ms_total"] * 1e-3)
         roof["frac_of_probe"] = round(ach / kpeak, 4)
-    whole_alu = ((tot["bfly_fwd"] + tot["bfly_inv"]) / peaks[0] + tot["mac"] / peaks[1]) / (ms_step * 1e-3)
+    whole_alu = ((tot["bfly_fwd"] + tot["bfly_inv"] + tot["bfly_c0_mac"]) / peaks[0] + tot["mac"] / peaks[1]) / (ms_step * 1e-3)
 
     mac_cap = bt.mac_cap
     # the other workloads, after the headline's buffers are released

@@ -124,7 +124,13 @@ typedef struct {
     uint32_t inv_polys;       /* masked inverse NTT: polynomials per workgroup, sharing each twiddle
                                  load (1, or 2 when inv_elog <= 4; 0 = 1) */
     uint32_t mac_pre;         /* masked conv: inverse NTT stages the LDS- or DMA-staged MAC applies to its
-                                 outputs before storing them (0, or 5 for 4x8 tiles, N >= 4096) */
+                                 outputs before storing them (0, or 5 for 4x8 tiles, N >= 4096); 6
+                                 (DMA-staged 4x8 tiles): the MAC carries out c0's whole pruned
+                                 inverse transform (the stages inside each 64-coefficient block, then
+                                 the sum over blocks, in splits) and the inverse NTT transforms c1
+                                 only, then adds the splits and the mask - only on layers in one row
+                                 tile whose extracted c0 coefficients all lie below 64 (the paper's
+                                 small late feature maps); elsewhere it acts as 0. Same outputs. */
 } hc_tuning;
 
 /* Create a context on HIP device `hip_device`: ring degree N (power of two,

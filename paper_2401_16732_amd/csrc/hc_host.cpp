@@ -312,6 +312,9 @@ hc::Shapes hc::layer_shapes(const hc_layer *ly, uint32_t B) {
     if (t.inv_polys) s.ipw = t.inv_polys;
     if (t.mac_rows) s.mac = mac_of(t);
   }
+  // c0's transform in the MAC only where the layer allows it (a context-wide
+  // tuning applies to every layer)
+  if (s.mac.pre == hc::kMacC0 && !hc::mac_c0_ok(ly->geom)) s.mac.pre = 0;
   if (!hc::intt_masked_ok(ly->ctx->logn, s.ie, s.ipw, s.mac.pre)) s.ipw = 1;  // e.g. a tuned e = 5 under a context's 2
   return s;
 }
@@ -567,7 +570,7 @@ hc_status hc_ctx_set_tuning(hc_ctx *c, const hc_tuning *t) {
   if (t->inv_polys &&
       !hc::intt_masked_ok(c->logn, t->inv_elog ? t->inv_elog : default_inv_elog(c->logn), t->inv_polys, 0))
     return fail(HC_EUNSUPPORTED, "inverse NTT polynomials per workgroup not available for this shape");
-  if (t->mac_pre && c->logn < 12) return fail(HC_EUNSUPPORTED, "MAC epilogue stages need N >= 4096");
+  if (t->mac_pre == hc::kMacPre && c->logn < 12) return fail(HC_EUNSUPPORTED, "MAC epilogue stages need N >= 4096");
   const bool any = t->mac_rows || t->mac_cols || t->mac_row_groups || t->mac_col_groups || t->mac_depth ||
                    t->mac_lds || t->mac_pre;
   const bool all = t->mac_rows && t->mac_cols && t->mac_row_groups && t->mac_col_groups;
@@ -1135,7 +1138,8 @@ const uint32_t kMacCand[][7] = {
     {4, 8, 2, 2, 3, 1, 5}, {4, 8, 2, 2, 3, 2, 0}, {4, 8, 2, 2, 4, 2, 0}, {4, 8, 2, 2, 6, 2, 0},
     {4, 8, 4, 2, 3, 2, 0}, {4, 8, 4, 2, 4, 2, 0}, {2, 8, 4, 2, 4, 2, 0}, {4, 4, 4, 2, 4, 2, 0},
     {2, 8, 2, 2, 4, 2, 0}, {4, 4, 2, 2, 4, 2, 0}, {4, 8, 2, 2, 3, 2, 5}, {4, 8, 2, 2, 4, 2, 5},
-    {4, 8, 4, 2, 4, 2, 5}};
+    {4, 8, 4, 2, 4, 2, 5}, {4, 8, 2, 2, 3, 2, 6}, {4, 8, 2, 2, 4, 2, 6}, {4, 8, 4, 2, 3, 2, 6},
+    {4, 8, 4, 2, 4, 2, 6}};
 
 }  // namespace
 
@@ -1204,8 +1208,9 @@ hc_status hc_batch_autotune(hc_batch *bt, const uint32_t *const *ct_in, const ui
     // MAC does part of the inverse transform, so compare MAC + inverse NTT
     // totals of the best of each with and without them.
     float best_total = 1e30f;
-    for (uint32_t pre : {0u, hc::kMacPre}) {
-      if (pre && c.logn < 12) continue;
+    for (uint32_t pre : {0u, hc::kMacPre, hc::kMacC0}) {
+      if (pre == hc::kMacPre && c.logn < 12) continue;
+      if (pre == hc::kMacC0 && !hc::mac_c0_ok(g)) continue;
       float mac_ms = 1e30f, inv_ms = 1e30f;
       hc_tuning t = best;
       for (const auto &m : kMacCand) {

@@ -71,8 +71,20 @@ bool ntt_variant_ok(uint32_t logn, uint32_t elog);
 // Inverse stages (index bits 0 .. kMacPre-1) the LDS-staged MAC can apply to
 // its outputs before storing them, for the masked inverse NTT to skip.
 constexpr uint32_t kMacPre = 5;
+// mac pre = kMacC0: the MAC carries out c0's whole masked inverse transform
+// up to the final sum (layers whose extracted c0 coefficients all lie below
+// 64, in one row tile: mac_c0_ok): per 64-coefficient block the stages on
+// index bits 0..5, then the sum over the blocks, which is all the pruned
+// top stages leave of c0. It writes c0_splits(g) partial sums per (image,
+// channel, limb) into the unused c0 slot of Yhat, Yhat[b][i][0][l][64 s + j],
+// and the masked inverse NTT then transforms c1 only and finishes c0 (adds
+// the splits, the mask, and extracts).
+constexpr uint32_t kMacC0 = 6;
+bool mac_c0_ok(const ConvGeom &g);
+uint32_t c0_splits(const ConvGeom &g);
 // The masked inverse NTT with npw polynomials per workgroup (1, or 2 for
-// elog <= 4) that starts at index bit pre (0, or kMacPre for logn >= 12).
+// elog <= 4) that starts at index bit pre (0, or kMacPre for logn >= 12), or
+// that follows a MAC with pre = kMacC0.
 bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre);
 bool mac_variant_ok(const MacShape &m);
 // The MAC addresses its image and channel tiles with 32-bit byte offsets.

@@ -11,7 +11,7 @@ namespace hc {
 template <int LOGN>
 hipError_t intt_masked_logn(const ConvGeom &g, uint32_t elog, uint32_t npw, uint32_t pre, const uint32_t *y,
                             const uint32_t *m, uint32_t *c0, uint32_t *c1, uint32_t B, const LimbConsts &c,
-                            const Twiddles &tw, const OutPtrs &out, hipStream_t st);
+                            const Twiddles &tw, const OutPtrs &out, hipStream_t st, bool c1_only);
 
 #ifdef HC_INTT_MASKED_IMPL
 // Output and mask buffers are global memory; table entries are plain
@@ -28,12 +28,13 @@ using gu32 = __attribute__((address_space(1))) uint32_t;
 // exceed every extracted coefficient index); c1 is always transformed whole.
 // M: polynomials per workgroup, those of M consecutive (image, output
 // ciphertext) indices bo with the same half p and limb l; workgroup w is
-// ((pair 2 + p) L + l), bo = pair M + m. Slots past B O compute a copy of
+// ((pair 2 + p) L + l), bo = pair M + m, or (pair L + l) with p = 1 in the
+// C1O form (c1 only; c0 finished elsewhere). Slots past B O compute a copy of
 // slot 0 and store nothing. PRE: the stages on index bits below PRE were done
 // by the multiply-accumulate (Yhat holds their output). Yhat carries the
 // factor N^-1 already (the weights are stored scaled by it), so the last stage
 // does not multiply by it.
-template <int LOGN, int ELOG, int PS, int M, int PRE>
+template <int LOGN, int ELOG, int PS, int M, int PRE, bool C1O = false>
 __global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per_eu(ntt_min_waves(ELOG, M)))) void k_intt_masked(const uint32_t *yhat, const uint32_t *mask,
                                                                      uint32_t *c0_ext, uint32_t *c1_out, ConvGeom g,
                                                                      uint32_t B, LimbConsts c, Twiddles tws,
@@ -43,8 +44,8 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per
   const uint32_t tid = threadIdx.x;
   const uint32_t wg = blockIdx.x;
   const uint32_t l = wg % g.L;
-  const uint32_t p = (wg / g.L) % 2;
-  const size_t pair = wg / (2 * g.L);
+  const uint32_t p = C1O ? 1u : (wg / g.L) % 2;
+  const size_t pair = wg / ((C1O ? 1u : 2u) * g.L);
   const size_t nbo = (size_t)B * g.O;
   size_t bo[M];
   bool valid[M];
@@ -134,24 +135,35 @@ __global__ __launch_bounds__(1 << (LOGN - ELOG)) __attribute__((amdgpu_waves_per
 
 template <int LOGN, int ELOG, int PS, int M, int PRE>
 static hipError_t invm_ps(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
-                          uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
+                          uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st,
+                          bool c1_only) {
   const size_t nbo = (size_t)B * g.O;
-  const size_t nwg = (nbo + M - 1) / M * 2 * g.L;
+  const size_t nwg = (nbo + M - 1) / M * (c1_only ? 1 : 2) * g.L;
   if (nwg == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG, PS, M, PRE>), dim3((uint32_t)nwg), dim3(1 << (LOGN - ELOG)), 0, st,
-                     y, m, c0, c1, g, B, c, tw, out);
+  if (c1_only) {
+    if constexpr (PS == 0 && PRE == 0)
+      hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG, 0, M, 0, true>), dim3((uint32_t)nwg), dim3(1 << (LOGN - ELOG)), 0,
+                         st, y, m, c0, c1, g, B, c, tw, out);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((k_intt_masked<LOGN, ELOG, PS, M, PRE>), dim3((uint32_t)nwg), dim3(1 << (LOGN - ELOG)), 0, st,
+                       y, m, c0, c1, g, B, c, tw, out);
+  }
   return hipGetLastError();
 }
 template <int LOGN, int ELOG, int M, int PRE>
 static hipError_t invm_pm(const ConvGeom &g, const uint32_t *y, const uint32_t *m, uint32_t *c0, uint32_t *c1,
-                          uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
+                          uint32_t B, const LimbConsts &c, const Twiddles &tw, const OutPtrs &out, hipStream_t st,
+                          bool c1_only) {
+  if (c1_only) return invm_ps<LOGN, ELOG, 0, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st, true);
   const int ps = LOGN - (int)g.prune_bits;
-  if (ps >= 7) return invm_ps<LOGN, ELOG, 7, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 5) return invm_ps<LOGN, ELOG, 5, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 3) return invm_ps<LOGN, ELOG, 3, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 2) return invm_ps<LOGN, ELOG, 2, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
-  if (ps >= 1) return invm_ps<LOGN, ELOG, 1, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
-  return invm_ps<LOGN, ELOG, 0, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st);
+  if (ps >= 7) return invm_ps<LOGN, ELOG, 7, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
+  if (ps >= 5) return invm_ps<LOGN, ELOG, 5, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
+  if (ps >= 3) return invm_ps<LOGN, ELOG, 3, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
+  if (ps >= 2) return invm_ps<LOGN, ELOG, 2, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
+  if (ps >= 1) return invm_ps<LOGN, ELOG, 1, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
+  return invm_ps<LOGN, ELOG, 0, M, PRE>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
 }
 // Pruning fewer stages than allowed is always exact: take the largest
 // instantiated count not above LOGN - prune_bits. Two polynomials per
@@ -160,18 +172,18 @@ static hipError_t invm_pm(const ConvGeom &g, const uint32_t *y, const uint32_t *
 template <int LOGN, int ELOG>
 static hipError_t invm_t(const ConvGeom &g, uint32_t npw, uint32_t pre, const uint32_t *y, const uint32_t *m,
                          uint32_t *c0, uint32_t *c1, uint32_t B, const LimbConsts &c, const Twiddles &tw,
-                         const OutPtrs &out, hipStream_t st) {
+                         const OutPtrs &out, hipStream_t st, bool c1_only) {
   if (pre == 0) {
-    if (npw == 1) return invm_pm<LOGN, ELOG, 1, 0>(g, y, m, c0, c1, B, c, tw, out, st);
+    if (npw == 1) return invm_pm<LOGN, ELOG, 1, 0>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
     if constexpr (ELOG <= 4) {
-      if (npw == 2) return invm_pm<LOGN, ELOG, 2, 0>(g, y, m, c0, c1, B, c, tw, out, st);
+      if (npw == 2) return invm_pm<LOGN, ELOG, 2, 0>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
     }
   }
   if constexpr (LOGN >= 12) {
     if (pre == kMacPre) {
-      if (npw == 1) return invm_pm<LOGN, ELOG, 1, kMacPre>(g, y, m, c0, c1, B, c, tw, out, st);
+      if (npw == 1) return invm_pm<LOGN, ELOG, 1, kMacPre>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
       if constexpr (ELOG <= 4) {
-        if (npw == 2) return invm_pm<LOGN, ELOG, 2, kMacPre>(g, y, m, c0, c1, B, c, tw, out, st);
+        if (npw == 2) return invm_pm<LOGN, ELOG, 2, kMacPre>(g, y, m, c0, c1, B, c, tw, out, st, c1_only);
       }
     }
   }
@@ -181,17 +193,17 @@ static hipError_t invm_t(const ConvGeom &g, uint32_t npw, uint32_t pre, const ui
 template <int LOGN>
 hipError_t intt_masked_logn(const ConvGeom &g, uint32_t elog, uint32_t npw, uint32_t pre, const uint32_t *y,
                             const uint32_t *m, uint32_t *c0, uint32_t *c1, uint32_t B, const LimbConsts &c,
-                            const Twiddles &tw, const OutPtrs &out, hipStream_t st) {
+                            const Twiddles &tw, const OutPtrs &out, hipStream_t st, bool c1_only) {
   if constexpr (LOGN <= 11) {
-    if (elog == 3) return invm_t<LOGN, 3>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st);
-    if (elog == 4) return invm_t<LOGN, 4>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st);
+    if (elog == 3) return invm_t<LOGN, 3>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st, c1_only);
+    if (elog == 4) return invm_t<LOGN, 4>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st, c1_only);
   } else if constexpr (LOGN <= 13) {
-    if (elog == 3) return invm_t<LOGN, 3>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st);
-    if (elog == 4) return invm_t<LOGN, 4>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st);
-    if (elog == 5) return invm_t<LOGN, 5>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st);
+    if (elog == 3) return invm_t<LOGN, 3>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st, c1_only);
+    if (elog == 4) return invm_t<LOGN, 4>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st, c1_only);
+    if (elog == 5) return invm_t<LOGN, 5>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st, c1_only);
   } else {
-    if (elog == 4) return invm_t<LOGN, 4>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st);
-    if (elog == 5) return invm_t<LOGN, 5>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st);
+    if (elog == 4) return invm_t<LOGN, 4>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st, c1_only);
+    if (elog == 5) return invm_t<LOGN, 5>(g, npw, pre, y, m, c0, c1, B, c, tw, out, st, c1_only);
   }
   return hipErrorInvalidValue;
 }

@@ -5,5 +5,5 @@
 namespace hc {
 template hipError_t intt_masked_logn<13>(const ConvGeom &, uint32_t, uint32_t, uint32_t, const uint32_t *,
                                             const uint32_t *, uint32_t *, uint32_t *, uint32_t,
-                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t);
+                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t, bool);
 }  // namespace hc

@@ -5,11 +5,11 @@
 namespace hc {
 template hipError_t intt_masked_logn<10>(const ConvGeom &, uint32_t, uint32_t, uint32_t, const uint32_t *,
                                             const uint32_t *, uint32_t *, uint32_t *, uint32_t,
-                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t);
+                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t, bool);
 template hipError_t intt_masked_logn<11>(const ConvGeom &, uint32_t, uint32_t, uint32_t, const uint32_t *,
                                             const uint32_t *, uint32_t *, uint32_t *, uint32_t,
-                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t);
+                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t, bool);
 template hipError_t intt_masked_logn<12>(const ConvGeom &, uint32_t, uint32_t, uint32_t, const uint32_t *,
                                             const uint32_t *, uint32_t *, uint32_t *, uint32_t,
-                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t);
+                                            const LimbConsts &, const Twiddles &, const OutPtrs &, hipStream_t, bool);
 }  // namespace hc

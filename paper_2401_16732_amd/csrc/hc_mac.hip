@@ -670,6 +670,236 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
   }
 }
 
+// Multiply-accumulate that also carries out c0's masked inverse transform up
+// to its final sum (MacShape pre = kMacC0; layers with mac_c0_ok). With every
+// extracted c0 coefficient below 64, the pruned transform is the
+// Gentleman-Sande stages on index bits 0..5 inside each 64-coefficient block,
+// then the plain sum of the blocks (the top stages' sum halves). The tile is
+// k_mac_dma's (4 images x 8 channels per thread, RG x CG waves, S stages), but
+// a workgroup owns (image tile, channel tile, limb, split sp) and walks the
+// blocks kb of its split, nkb / nsplit of them. Per block: the steps over the
+// input ciphertexts as in k_mac_dma; c1's sums go to Yhat; c0's 32 sums per
+// lane (one coefficient of 32 polynomials) go through the wave's LDS region
+// so that lane (P, h) = (lane mod 32, lane / 32) holds coefficients
+// 32 h .. 32 h + 31 of polynomial P; stages on bits 0..4 run in registers
+// (twiddles per half h, both loaded as scalars), the stage on bit 5 pairs
+// lane L with L xor 32, and the block's result is added to the lane's running
+// sums in [0, 2q). At the end every lane writes its 32 sums to
+// Yhat[b][i][0][l][64 sp + 32 h ..], the unused c0 slot of its polynomial.
+template <int RG, int CG, int S>
+__global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__restrict__ X,
+                                                          const uint32_t *__restrict__ Wt,
+                                                          uint32_t *__restrict__ Y, ConvGeom g, uint32_t B,
+                                                          uint32_t nib, uint32_t nkb, LimbConsts c,
+                                                          uint32_t nsplit, const uint2 *__restrict__ twinv) {
+  constexpr int BT = 4, CT = 8;
+  constexpr int NT = 64 * RG * CG;
+  constexpr int NX = RG * BT * 2, NW = CG * CT;          // segments per step
+  constexpr int XB = NX * 256 / NT, WB = NW * 256 / NT;  // bytes per thread per step
+  static_assert(NX * 256 % NT == 0 && NW * 256 % NT == 0 && XB % 4 == 0 && WB % 4 == 0, "shares must be whole");
+  constexpr int XW = XB % 16 == 0 ? 16 : 4, WWD = WB % 16 == 0 ? 16 : 4;  // access widths
+  constexpr int KX = XB / XW, KW = WB / WWD;                              // accesses per thread per step
+  constexpr int LPS = KX + KW;
+  static_assert(S >= 2 && (S - 1) * LPS <= 63, "loads in flight beyond the vector memory counter");
+  constexpr uint32_t BUFB = (NX + NW) * 256;  // bytes per stage
+  constexpr uint32_t BUFW = BUFB / 4;
+  constexpr uint32_t RS = 68;                          // region row: 64 coefficients + 4 pad (words)
+  constexpr uint32_t EPB = RG * CG * 32 * RS * 4;      // the waves' regions (32 rows each)
+  __shared__ uint4 stage4[(S * BUFB > EPB ? S * BUFB : EPB) / 16];
+  char *stage = (char *)stage4;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t lane = tid & 63u;
+  const uint32_t rg = wave % RG, cg = wave / RG;
+  const uint32_t LN = g.L * g.N;
+  const uint32_t G_w = g.G_w, last = G_w - 1;
+  const uint32_t LOGN = 31 - __builtin_clz(g.N);
+  const size_t xstep = (size_t)8 * LN, wstep = (size_t)256 * g.w_ld;  // bytes (one row tile)
+  const uint32_t *xs0 = (const uint32_t *)stage + (rg * BT * 2) * 64 + lane;
+  const uint32_t *ws0 = (const uint32_t *)stage + (NX + cg * CT) * 64 + lane;
+  // workgroup -> (image tile, channel tile, split, limb), image tiles fastest;
+  // the workgroups of one XCD take consecutive ones
+  const uint32_t nwg = gridDim.x;
+  uint32_t wg = blockIdx.x;
+  if ((nwg & 7u) == 0) wg = (wg & 7u) * (nwg >> 3) + (wg >> 3);
+  const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
+  const uint32_t bt = wg % nbt;
+  uint32_t r = wg / nbt;
+  const uint32_t ib = r % nib;
+  r /= nib;
+  const uint32_t sp = r % nsplit;
+  const uint32_t l = r / nsplit;
+  const uint32_t bw = bt * RG * BT, iw = ib * CG * CT;
+  const uint32_t nbw = min((uint32_t)(RG * BT), B - bw), ncw = min((uint32_t)(CG * CT), g.c_out - iw);
+  uint32_t xoff[KX], woff[KW];
+#pragma unroll
+  for (int k = 0; k < KX; ++k) {
+    const uint32_t e = (tid + k * NT) * XW, seg = e >> 8, i = seg >> 1;
+    xoff[k] = (((i < nbw ? i : 0u) * g.G * 2 + (seg & 1u)) * LN) * 4u + (e & 255u);
+  }
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const uint32_t e = (tid + k * NT) * WWD, cc = e >> 8;
+    woff[k] = (cc < ncw ? cc : 0u) * 256u + (e & 255u);
+  }
+  const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l], r2p = c.r2_p[l], onep = c.one_p[l];
+  const uint32_t q2 = 2 * q, nq = 0u - q;
+  const uint32_t i0 = iw + cg * CT, b0 = bw + rg * BT;
+  const bool tile_on = i0 < g.c_out && b0 < B;  // uniform over the wave
+  const uint32_t nc = tile_on ? min((uint32_t)CT, g.c_out - i0) : 0u, nb = tile_on ? min((uint32_t)BT, B - b0) : 0u;
+  // this lane's polynomial and half in the epilogue
+  const uint32_t P = lane & 31u, h = lane >> 5, hm = 0u - h;
+  const uint32_t pcc = P / BT, pbb = P % BT;
+  uint32_t *region = (uint32_t *)stage + wave * 32 * RS;
+  uint32_t sum[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) sum[j] = 0;
+  const uint32_t kbs = nkb / nsplit, kb0 = sp * kbs;
+  for (uint32_t kb = kb0; kb < kb0 + kbs; ++kb) {
+    const char *xbase = (const char *)(X + (size_t)bw * g.G * 2 * LN + (size_t)l * g.N + (size_t)kb * 64);
+    const char *wbase = (const char *)(Wt + (((size_t)l * nkb + kb) * g.G_w * g.w_ld + iw) * 64);
+    auto issue = [&](uint32_t gw, uint32_t st) {
+      const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(xbase + gw * xstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+      const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(wbase + gw * wstep), (short)0, (int)0xffffffffu, (int)kBufferWord3);
+      char *sb = stage + st * BUFB;
+#pragma unroll
+      for (int k = 0; k < KX; ++k) load_to_lds<XW>(xr, sb + (wave * 64 + k * NT) * XW, xoff[k]);
+#pragma unroll
+      for (int k = 0; k < KW; ++k) load_to_lds<WWD>(wr, sb + NX * 256 + (wave * 64 + k * NT) * WWD, woff[k]);
+    };
+    uint64_t acc[CT][BT][2];
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+#pragma unroll
+    for (int j = 0; j < S - 1; ++j) issue(min((uint32_t)j, last), (uint32_t)j);
+    uint32_t since_fold = 0;
+    for (uint32_t g0 = 0; g0 < G_w; g0 += S) {
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const uint32_t gw = g0 + j;
+        if (gw >= G_w) break;  // uniform
+        wait_vmcnt<(S - 2) * LPS>();
+        asm volatile("s_barrier" ::: "memory");
+        issue(min(gw + S - 1, last), (uint32_t)((j + S - 1) % S));
+        const uint32_t *xs = xs0 + j * BUFW, *wsp = ws0 + j * BUFW;
+        uint32_t w[CT], x[BT][2];
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc) w[cc] = wsp[cc * 64];
+#pragma unroll
+        for (int bb = 0; bb < BT; ++bb) {
+          x[bb][0] = xs[(bb * 2) * 64];
+          x[bb][1] = xs[(bb * 2 + 1) * 64];
+        }
+#pragma unroll
+        for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+          for (int bb = 0; bb < BT; ++bb) {
+            acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
+            acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
+          }
+        if (++since_fold == fold) {
+          since_fold = 0;
+#pragma unroll
+          for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+            for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+              for (int pp = 0; pp < 2; ++pp)
+                acc[cc][bb][pp] = (uint64_t)(uint32_t)(acc[cc][bb][pp] >> 32) * r2 + (uint32_t)acc[cc][bb][pp];
+        }
+      }
+    }
+    // the loads past the last step have landed and every wave is done with
+    // the stages: they become the waves' regions
+    wait_vmcnt<0>();
+    asm volatile("s_barrier" ::: "memory");
+    // c1: the block's sums as k_mac_dma stores them
+    if (tile_on) {
+#pragma unroll
+      for (int cc = 0; cc < CT; ++cc) {
+        if ((uint32_t)cc >= nc) continue;
+#pragma unroll
+        for (int bb = 0; bb < BT; ++bb) {
+          if ((uint32_t)bb >= nb) continue;
+          uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + i0 + cc) * 2 + 1) * LN + (size_t)l * g.N + (size_t)kb * 64;
+          const __amdgpu_buffer_rsrc_t yr =
+              __builtin_amdgcn_make_buffer_rsrc((void *)y, (short)0, (int)0xffffffffu, (int)kBufferWord3);
+          __builtin_amdgcn_raw_buffer_store_b32(reduce64_lazy(acc[cc][bb][1], q, r2, r2p, onep), yr, lane * 4u, 0, 0);
+        }
+      }
+    }
+    // c0: row P of the region holds the block of polynomial P = cc BT + bb
+#pragma unroll
+    for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) region[(cc * BT + bb) * RS + lane] = reduce64_lazy(acc[cc][bb][0], q, r2, r2p, onep);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t v[32];
+    const uint4 *r4 = (const uint4 *)(region + P * RS + h * 32);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint4 t4 = r4[k];
+      v[4 * k] = t4.x, v[4 * k + 1] = t4.y, v[4 * k + 2] = t4.z, v[4 * k + 3] = t4.w;
+    }
+    // stages on bits 0..4 of j = kb 64 + 32 h + u: twiddle index
+    // 2^(LOGN-1-b) + (j >> (b+1)); the 32 >> b of a stage are contiguous,
+    // half h takes the upper 16 >> b
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1 - b)) + ((kb * 64) >> (b + 1)));
+      uint32_t d[16], hi[16], wv[16], wpv[16];
+#pragma unroll
+      for (int t = 0; t < (16 >> b); ++t) {
+        // half 1 takes the upper twiddle: w0 ^ (hm & (w0 ^ w1)), hm = -h
+        const uint64_t w0 = tw[t], w1 = tw[(16 >> b) + t];
+        const uint32_t x0 = (uint32_t)w0 ^ (uint32_t)w1, x1 = (uint32_t)(w0 >> 32) ^ (uint32_t)(w1 >> 32);
+        wv[t] = (uint32_t)w0 ^ (hm & x0);
+        wpv[t] = (uint32_t)(w0 >> 32) ^ (hm & x1);
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
+        const uint32_t A = v[u], Bv = v[u2];
+        d[k] = A - Bv + q2;
+        v[u] = csub(A + Bv, q2);
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) hi[k] = __umulhi(d[k], wpv[k >> b]);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
+        v[u2] = mad_lo_s(hi[k], nq, mul64<false>(d[k], wv[k >> b]));  // Shoup: in [0, 2q)
+      }
+    }
+    // stage on bit 5: (u, u + 32) sit in lanes (P, 0) and (P, 1); one twiddle
+    {
+      const uint64_t w5 = *(const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 6)) + kb);
+      const uint32_t w = (uint32_t)w5, wp = (uint32_t)(w5 >> 32);
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v[j], 32);
+        const uint32_t s = csub(v[j] + o, q2);
+        const uint32_t dd = o - v[j] + q2;  // u - v on the upper half
+        const uint32_t t = mad_lo_s(__umulhi(dd, wp), nq, mul64<true>(dd, w));
+        sum[j] = csub(sum[j] + (h ? t : s), q2);
+      }
+    }
+    // every wave is done with its region (the stages of the next block)
+    __syncthreads();
+  }
+  if (tile_on && pcc < nc && pbb < nb) {
+    uint4 *dst = (uint4 *)(Y + (((size_t)(b0 + pbb) * g.O + i0 + pcc) * 2) * LN + (size_t)l * g.N + sp * 64 + h * 32);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) dst[k] = make_uint4(sum[4 * k], sum[4 * k + 1], sum[4 * k + 2], sum[4 * k + 3]);
+  }
+}
+
 template <int BT, int CT, int RG, int CG, int NS, int LDS, int PRE>
 static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w, uint32_t *y, uint32_t B,
                         const LimbConsts &c, const Twiddles &tw, hipStream_t st, uint32_t max_wgs) {
@@ -679,7 +909,13 @@ static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w,
   const uint32_t nbt = (B + RG * BT - 1) / (RG * BT);
   const size_t nwg = (size_t)nib * g.T * nkb * g.L * nbt;
   if (nwg == 0) return hipSuccess;
-  if constexpr (LDS == 2) {
+  if constexpr (PRE == (int)kMacC0) {
+    static_assert(LDS == 2 && BT == 4 && CT == 8, "c0's transform in the MAC: the DMA-staged 4 x 8 tile");
+    // one workgroup per (image tile, channel tile, split, limb); no cap
+    const uint32_t ns = c0_splits(g);
+    hipLaunchKernelGGL((k_mac_c0x<RG, CG, NS>), dim3((uint32_t)((size_t)nib * nbt * ns * g.L)), dim3(64 * RG * CG),
+                       0, st, x, w, y, g, B, nib, nkb, c, ns, tw.inv);
+  } else if constexpr (LDS == 2) {
     // a cap (a multiple of 8, so that the XCD arrangement holds) turns the
     // launch into workgroups that loop over the tiles
     const size_t cap = max_wgs >= 8 ? (size_t)(max_wgs & ~7u) : nwg;
@@ -701,7 +937,25 @@ static hipError_t mac_t(const ConvGeom &g, const uint32_t *x, const uint32_t *w,
 bool mac_offsets_fit(const ConvGeom &g, const MacShape &m) {
   const uint64_t ln = (uint64_t)g.L * g.N * 4;
   const uint64_t bi = m.lds ? (uint64_t)m.rg * m.bt : m.bt;
+  if (m.pre == kMacC0 && !mac_c0_ok(g)) return false;
   return bi * g.G * 2 * ln < (1ull << 32) && g.w_ld >= g.c_out;
+}
+
+// c0's transform fits the MAC where every extracted coefficient lies in the
+// first block of 64 and the layer is one row tile (its output polynomials are
+// (image, channel), with c0 slots of N words for the partial sums).
+bool mac_c0_ok(const ConvGeom &g) { return g.T == 1 && g.prune_bits <= 6 && g.N >= 1024; }
+
+// Splits of the 64-coefficient blocks over workgroups: enough workgroups
+// (channel tiles of 16 x 2 image tiles x limbs x splits >= 1024), at most a
+// quarter of the blocks per split count. Depends on the layer only, so that
+// the MAC and the finishing pass agree for any group of its images.
+uint32_t c0_splits(const ConvGeom &g) {
+  const uint32_t nkb = g.N / 64;
+  const uint64_t base = (uint64_t)((g.c_out + 15) / 16) * 2 * g.L;
+  uint32_t s = 1;
+  while (s * 4 < nkb && base * s < 1024) s *= 2;
+  return s;
 }
 
 // (images per thread, channels per thread, image groups, channel groups,
@@ -718,7 +972,8 @@ bool mac_offsets_fit(const ConvGeom &g, const MacShape &m) {
   X(4, 8, 2, 2, 3, 1, 5) X(4, 8, 2, 2, 3, 2, 0) X(4, 8, 2, 2, 4, 2, 0) X(4, 8, 2, 2, 6, 2, 0)                   \
   X(4, 8, 4, 2, 3, 2, 0) X(4, 8, 4, 2, 4, 2, 0) X(2, 8, 4, 2, 4, 2, 0) X(4, 4, 4, 2, 4, 2, 0)                   \
   X(2, 8, 2, 2, 4, 2, 0) X(4, 4, 2, 2, 4, 2, 0) X(4, 8, 2, 2, 3, 2, 5) X(4, 8, 2, 2, 4, 2, 5)                   \
-  X(4, 8, 4, 2, 4, 2, 5)
+  X(4, 8, 4, 2, 4, 2, 5) X(4, 8, 2, 2, 3, 2, 6) X(4, 8, 2, 2, 4, 2, 6) X(4, 8, 4, 2, 3, 2, 6)                   \
+  X(4, 8, 4, 2, 4, 2, 6)
 
 bool mac_variant_ok(const MacShape &m) {
 #define HC_MAC_OK(B_, C_, R_, G_, S_, D_, P_)                                                                 \
@@ -731,7 +986,7 @@ bool mac_variant_ok(const MacShape &m) {
 
 hipError_t launch_mac(const ConvGeom &g, const MacShape &m, const uint32_t *x, const uint32_t *w, uint32_t *y,
                       uint32_t B, const LimbConsts &c, const Twiddles &tw, hipStream_t st, uint32_t max_wgs) {
-  if (m.pre && g.N < 4096) return hipErrorInvalidValue;  // the epilogue's twiddle layout needs N >= 4096
+  if (m.pre == kMacPre && g.N < 4096) return hipErrorInvalidValue;  // the epilogue's twiddle layout needs N >= 4096
 #define HC_MAC_CASE(B_, C_, R_, G_, S_, D_, P_)                                                               \
   if (m.bt == B_ && m.ct == C_ && m.rg == R_ && m.cg == G_ && m.depth == S_ && m.lds == D_ && m.pre == P_) \
     return mac_t<B_, C_, R_, G_, S_, D_, P_>(g, x, w, y, B, c, tw, st, max_wgs);

@@ -374,7 +374,43 @@ hipError_t launch_scale_ninv(uint32_t *p, size_t n, uint32_t N, const LimbConsts
 
 bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre) {
   return ntt_variant_ok(logn, elog) && (npw == 1 || (npw == 2 && elog <= 4)) &&
-         (pre == 0 || (pre == kMacPre && logn >= 12));
+         (pre == 0 || pre == kMacC0 || (pre == kMacPre && logn >= 12));
+}
+
+// c0 after a MAC with pre = kMacC0: output (b, i, l, oy, ox) (ox fastest) is
+// the sum of the splits' partial sums at its coefficient e = s w_pad oy + s ox,
+// Yhat[b][i][0][l][64 sp + e], plus Delta_l (r mod q_l), r the mask's centred
+// value - the masked inverse NTT's extraction, on the same values.
+__global__ __launch_bounds__(256) void k_c0_finish(const uint32_t *__restrict__ y, const uint32_t *__restrict__ mask,
+                                                   uint32_t *__restrict__ c0_ext, ConvGeom g, uint32_t B,
+                                                   LimbConsts c, uint32_t ns, OutPtrs out) {
+  const size_t hw = (size_t)g.ho * g.wo;
+  const size_t total = (size_t)B * g.c_out * g.L * hw;
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const uint32_t ox = (uint32_t)(id % g.wo);
+  size_t r = id / g.wo;
+  const uint32_t oy = (uint32_t)(r % g.ho);
+  r /= g.ho;
+  const uint32_t l = (uint32_t)(r % g.L);
+  r /= g.L;
+  const uint32_t i = (uint32_t)(r % g.c_out);
+  const size_t b = r / g.c_out;
+  const uint32_t q = c.q[l], q2 = 2 * q;
+  const uint32_t e = g.s * g.w_pad * oy + g.s * ox;
+  const uint32_t *src = y + ((b * g.O + i) * 2 * g.L + l) * (size_t)g.N + e;
+  uint32_t sum = 0;
+  for (uint32_t s = 0; s < ns; ++s) sum = csub(sum + src[s * 64], q2);
+  const size_t pix = (size_t)oy * g.wo + ox;
+  const uint32_t rv = out.n ? ((const uint32_t *)out.mask[b])[i * hw + pix] : mask[(b * g.c_out + i) * hw + pix];
+  const uint32_t t = c.t, half = c.t / 2;
+  const uint32_t rc = rv > half ? rv - t + q : rv;  // centred lift of r, taken mod q
+  const uint32_t add = csub(shoup_lazy(rc, c.delta[l], c.delta_p[l], q), q);
+  const uint32_t v = csub(csub(sum, q) + add, q);
+  if (out.n)
+    ((uint32_t *)out.c0[b])[((size_t)i * g.L + l) * hw + pix] = v;
+  else
+    c0_ext[((b * g.c_out + i) * g.L + l) * hw + pix] = v;
 }
 
 hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre,
@@ -384,14 +420,24 @@ hipError_t launch_intt_masked(const ConvGeom &g, uint32_t logn, uint32_t elog, u
   if (tab && (tab->n != B || B > kMaxTab)) return hipErrorInvalidValue;
   if (!intt_masked_ok(logn, elog, npw, pre)) return hipErrorInvalidValue;
   const OutPtrs &t = tab ? *tab : none;
+  // after a MAC that finished c0's transform: c1 only, then c0's finish
+  const bool c1_only = pre == kMacC0;
+  if (c1_only && !mac_c0_ok(g)) return hipErrorInvalidValue;
+  const uint32_t ipre = c1_only ? 0u : pre;
+  hipError_t e = hipErrorInvalidValue;
   switch (logn) {
-    case 10: return intt_masked_logn<10>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
-    case 11: return intt_masked_logn<11>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
-    case 12: return intt_masked_logn<12>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
-    case 13: return intt_masked_logn<13>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
-    case 14: return intt_masked_logn<14>(g, elog, npw, pre, y, m, c0, c1, B, c, tw, t, st);
+    case 10: e = intt_masked_logn<10>(g, elog, npw, ipre, y, m, c0, c1, B, c, tw, t, st, c1_only); break;
+    case 11: e = intt_masked_logn<11>(g, elog, npw, ipre, y, m, c0, c1, B, c, tw, t, st, c1_only); break;
+    case 12: e = intt_masked_logn<12>(g, elog, npw, ipre, y, m, c0, c1, B, c, tw, t, st, c1_only); break;
+    case 13: e = intt_masked_logn<13>(g, elog, npw, ipre, y, m, c0, c1, B, c, tw, t, st, c1_only); break;
+    case 14: e = intt_masked_logn<14>(g, elog, npw, ipre, y, m, c0, c1, B, c, tw, t, st, c1_only); break;
   }
-  return hipErrorInvalidValue;
+  if (e != hipSuccess || !c1_only) return e;
+  const size_t total = (size_t)B * g.c_out * g.L * g.ho * g.wo;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_c0_finish, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, y, m, c0, g, B, c,
+                     c0_splits(g), t);
+  return hipGetLastError();
 }
 
 hipError_t launch_weight_scatter(const ConvGeom &g, const int8_t *f, uint32_t *w, const LimbConsts &c,

@@ -191,7 +191,8 @@ MAC_VARIANTS = [(1, 8, 1, 4, 2, 0, 0), (1, 4, 1, 4, 2, 0, 0), (2, 4, 1, 4, 2, 0,
                 (4, 8, 2, 2, 3, 1, 5), (4, 8, 2, 2, 3, 2, 0), (4, 8, 2, 2, 4, 2, 0), (4, 8, 2, 2, 6, 2, 0),
                 (4, 8, 4, 2, 3, 2, 0), (4, 8, 4, 2, 4, 2, 0), (2, 8, 4, 2, 4, 2, 0), (4, 4, 4, 2, 4, 2, 0),
                 (2, 8, 2, 2, 4, 2, 0), (4, 4, 2, 2, 4, 2, 0), (4, 8, 2, 2, 3, 2, 5), (4, 8, 2, 2, 4, 2, 5),
-                (4, 8, 4, 2, 4, 2, 5)]
+                (4, 8, 4, 2, 4, 2, 5), (4, 8, 2, 2, 3, 2, 6), (4, 8, 2, 2, 4, 2, 6), (4, 8, 4, 2, 3, 2, 6),
+                (4, 8, 4, 2, 4, 2, 6)]
 
 
 def mac_tuning(v, inv_elog=0, inv_polys=0):
@@ -339,6 +340,52 @@ def test_pruned_inverse_shapes_every_output(hc, spec):
         c0, c1 = host(c0), host(c1)
         for b in range(B):
             assert (c0[b] == exp[b][0]).all() and (c1[b] == exp[b][1]).all(), (tune, b)
+
+
+C0_IN_MAC = [  # (N, L, t, spec): every extracted c0 coefficient below 64, one row tile
+    (8192, 3, 2 ** 20, W.ConvSpec(20, 20, 7, 7, 1, 1, "1x1 7x7 G1")),
+    (8192, 3, 2 ** 20, W.ConvSpec(400, 37, 7, 7, 1, 1, "1x1 7x7 G3")),
+    (8192, 2, 2 ** 17, W.ConvSpec(1800, 20, 7, 7, 3, 1, "3x3 7x7 G18")),
+    (8192, 3, 2 ** 20, W.ConvSpec(60, 9, 6, 6, 3, 2, "3x3 6x6 s2")),
+    (8192, 3, 2 ** 20, W.ConvSpec(30, 17, 8, 8, 1, 1, "1x1 8x8")),
+    (4096, 2, 2 ** 17, W.ConvSpec(90, 20, 4, 4, 5, 1, "5x5 4x4")),
+    (16384, 4, 2 ** 24, W.ConvSpec(700, 24, 7, 7, 1, 1, "N16384")),
+]
+
+
+@pytest.mark.parametrize("N,L,t,spec", C0_IN_MAC, ids=lambda v: v.name if hasattr(v, "name") else str(v))
+@pytest.mark.parametrize("B", [1, 5])
+def test_c0_transform_in_mac_every_output(hc, N, L, t, spec, B):
+    """The MAC tiles that carry out c0's masked inverse transform (the six
+    stages of each 64-coefficient block, the sum over blocks in splits) and
+    leave c1 to a c1-only inverse NTT, on layers whose extracted c0
+    coefficients all lie below 64: 1 to 18 input ciphertexts (a fold), ragged channel
+    and image tiles, stride 2, N = 4096 to 16384 and 2 to 4 primes, each
+    inverse shape for c1: every output against the oracle."""
+    c = _ctx(hc, N, L, t)
+    P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
+    assert not P.tiled
+    e_max = max(P.out_pos(oy, ox)[1] for oy in range(P.ho) for ox in range(P.wo))
+    assert e_max < 64, e_max
+    g = W.rng(N + spec.c_i + B)
+    f = W.gen_filters(g, spec)
+    x = W.gen_ct_limbs(g, (B, P.G, 2), c.primes, N)
+    r = W.gen_mask(g, (B, spec.c_o, P.ho, P.wo), t)
+    ly = hc.Layer(c, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride, f)
+    exp = [conv.mask_extract(calg1.alg1_layer(x[b], f, P, c.primes), r[b], P, c.primes, t) for b in range(B)]
+    dx, dr = dev(x), dev(r)
+    ws = zeros((ly.workspace_words(B, True),))
+    elogs = (4, 5) if N == 16384 else (3, 4)
+    for v in [v for v in MAC_VARIANTS if v[6] == 6]:
+        for ie, npw in [(e, 1) for e in elogs] + [(4, 2)]:
+            print(f"{spec.name} B={B} mac {v} c1 inverse e={ie} x{npw}", flush=True)
+            c.set_tuning(*mac_tuning(v, ie, npw))
+            c0, c1 = zeros(ly.c0_shape(B)), zeros(ly.c1_shape(B))
+            ly.conv_masked(dx, dr, c0, c1, B, ws)
+            c0, c1 = host(c0), host(c1)
+            for b in range(B):
+                assert (c0[b] == exp[b][0]).all(), (v, ie, npw, b, "c0")
+                assert (c1[b] == exp[b][1]).all(), (v, ie, npw, b, "c1")
 
 
 def test_resnet18_cifar_every_output(hc):

@@ -159,3 +159,38 @@ def test_dma_mac_tile_loop_ragged(hc, cap):
         bt.close()
     for ly in layers:
         ly.close()
+
+
+def test_c0_transform_in_mac_graph_eager_pipelined(hc):
+    """ResNet-50's 7x7 layers (1x1 and 3x3, one with client subsampling) with
+    the MAC tiles that carry out c0's transform: the batch graph, the eager run
+    and the two-stream pipeline over channel chunks (each chunk its own split
+    count) give the outputs of the plain tiles."""
+    import torch
+    N, L, t, B = 8192, 3, 2 ** 20, 16
+    ctx, layers, ct_in, mask, outs = _case(hc, "resnet50_224", ("s4.b0.proj", "s4.b1.c1", "s4.b1.c2", "s4.b1.c3"),
+                                           N, L, t, B, 69)
+    ctx.set_tuning(0, 0, 4, 8, 2, 2, 4, 2, 0, 0)
+    ref = hc.Batch(ctx, layers, B)
+    g0, g1 = outs()
+    ref.run(ct_in, mask, g0, g1)
+    torch.cuda.synchronize()
+    ref.close()
+    for tile in ((4, 8, 2, 2, 4, 2), (4, 8, 4, 2, 3, 2)):
+        ctx.set_tuning(0, 0, *tile, 0, 6)
+        bt = hc.Batch(ctx, layers, B)
+        for mode in ("graph", "eager", "pipelined 24 MiB x3"):
+            print(f"c0 in the MAC, tile {tile}, {mode}", flush=True)
+            p0, p1 = outs()
+            if mode == "graph":
+                bt.run(ct_in, mask, p0, p1)
+            elif mode == "eager":
+                bt.run_eager(ct_in, mask, p0, p1)
+            else:
+                bt.run_pipelined(ct_in, mask, p0, p1, chunk_bytes=24 << 20, nbuf=3)
+            torch.cuda.synchronize()
+            for k in range(len(layers)):
+                assert torch.equal(p0[k], g0[k]) and torch.equal(p1[k], g1[k]), (tile, mode, k)
+        bt.close()
+    for ly in layers:
+        ly.close()
