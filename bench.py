@@ -154,10 +154,10 @@ def measured_traffic(kernel: str, tag: str):
 def c0_in_mac(ly, B):
     """Whether the layer's shapes for B images have the MAC carry out c0's
     transform (mac_pre = 6)."""
-    return ly.tuning(B)[1][9] == 6
+    return hasattr(ly, "tuning") and ly.tuning(B)[1][9] == 6
 
 
-def layer_counts(ly, B, N, L):
+def layer_counts(ly, B, N, L, c0_mac=None):
     """Algorithmic work of one layer on B images (no scratch round trips).
     Inverse-NTT butterflies are counted as full transforms of every output
     polynomial (c0's pruned stages included); where the MAC carries out c0's
@@ -168,7 +168,7 @@ def layer_counts(ly, B, N, L):
     logn = int(math.log2(N))
     pin = B * lay.in_cts * 2 * L
     pout = B * lay.out_cts * 2 * L
-    pc0 = pout // 2 if c0_in_mac(ly, B) else 0
+    pc0 = pout // 2 if (c0_in_mac(ly, B) if c0_mac is None else c0_mac) else 0
     return {
         "bfly_fwd": pin * (N // 2) * logn,
         "bfly_inv": (pout - pc0) * (N // 2) * logn,

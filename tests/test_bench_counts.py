@@ -13,10 +13,10 @@ from paper_2401_16732_amd import hconv
 from paper_2401_16732_amd import workloads as W
 
 
-def _counts_library(spec, N, L, B):
+def _counts_library(spec, N, L, B, c0_mac=False):
     lay = hconv.plan_ring(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
     ly = types.SimpleNamespace(layout=lay, shape=(spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride))
-    return bench.layer_counts(ly, B, N, L)
+    return bench.layer_counts(ly, B, N, L, c0_mac=c0_mac)
 
 
 def _counts_rules(spec, N, L, B):
@@ -56,3 +56,19 @@ def test_resnet50_per_image_totals():
     assert round((tot["bfly_fwd"] + tot["bfly_inv"]) / 1e9, 2) == 9.08
     per_transform = (8192 // 2) * 13 * 6
     assert tot["bfly_fwd"] == 1406 * per_transform and tot["bfly_inv"] == 27008 * per_transform
+
+
+def test_counts_with_c0_in_the_mac():
+    """Where the MAC carries out c0's transform, the inverse NTT stage counts
+    c1's butterflies only and the MAC stage c0's (half each); the totals and
+    the interface bytes of the other stages are unchanged, and Yhat's c0 half
+    leaves both the MAC's and the inverse NTT's bytes."""
+    spec = W.ConvSpec(512, 2048, 7, 7, 1, 1)
+    a = _counts_library(spec, 8192, 3, 16)
+    b = _counts_library(spec, 8192, 3, 16, c0_mac=True)
+    assert a["bfly_c0_mac"] == 0
+    assert b["bfly_inv"] == b["bfly_c0_mac"] == a["bfly_inv"] // 2
+    y_c0 = 16 * 2048 * 3 * 8192 * 4
+    assert a["bytes_mac"] - b["bytes_mac"] == y_c0 and a["bytes_inv"] - b["bytes_inv"] == y_c0
+    for k in ("mac", "bfly_fwd", "mask", "bytes_fwd", "bytes_path", "bytes_w"):
+        assert a[k] == b[k], k
