@@ -76,7 +76,8 @@ constexpr uint32_t kMacPre = 5;
 // 64, in one row tile: mac_c0_ok): per 64-coefficient block the stages on
 // index bits 0..5, then the sum over the blocks, which is all the pruned
 // top stages leave of c0. It writes c0_splits(g) partial sums per (image,
-// channel, limb) into the unused c0 slot of Yhat, Yhat[b][i][0][l][64 s + j],
+// channel, limb) into the unused c0 slot of Yhat, coefficient j of split s at
+// Yhat[b][i][0][l][64 s + 32 (j mod 2) + j / 2],
 // and the masked inverse NTT then transforms c1 only and finishes c0 (adds
 // the splits, the mask, and extracts).
 constexpr uint32_t kMacC0 = 6;

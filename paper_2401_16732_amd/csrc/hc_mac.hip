@@ -680,12 +680,13 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
 // blocks kb of its split, nkb / nsplit of them. Per block: the steps over the
 // input ciphertexts as in k_mac_dma; c1's sums go to Yhat; c0's 32 sums per
 // lane (one coefficient of 32 polynomials) go through the wave's LDS region
-// so that lane (P, h) = (lane mod 32, lane / 32) holds coefficients
-// 32 h .. 32 h + 31 of polynomial P; stages on bits 0..4 run in registers
-// (twiddles per half h, both loaded as scalars), the stage on bit 5 pairs
-// lane L with L xor 32, and the block's result is added to the lane's running
-// sums in [0, 2q). At the end every lane writes its 32 sums to
-// Yhat[b][i][0][l][64 sp + 32 h ..], the unused c0 slot of its polynomial.
+// so that lane (P, h) = (lane mod 32, lane / 32) holds coefficients 2 u + h,
+// u < 32, of polynomial P; the stage on bit 0 pairs lane L with L xor 32, the
+// stages on bits 1..5 run in registers (every twiddle the same in all lanes,
+// scalar loads), and the block's result is added to the lane's running sums
+// in [0, 2q). At the end every lane writes its 32 sums to
+// Yhat[b][i][0][l][64 sp + 32 h + u], the unused c0 slot of its polynomial
+// (coefficient 2 u + h of the split's partial sum).
 template <int RG, int CG, int S>
 __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__restrict__ X,
                                                           const uint32_t *__restrict__ Wt,
@@ -748,7 +749,7 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
   const bool tile_on = i0 < g.c_out && b0 < B;  // uniform over the wave
   const uint32_t nc = tile_on ? min((uint32_t)CT, g.c_out - i0) : 0u, nb = tile_on ? min((uint32_t)BT, B - b0) : 0u;
   // this lane's polynomial and half in the epilogue
-  const uint32_t P = lane & 31u, h = lane >> 5, hm = 0u - h;
+  const uint32_t P = lane & 31u, h = lane >> 5;
   const uint32_t pcc = P / BT, pbb = P % BT;
   uint32_t *region = (uint32_t *)stage + wave * 32 * RS;
   uint32_t sum[32];
@@ -769,11 +770,8 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
 #pragma unroll
       for (int k = 0; k < KW; ++k) load_to_lds<WWD>(wr, sb + NX * 256 + (wave * 64 + k * NT) * WWD, woff[k]);
     };
+    // (the first step sets the accumulators: no zeroing pass per block)
     uint64_t acc[CT][BT][2];
-#pragma unroll
-    for (int cc = 0; cc < CT; ++cc)
-#pragma unroll
-      for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
 #pragma unroll
     for (int j = 0; j < S - 1; ++j) issue(min((uint32_t)j, last), (uint32_t)j);
     uint32_t since_fold = 0;
@@ -794,13 +792,23 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
           x[bb][0] = xs[(bb * 2) * 64];
           x[bb][1] = xs[(bb * 2 + 1) * 64];
         }
+        if (j == 0 && gw == 0) {
 #pragma unroll
-        for (int cc = 0; cc < CT; ++cc)
+          for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-          for (int bb = 0; bb < BT; ++bb) {
-            acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
-            acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
-          }
+            for (int bb = 0; bb < BT; ++bb) {
+              acc[cc][bb][0] = (uint64_t)w[cc] * x[bb][0];
+              acc[cc][bb][1] = (uint64_t)w[cc] * x[bb][1];
+            }
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+            for (int bb = 0; bb < BT; ++bb) {
+              acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
+              acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
+            }
+        }
         if (++since_fold == fold) {
           since_fold = 0;
 #pragma unroll
@@ -832,11 +840,14 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
         }
       }
     }
-    // c0: row P of the region holds the block of polynomial P = cc BT + bb
+    // c0: row P of the region holds the block of polynomial P = cc BT + bb,
+    // deinterleaved (coefficient k at column 32 (k mod 2) + k / 2), so that
+    // lane (P, h) reads coefficients 2 u + h, u < 32, as one run
+    const uint32_t col = (lane & 1u) * 32u + (lane >> 1);
 #pragma unroll
     for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-      for (int bb = 0; bb < BT; ++bb) region[(cc * BT + bb) * RS + lane] = reduce64_lazy(acc[cc][bb][0], q, r2, r2p, onep);
+      for (int bb = 0; bb < BT; ++bb) region[(cc * BT + bb) * RS + col] = reduce64_lazy(acc[cc][bb][0], q, r2, r2p, onep);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -847,21 +858,27 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
       const uint4 t4 = r4[k];
       v[4 * k] = t4.x, v[4 * k + 1] = t4.y, v[4 * k + 2] = t4.z, v[4 * k + 3] = t4.w;
     }
-    // stages on bits 0..4 of j = kb 64 + 32 h + u: twiddle index
-    // 2^(LOGN-1-b) + (j >> (b+1)); the 32 >> b of a stage are contiguous,
-    // half h takes the upper 16 >> b
+    // stage on bit 0: (2u, 2u + 1) sit in lanes (P, 0) and (P, 1); twiddle
+    // index 2^(LOGN-1) + 32 kb + u, the same for both
+    {
+      const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1)) + kb * 32);
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        const uint64_t wu = tw[u];
+        const uint32_t o = (uint32_t)__shfl_xor((int)v[u], 32);
+        const uint32_t sm = csub(v[u] + o, q2);
+        const uint32_t dd = o - v[u] + q2;  // x_2u - x_2u+1 on the upper half
+        const uint32_t t = mad_lo_s(__umulhi(dd, (uint32_t)(wu >> 32)), nq, mul64<true>(dd, (uint32_t)wu));
+        v[u] = h ? t : sm;
+      }
+    }
+    // stages on bits 1..5 of j = 64 kb + 2u + h, bits 0..4 of u, in registers:
+    // twiddle index 2^(LOGN-1-b) + (j >> (b+1)) = 2^(LOGN-1-b) + 2^(5-b) kb +
+    // (u >> b) for bit b, the same in every lane
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
-      const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1 - b)) + ((kb * 64) >> (b + 1)));
-      uint32_t d[16], hi[16], wv[16], wpv[16];
-#pragma unroll
-      for (int t = 0; t < (16 >> b); ++t) {
-        // half 1 takes the upper twiddle: w0 ^ (hm & (w0 ^ w1)), hm = -h
-        const uint64_t w0 = tw[t], w1 = tw[(16 >> b) + t];
-        const uint32_t x0 = (uint32_t)w0 ^ (uint32_t)w1, x1 = (uint32_t)(w0 >> 32) ^ (uint32_t)(w1 >> 32);
-        wv[t] = (uint32_t)w0 ^ (hm & x0);
-        wpv[t] = (uint32_t)(w0 >> 32) ^ (hm & x1);
-      }
+      const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 2 - b)) + ((kb * 64) >> (b + 2)));
+      uint32_t d[16], hi[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
@@ -870,26 +887,15 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
         v[u] = csub(A + Bv, q2);
       }
 #pragma unroll
-      for (int k = 0; k < 16; ++k) hi[k] = __umulhi(d[k], wpv[k >> b]);
+      for (int k = 0; k < 16; ++k) hi[k] = __umulhi(d[k], (uint32_t)(tw[k >> b] >> 32));
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
-        v[u2] = mad_lo_s(hi[k], nq, mul64<false>(d[k], wv[k >> b]));  // Shoup: in [0, 2q)
+        v[u2] = mad_lo_s(hi[k], nq, mul64<true>(d[k], (uint32_t)tw[k >> b]));  // Shoup: in [0, 2q)
       }
     }
-    // stage on bit 5: (u, u + 32) sit in lanes (P, 0) and (P, 1); one twiddle
-    {
-      const uint64_t w5 = *(const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 6)) + kb);
-      const uint32_t w = (uint32_t)w5, wp = (uint32_t)(w5 >> 32);
 #pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        const uint32_t o = (uint32_t)__shfl_xor((int)v[j], 32);
-        const uint32_t s = csub(v[j] + o, q2);
-        const uint32_t dd = o - v[j] + q2;  // u - v on the upper half
-        const uint32_t t = mad_lo_s(__umulhi(dd, wp), nq, mul64<true>(dd, w));
-        sum[j] = csub(sum[j] + (h ? t : s), q2);
-      }
-    }
+    for (int u = 0; u < 32; ++u) sum[u] = csub(sum[u] + v[u], q2);
     // every wave is done with its region (the stages of the next block)
     __syncthreads();
   }

@@ -379,8 +379,9 @@ bool intt_masked_ok(uint32_t logn, uint32_t elog, uint32_t npw, uint32_t pre) {
 
 // c0 after a MAC with pre = kMacC0: output (b, i, l, oy, ox) (ox fastest) is
 // the sum of the splits' partial sums at its coefficient e = s w_pad oy + s ox,
-// Yhat[b][i][0][l][64 sp + e], plus Delta_l (r mod q_l), r the mask's centred
-// value - the masked inverse NTT's extraction, on the same values.
+// Yhat[b][i][0][l][64 sp + 32 (e mod 2) + e / 2], plus Delta_l (r mod q_l), r
+// the mask's centred value - the masked inverse NTT's extraction, on the same
+// values.
 __global__ __launch_bounds__(256) void k_c0_finish(const uint32_t *__restrict__ y, const uint32_t *__restrict__ mask,
                                                    uint32_t *__restrict__ c0_ext, ConvGeom g, uint32_t B,
                                                    LimbConsts c, uint32_t ns, OutPtrs out) {
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(256) void k_c0_finish(const uint32_t *__restrict__ 
   const size_t b = r / g.c_out;
   const uint32_t q = c.q[l], q2 = 2 * q;
   const uint32_t e = g.s * g.w_pad * oy + g.s * ox;
-  const uint32_t *src = y + ((b * g.O + i) * 2 * g.L + l) * (size_t)g.N + e;
+  const uint32_t *src = y + ((b * g.O + i) * 2 * g.L + l) * (size_t)g.N + (e & 1u) * 32u + (e >> 1);
   uint32_t sum = 0;
   for (uint32_t s = 0; s < ns; ++s) sum = csub(sum + src[s * 64], q2);
   const size_t pix = (size_t)oy * g.wo + ox;

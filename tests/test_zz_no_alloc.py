@@ -89,3 +89,24 @@ def test_noalloc_refuses_a_layer_beyond_its_scratch(hc):
     assert P.O == 2048
     ly.close()
     c.close()
+
+
+def test_noalloc_with_c0_transform_in_the_mac(hc):
+    """A 7x7 layer whose MAC carries out c0's transform (mac_pre = 6: c0's
+    partial sums in the scratch's Yhat, c1-only inverse NTT, finishing pass):
+    two no-allocation calls in a row (3 images, then 1) equal the workspace
+    path's and the oracle's outputs."""
+    N, L, t = 8192, 3, 2 ** 20
+    c = hc.Context(N, L, t)
+    c.set_tuning(0, 0, 4, 8, 2, 2, 4, 2, 0, 6)
+    spec = W.ConvSpec(400, 40, 7, 7, 1, 1, "7x7")
+    for B, seed in ((3, 903), (1, 904)):
+        P, f, x, r, ly = _case(hc, c, spec, B, seed)
+        assert ly.workspace_words(B, True) * 4 <= hc.Layer.NOALLOC_SCRATCH_BYTES
+        print(f"noalloc with c0 in the MAC: 400->40 7x7, B={B}", flush=True)
+        (a0, a1), (b0, b1) = _both(ly, x, r, B)
+        assert (a0 == b0).all() and (a1 == b1).all()
+        e0, e1 = conv.mask_extract(calg1.alg1_layer(x[B - 1], f, P, c.primes), r[B - 1], P, c.primes, t)
+        assert (a0[B - 1] == e0).all() and (a1[B - 1] == e1).all()
+        ly.close()
+    c.close()
