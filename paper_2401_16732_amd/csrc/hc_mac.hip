@@ -606,11 +606,16 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
       for (int k = 0; k < KW; ++k) load_to_lds<WWD>(wr, sb + NX * 256 + (wave * 64 + k * NT) * WWD, woff[k]);
     };
     const uint32_t q = c.q[l], r2 = c.r2[l], fold = c.fold[l];
+    // (without epilogue stages the first step sets the accumulators: no
+    // zeroing pass per tile; with them the registers are too tight for two
+    // forms of the step)
     uint64_t acc[CT][BT][2];
+    if constexpr (PRE != 0) {
 #pragma unroll
-    for (int cc = 0; cc < CT; ++cc)
+      for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-      for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+        for (int bb = 0; bb < BT; ++bb) acc[cc][bb][0] = acc[cc][bb][1] = 0;
+    }
 #pragma unroll
     for (int j = 0; j < S - 1; ++j) issue(min((uint32_t)j, last), (uint32_t)j);
     uint32_t since_fold = 0;
@@ -631,13 +636,23 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
           x[bb][0] = xs[(bb * 2) * 64];
           x[bb][1] = xs[(bb * 2 + 1) * 64];
         }
+        if (PRE == 0 && j == 0 && gw == 0) {
 #pragma unroll
-        for (int cc = 0; cc < CT; ++cc)
+          for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-          for (int bb = 0; bb < BT; ++bb) {
-            acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
-            acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
-          }
+            for (int bb = 0; bb < BT; ++bb) {
+              acc[cc][bb][0] = (uint64_t)w[cc] * x[bb][0];
+              acc[cc][bb][1] = (uint64_t)w[cc] * x[bb][1];
+            }
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+            for (int bb = 0; bb < BT; ++bb) {
+              acc[cc][bb][0] += (uint64_t)w[cc] * x[bb][0];
+              acc[cc][bb][1] += (uint64_t)w[cc] * x[bb][1];
+            }
+        }
         if (++since_fold == fold) {
           since_fold = 0;
 #pragma unroll
