@@ -350,6 +350,8 @@ C0_IN_MAC = [  # (N, L, t, spec): every extracted c0 coefficient below 64, one r
     (8192, 3, 2 ** 20, W.ConvSpec(30, 17, 8, 8, 1, 1, "1x1 8x8")),
     (4096, 2, 2 ** 17, W.ConvSpec(90, 20, 4, 4, 5, 1, "5x5 4x4")),
     (16384, 4, 2 ** 24, W.ConvSpec(700, 24, 7, 7, 1, 1, "N16384")),
+    (2048, 2, 2 ** 17, W.ConvSpec(40, 12, 5, 5, 3, 1, "N2048")),
+    (1024, 1, 3, W.ConvSpec(30, 10, 4, 4, 3, 1, "N1024 L1")),
 ]
 
 
@@ -360,7 +362,7 @@ def test_c0_transform_in_mac_every_output(hc, N, L, t, spec, B):
     stages of each 64-coefficient block, the sum over blocks in splits) and
     leave c1 to a c1-only inverse NTT, on layers whose extracted c0
     coefficients all lie below 64: 1 to 18 input ciphertexts (a fold), ragged channel
-    and image tiles, stride 2, N = 4096 to 16384 and 2 to 4 primes, each
+    and image tiles, stride 2, N = 1024 to 16384 and 1 to 4 primes, each
     inverse shape for c1: every output against the oracle."""
     c = _ctx(hc, N, L, t)
     P = layout.plan(N, spec.c_i, spec.c_o, spec.h, spec.w, spec.f_w, spec.stride)
@@ -375,7 +377,7 @@ def test_c0_transform_in_mac_every_output(hc, N, L, t, spec, B):
     exp = [conv.mask_extract(calg1.alg1_layer(x[b], f, P, c.primes), r[b], P, c.primes, t) for b in range(B)]
     dx, dr = dev(x), dev(r)
     ws = zeros((ly.workspace_words(B, True),))
-    elogs = (4, 5) if N == 16384 else (3, 4)
+    elogs = (4, 5) if N == 16384 else (3, 4)  # shapes every ring size has
     for v in [v for v in MAC_VARIANTS if v[6] == 6]:
         for ie, npw in [(e, 1) for e in elogs] + [(4, 2)]:
             print(f"{spec.name} B={B} mac {v} c1 inverse e={ie} x{npw}", flush=True)
