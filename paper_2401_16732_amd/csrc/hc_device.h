@@ -26,7 +26,10 @@ __device__ __forceinline__ uint32_t shoup_lazy(uint32_t a, uint32_t w, uint32_t 
   uint32_t Q = __umulhi(a, wp);
   return a * w - Q * q;  // in [0, 2q) for any a < 2^32
 }
-__device__ __forceinline__ uint32_t csub(uint32_t a, uint32_t m) { return a >= m ? a - m : a; }
+// a >= m ? a - m : a, for any a, m < 2^32: when a < m the wrapped a - m is
+// above a, so the unsigned minimum picks a (one subtraction and one minimum,
+// no compare writing the condition mask)
+__device__ __forceinline__ uint32_t csub(uint32_t a, uint32_t m) { return min(a, a - m); }
 
 // v_mad_u64_u32 (a * b + c over 64 bits) issues at the rate of a 32-bit
 // multiply. Shoup's product a w - floor(a w' / 2^32) q only needs its low 32

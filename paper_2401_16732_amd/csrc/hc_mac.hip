@@ -5,6 +5,28 @@
 namespace hc {
 
 // ---------------------------------------------------------------- multiply-accumulate
+// reduce64_lazy of sums pp of a register tile, with the first multiply-add of
+// every sum issued before the second ones (no multiply-add waits on the one
+// just before it); the same values as reduce64_lazy
+template <int CT, int BT>
+__device__ __forceinline__ void reduce_tile_lazy(uint64_t (&acc)[CT][BT][2], int pp, uint32_t (&out)[CT][BT],
+                                                 uint32_t q, uint32_t r2, uint32_t r2p, uint32_t onep) {
+  uint32_t Q[CT][BT];
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) {
+      const uint64_t a = acc[cc][bb][pp];
+      const uint32_t hi = (uint32_t)(a >> 32), lo = (uint32_t)a;
+      Q[cc][bb] = __umulhi(hi, r2p) + __umulhi(lo, onep);
+      acc[cc][bb][pp] = mad64_s(hi, r2, a);
+    }
+#pragma unroll
+  for (int cc = 0; cc < CT; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) out[cc][bb] = csub(mad_lo_s(Q[cc][bb], 0u - q, acc[cc][bb][pp]), 2 * q);
+}
+
 // A wave's tile of sums leaves as Yhat values in [0, 2q) (the inverse NTT's
 // input range): nc channels x nb images x 2 polynomials, 64 coefficients from
 // kb 64, lane `lane4 / 4` storing one. Each polynomial segment is a raw buffer
@@ -248,12 +270,15 @@ __device__ __forceinline__ void pre_epilogue(const uint64_t (&acc)[CT][BT][2], u
         d[k] = X - Yv + q2;
         v[u] = csub(X + Yv, q2);
       }
+      uint64_t dw[16];  // (the products first: no multiply waits on the one before it)
 #pragma unroll
       for (int k = 0; k < 16; ++k) hi[k] = __umulhi(d[k], (uint32_t)(tw[k >> b] >> 32));
 #pragma unroll
+      for (int k = 0; k < 16; ++k) dw[k] = mul64<true>(d[k], (uint32_t)tw[k >> b]);
+#pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
-        v[u2] = mad_lo_s(hi[k], nq, mul64<true>(d[k], (uint32_t)tw[k >> b]));  // Shoup: in [0, 2q)
+        v[u2] = mad_lo_s(hi[k], nq, dw[k]);  // Shoup: in [0, 2q)
       }
     }
     // back through the wave's region so that every store instruction
@@ -696,7 +721,8 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_dma(const uint32_t *__rest
 // input ciphertexts as in k_mac_dma; c1's sums go to Yhat; c0's 32 sums per
 // lane (one coefficient of 32 polynomials) go through the wave's LDS region
 // so that lane (P, h) = (lane mod 32, lane / 32) holds coefficients 2 u + h,
-// u < 32, of polynomial P; the stage on bit 0 pairs lane L with L xor 32, the
+// u < 32, of polynomial P; the stage on bit 0 pairs lane L with L xor 32
+// (swaps of the wave's halves, one butterfly per lane, per-lane twiddles), the
 // stages on bits 1..5 run in registers (every twiddle the same in all lanes,
 // scalar loads), and the block's result is added to the lane's running sums
 // in [0, 2q). At the end every lane writes its 32 sums to
@@ -841,6 +867,8 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
     wait_vmcnt<0>();
     asm volatile("s_barrier" ::: "memory");
     // c1: the block's sums as k_mac_dma stores them
+    uint32_t red[CT][BT];
+    reduce_tile_lazy<CT, BT>(acc, 1, red, q, r2, r2p, onep);
     if (tile_on) {
 #pragma unroll
       for (int cc = 0; cc < CT; ++cc) {
@@ -851,18 +879,27 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
           uint32_t *y = Y + (((size_t)(b0 + bb) * g.O + i0 + cc) * 2 + 1) * LN + (size_t)l * g.N + (size_t)kb * 64;
           const __amdgpu_buffer_rsrc_t yr =
               __builtin_amdgcn_make_buffer_rsrc((void *)y, (short)0, (int)0xffffffffu, (int)kBufferWord3);
-          __builtin_amdgcn_raw_buffer_store_b32(reduce64_lazy(acc[cc][bb][1], q, r2, r2p, onep), yr, lane * 4u, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(red[cc][bb], yr, lane * 4u, 0, 0);
         }
       }
+    }
+    // the stage on bit 0's twiddles for this lane's butterflies, index
+    // 2^(LOGN-1) + 32 kb + 16 h + u for u < 16 ({w, w'} of u = 2k, 2k + 1 in w4[k])
+    uint4 w4[8];
+    {
+      const uint4 *tw4 = (const uint4 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1)) + kb * 32 + h * 16);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w4[k] = tw4[k];
     }
     // c0: row P of the region holds the block of polynomial P = cc BT + bb,
     // deinterleaved (coefficient k at column 32 (k mod 2) + k / 2), so that
     // lane (P, h) reads coefficients 2 u + h, u < 32, as one run
     const uint32_t col = (lane & 1u) * 32u + (lane >> 1);
+    reduce_tile_lazy<CT, BT>(acc, 0, red, q, r2, r2p, onep);
 #pragma unroll
     for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-      for (int bb = 0; bb < BT; ++bb) region[(cc * BT + bb) * RS + col] = reduce64_lazy(acc[cc][bb][0], q, r2, r2p, onep);
+      for (int bb = 0; bb < BT; ++bb) region[(cc * BT + bb) * RS + col] = red[cc][bb];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -873,19 +910,21 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
       const uint4 t4 = r4[k];
       v[4 * k] = t4.x, v[4 * k + 1] = t4.y, v[4 * k + 2] = t4.z, v[4 * k + 3] = t4.w;
     }
-    // stage on bit 0: (2u, 2u + 1) sit in lanes (P, 0) and (P, 1); twiddle
-    // index 2^(LOGN-1) + 32 kb + u, the same for both
-    {
-      const_u64 *tw = (const_u64 *)(twinv + (size_t)l * g.N + (1u << (LOGN - 1)) + kb * 32);
+    // stage on bit 0: (2u, 2u + 1) sit in lanes (P, 0) and (P, 1) of v[u]. A
+    // swap of the wave's halves between v[u] and v[u + 16] (u < 16) gives lane
+    // (P, 0) the pair of u and lane (P, 1) the pair of u + 16, so every lane
+    // computes one whole butterfly; a second swap restores the layout
 #pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        const uint64_t wu = tw[u];
-        const uint32_t o = (uint32_t)__shfl_xor((int)v[u], 32);
-        const uint32_t sm = csub(v[u] + o, q2);
-        const uint32_t dd = o - v[u] + q2;  // x_2u - x_2u+1 on the upper half
-        const uint32_t t = mad_lo_s(__umulhi(dd, (uint32_t)(wu >> 32)), nq, mul64<true>(dd, (uint32_t)wu));
-        v[u] = h ? t : sm;
-      }
+    for (int u = 0; u < 16; ++u) {
+      const auto p = __builtin_amdgcn_permlane32_swap(v[u], v[u + 16], false, false);
+      const uint32_t e = p[0], o = p[1];
+      const uint4 w2 = w4[u >> 1];
+      const uint32_t w = (u & 1) ? w2.z : w2.x, wp = (u & 1) ? w2.w : w2.y;
+      const uint32_t s = csub(e + o, q2);
+      const uint32_t t = shoup_mad<false>(e - o + q2, w, wp, nq);
+      const auto r = __builtin_amdgcn_permlane32_swap(s, t, false, false);
+      v[u] = r[0];
+      v[u + 16] = r[1];
     }
     // stages on bits 1..5 of j = 64 kb + 2u + h, bits 0..4 of u, in registers:
     // twiddle index 2^(LOGN-1-b) + (j >> (b+1)) = 2^(LOGN-1-b) + 2^(5-b) kb +
@@ -901,12 +940,15 @@ __global__ __launch_bounds__(64 * RG * CG) void k_mac_c0x(const uint32_t *__rest
         d[k] = A - Bv + q2;
         v[u] = csub(A + Bv, q2);
       }
+      uint64_t dw[16];  // (the products first: no multiply waits on the one before it)
 #pragma unroll
       for (int k = 0; k < 16; ++k) hi[k] = __umulhi(d[k], (uint32_t)(tw[k >> b] >> 32));
 #pragma unroll
+      for (int k = 0; k < 16; ++k) dw[k] = mul64<true>(d[k], (uint32_t)tw[k >> b]);
+#pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int u = ((k >> b) << (b + 1)) | (k & ((1 << b) - 1)), u2 = u | (1 << b);
-        v[u2] = mad_lo_s(hi[k], nq, mul64<true>(d[k], (uint32_t)tw[k >> b]));  // Shoup: in [0, 2q)
+        v[u2] = mad_lo_s(hi[k], nq, dw[k]);  // Shoup: in [0, 2q)
       }
     }
 #pragma unroll
